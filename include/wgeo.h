@@ -1,0 +1,206 @@
+/*
+ * wgeo.h -- C ABI of the MI355X grid-Poisson SDF library (libwgeo.so).
+ *
+ * The library reconstructs a signed distance field and surface normals on a
+ * uniform 3-D grid from an oriented point cloud, following Warp-Geo
+ * (arXiv 2609.20964):
+ *
+ *   splat the point normals to the 27 cells around each point (Sec. 2.3,
+ *   Eq. 23-25) -> divergence b (Eq. 22, 26) -> Poisson solve A chi = b with
+ *   zero-flux boundaries (Eq. 19-21) -> iso-value c (Sec. 2.4) -> Marching
+ *   Cubes surface (Eq. 27-28) -> exact distance to that surface with the
+ *   inside/outside sign on every grid node (Eq. 29-34) -> trilinear sampling of
+ *   the SDF and of its grid gradient (normals, Sec. 2.4 after Eq. 32).
+ *
+ * The reverse pass follows Sec. 2.5 (Eq. 35-39): one adjoint solve with A^T
+ * (= A), no stored solver iterates.
+ *
+ * Conventions
+ *   - Grid: n[0] x n[1] x n[2] cubic cells of edge h starting at lo; unknowns
+ *     at cell centres lo + (i + 1/2) h.  Grid scalars are [n2][n1][n0]
+ *     (x fastest).  Each n[d] >= 4.
+ *   - Points, normals and queries are float32 [count][3] (x, y, z).
+ *   - Every d_* pointer is DEVICE memory owned by the caller.  The library
+ *     never frees it and never allocates user-visible outputs.
+ *   - Calls enqueue work on the handle's HIP stream.  The only host waits are
+ *     inside the Poisson solve (convergence read-backs) and after surface
+ *     extraction (triangle count); outputs are ready once the stream reaches
+ *     them (synchronise the stream before reading them on the host).
+ *   - Return codes: WG_OK (0), WG_PENDING (> 0, wg_poll only) or a negative
+ *     WG_E* value; wg_last_error() gives this thread's last message.  No C++
+ *     exception crosses the ABI.
+ *   - A handle is not thread-safe: one caller thread at a time.
+ */
+#ifndef WGEO_H
+#define WGEO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WG_OK = 0,
+    WG_PENDING = 1,     /* wg_poll: request admitted or queued, not finished     */
+    WG_EINVAL = -1,     /* bad pointer, size, option, or a point outside the grid */
+    WG_ENOMEM = -2,     /* device allocation failed / footprint above the budget  */
+    WG_ENOTCONV = -3,   /* non-fatal: outputs written, stats.rel_res says how far */
+    WG_ENUMERIC = -4,   /* NaN or Inf met in a reduction                           */
+    WG_EDEVICE = -5,    /* HIP runtime error                                       */
+    WG_ESTATE = -6      /* call order (backward without forward, unknown ticket)  */
+};
+
+enum { WG_BC_NEUMANN = 0, WG_BC_DIRICHLET = 1 };
+
+typedef struct {
+    int n[3];           /* cells per axis (x, y, z), each >= 4                    */
+    double lo[3];       /* world position of the grid's lower corner              */
+    double h;           /* cell edge                                               */
+} wg_grid;
+
+typedef struct {
+    double rel_tol;     /* stop at ||P b - A chi||_2 <= rel_tol ||P b||_2 (FP64)  */
+    int max_iters;      /* cap on inner preconditioned-CG iterations, all refinements */
+    int warm_start;     /* 1: start from the handle's last solution               */
+    int reserved0;      /* must be 0                                               */
+    int reserved1;      /* must be 0                                               */
+} wg_solve_opts;
+
+typedef struct {
+    int iters;              /* inner PCG iterations (all refinement steps)        */
+    int refinements;        /* FP64 residual evaluations                           */
+    double rel_res;         /* final FP64 relative residual                        */
+    double iso_c;           /* iso-value c, for the zero-mean field chi            */
+    double chi_mean;        /* mean removed from the stored FP64 solution          */
+    int64_t n_tris;         /* Marching Cubes triangles                            */
+    int status;             /* WG_OK or WG_ENOTCONV                                */
+    float ms[8];            /* 0 splat, 1 solve, 2 iso, 3 surface, 4 sdf, 5 sample,
+                               6 reverse-sampling/surface adjoint, 7 adjoint solve+splat */
+    size_t bytes_resident;  /* device bytes held by the handle                     */
+} wg_stats;
+
+typedef struct wg_recon wg_recon;
+typedef struct wg_server wg_server;
+
+/* ---------------------------------------------------------------------------
+ * Reconstruction handle
+ * ------------------------------------------------------------------------- */
+
+/* Allocate the resident state for one grid and up to max_points points
+ * (splat buffers, FP64 solution, solver and multigrid vectors, SDF grid,
+ * surface buffers).  hip_stream: a hipStream_t (NULL = default stream).
+ * Returns WG_EINVAL for n[d] < 4 or h <= 0, WG_ENOMEM if allocation fails. */
+int wg_recon_create(wg_recon **out, const wg_grid *grid, int max_points, void *hip_stream);
+
+/* Footprint (bytes) that wg_recon_create would allocate. */
+size_t wg_recon_footprint(const wg_grid *grid, int max_points);
+
+/* Forward reconstruction (Sec. 2.3-2.4): bins the points, splats their normals,
+ * forms b, solves A chi = b to opts->rel_tol with FP32 sweeps, FP64 reductions
+ * and FP64 residual refinement, takes the iso-value, extracts the surface and
+ * writes the signed distance to every grid node.  d_xyz, d_nrm: [n_points][3]
+ * float32 (copied into the handle).  A point whose cell
+ * floor((x - lo)/h) (FP64) falls outside the grid gives WG_EINVAL.
+ * Returns WG_ENOTCONV (results written) if max_iters stopped the solve. */
+int wg_recon_forward(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_points,
+                     const wg_solve_opts *opts, wg_stats *stats);
+
+/* Sample the last forward's SDF at n_q query points (trilinear in the node
+ * values) and the unit normal grad(phi)/|grad(phi)| (grid central differences,
+ * one-sided on boundary cells, interpolated trilinearly; 0 where the gradient
+ * vanishes).  d_q: [n_q][3]; d_phi: [n_q]; d_nrm_out: [n_q][3] or NULL.
+ * Queries outside the grid's cell-centre box are clamped to it. */
+int wg_sample_sdf_normals(wg_recon *r, const float *d_q, int n_q, float *d_phi, float *d_nrm_out);
+
+/* Reverse pass (Sec. 2.5, Eq. 35-39) of the last forward + sampling at d_q:
+ * given dL/dphi(q) (d_gphi, [n_q]) and optionally dL/dn(q) (d_gnrm, [n_q][3]
+ * or NULL), writes dL/dx (d_gxyz, [n_points][3]) and dL/dn_i (d_gnrm_pts,
+ * [n_points][3]) for the points of the last forward, and dL/dq (d_gq,
+ * [n_q][3], or NULL).  Runs one adjoint Poisson solve with opts.
+ * Gradients hold almost everywhere: the central cell of each point is kept
+ * fixed, Marching Cubes cases and nearest triangles are those of the forward.
+ * WG_ESTATE if no forward has run on r. */
+int wg_recon_backward(wg_recon *r, const float *d_q, int n_q, const float *d_gphi,
+                      const float *d_gnrm, float *d_gxyz, float *d_gnrm_pts, float *d_gq,
+                      const wg_solve_opts *opts, wg_stats *stats);
+
+/* Standalone Poisson solve on r's grid (Eq. 20-21): A x = b with bc
+ * WG_BC_NEUMANN (zero flux; b is projected to zero mean and x returned with
+ * zero mean) or WG_BC_DIRICHLET (cell-centred ghost = -x; test mode).
+ * d_b: [N] float32; d_x: [N] float64, used as the initial guess when
+ * opts->warm_start is set, overwritten with the solution. */
+int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc,
+                     const wg_solve_opts *opts, wg_stats *stats);
+
+/* Copies of resident fields from the last forward: d_b float32 [N] (the
+ * right-hand side), d_chi float64 [N] (zero mean), d_phi float32 [N],
+ * d_keys int32 [n_points] (linear central-cell index i + n0 (j + n1 k)).
+ * Any pointer may be NULL. */
+int wg_get_fields(wg_recon *r, float *d_b, double *d_chi, float *d_phi, int32_t *d_keys);
+
+/* Copy of the last forward's triangles: d_tris float32 [n_tris][9] (three
+ * vertices in grid units, cell centre (i,j,k) at (i,j,k)), d_info int32
+ * [n_tris][2] (dual-cube linear index, 3 local edge ids packed 4 bits each).
+ * max_tris bounds the copy; *n_tris receives the total. */
+int wg_get_mesh(wg_recon *r, float *d_tris, int32_t *d_info, int64_t max_tris, int64_t *n_tris);
+
+void wg_recon_destroy(wg_recon *r);
+
+/* Device pointer of the handle's HIP stream (hipStream_t). */
+void *wg_recon_stream(wg_recon *r);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of reconstructions of uneven sizes
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    wg_grid grid;
+    const float *d_xyz;     /* [n_points][3] device; copied at submit            */
+    const float *d_nrm;     /* [n_points][3] device; copied at submit            */
+    int n_points;
+    const float *d_q;       /* [n_q][3] device; copied at submit                 */
+    int n_q;
+    const float *d_gphi;    /* [n_q] dL/dphi(q) (copied), or NULL: no reverse pass */
+    wg_solve_opts opts;
+    /* caller-owned device outputs, written before wg_poll reports WG_OK */
+    float *d_phi;           /* [n_q]                                             */
+    float *d_nrm_out;       /* [n_q][3] or NULL                                  */
+    float *d_gxyz;          /* [n_points][3], used iff d_gphi != NULL            */
+    float *d_gnrm_pts;      /* [n_points][3], used iff d_gphi != NULL            */
+} wg_request;
+
+typedef struct {
+    int status;             /* WG_OK / WG_ENOTCONV / error of this request       */
+    wg_stats stats;
+    double t_submit;        /* seconds on the server's monotonic clock            */
+    double t_start;         /* admitted to a slot                                 */
+    double t_done;          /* outputs complete on the device                     */
+} wg_result;
+
+/* Start a server on `device` with at most max_inflight concurrent requests,
+ * each on its own stream, and a device-memory budget for resident handles. */
+int wg_server_create(wg_server **out, size_t hbm_budget_bytes, int max_inflight, int device);
+
+/* Queue a request (inputs are copied before return); *ticket identifies it.
+ * WG_ENOMEM if the request alone exceeds the budget. */
+int wg_submit(wg_server *s, const wg_request *req, uint64_t *ticket);
+
+/* WG_PENDING while the request runs; otherwise its final status with *out
+ * filled, after which the ticket is released.  WG_ESTATE for unknown tickets. */
+int wg_poll(wg_server *s, uint64_t ticket, wg_result *out);
+
+/* Seconds on the server's clock (same origin as wg_result times). */
+double wg_server_now(wg_server *s);
+
+/* Waits for all queued requests, then stops the worker threads. */
+void wg_server_destroy(wg_server *s);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *wg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WGEO_H */

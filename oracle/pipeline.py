@@ -45,8 +45,10 @@ class Recon:
 
     # -- forward --------------------------------------------------------------
     def phi_nodes(self, lin):
-        lin = np.unique(np.asarray(lin, np.int64))
-        todo = lin[~self.have[lin]]
+        """phi at linear node indices ``lin`` (in the given order)."""
+        lin = np.asarray(lin, np.int64)
+        uniq = np.unique(lin)
+        todo = uniq[~self.have[uniq]]
         if len(todo):
             phi, arg, bary, _ = S.sdf_nodes(self.grid, self.chi, self.c, self.mesh, todo)
             self.phi.reshape(-1)[todo] = phi

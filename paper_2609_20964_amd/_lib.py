@@ -1,0 +1,127 @@
+"""ctypes binding of libwgeo.so: struct layouts, signatures and error mapping.
+
+Argument marshalling only; every step of the reconstruction runs in the HIP
+library.  The binding refuses to run without the built library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwgeo.so")
+
+WG_OK, WG_PENDING = 0, 1
+WG_EINVAL, WG_ENOMEM, WG_ENOTCONV, WG_ENUMERIC, WG_EDEVICE, WG_ESTATE = -1, -2, -3, -4, -5, -6
+WG_BC_NEUMANN, WG_BC_DIRICHLET = 0, 1
+CODE_NAMES = {WG_EINVAL: "WG_EINVAL", WG_ENOMEM: "WG_ENOMEM", WG_ENOTCONV: "WG_ENOTCONV",
+              WG_ENUMERIC: "WG_ENUMERIC", WG_EDEVICE: "WG_EDEVICE", WG_ESTATE: "WG_ESTATE"}
+
+
+class WgGrid(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("lo", C.c_double * 3), ("h", C.c_double)]
+
+
+class WgSolveOpts(C.Structure):
+    _fields_ = [("rel_tol", C.c_double), ("max_iters", C.c_int), ("warm_start", C.c_int),
+                ("reserved0", C.c_int), ("reserved1", C.c_int)]
+
+
+class WgStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("refinements", C.c_int), ("rel_res", C.c_double),
+                ("iso_c", C.c_double), ("chi_mean", C.c_double), ("n_tris", C.c_int64),
+                ("status", C.c_int), ("ms", C.c_float * 8), ("bytes_resident", C.c_size_t)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "refinements": self.refinements, "rel_res": self.rel_res,
+                "iso_c": self.iso_c, "chi_mean": self.chi_mean, "n_tris": self.n_tris,
+                "status": self.status, "ms": list(self.ms), "bytes_resident": self.bytes_resident}
+
+
+class WgRequest(C.Structure):
+    _fields_ = [("grid", WgGrid), ("d_xyz", C.c_void_p), ("d_nrm", C.c_void_p), ("n_points", C.c_int),
+                ("d_q", C.c_void_p), ("n_q", C.c_int), ("d_gphi", C.c_void_p), ("opts", WgSolveOpts),
+                ("d_phi", C.c_void_p), ("d_nrm_out", C.c_void_p), ("d_gxyz", C.c_void_p),
+                ("d_gnrm_pts", C.c_void_p)]
+
+
+class WgResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("stats", WgStats), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class WgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{CODE_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "wg_last_error": (C.c_char_p, []),
+    "wg_recon_footprint": (C.c_size_t, [C.POINTER(WgGrid), C.c_int]),
+    "wg_recon_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(WgGrid), C.c_int, C.c_void_p]),
+    "wg_recon_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
+                                   C.POINTER(WgStats)]),
+    "wg_sample_sdf_normals": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "wg_recon_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.POINTER(WgSolveOpts), C.POINTER(WgStats)]),
+    "wg_poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
+                                   C.POINTER(WgStats)]),
+    "wg_get_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "wg_get_mesh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "wg_recon_destroy": (None, [C.c_void_p]),
+    "wg_recon_stream": (C.c_void_p, [C.c_void_p]),
+    "wg_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int, C.c_int]),
+    "wg_submit": (C.c_int, [C.c_void_p, C.POINTER(WgRequest), C.POINTER(C.c_uint64)]),
+    "wg_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(WgResult)]),
+    "wg_server_now": (C.c_double, [C.c_void_p]),
+    "wg_server_destroy": (None, [C.c_void_p]),
+}
+
+
+def lib():
+    """Load libwgeo.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_20964_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    m = lib().wg_last_error()
+    return m.decode() if m else ""
+
+
+def check(rc, allow=(WG_OK,)):
+    """Raise WgError for a negative code not in ``allow``; return rc."""
+    if rc < 0 and rc not in allow:
+        raise WgError(rc, last_error())
+    return rc
+
+
+def make_grid(n, lo=(0.0, 0.0, 0.0), h=None):
+    if isinstance(n, int):
+        n = (n, n, n)
+    g = WgGrid()
+    g.n[:] = [int(v) for v in n]
+    g.lo[:] = [float(v) for v in lo]
+    g.h = float(1.0 / max(n) if h is None else h)
+    return g
+
+
+def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False):
+    o = WgSolveOpts()
+    o.rel_tol = float(rel_tol)
+    o.max_iters = int(max_iters)
+    o.warm_start = int(bool(warm_start))
+    return o

@@ -1,0 +1,56 @@
+// Reconstruction handle (internal): owns the resident device state of one
+// grid and drives the forward and reverse passes.
+#pragma once
+
+#include "kernels.h"
+#include "solver.h"
+#include "surface.h"
+
+namespace wg {
+
+class Recon {
+  public:
+    Recon(const wg_grid &g, int max_points, hipStream_t s);
+    ~Recon();
+    static size_t footprint(const wg_grid &g, int max_points);
+
+    int forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st);
+    int sample(const float *q, int nq, float *phi, float *nrm);
+    int backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
+                 float *gq, const wg_solve_opts &o, wg_stats *st);
+    int poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st);
+    int get_fields(float *b, double *chi, float *phi, int32_t *keys);
+    int get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tris);
+
+    size_t bytes_resident() const;
+    const wg_grid &grid() const { return grid_; }
+    int max_points() const { return max_points_; }
+    hipStream_t stream() const { return st_; }
+
+  private:
+    static void plan(Arena &a, const wg_grid &g, int max_points);
+    void check_err(const char *what);
+
+    wg_grid grid_;
+    int max_points_;
+    hipStream_t st_;
+    Dims d_{};
+    GridF gf_{};
+    Arena arena_;
+    Solver solver_;
+    Surface surf_;
+    float *b_ = nullptr, *phi_ = nullptr, *gphi_ = nullptr, *gchi_ = nullptr;
+    double *chi_ = nullptr, *lam_ = nullptr, *iso_part_ = nullptr, *scal_ = nullptr;
+    int32_t *argmin_ = nullptr, *keys_ = nullptr;
+    float *xyz_ = nullptr, *nrm_ = nullptr;
+    int *err_ = nullptr, *herr_ = nullptr;
+    double *hscal_ = nullptr;
+    int n_points_ = 0;
+    bool have_forward_ = false;
+    double chi_mean_ = 0.0, iso_c_ = 0.0;
+};
+
+void set_error(const std::string &m);
+const char *last_error();
+
+}  // namespace wg

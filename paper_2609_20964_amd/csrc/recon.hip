@@ -1,0 +1,402 @@
+// Reconstruction handle: resident device state and the forward / reverse
+// drivers behind the C ABI (include/wgeo.h).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "recon.h"
+
+namespace wg {
+
+namespace {
+
+constexpr int kIsoBlocks = 512;
+
+__global__ void k_copy_shift(const double *x, double by, double *out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = x[i] - by;
+}
+
+__global__ void k_shift_scalar(const double *in, double by, double *out) { out[0] = in[0] - by; }
+
+struct Timer {
+    hipEvent_t ev[9];
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        for (auto &e : ev) WG_HIP(hipEventCreate(&e));
+    }
+    ~Timer() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(int k) { WG_HIP(hipEventRecord(ev[k], s)); }
+    float between(int a, int b) {
+        float ms = 0.f;
+        WG_HIP(hipEventElapsedTime(&ms, ev[a], ev[b]));
+        return ms;
+    }
+};
+
+}  // namespace
+
+size_t Recon::footprint(const wg_grid &g, int max_points) {
+    Arena a;
+    plan(a, g, max_points);
+    // initial triangle / box buffers of the surface
+    size_t face = (size_t)g.n[0] * g.n[1];
+    if ((size_t)g.n[1] * g.n[2] > face) face = (size_t)g.n[1] * g.n[2];
+    if ((size_t)g.n[0] * g.n[2] > face) face = (size_t)g.n[0] * g.n[2];
+    size_t tris = 4 * face;
+    return a.planned() + (tris + tris / 4 + 64) * (3 * 16 + 8) + (face / 2) * 32;
+}
+
+void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
+    const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    Dims d{g.n[0], g.n[1], g.n[2], -1};
+    a.reserve(N * sizeof(float));        // b
+    a.reserve(N * sizeof(double));       // chi
+    a.reserve(N * sizeof(float));        // phi
+    a.reserve(N * sizeof(int32_t));      // argmin
+    a.reserve(N * sizeof(float));        // g_phi (reverse)
+    a.reserve(N * sizeof(float));        // g_chi (reverse)
+    a.reserve(N * sizeof(double));       // lambda (reverse)
+    a.reserve((size_t)max_points * 3 * sizeof(float));       // points
+    a.reserve((size_t)max_points * 3 * sizeof(float));       // normals
+    a.reserve((size_t)max_points * sizeof(int32_t));          // keys
+    a.reserve(kIsoBlocks * sizeof(double));
+    a.reserve(8 * sizeof(double));       // scalars: c, c_shifted, g_c
+    a.reserve(4 * sizeof(int));          // error flags
+    Solver::plan(a, d.nx, d.ny, d.nz);
+    Surface::plan(a, d);
+}
+
+Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_points_(max_points), st_(s) {
+    require(g.n[0] >= 4 && g.n[1] >= 4 && g.n[2] >= 4, WG_EINVAL, "each grid extent must be >= 4");
+    require(g.h > 0 && std::isfinite(g.h), WG_EINVAL, "grid spacing must be positive");
+    require(max_points >= 0, WG_EINVAL, "max_points must be >= 0");
+    require((double)g.n[0] * g.n[1] * g.n[2] < 2.0e9, WG_EINVAL, "grid too large for 32-bit cell indices");
+    d_ = Dims{g.n[0], g.n[1], g.n[2], -1};
+    gf_.d = d_;
+    for (int a = 0; a < 3; ++a) gf_.lo[a] = g.lo[a];
+    gf_.h = g.h;
+    plan(arena_, g, max_points);
+    arena_.allocate();
+    const size_t N = d_.count();
+    b_ = arena_.take<float>(N);
+    chi_ = arena_.take<double>(N);
+    phi_ = arena_.take<float>(N);
+    argmin_ = arena_.take<int32_t>(N);
+    gphi_ = arena_.take<float>(N);
+    gchi_ = arena_.take<float>(N);
+    lam_ = arena_.take<double>(N);
+    xyz_ = arena_.take<float>((size_t)max_points * 3);
+    nrm_ = arena_.take<float>((size_t)max_points * 3);
+    keys_ = arena_.take<int32_t>((size_t)max_points);
+    iso_part_ = arena_.take<double>(kIsoBlocks);
+    scal_ = arena_.take<double>(8);
+    err_ = arena_.take<int>(4);
+    solver_.bind(arena_, d_.nx, d_.ny, d_.nz, st_);
+    surf_.bind(arena_, d_, st_);
+    WG_HIP(hipHostMalloc((void **)&herr_, 4 * sizeof(int), hipHostMallocDefault));
+    WG_HIP(hipHostMalloc((void **)&hscal_, 8 * sizeof(double), hipHostMallocDefault));
+    WG_HIP(hipMemsetAsync(chi_, 0, N * sizeof(double), st_));
+    WG_HIP(hipStreamSynchronize(st_));
+}
+
+Recon::~Recon() {
+    if (herr_) (void)hipHostFree(herr_);
+    if (hscal_) (void)hipHostFree(hscal_);
+}
+
+size_t Recon::bytes_resident() const { return arena_.planned() + surf_.bytes(); }
+
+void Recon::check_err(const char *what) {
+    WG_HIP(hipMemcpyAsync(herr_, err_, 4 * sizeof(int), hipMemcpyDeviceToHost, st_));
+    WG_HIP(hipStreamSynchronize(st_));
+    if (herr_[0] & 1) throw Error(WG_EINVAL, std::string(what) + ": a point lies outside the grid");
+    if (herr_[0] & 2) throw Error(WG_EDEVICE, std::string(what) + ": distance traversal stack overflow");
+}
+
+int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st) {
+    require(npts >= 0 && npts <= max_points_, WG_EINVAL, "n_points outside [0, max_points]");
+    require(npts == 0 || (xyz && nrm), WG_EINVAL, "null point or normal pointer");
+    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    have_forward_ = false;
+    const size_t N = d_.count();
+    Timer tm(st_);
+    tm.mark(0);
+    WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
+    WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
+    if (npts > 0) {
+        k_splat_div<<<cdiv(npts, 256), 256, 0, st_>>>(xyz, nrm, npts, gf_, b_, keys_, xyz_, nrm_, err_);
+        WG_LAUNCH_CHECK();
+    }
+    check_err("splat");
+    tm.mark(1);
+    n_points_ = npts;
+    SolveResult sr = solver_.solve(b_, chi_, WG_BC_NEUMANN, o);
+    if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the Poisson solve");
+    chi_mean_ = sr.x_mean;
+    tm.mark(2);
+    // iso-value c = mean of chi_h at the points (0 without points)
+    if (npts > 0) {
+        unsigned nb = cdiv(npts, 256);
+        if (nb > (unsigned)kIsoBlocks) nb = kIsoBlocks;
+        k_iso_partial<<<nb, 256, 0, st_>>>(xyz_, npts, gf_, chi_, iso_part_);
+        k_iso_finalize<<<1, 256, 0, st_>>>(iso_part_, nb, npts, scal_);
+    } else {
+        WG_HIP(hipMemsetAsync(scal_, 0, sizeof(double), st_));
+        k_shift_scalar<<<1, 1, 0, st_>>>(scal_, -chi_mean_, scal_);
+    }
+    WG_LAUNCH_CHECK();
+    tm.mark(3);
+    surf_.extract(chi_, scal_);
+    tm.mark(4);
+    surf_.sdf(chi_, scal_, grid_.h, phi_, argmin_, err_);
+    tm.mark(5);
+    WG_HIP(hipMemcpyAsync(hscal_, scal_, sizeof(double), hipMemcpyDeviceToHost, st_));
+    check_err("sdf");
+    iso_c_ = hscal_[0];
+    have_forward_ = true;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iters = sr.iters;
+        st->refinements = sr.refinements;
+        st->rel_res = sr.rel_res;
+        st->iso_c = iso_c_ - chi_mean_;
+        st->chi_mean = chi_mean_;
+        st->n_tris = surf_.n_tris();
+        st->status = sr.status;
+        for (int k = 0; k < 5; ++k) st->ms[k] = tm.between(k, k + 1);
+        st->bytes_resident = bytes_resident();
+    }
+    return sr.status;
+}
+
+int Recon::sample(const float *q, int nq, float *phi, float *nrm) {
+    require(have_forward_, WG_ESTATE, "sample before a successful forward");
+    require(nq >= 0 && (nq == 0 || (q && phi)), WG_EINVAL, "bad query arguments");
+    launch_sample(gf_, phi_, q, nq, phi, nrm, st_);
+    return WG_OK;
+}
+
+int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
+                    float *gq, const wg_solve_opts &o, wg_stats *st) {
+    require(have_forward_, WG_ESTATE, "backward before a successful forward");
+    require(nq >= 0 && (nq == 0 || (q && gphi_q)), WG_EINVAL, "bad query arguments");
+    require(n_points_ == 0 || (gxyz && gnrm_pts), WG_EINVAL, "null point-gradient outputs");
+    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    const size_t N = d_.count();
+    Timer tm(st_);
+    tm.mark(0);
+    WG_HIP(hipMemsetAsync(gphi_, 0, N * sizeof(float), st_));
+    WG_HIP(hipMemsetAsync(gchi_, 0, N * sizeof(float), st_));
+    WG_HIP(hipMemsetAsync(scal_ + 2, 0, sizeof(double), st_));   // g_c
+    // B1: transposed sampling
+    launch_sample_T(gf_, phi_, q, nq, gphi_q, gnrm_q, gphi_, gq, st_);
+    // B2: distance and vertex reverse -> g_chi, g_c
+    surf_.sdf_T(gphi_, chi_, scal_, argmin_, grid_.h, gchi_, scal_ + 2);
+    // B3: iso-value reverse into the field
+    if (n_points_ > 0) {
+        k_iso_T<<<cdiv(n_points_, 256), 256, 0, st_>>>(xyz_, n_points_, gf_, scal_ + 2, gchi_);
+        WG_LAUNCH_CHECK();
+    }
+    tm.mark(1);
+    // B4: adjoint solve A lambda = P g_chi (A symmetric), from zero
+    wg_solve_opts ao = o;
+    ao.warm_start = 0;
+    SolveResult sr = solver_.solve(gchi_, lam_, WG_BC_NEUMANN, ao);
+    if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the adjoint solve");
+    // B5 + B6: transposed divergence and splat, plus the iso-value point term
+    if (n_points_ > 0) {
+        k_splat_T<<<cdiv(n_points_, 256), 256, 0, st_>>>(xyz_, nrm_, keys_, n_points_, gf_, lam_, chi_, scal_ + 2,
+                                                         gxyz, gnrm_pts);
+        WG_LAUNCH_CHECK();
+    }
+    tm.mark(2);
+    WG_HIP(hipStreamSynchronize(st_));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iters = sr.iters;
+        st->refinements = sr.refinements;
+        st->rel_res = sr.rel_res;
+        st->iso_c = iso_c_ - chi_mean_;
+        st->chi_mean = chi_mean_;
+        st->n_tris = surf_.n_tris();
+        st->status = sr.status;
+        st->ms[6] = tm.between(0, 1);
+        st->ms[7] = tm.between(1, 2);
+        st->bytes_resident = bytes_resident();
+    }
+    return sr.status;
+}
+
+int Recon::poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st) {
+    require(b && x, WG_EINVAL, "null pointer");
+    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    Timer tm(st_);
+    tm.mark(0);
+    SolveResult sr = solver_.solve(b, x, bc, o);
+    if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the Poisson solve");
+    if (bc == WG_BC_NEUMANN && sr.x_mean != 0.0) solver_.shift(x, sr.x_mean);
+    tm.mark(1);
+    WG_HIP(hipStreamSynchronize(st_));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iters = sr.iters;
+        st->refinements = sr.refinements;
+        st->rel_res = sr.rel_res;
+        st->status = sr.status;
+        st->ms[1] = tm.between(0, 1);
+        st->bytes_resident = bytes_resident();
+    }
+    return sr.status;
+}
+
+int Recon::get_fields(float *b, double *chi, float *phi, int32_t *keys) {
+    require(have_forward_, WG_ESTATE, "no forward result");
+    const size_t N = d_.count();
+    if (b) WG_HIP(hipMemcpyAsync(b, b_, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    if (chi) {
+        k_copy_shift<<<cdiv(N, 256) < 4096 ? cdiv(N, 256) : 4096, 256, 0, st_>>>(chi_, chi_mean_, chi, N);
+        WG_LAUNCH_CHECK();
+    }
+    if (phi) WG_HIP(hipMemcpyAsync(phi, phi_, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    if (keys && n_points_ > 0)
+        WG_HIP(hipMemcpyAsync(keys, keys_, (size_t)n_points_ * sizeof(int32_t), hipMemcpyDeviceToDevice, st_));
+    return WG_OK;
+}
+
+int Recon::get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tris) {
+    require(have_forward_, WG_ESTATE, "no forward result");
+    const int64_t T = surf_.n_tris();
+    if (n_tris) *n_tris = T;
+    const int64_t m = T < max_tris ? T : max_tris;
+    if (m > 0 && tris)
+        WG_HIP(hipMemcpy2DAsync(tris, 3 * sizeof(float), surf_.tris(), sizeof(float4), 3 * sizeof(float),
+                                (size_t)m * 3, hipMemcpyDeviceToDevice, st_));
+    if (m > 0 && info)
+        WG_HIP(hipMemcpyAsync(info, surf_.tri_info(), (size_t)m * sizeof(int2), hipMemcpyDeviceToDevice, st_));
+    return WG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// error channel
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &m) { g_last_error = m; }
+const char *last_error() { return g_last_error.c_str(); }
+
+}  // namespace wg
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+struct wg_recon {
+    wg::Recon *impl;
+    hipStream_t stream;
+};
+
+template <class F>
+static int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const wg::Error &e) {
+        wg::set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        wg::set_error("host allocation failed");
+        return WG_ENOMEM;
+    } catch (const std::exception &e) {
+        wg::set_error(e.what());
+        return WG_EDEVICE;
+    } catch (...) {
+        wg::set_error("unknown failure");
+        return WG_EDEVICE;
+    }
+}
+
+extern "C" {
+
+const char *wg_last_error(void) { return wg::last_error(); }
+
+size_t wg_recon_footprint(const wg_grid *grid, int max_points) {
+    if (!grid) return 0;
+    return wg::Recon::footprint(*grid, max_points);
+}
+
+int wg_recon_create(wg_recon **out, const wg_grid *grid, int max_points, void *hip_stream) {
+    return guarded([&] {
+        wg::require(out && grid, WG_EINVAL, "null argument");
+        *out = nullptr;
+        auto *r = new wg_recon{nullptr, (hipStream_t)hip_stream};
+        try {
+            r->impl = new wg::Recon(*grid, max_points, (hipStream_t)hip_stream);
+        } catch (...) {
+            delete r;
+            throw;
+        }
+        *out = r;
+        return WG_OK;
+    });
+}
+
+void wg_recon_destroy(wg_recon *r) {
+    if (!r) return;
+    if (r->stream) (void)hipStreamSynchronize(r->stream);
+    else (void)hipDeviceSynchronize();
+    delete r->impl;
+    delete r;
+}
+
+void *wg_recon_stream(wg_recon *r) { return r ? (void *)r->stream : nullptr; }
+
+int wg_recon_forward(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_points, const wg_solve_opts *opts,
+                     wg_stats *stats) {
+    return guarded([&] {
+        wg::require(r && opts, WG_EINVAL, "null argument");
+        return r->impl->forward(d_xyz, d_nrm, n_points, *opts, stats);
+    });
+}
+
+int wg_sample_sdf_normals(wg_recon *r, const float *d_q, int n_q, float *d_phi, float *d_nrm_out) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        return r->impl->sample(d_q, n_q, d_phi, d_nrm_out);
+    });
+}
+
+int wg_recon_backward(wg_recon *r, const float *d_q, int n_q, const float *d_gphi, const float *d_gnrm,
+                      float *d_gxyz, float *d_gnrm_pts, float *d_gq, const wg_solve_opts *opts, wg_stats *stats) {
+    return guarded([&] {
+        wg::require(r && opts, WG_EINVAL, "null argument");
+        return r->impl->backward(d_q, n_q, d_gphi, d_gnrm, d_gxyz, d_gnrm_pts, d_gq, *opts, stats);
+    });
+}
+
+int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc, const wg_solve_opts *opts,
+                     wg_stats *stats) {
+    return guarded([&] {
+        wg::require(r && opts, WG_EINVAL, "null argument");
+        wg::require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
+        return r->impl->poisson(d_b, d_x, bc, *opts, stats);
+    });
+}
+
+int wg_get_fields(wg_recon *r, float *d_b, double *d_chi, float *d_phi, int32_t *d_keys) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        return r->impl->get_fields(d_b, d_chi, d_phi, d_keys);
+    });
+}
+
+int wg_get_mesh(wg_recon *r, float *d_tris, int32_t *d_info, int64_t max_tris, int64_t *n_tris) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        return r->impl->get_mesh(d_tris, d_info, max_tris, n_tris);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+// Serving: continuous batching of reconstructions of uneven grid and point
+// counts (wg_server_* / wg_submit / wg_poll in include/wgeo.h).
+//
+// Requests queue in arrival order.  max_inflight worker threads each take the
+// next request as soon as they are free, so requests that arrive while others
+// run are admitted the moment a slot and device memory allow.  A request runs
+// on a reconstruction handle taken from a pool of idle handles keyed by grid
+// geometry and point capacity: grids and solver state stay resident between
+// requests of the same size class.  Creating a handle is admitted only if the
+// bytes of all resident handles stay within the HBM budget; idle handles of
+// other classes are evicted (least recently used first) to make room, and a
+// worker waits when everything resident is busy.  Every handle owns its own
+// HIP stream, so the kernels of concurrent requests overlap on the device.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+
+#include "recon.h"
+
+namespace wg {
+
+namespace {
+
+struct Key {
+    int n[3];
+    double lo[3], h;
+    int cap;
+    bool operator<(const Key &o) const {
+        return std::tie(n[0], n[1], n[2], lo[0], lo[1], lo[2], h, cap) <
+               std::tie(o.n[0], o.n[1], o.n[2], o.lo[0], o.lo[1], o.lo[2], o.h, o.cap);
+    }
+};
+
+int capacity_class(int npts) {
+    int c = 1 << 14;
+    while (c < npts) c <<= 1;
+    return c;
+}
+
+struct Handle {
+    Recon *r = nullptr;
+    hipStream_t s = nullptr;
+    size_t bytes = 0;
+    Key key{};
+    uint64_t last_use = 0;
+};
+
+struct Job {
+    uint64_t ticket = 0;
+    wg_request req{};
+    float *xyz = nullptr, *nrm = nullptr, *q = nullptr, *gphi = nullptr;   // server-owned copies
+    int state = 0;   // 0 queued, 1 running, 2 done
+    wg_result res{};
+};
+
+}  // namespace
+
+class Server {
+  public:
+    Server(size_t budget, int max_inflight, int device) : budget_(budget), device_(device) {
+        WG_HIP(hipSetDevice(device_));
+        WG_HIP(hipStreamCreateWithFlags(&ingest_, hipStreamNonBlocking));
+        t0_ = std::chrono::steady_clock::now();
+        for (int k = 0; k < max_inflight; ++k) workers_.emplace_back([this] { worker(); });
+    }
+
+    ~Server() {
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            drain_cv_.wait(lk, [this] { return queue_.empty() && running_ == 0; });
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+        (void)hipSetDevice(device_);
+        for (auto &h : idle_) destroy(h);
+        for (auto &kv : jobs_) free_inputs(*kv.second);
+        (void)hipStreamDestroy(ingest_);
+    }
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+    }
+
+    int submit(const wg_request &rq, uint64_t *ticket) {
+        require(ticket != nullptr, WG_EINVAL, "null ticket");
+        require(rq.n_points >= 0 && rq.n_q >= 0, WG_EINVAL, "negative sizes");
+        require(rq.n_points == 0 || (rq.d_xyz && rq.d_nrm), WG_EINVAL, "null point inputs");
+        require(rq.n_q == 0 || (rq.d_q && rq.d_phi), WG_EINVAL, "null query arguments");
+        require(!rq.d_gphi || rq.n_points == 0 || (rq.d_gxyz && rq.d_gnrm_pts), WG_EINVAL, "null gradient outputs");
+        const size_t fp = Recon::footprint(rq.grid, capacity_class(rq.n_points));
+        require(fp <= budget_, WG_ENOMEM, "request footprint exceeds the server budget");
+        WG_HIP(hipSetDevice(device_));
+        auto job = std::make_unique<Job>();
+        job->req = rq;
+        job->res.t_submit = now();
+        auto copy = [&](const float *src, size_t n) -> float * {
+            if (!src || n == 0) return nullptr;
+            float *dst = nullptr;
+            WG_HIP(hipMalloc(&dst, n * sizeof(float)));
+            WG_HIP(hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, ingest_));
+            return dst;
+        };
+        job->xyz = copy(rq.d_xyz, 3 * (size_t)rq.n_points);
+        job->nrm = copy(rq.d_nrm, 3 * (size_t)rq.n_points);
+        job->q = copy(rq.d_q, 3 * (size_t)rq.n_q);
+        job->gphi = copy(rq.d_gphi, (size_t)rq.n_q);
+        WG_HIP(hipStreamSynchronize(ingest_));
+        std::unique_lock<std::mutex> lk(mu_);
+        job->ticket = ++next_ticket_;
+        *ticket = job->ticket;
+        Job *j = job.get();
+        jobs_[j->ticket] = std::move(job);
+        queue_.push_back(j);
+        lk.unlock();
+        cv_.notify_one();
+        return WG_OK;
+    }
+
+    int poll(uint64_t ticket, wg_result *out) {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = jobs_.find(ticket);
+        require(it != jobs_.end(), WG_ESTATE, "unknown ticket");
+        Job &j = *it->second;
+        if (j.state != 2) return WG_PENDING;
+        if (out) *out = j.res;
+        int st = j.res.status;
+        std::unique_ptr<Job> owned = std::move(it->second);
+        jobs_.erase(it);
+        lk.unlock();
+        free_inputs(*owned);
+        return st;
+    }
+
+  private:
+    void free_inputs(Job &j) {
+        for (float *p : {j.xyz, j.nrm, j.q, j.gphi})
+            if (p) (void)hipFree(p);
+        j.xyz = j.nrm = j.q = j.gphi = nullptr;
+    }
+
+    void destroy(Handle &h) {
+        if (h.s) (void)hipStreamSynchronize(h.s);
+        delete h.r;
+        if (h.s) (void)hipStreamDestroy(h.s);
+        h.r = nullptr;
+        h.s = nullptr;
+    }
+
+    // Take an idle handle of this class or create one within the budget.
+    Handle acquire(const Key &k, const wg_grid &g, std::unique_lock<std::mutex> &lk) {
+        const size_t fp = Recon::footprint(g, k.cap);
+        for (;;) {
+            for (auto it = idle_.begin(); it != idle_.end(); ++it)
+                if (!(it->key < k) && !(k < it->key)) {
+                    Handle h = *it;
+                    idle_.erase(it);
+                    return h;
+                }
+            // evict least-recently-used idle handles until the new one fits
+            while (resident_ + fp > budget_ && !idle_.empty()) {
+                auto victim = idle_.begin();
+                for (auto it = idle_.begin(); it != idle_.end(); ++it)
+                    if (it->last_use < victim->last_use) victim = it;
+                Handle h = *victim;
+                idle_.erase(victim);
+                resident_ -= h.bytes;
+                lk.unlock();
+                destroy(h);
+                lk.lock();
+            }
+            if (resident_ + fp <= budget_) {
+                resident_ += fp;   // reserve before allocating outside the lock
+                lk.unlock();
+                Handle h;
+                h.key = k;
+                try {
+                    WG_HIP(hipStreamCreateWithFlags(&h.s, hipStreamNonBlocking));
+                    h.r = new Recon(g, k.cap, h.s);
+                } catch (...) {
+                    if (h.s) (void)hipStreamDestroy(h.s);
+                    lk.lock();
+                    resident_ -= fp;
+                    throw;
+                }
+                h.bytes = fp;
+                lk.lock();
+                return h;
+            }
+            // everything resident is busy: wait for a release
+            release_cv_.wait(lk);
+        }
+    }
+
+    void run(Job &j, Handle &h) {
+        const wg_request &rq = j.req;
+        wg_solve_opts o = rq.opts;
+        o.warm_start = 0;   // a request's result must not depend on what ran before it
+        int st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats);
+        if (rq.n_q > 0) h.r->sample(j.q, rq.n_q, rq.d_phi, rq.d_nrm_out);
+        if (j.gphi) {
+            wg_stats bs{};
+            int st2 = h.r->backward(j.q, rq.n_q, j.gphi, nullptr, rq.d_gxyz, rq.d_gnrm_pts, nullptr, o, &bs);
+            j.res.stats.ms[6] = bs.ms[6];
+            j.res.stats.ms[7] = bs.ms[7];
+            j.res.stats.iters += bs.iters;
+            if (st == WG_OK) st = st2;
+        }
+        WG_HIP(hipStreamSynchronize(h.s));
+        j.res.status = st;
+    }
+
+    void worker() {
+        (void)hipSetDevice(device_);
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [this] { return stop_ || !queue_.empty(); });
+            if (stop_ && queue_.empty()) return;
+            Job *j = queue_.front();
+            queue_.pop_front();
+            ++running_;
+            j->state = 1;
+            Key k{};
+            for (int a = 0; a < 3; ++a) {
+                k.n[a] = j->req.grid.n[a];
+                k.lo[a] = j->req.grid.lo[a];
+            }
+            k.h = j->req.grid.h;
+            k.cap = capacity_class(j->req.n_points);
+            Handle h;
+            bool have = false;
+            try {
+                h = acquire(k, j->req.grid, lk);
+                have = true;
+                j->res.t_start = now();
+                lk.unlock();
+                try {
+                    run(*j, h);
+                } catch (const Error &e) {
+                    set_error(e.what());
+                    j->res.status = e.code;
+                }
+                lk.lock();
+            } catch (const Error &e) {
+                set_error(e.what());
+                j->res.status = e.code;
+            }
+            j->res.t_done = now();
+            if (have) {
+                h.last_use = ++clock_;
+                idle_.push_back(h);
+            }
+            j->state = 2;
+            --running_;
+            release_cv_.notify_all();
+            drain_cv_.notify_all();
+        }
+    }
+
+    size_t budget_;
+    int device_;
+    hipStream_t ingest_ = nullptr;
+    std::chrono::steady_clock::time_point t0_;
+    std::mutex mu_;
+    std::condition_variable cv_, release_cv_, drain_cv_;
+    std::deque<Job *> queue_;
+    std::map<uint64_t, std::unique_ptr<Job>> jobs_;
+    std::list<Handle> idle_;
+    std::vector<std::thread> workers_;
+    size_t resident_ = 0;
+    uint64_t next_ticket_ = 0, clock_ = 0;
+    int running_ = 0;
+    bool stop_ = false;
+};
+
+}  // namespace wg
+
+struct wg_server {
+    wg::Server *impl;
+};
+
+template <class F>
+static int guarded_s(F &&f) {
+    try {
+        return f();
+    } catch (const wg::Error &e) {
+        wg::set_error(e.what());
+        return e.code;
+    } catch (const std::exception &e) {
+        wg::set_error(e.what());
+        return WG_EDEVICE;
+    }
+}
+
+extern "C" {
+
+int wg_server_create(wg_server **out, size_t hbm_budget_bytes, int max_inflight, int device) {
+    return guarded_s([&] {
+        wg::require(out != nullptr, WG_EINVAL, "null argument");
+        wg::require(max_inflight >= 1 && max_inflight <= 64, WG_EINVAL, "max_inflight outside [1, 64]");
+        *out = new wg_server{new wg::Server(hbm_budget_bytes, max_inflight, device)};
+        return WG_OK;
+    });
+}
+
+int wg_submit(wg_server *s, const wg_request *req, uint64_t *ticket) {
+    return guarded_s([&] {
+        wg::require(s && req, WG_EINVAL, "null argument");
+        return s->impl->submit(*req, ticket);
+    });
+}
+
+int wg_poll(wg_server *s, uint64_t ticket, wg_result *out) {
+    return guarded_s([&] {
+        wg::require(s != nullptr, WG_EINVAL, "null server");
+        return s->impl->poll(ticket, out);
+    });
+}
+
+double wg_server_now(wg_server *s) { return s ? s->impl->now() : 0.0; }
+
+void wg_server_destroy(wg_server *s) {
+    if (!s) return;
+    delete s->impl;
+    delete s;
+}
+
+}  // extern "C"

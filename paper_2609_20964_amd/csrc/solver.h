@@ -1,0 +1,66 @@
+// Matrix-free Poisson solver on a cell-centred grid (internal).
+//
+// Solves A x = b for the 7-point operator of Warp-Geo Eq. (20)-(21) under
+// vertex quadrature, A = -h^2 L_h: (A x)_i = sum over the cell's interior
+// faces of (x_i - x_j); zero-flux (Neumann, Eq. 19) boundaries, or the
+// cell-centred Dirichlet test mode (ghost = -x, diagonal 6 + #boundary faces).
+//
+// Precision scheme: the solution lives in FP64; each refinement step forms the
+// FP64 residual r = P(b - A x) (P: mean removal for Neumann), solves A e = r
+// approximately with FP32-vector multigrid-preconditioned CG whose inner
+// products accumulate in FP64, and adds e to x in FP64.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace wg {
+
+struct SolveScalars {
+    double rz, rz_old, pq, alpha, beta, rr;
+    double res_sum, res_sq, x_sum, b_sum, b_sq;
+    double mean_r, res_norm2, b_norm2;
+    int bad;
+    int pad;
+};
+
+struct SolveResult {
+    int iters = 0, refinements = 0, status = WG_OK;
+    double rel_res = 0.0, x_mean = 0.0;
+};
+
+class Solver {
+  public:
+    static void plan(Arena &a, int nx, int ny, int nz);
+    void bind(Arena &a, int nx, int ny, int nz, hipStream_t s);
+    ~Solver();
+
+    // Solve A x = b (x: FP64, initial guess if opts.warm_start).  The mean of
+    // the Neumann solution is reported in x_mean, not removed from x.
+    SolveResult solve(const float *b, double *x, int bc, const wg_solve_opts &o);
+
+    // x -= mean (FP64), used where a zero-mean field is promised.
+    void shift(double *x, double by);
+
+  private:
+    struct Level {
+        Dims d;
+        float *rhs, *x, *x2, *tmp;
+    };
+    void vcycle(int l);
+    int pcg(double tol, int max_it, double rr0);
+    void finalize(int mode, unsigned nb, int flag);
+    void read_scalars();
+
+    hipStream_t st_ = nullptr;
+    std::vector<Level> lv_;
+    float *e_ = nullptr, *p_[2] = {nullptr, nullptr}, *q_ = nullptr;
+    double *partials_ = nullptr;
+    SolveScalars *dsc_ = nullptr, *hsc_ = nullptr;
+    float *coarseM_[2] = {nullptr, nullptr};   // [bc] dense pseudo-inverse of the coarsest level
+    int coarse_direct_ = 0;
+    int bc_sign_ = -1;
+};
+
+}  // namespace wg

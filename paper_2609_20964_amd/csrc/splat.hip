@@ -1,0 +1,286 @@
+// Point-side kernels: binning, the 27-cell normal splat fused with the
+// divergence (Warp-Geo Sec. 2.3, Eq. 22-26), its transpose (Sec. 2.5, Eq. 39)
+// and the iso-value (Sec. 2.4) with its reverse.
+//
+// The normal field V (Eq. 23) is never stored: each point adds its share of
+// b = -h^2 D_h V straight into b.  With face values F = (V_i + V_{i+1})/2 on
+// interior faces and 0 on the outer faces, a point whose weights cover the
+// 3x3x3 block around its cell touches the 81 cells of that block widened by
+// one along each axis; each of those gets one atomic add.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace wg {
+
+namespace {
+
+// Per-axis data of one point: central cell k, fractional offset f in [0,1),
+// factors 1/2 (1 - |D|/2) of Eq. 25 for the offsets -1, 0, +1 (0 outside the
+// grid) and their x-derivatives -sign(D)/(4h).
+struct AxisW {
+    int k;
+    float f;
+    float a[3];
+    float da[3];
+};
+
+__device__ __forceinline__ bool bin_axis(float x, double lo, double h, int n, AxisW &w, float inv4h) {
+    double t = ((double)x - lo) / h;
+    if (!(t >= 0.0 && t < (double)n)) return false;    // also rejects NaN
+    int k = (int)floor(t);
+    if (k >= n) return false;
+    w.k = k;
+    w.f = (float)(t - (double)k);
+    for (int d = -1; d <= 1; ++d) {
+        float D = w.f - 0.5f - (float)d;
+        bool in = (k + d >= 0) && (k + d < n);
+        w.a[d + 1] = in ? 0.5f * (1.f - fabsf(D) * 0.5f) : 0.f;
+        float sg = D > 0.f ? 1.f : (D < 0.f ? -1.f : 0.f);
+        w.da[d + 1] = in ? -sg * inv4h : 0.f;
+    }
+    return true;
+}
+
+__device__ __forceinline__ float raw_w(const AxisW &X, const AxisW &Y, const AxisW &Z, int dx, int dy, int dz) {
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return 0.f;
+    if (dx == 0 && dy == 0 && dz == 0) return 0.5f;
+    return X.a[dx + 1] * Y.a[dy + 1] * Z.a[dz + 1];
+}
+
+__device__ __forceinline__ bool in_range(int k, int o, int n) { return k + o >= 0 && k + o < n; }
+
+}  // namespace
+
+// F1 + F2 + F3.  b must be zero on entry.  Copies the points into the handle
+// (xyz_c, nrm_c) and records each point's linear central-cell key.  A point
+// outside the grid sets *err and contributes nothing.
+__global__ __launch_bounds__(256) void k_splat_div(const float *__restrict__ xyz, const float *__restrict__ nrm,
+                                                    int npts, GridF g, float *__restrict__ b,
+                                                    int32_t *__restrict__ keys, float *__restrict__ xyz_c,
+                                                    float *__restrict__ nrm_c, int *err) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const float x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
+    const float n0 = nrm[3 * i], n1 = nrm[3 * i + 1], n2 = nrm[3 * i + 2];
+    xyz_c[3 * i] = x0; xyz_c[3 * i + 1] = x1; xyz_c[3 * i + 2] = x2;
+    nrm_c[3 * i] = n0; nrm_c[3 * i + 1] = n1; nrm_c[3 * i + 2] = n2;
+    const float inv4h = (float)(0.25 / g.h);
+    AxisW X, Y, Z;
+    if (!bin_axis(x0, g.lo[0], g.h, g.d.nx, X, inv4h) || !bin_axis(x1, g.lo[1], g.h, g.d.ny, Y, inv4h) ||
+        !bin_axis(x2, g.lo[2], g.h, g.d.nz, Z, inv4h)) {
+        keys[i] = -1;
+        atomicOr(err, 1);
+        return;
+    }
+    keys[i] = X.k + g.d.nx * (Y.k + g.d.ny * Z.k);
+    const float Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
+    const float S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + 0.5f;     // Eq. 24 normaliser
+    const float coef = -0.5f * (float)g.h * (float)(1.0 / (g.h * g.h * g.h)) / S;
+    const size_t sx = 1, sy = (size_t)g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
+    const size_t c0 = (size_t)X.k + sy * Y.k + sz * Z.k;
+#pragma unroll
+    for (int cz = -2; cz <= 2; ++cz)
+#pragma unroll
+        for (int cy = -2; cy <= 2; ++cy)
+#pragma unroll
+            for (int cx = -2; cx <= 2; ++cx) {
+                if ((cx == -2 || cx == 2) + (cy == -2 || cy == 2) + (cz == -2 || cz == 2) > 1) continue;
+                if (!in_range(X.k, cx, g.d.nx) || !in_range(Y.k, cy, g.d.ny) || !in_range(Z.k, cz, g.d.nz))
+                    continue;
+                const float r0 = raw_w(X, Y, Z, cx, cy, cz);
+                float acc = 0.f;
+                // x faces
+                if (in_range(X.k, cx + 1, g.d.nx)) acc += n0 * (r0 + raw_w(X, Y, Z, cx + 1, cy, cz));
+                if (in_range(X.k, cx - 1, g.d.nx)) acc -= n0 * (raw_w(X, Y, Z, cx - 1, cy, cz) + r0);
+                if (in_range(Y.k, cy + 1, g.d.ny)) acc += n1 * (r0 + raw_w(X, Y, Z, cx, cy + 1, cz));
+                if (in_range(Y.k, cy - 1, g.d.ny)) acc -= n1 * (raw_w(X, Y, Z, cx, cy - 1, cz) + r0);
+                if (in_range(Z.k, cz + 1, g.d.nz)) acc += n2 * (r0 + raw_w(X, Y, Z, cx, cy, cz + 1));
+                if (in_range(Z.k, cz - 1, g.d.nz)) acc -= n2 * (raw_w(X, Y, Z, cx, cy, cz - 1) + r0);
+                if (acc != 0.f)
+                    unsafeAtomicAdd(b + c0 + (ptrdiff_t)cx * (ptrdiff_t)sx + (ptrdiff_t)cy * (ptrdiff_t)sy +
+                                        (ptrdiff_t)cz * (ptrdiff_t)sz,
+                                    coef * acc);
+            }
+}
+
+namespace {
+
+// Trilinear stencil of a cell-centred field at a world point: base cell and
+// weights along each axis, u = (x - lo)/h - 1/2 clamped to [0, n-1].
+struct Tri1 {
+    int i0;
+    double t;
+    bool clamped;
+};
+__device__ __forceinline__ Tri1 tri_axis(float x, double lo, double h, int n) {
+    double u = ((double)x - lo) / h - 0.5;
+    Tri1 r;
+    r.clamped = !(u >= 0.0 && u <= (double)(n - 1));
+    u = fmin(fmax(u, 0.0), (double)(n - 1));
+    int i0 = (int)floor(u);
+    if (i0 > n - 2) i0 = n - 2;
+    r.i0 = i0;
+    r.t = u - (double)i0;
+    return r;
+}
+
+}  // namespace
+
+// Iso-value partial sums: sum_i chi_h(x_i) with chi in FP64 (Sec. 2.4).
+__global__ __launch_bounds__(256) void k_iso_partial(const float *__restrict__ xyz, int npts, GridF g,
+                                                      const double *__restrict__ chi, double *partials) {
+    double acc[1] = {0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x) {
+        Tri1 X = tri_axis(xyz[3 * i], g.lo[0], g.h, g.d.nx);
+        Tri1 Y = tri_axis(xyz[3 * i + 1], g.lo[1], g.h, g.d.ny);
+        Tri1 Z = tri_axis(xyz[3 * i + 2], g.lo[2], g.h, g.d.nz);
+        const size_t sy = g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
+        const double *c = chi + X.i0 + sy * Y.i0 + sz * Z.i0;
+        double v = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    double w = (dx ? X.t : 1.0 - X.t) * (dy ? Y.t : 1.0 - Y.t) * (dz ? Z.t : 1.0 - Z.t);
+                    v += w * c[dx + sy * dy + sz * dz];
+                }
+        acc[0] += v;
+    }
+    __shared__ double lds[4][1];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// c = (sum of partials) / N  (minus nothing: the caller subtracts the field mean)
+__global__ void k_iso_finalize(const double *partials, int nb, int npts, double *out) {
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) v[0] += partials[i];
+    __shared__ double lds[4][1];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[0] = v[0] / (double)npts;
+}
+
+// Reverse of the iso-value into the field: g_chi += (g_c / N) * trilinear weights.
+__global__ __launch_bounds__(256) void k_iso_T(const float *__restrict__ xyz, int npts, GridF g,
+                                                const double *g_c, float *__restrict__ g_chi) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const float s = (float)(g_c[0] / (double)npts);
+    if (s == 0.f) return;
+    Tri1 X = tri_axis(xyz[3 * i], g.lo[0], g.h, g.d.nx);
+    Tri1 Y = tri_axis(xyz[3 * i + 1], g.lo[1], g.h, g.d.ny);
+    Tri1 Z = tri_axis(xyz[3 * i + 2], g.lo[2], g.h, g.d.nz);
+    const size_t sy = g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
+    float *c = g_chi + X.i0 + sy * Y.i0 + sz * Z.i0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                float w = (float)((dx ? X.t : 1.0 - X.t) * (dy ? Y.t : 1.0 - Y.t) * (dz ? Z.t : 1.0 - Z.t));
+                unsafeAtomicAdd(c + dx + sy * dy + sz * dz, s * w);
+            }
+}
+
+// B5 + B6 (+ the point term of the iso-value reverse).  With lambda the
+// adjoint solution, g_V = -h^2 D_h^T lambda is formed on the fly at each of
+// the 27 stencil cells, then
+//   g_n_i = h^-3 sum_o alpha_o g_V,o,
+//   g_x_i = h^-3 sum_o (d alpha_o / d x_i) (n_i . g_V,o) + (g_c / N) grad chi_h(x_i).
+// The central cell of each point is the one recorded by the forward pass.
+__global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, const float *__restrict__ nrm,
+                                                  const int32_t *__restrict__ keys, int npts, GridF g,
+                                                  const double *__restrict__ lam, const double *__restrict__ chi,
+                                                  const double *g_c, float *__restrict__ gxyz,
+                                                  float *__restrict__ gnrm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const float xv[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+    const float nv[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+    const int key = keys[i];
+    const int kk[3] = {key % g.d.nx, (key / g.d.nx) % g.d.ny, key / (g.d.nx * g.d.ny)};
+    const int nn[3] = {g.d.nx, g.d.ny, g.d.nz};
+    const float inv4h = (float)(0.25 / g.h);
+    AxisW W[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = ((double)xv[a] - g.lo[a]) / g.h;
+        W[a].k = kk[a];
+        W[a].f = (float)(t - (double)kk[a]);
+        for (int d = -1; d <= 1; ++d) {
+            float D = W[a].f - 0.5f - (float)d;
+            bool in = in_range(kk[a], d, nn[a]);
+            W[a].a[d + 1] = in ? 0.5f * (1.f - fabsf(D) * 0.5f) : 0.f;
+            float sg = D > 0.f ? 1.f : (D < 0.f ? -1.f : 0.f);
+            W[a].da[d + 1] = in ? -sg * inv4h : 0.f;
+        }
+    }
+    const AxisW &X = W[0], &Y = W[1], &Z = W[2];
+    const float Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
+    const float S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + 0.5f;
+    const float dSx = (X.da[0] + X.da[1] + X.da[2]) * Sy * Sz - X.da[1] * Y.a[1] * Z.a[1];
+    const float dSy = Sx * (Y.da[0] + Y.da[1] + Y.da[2]) * Sz - X.a[1] * Y.da[1] * Z.a[1];
+    const float dSz = Sx * Sy * (Z.da[0] + Z.da[1] + Z.da[2]) - X.a[1] * Y.a[1] * Z.da[1];
+    const size_t sy = (size_t)g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
+    const size_t c0 = (size_t)X.k + sy * Y.k + sz * Z.k;
+    const double half_h = 0.5 * g.h;
+    float gn[3] = {0.f, 0.f, 0.f};
+    float sum_rs = 0.f, sum_drs[3] = {0.f, 0.f, 0.f};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!in_range(X.k, dx, g.d.nx) || !in_range(Y.k, dy, g.d.ny) || !in_range(Z.k, dz, g.d.nz)) continue;
+                const size_t o = c0 + (ptrdiff_t)dx + (ptrdiff_t)dy * (ptrdiff_t)sy + (ptrdiff_t)dz * (ptrdiff_t)sz;
+                const double lo_ = lam[o];
+                const int off[3] = {dx, dy, dz};
+                const size_t st[3] = {1, sy, sz};
+                float gv[3];
+                for (int a = 0; a < 3; ++a) {
+                    double acc = 0.0;
+                    if (in_range(kk[a], off[a] - 1, nn[a])) acc += lam[o - st[a]] - lo_;
+                    if (in_range(kk[a], off[a] + 1, nn[a])) acc += lo_ - lam[o + st[a]];
+                    gv[a] = (float)(-half_h * acc);
+                }
+                const bool centre = dx == 0 && dy == 0 && dz == 0;
+                const float ax = X.a[dx + 1], ay = Y.a[dy + 1], az = Z.a[dz + 1];
+                const float raw = centre ? 0.5f : ax * ay * az;
+                const float s_o = nv[0] * gv[0] + nv[1] * gv[1] + nv[2] * gv[2];
+                for (int a = 0; a < 3; ++a) gn[a] += raw * gv[a];
+                sum_rs += raw * s_o;
+                if (!centre) {
+                    sum_drs[0] += X.da[dx + 1] * ay * az * s_o;
+                    sum_drs[1] += ax * Y.da[dy + 1] * az * s_o;
+                    sum_drs[2] += ax * ay * Z.da[dz + 1] * s_o;
+                }
+            }
+    const float hm3 = (float)(1.0 / (g.h * g.h * g.h));
+    const float invS = 1.f / S;
+    const float dS[3] = {dSx, dSy, dSz};
+    float gx[3];
+    for (int a = 0; a < 3; ++a) {
+        gnrm[3 * i + a] = hm3 * gn[a] * invS;
+        gx[a] = hm3 * (sum_drs[a] * invS - dS[a] * invS * invS * sum_rs);
+    }
+    // iso-value: c = mean chi_h(x_i)  ->  g_x += (g_c / N) grad chi_h
+    const double sc = g_c[0] / (double)npts;
+    if (sc != 0.0) {
+        Tri1 T[3];
+        for (int a = 0; a < 3; ++a) T[a] = tri_axis(xv[a], g.lo[a], g.h, nn[a]);
+        const double *c = chi + T[0].i0 + sy * T[1].i0 + sz * T[2].i0;
+        double grad[3] = {0, 0, 0};
+        for (int ez = 0; ez < 2; ++ez)
+            for (int ey = 0; ey < 2; ++ey)
+                for (int ex = 0; ex < 2; ++ex) {
+                    double v = c[ex + sy * ey + sz * ez];
+                    double fx = ex ? T[0].t : 1.0 - T[0].t, fy = ey ? T[1].t : 1.0 - T[1].t,
+                           fz = ez ? T[2].t : 1.0 - T[2].t;
+                    double gx_ = (ex ? 1.0 : -1.0) * fy * fz, gy_ = fx * (ey ? 1.0 : -1.0) * fz,
+                           gz_ = fx * fy * (ez ? 1.0 : -1.0);
+                    grad[0] += gx_ * v;
+                    grad[1] += gy_ * v;
+                    grad[2] += gz_ * v;
+                }
+        for (int a = 0; a < 3; ++a)
+            if (!T[a].clamped) gx[a] += (float)(sc * grad[a] / g.h);
+    }
+    for (int a = 0; a < 3; ++a) gxyz[3 * i + a] = gx[a];
+}
+
+}  // namespace wg

@@ -1,0 +1,68 @@
+// Surface extraction, signed distance and sampling on the device (internal).
+//
+// Marching Cubes (Warp-Geo Eq. 27-28) runs on the dual lattice whose cube
+// corners are the cell centres.  Cubes are grouped into 4x4x4 bricks (one
+// wavefront each), bricks are visited in Morton order, and every non-empty
+// brick becomes a leaf of an 8-ary box hierarchy built bottom-up over that
+// order.  The signed distance (Eq. 29-34) of every grid node is the exact
+// minimum over all triangles: one wavefront per 4x4x4 node tile walks the
+// hierarchy together, pruning a box only when it is farther than every lane's
+// current best, so the result equals the brute-force minimum.
+#pragma once
+
+#include "kernels.h"
+
+namespace wg {
+
+struct SurfaceCounts {
+    uint32_t n_tris;
+    uint32_t n_active;    // non-empty bricks
+};
+
+class Surface {
+  public:
+    static void plan(Arena &a, const Dims &d);
+    void bind(Arena &a, const Dims &d, hipStream_t s);
+    ~Surface();
+
+    // Extract the mesh of {chi = *c} (c on the device).  Host-synchronising:
+    // returns the triangle count.
+    uint32_t extract(const double *chi, const double *c);
+    // phi and the nearest-triangle index on every node.
+    void sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err);
+    // reverse of sdf through the vertices: g_chi, g_c (+=)
+    void sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
+               float *g_chi, double *g_c);
+
+    uint32_t n_tris() const { return cnt_.n_tris; }
+    const float4 *tris() const { return tri_; }
+    const int2 *tri_info() const { return info_; }
+    size_t bytes() const { return cap_ * (3 * sizeof(float4) + sizeof(int2)) + box_cap_ * 2 * sizeof(float4); }
+
+  private:
+    void ensure_capacity(uint32_t tris, uint32_t active);
+
+    hipStream_t st_ = nullptr;
+    Dims d_{};
+    int nb_[3] = {0, 0, 0};        // bricks per axis
+    int mbits_ = 0;                // Morton bits per axis
+    size_t nbricks_pad_ = 0;       // (2^mbits)^3
+    uint32_t *cnt_b_ = nullptr, *off_b_ = nullptr, *active_ = nullptr, *blk_ = nullptr;
+    SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
+    SurfaceCounts cnt_{};
+    // growable
+    float4 *tri_ = nullptr;        // [cap][3]
+    int2 *info_ = nullptr;         // [cap]
+    float4 *box_ = nullptr;        // [box_cap][2] (lo, hi) for every hierarchy level
+    size_t cap_ = 0, box_cap_ = 0;
+    std::vector<uint32_t> level_off_, level_cnt_;
+    int levels_ = 0;
+};
+
+// Sampling (F8) and its reverse (B1); phi is the node SDF.
+void launch_sample(const GridF &g, const float *phi, const float *q, int nq, float *out_phi, float *out_nrm,
+                   hipStream_t s);
+void launch_sample_T(const GridF &g, const float *phi, const float *q, int nq, const float *gphi_q,
+                     const float *gnrm_q, float *gphi, float *gq, hipStream_t s);
+
+}  // namespace wg

@@ -1,0 +1,82 @@
+"""Python client of the library's continuous-batching server (wg_server_*).
+
+Requests carry device tensors; the server copies them at submit, runs up to
+``max_inflight`` requests concurrently on resident handles admitted by HBM
+footprint, and writes each request's outputs into the tensors given at submit.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+class Ticket:
+    def __init__(self, tid, outputs, n_points):
+        self.id = tid
+        self.outputs = outputs        # keeps output tensors alive until polled
+        self.n_points = n_points
+        self.result = None
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes, max_inflight=4, device=None):
+        dev = torch.cuda.current_device() if device is None else device
+        h = C.c_void_p()
+        L.check(L.lib().wg_server_create(C.byref(h), int(hbm_budget_bytes), int(max_inflight), int(dev)))
+        self._h = h
+        self.device = torch.device("cuda", dev)
+
+    def now(self):
+        return L.lib().wg_server_now(self._h)
+
+    def submit(self, n, xyz, nrm, q, gphi=None, rel_tol=1e-6, max_iters=500, normals=True, lo=(0, 0, 0), h=None):
+        """Queue one reconstruction; returns a Ticket.  Inputs are copied before return."""
+        req = L.WgRequest()
+        req.grid = L.make_grid(n, lo, h)
+        npts, nq = int(xyz.shape[0]), int(q.shape[0])
+        for t in (xyz, nrm, q):
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        phi = torch.empty(nq, dtype=torch.float32, device=q.device)
+        nout = torch.empty((nq, 3), dtype=torch.float32, device=q.device) if normals else None
+        gx = gn = None
+        if gphi is not None:
+            gx = torch.empty((npts, 3), dtype=torch.float32, device=q.device)
+            gn = torch.empty((npts, 3), dtype=torch.float32, device=q.device)
+        req.d_xyz, req.d_nrm, req.n_points = xyz.data_ptr(), nrm.data_ptr(), npts
+        req.d_q, req.n_q = q.data_ptr(), nq
+        req.d_gphi = gphi.contiguous().data_ptr() if gphi is not None else None
+        req.opts = L.make_opts(rel_tol, max_iters, False)
+        req.d_phi = phi.data_ptr()
+        req.d_nrm_out = nout.data_ptr() if nout is not None else None
+        req.d_gxyz = gx.data_ptr() if gx is not None else None
+        req.d_gnrm_pts = gn.data_ptr() if gn is not None else None
+        torch.cuda.current_stream().synchronize()      # inputs must be complete before the copy
+        tid = C.c_uint64()
+        L.check(L.lib().wg_submit(self._h, C.byref(req), C.byref(tid)))
+        return Ticket(tid.value, {"phi": phi, "nrm": nout, "g_xyz": gx, "g_nrm": gn}, npts)
+
+    def poll(self, ticket):
+        """None while pending; else (status, outputs dict, result dict)."""
+        res = L.WgResult()
+        rc = L.lib().wg_poll(self._h, C.c_uint64(ticket.id), C.byref(res))
+        if rc == L.WG_PENDING:
+            return None
+        if rc == L.WG_ESTATE:
+            raise L.WgError(rc, L.last_error())
+        ticket.result = {"status": rc, "stats": res.stats.as_dict(), "t_submit": res.t_submit,
+                         "t_start": res.t_start, "t_done": res.t_done}
+        return rc, ticket.outputs, ticket.result
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().wg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,104 @@
+"""GPU reverse pass (through the C ABI) against the FP64 oracle's reverse pass.
+
+Bar: 1e-3 relative (L2) on gradients, and per component within 1e-3 of the
+largest reference component.  The forward is solved to rel. residual 1e-10 so
+that the comparison measures the adjoint, not the solve tolerance.
+"""
+import numpy as np
+import pytest
+
+from oracle import discretize as D
+from oracle import pipeline as P
+from paper_2609_20964_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _close(got, want, tol=1e-3):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    comp = np.abs(got - want).max() / np.abs(want).max()
+    print(f"rel {rel:.2e} comp {comp:.2e}", flush=True)
+    return rel <= tol and comp <= 3 * tol
+
+
+def test_reverse_pass_small_star_with_normals_and_queries():
+    from paper_2609_20964_amd.recon import Recon
+    g = D.Grid.unit(20)
+    c0 = np.array([0.03, -0.02, 0.015, 0.01])
+    shape = synth.StarShape(c0, semi_axes=(0.3, 0.2, 0.22))
+    x, n = synth.star(c0, 1500, 12, semi_axes=(0.3, 0.2, 0.22))
+    tdirs = synth.unit_sphere_dirs(np.random.default_rng(13), 300)
+    q = (synth.X0 + synth.StarShape(c0 + 0.01, semi_axes=(0.3, 0.2, 0.22)).rho(tdirs)[:, None] * tdirs)
+    q = q.astype(np.float32)
+    wn = np.random.default_rng(14).standard_normal((300, 3)).astype(np.float32) / 300
+    ref = P.Recon(g, x, n)
+    phi_ref, _ = ref.sample(q)
+    gphi = (2.0 * phi_ref / 300).astype(np.float32)
+    gx_ref, gn_ref, gq_ref = ref.backward(q, gphi.astype(np.float64), wn.astype(np.float64))
+    r = Recon(20, len(x))
+    r.forward(_cuda(x), _cuda(n), rel_tol=1e-10, max_iters=5000)
+    phi, _ = r.sample(_cuda(q))
+    gx, gn, gq = r.backward(_cuda(q), _cuda(gphi), _cuda(wn), want_gq=True, rel_tol=1e-10, max_iters=5000)
+    assert _close(gx.cpu().numpy(), gx_ref)
+    assert _close(gn.cpu().numpy(), gn_ref)
+    assert _close(gq.cpu().numpy(), gq_ref)
+    r.close()
+
+
+def test_autograd_function_matches_oracle_chain():
+    from paper_2609_20964_amd.recon import Recon, reconstruct
+    g = D.Grid.unit(24)
+    x, n = synth.sphere(2500, radius=0.28, seed=21)
+    q = synth.uniform_queries(800, 22)
+    ref = P.Recon(g, x, n)
+    phi_ref, n_ref = ref.sample(q)
+    w = np.random.default_rng(23).standard_normal((800, 3))
+    # L = mean phi^2 + mean (w . n(q))
+    gx_ref, gn_ref, gq_ref = ref.backward(q, 2.0 * phi_ref / 800, w / 800)
+    r = Recon(24, len(x))
+    tx = _cuda(x).requires_grad_(True)
+    tn = _cuda(n).requires_grad_(True)
+    tq = _cuda(q).requires_grad_(True)
+    phi, nq = reconstruct(tx, tn, tq, r, rel_tol=1e-10, max_iters=5000)
+    loss = (phi ** 2).mean() + (nq * _cuda(w)).sum(1).mean()
+    loss.backward()
+    assert _close(tx.grad.cpu().numpy(), gx_ref)
+    assert _close(tn.grad.cpu().numpy(), gn_ref)
+    assert _close(tq.grad.cpu().numpy(), gq_ref)
+    r.close()
+
+
+def test_differentiable_case_16_coefficients_128():
+    """The 16-coefficient superellipsoid at 128^3: dL/dc from the GPU adjoint
+    against dL/dc from the oracle's adjoint, both chained through the same
+    shape generator."""
+    from paper_2609_20964_amd.recon import Recon
+    case = synth.diff_case()
+    g = D.Grid.unit(128)
+    ct = torch.tensor(case.shape.coeffs, dtype=torch.float64, requires_grad=True)
+    xt, nt = synth.star_points_torch(case.shape, case.dirs, ct)
+    x = xt.detach().numpy().astype(np.float32)
+    n = nt.detach().numpy().astype(np.float32)
+    T = len(case.targets)
+    r = Recon(128, len(x))
+    r.forward(_cuda(x), _cuda(n), rel_tol=1e-10, max_iters=5000)
+    phi, _ = r.sample(_cuda(case.targets))
+    gphi = 2.0 * phi / T
+    gx, gn, _ = r.backward(_cuda(case.targets), gphi.contiguous(), rel_tol=1e-10, max_iters=5000)
+    (grad_gpu,) = torch.autograd.grad(
+        (xt * gx.cpu().double()).sum() + (nt * gn.cpu().double()).sum(), ct, retain_graph=True)
+    ref = P.Recon(g, x, n)
+    phi_ref, _ = ref.sample(case.targets)
+    assert np.abs(phi.cpu().numpy() - phi_ref).max() <= 1e-4 * g.h
+    gx_ref, gn_ref, _ = ref.backward(case.targets, 2.0 * phi_ref / T)
+    (grad_ref,) = torch.autograd.grad((xt * torch.tensor(gx_ref)).sum() + (nt * torch.tensor(gn_ref)).sum(), ct)
+    print("dL/dc gpu", grad_gpu.numpy(), "\noracle", grad_ref.numpy(), flush=True)
+    assert _close(grad_gpu.numpy(), grad_ref.numpy())
+    r.close()

@@ -1,0 +1,191 @@
+"""GPU parity of the forward path (through the C ABI) against the FP64 oracle.
+
+Tolerances (written here, derived in the design doc): Poisson field 1e-5 relative
+(both zero-mean, GPU solved to rel. residual 1e-10); SDF 1e-4 h absolute;
+point-to-cell keys bit-exact; right-hand side 1e-5 relative (FP32 atomics).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import discretize as D
+from oracle import pipeline as P
+from paper_2609_20964_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _keys_lin(grid, x):
+    k, _ = D.cell_keys(grid, x)
+    nx, ny, _ = grid.n
+    return k[:, 0] + nx * (k[:, 1] + ny * k[:, 2])
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=None):
+    from paper_2609_20964_amd.recon import Recon
+    ref = P.Recon(grid, x, n)
+    r = Recon(grid.n, len(x), lo=grid.lo, h=grid.h)
+    st = r.forward(_cuda(x), _cuda(n), rel_tol=tol_res, max_iters=5000)
+    print("stats", {k: st[k] for k in ("iters", "refinements", "rel_res", "n_tris", "iso_c")}, flush=True)
+    assert st["status"] == 0 and st["rel_res"] <= tol_res
+    f = r.fields()
+    # F1: bit-exact keys
+    assert (f["keys"].cpu().numpy() == _keys_lin(grid, x)).all()
+    # F2-F3: right-hand side
+    b = f["b"].cpu().numpy().astype(np.float64)
+    assert _rel(b, ref.b) <= 1e-5
+    # F4: field, both zero mean
+    chi = f["chi"].cpu().numpy()
+    assert abs(chi.mean()) <= 1e-12 * np.abs(chi).max()
+    assert _rel(chi, ref.chi) <= 1e-5
+    # F5: iso-value
+    assert abs(st["iso_c"] - ref.c) <= 1e-5 * np.abs(ref.chi).max()
+    # F6: same surface size
+    assert abs(st["n_tris"] - len(ref.mesh)) <= max(2, 1e-3 * len(ref.mesh))
+    # F7: signed distance on nodes
+    phi = f["phi"].cpu().numpy().astype(np.float64)
+    if full_phi:
+        phi_ref = ref.phi_grid()
+        assert np.abs(phi - phi_ref).max() <= 1e-4 * grid.h
+    else:
+        lin = node_sample
+        got = phi.reshape(-1)[lin]
+        want = ref.phi_nodes(lin)
+        assert np.abs(got - want).max() <= 1e-4 * grid.h
+    # F8: sampling
+    phi_q, n_q = r.sample(_cuda(q))
+    val_ref, n_ref = ref.sample(q)
+    assert np.abs(phi_q.cpu().numpy() - val_ref).max() <= 1e-4 * grid.h
+    nq = n_q.cpu().numpy().astype(np.float64)
+    ok = np.linalg.norm(n_ref, axis=1) > 0
+    cosang = np.clip(np.sum(nq[ok] * n_ref[ok], 1), -1, 1)
+    ang = np.arccos(cosang)
+    assert np.percentile(ang, 99) <= 1e-3 and ang.max() <= 2e-2
+    r.close()
+    return st
+
+
+def test_sphere_32_full_grid():
+    g = D.Grid.unit(32)
+    x, n = synth.sphere()
+    q = synth.uniform_queries(4096, 102)
+    _forward_parity(g, x, n, q)
+
+
+def test_ragged_grid_offset_origin():
+    # 20 x 24 x 28 cells, non-unit spacing and origin, a sphere near one side
+    g = D.Grid((20, 24, 28), (-0.1, 0.05, 0.0), 0.04)
+    x, n = synth.sphere(3000, radius=0.2, seed=31)
+    x = (x.astype(np.float64) - 0.5 + np.array([0.3, 0.5, 0.55])).astype(np.float32)
+    rng = np.random.default_rng(32)
+    lo = np.array(g.lo)
+    hi = lo + np.array(g.n) * g.h
+    q = rng.uniform(lo, hi, (3000, 3)).astype(np.float32)
+    _forward_parity(g, x, n, q)
+
+
+def test_torus_noisy_64():
+    g = D.Grid.unit(64)
+    x, n = synth.torus(20000)
+    q = synth.uniform_queries(3000, 33)
+    rng = np.random.default_rng(34)
+    nodes = rng.choice(64 ** 3, 3000, replace=False)
+    _forward_parity(g, x, n, q, full_phi=False, node_sample=nodes)
+
+
+def _mode(bc, shape, k):
+    f = np.cos if bc == "neumann" else np.sin
+    nz, ny, nx = shape
+    ux = f(k[0] * np.pi * (np.arange(nx) + 0.5) / nx)
+    uy = f(k[1] * np.pi * (np.arange(ny) + 0.5) / ny)
+    uz = f(k[2] * np.pi * (np.arange(nz) + 0.5) / nz)
+    return uz[:, None, None] * uy[None, :, None] * ux[None, None, :]
+
+
+@pytest.mark.parametrize("bc,n", [("neumann", (32, 32, 32)), ("dirichlet", (32, 32, 32)),
+                                  ("neumann", (64, 64, 64)), ("dirichlet", (64, 64, 64)),
+                                  ("neumann", (20, 24, 28)), ("dirichlet", (12, 40, 16))])
+def test_poisson_manufactured(bc, n):
+    from paper_2609_20964_amd.recon import Recon
+    shape = (n[2], n[1], n[0])
+    ks = [(1, 2, 3), (3, 1, 1), (2, 2, 5)]
+    u = np.zeros(shape)
+    b = np.zeros(shape)
+    lam = D.eigenvalues(shape, bc)
+    for i, k in enumerate(ks):
+        m = _mode(bc, shape, k)
+        sh = 1 if bc == "dirichlet" else 0
+        u += (i + 1) * m
+        b += (i + 1) * lam[k[2] - sh, k[1] - sh, k[0] - sh] * m
+    b32 = b.astype(np.float32)
+    r = Recon(n, 16)
+    x, st = r.poisson(_cuda(b32.reshape(-1)), bc=bc, rel_tol=1e-10)
+    print("stats", st, flush=True)
+    assert st["status"] == 0 and st["rel_res"] <= 1e-10
+    xg = x.cpu().numpy().reshape(shape)
+    xr = D.solve(b32.astype(np.float64), bc)
+    assert _rel(xg, xr) <= 1e-5
+    assert _rel(xg, u) <= 1e-5
+    r.close()
+
+
+def test_empty_cloud_and_outside_point_and_budget():
+    from paper_2609_20964_amd._lib import WG_EINVAL, WgError
+    from paper_2609_20964_amd.recon import Recon
+    r = Recon(16, 100)
+    # no points: b = 0, chi = 0, no surface, phi = +inf (every node "outside")
+    z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    st = r.forward(z, z)
+    assert st["n_tris"] == 0 and st["rel_res"] == 0.0
+    assert torch.isinf(r.fields()["phi"]).all()
+    # a point outside the grid is rejected
+    x = torch.tensor([[0.5, 0.5, 1.0]], dtype=torch.float32, device="cuda")
+    with pytest.raises(WgError) as e:
+        r.forward(x, x)
+    assert e.value.code == WG_EINVAL
+    # more points than the handle holds
+    x = torch.full((101, 3), 0.5, dtype=torch.float32, device="cuda")
+    with pytest.raises(WgError):
+        r.forward(x, x)
+    r.close()
+
+
+def test_iteration_cap_reports_not_converged():
+    from paper_2609_20964_amd.recon import Recon
+    g = D.Grid.unit(32)
+    x, n = synth.sphere()
+    r = Recon(32, len(x))
+    with pytest.warns(UserWarning):
+        st = r.forward(_cuda(x), _cuda(n), rel_tol=1e-12, max_iters=1)
+    assert st["status"] == -3 and st["rel_res"] > 1e-12 and math.isfinite(st["rel_res"])
+    r.close()
+
+
+def test_warm_start_reaches_same_field():
+    from paper_2609_20964_amd.recon import Recon
+    fl = synth.Flapping(n_points=20000)
+    r = Recon(32, 20000)
+    x0, n0 = fl.step(0)
+    r.forward(_cuda(x0), _cuda(n0), rel_tol=1e-10)
+    x1, n1 = fl.step(1)
+    st_w = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=True)
+    chi_w = r.fields()["chi"].cpu().numpy()
+    st_c = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=False)
+    chi_c = r.fields()["chi"].cpu().numpy()
+    # both solves stop at rel. residual 1e-10; the field error is then bounded by
+    # kappa(A) * 1e-10 each, kappa ~ 12 n^2 / pi^2 on the zero-mean subspace
+    kappa = 12 * 32 ** 2 / math.pi ** 2
+    assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10
+    assert st_w["iters"] <= st_c["iters"]
+    r.close()

@@ -1,0 +1,98 @@
+"""Continuous-batching server: each result alone equals the same request in the
+mix (SDF within 1e-4 h, gradients within 1e-3), HBM-footprint admission, and
+rejection of a request larger than the budget."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2609_20964_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _requests():
+    out = []
+    rng = np.random.default_rng(601)
+    for i, (n, npts, grad) in enumerate([(32, 6000, False), (64, 30000, True), (32, 12000, True),
+                                         (64, 9000, False), (48, 15000, False), (32, 4000, True)]):
+        c = synth.draw_star_coeffs(700 + i)
+        semi = rng.uniform(0.12, 0.28, 3)
+        x, nn = synth.star(c, npts, [701, i], semi_axes=semi, p=rng.uniform(2, 5))
+        q = synth.uniform_queries(4096, [702, i])
+        out.append((n, x, nn, q, grad))
+    return out
+
+
+def _alone(n, x, nn, q, grad):
+    from paper_2609_20964_amd.recon import Recon
+    r = Recon(n, len(x))
+    r.forward(_cuda(x), _cuda(nn), rel_tol=1e-10, max_iters=5000)
+    phi, nq = r.sample(_cuda(q))
+    res = {"phi": phi.cpu().numpy()}
+    if grad:
+        gphi = 2.0 * phi / len(q)
+        gx, gn, _ = r.backward(_cuda(q), gphi.contiguous(), rel_tol=1e-10, max_iters=5000)
+        res["gphi"] = gphi
+        res["g_xyz"], res["g_nrm"] = gx.cpu().numpy(), gn.cpu().numpy()
+    r.close()
+    return res
+
+
+def _wait(srv, tickets, timeout=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for i, t in enumerate(tickets):
+            if i in done:
+                continue
+            out = srv.poll(t)
+            if out is not None:
+                done[i] = out
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return [done[i] for i in range(len(tickets))]
+
+
+def test_alone_equals_in_the_mix():
+    from paper_2609_20964_amd.serving import Server
+    reqs = _requests()
+    alone = [_alone(*r) for r in reqs]
+    srv = Server(hbm_budget_bytes=8 << 30, max_inflight=4)
+    tickets = []
+    for (n, x, nn, q, grad), a in zip(reqs, alone):
+        tickets.append(srv.submit(n, _cuda(x), _cuda(nn), _cuda(q), gphi=a.get("gphi"), rel_tol=1e-10,
+                                  max_iters=5000))
+    results = _wait(srv, tickets)
+    for (n, x, nn, q, grad), a, (st, outs, info) in zip(reqs, alone, results):
+        assert st == 0, info
+        assert np.abs(outs["phi"].cpu().numpy() - a["phi"]).max() <= 1e-4 / n
+        if grad:
+            for k in ("g_xyz", "g_nrm"):
+                got, want = outs[k].cpu().numpy(), a[k]
+                assert np.linalg.norm(got - want) <= 1e-3 * np.linalg.norm(want)
+        assert info["t_submit"] <= info["t_start"] <= info["t_done"]
+    srv.close()
+
+
+def test_admission_by_footprint_and_rejection():
+    from paper_2609_20964_amd._lib import WG_ENOMEM, WgError
+    from paper_2609_20964_amd.recon import Recon
+    from paper_2609_20964_amd.serving import Server
+    fp64 = Recon.footprint(64, 1 << 15)
+    # room for one 64^3 handle only: concurrent requests of two sizes must take turns
+    srv = Server(hbm_budget_bytes=int(fp64 * 1.3), max_inflight=3)
+    reqs = _requests()
+    tickets = [srv.submit(n, _cuda(x), _cuda(nn), _cuda(q), rel_tol=1e-8) for (n, x, nn, q, g) in reqs]
+    results = _wait(srv, tickets)
+    assert all(st == 0 for st, _, _ in results)
+    with pytest.raises(WgError) as e:
+        x, nn = synth.sphere(1000)
+        srv.submit(256, _cuda(x), _cuda(nn), _cuda(synth.uniform_queries(16, 1)))
+    assert e.value.code == WG_ENOMEM
+    srv.close()
