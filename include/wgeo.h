@@ -197,6 +197,41 @@ double wg_server_now(wg_server *s);
 /* Waits for all queued requests, then stops the worker threads. */
 void wg_server_destroy(wg_server *s);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (instrumentation, off by default)
+ * ------------------------------------------------------------------------- */
+
+/* Kernel kinds: the fused splat + divergence; the finest-level PCG direction
+ * update fused with the 7-point operator; the finest-level weighted-Jacobi
+ * sweeps; the FP64 residual of the refinement; the multigrid transfers; the
+ * CG vector update; Marching Cubes (count, scan, emit, boxes); the distance
+ * walk; query sampling.  "units" accumulate the algorithmic bytes each launch
+ * must move (the bytes per cell, point or query of that kernel times the
+ * cells, points or queries it processes), except for the distance walk, whose
+ * units are grid nodes. */
+enum {
+    WG_PROF_SPLAT = 0,
+    WG_PROF_SWEEP = 1,
+    WG_PROF_SMOOTH = 2,
+    WG_PROF_RESID64 = 3,
+    WG_PROF_TRANSFER = 4,
+    WG_PROF_CGUPDATE = 5,
+    WG_PROF_MC = 6,
+    WG_PROF_SDF = 7,
+    WG_PROF_SAMPLE = 8,
+    WG_PROF_KINDS = 9
+};
+
+/* Enable timing for the kinds whose bit (1 << kind) is set (0 disables).
+ * Each timed launch is bracketed by two HIP events on its own stream. */
+void wg_profile_enable(unsigned kinds_mask);
+
+/* Totals since the last reset for one kind: summed launch durations (ms),
+ * launch count and processed units.  Waits for the pending events. */
+int wg_profile_read(int kind, double *total_ms, int64_t *launches, double *units);
+
+void wg_profile_reset(void);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *wg_last_error(void);
 

@@ -79,7 +79,26 @@ SIGNATURES = {
     "wg_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(WgResult)]),
     "wg_server_now": (C.c_double, [C.c_void_p]),
     "wg_server_destroy": (None, [C.c_void_p]),
+    "wg_profile_enable": (None, [C.c_uint]),
+    "wg_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "wg_profile_reset": (None, []),
 }
+
+PROF_KINDS = {"splat": 0, "sweep": 1, "smooth": 2, "resid64": 3, "transfer": 4, "cgupdate": 5, "mc": 6,
+              "sdf": 7, "sample": 8}
+
+
+def profile_enable(kinds):
+    mask = 0
+    for k in kinds:
+        mask |= 1 << PROF_KINDS[k]
+    lib().wg_profile_enable(mask)
+
+
+def profile_read(kind):
+    ms, n, u = C.c_double(), C.c_int64(), C.c_double()
+    check(lib().wg_profile_read(PROF_KINDS[kind], C.byref(ms), C.byref(n), C.byref(u)))
+    return {"ms": ms.value, "launches": n.value, "units": u.value}
 
 
 def lib():
@@ -125,3 +144,7 @@ def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False):
     o.max_iters = int(max_iters)
     o.warm_start = int(bool(warm_start))
     return o
+
+
+def profile_reset():
+    lib().wg_profile_reset()

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "prof.h"
 #include "recon.h"
 
 namespace wg {
@@ -127,6 +128,8 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
     WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
     if (npts > 0) {
+        // per point: 24 B read, 24 B copied, 4 B key, 81 four-byte atomic adds into b
+        prof::Scope ps(WG_PROF_SPLAT, st_, 376.0 * npts);
         k_splat_div<<<cdiv(npts, 256), 256, 0, st_>>>(xyz, nrm, npts, gf_, b_, keys_, xyz_, nrm_, err_);
         WG_LAUNCH_CHECK();
     }

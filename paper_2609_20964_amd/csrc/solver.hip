@@ -8,6 +8,7 @@
 // (fixed block order), summed by a single-block finalize kernel.
 #include <cmath>
 
+#include "prof.h"
 #include "solver.h"
 
 namespace wg {
@@ -465,9 +466,13 @@ void Solver::read_scalars() {
     WG_HIP(hipStreamSynchronize(st_));
 }
 
+// kind / bytes_per_cell: optional timing bracket (WG_PROF_*) and the sweep's
+// algorithmic bytes per cell.
 template <class Op>
-static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStream_t s) {
+static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStream_t s, int kind = -1,
+                           double bytes_per_cell = 0.0) {
     Tiles t = tiles_of(d);
+    prof::Scope ps(kind, s, bytes_per_cell * (double)d.count());
     k_stencil<Op><<<t.count(), TX * TY, 0, s>>>(op, d, t, partials);
     WG_LAUNCH_CHECK();
 }
@@ -493,17 +498,24 @@ void Solver::vcycle(int l) {
     }
     Level &C = lv_[l + 1];
     C.d.bc_sign = bc_sign_;
-    launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
-    launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
-    launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_);
-    k_restrict<<<cdiv(C.d.count(), 256), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d);
-    WG_LAUNCH_CHECK();
+    const int ks = l == 0 ? WG_PROF_SMOOTH : -1, kt = l == 0 ? WG_PROF_TRANSFER : -1;
+    launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 8.0);
+    launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_, ks, 12.0);
+    launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_, ks, 12.0);
+    {
+        prof::Scope ps(kt, st_, 4.0 * (double)(L.d.count() + C.d.count()));
+        k_restrict<<<cdiv(C.d.count(), 256), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d);
+        WG_LAUNCH_CHECK();
+    }
     vcycle(l + 1);
-    k_prolong_add<<<cdiv(L.d.count(), 256), 256, 0, st_>>>(C.x, C.d, L.x, L.d);
-    WG_LAUNCH_CHECK();
-    launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
+    {
+        prof::Scope ps(kt, st_, 8.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
+        k_prolong_add<<<cdiv(L.d.count(), 256), 256, 0, st_>>>(C.x, C.d, L.x, L.d);
+        WG_LAUNCH_CHECK();
+    }
+    launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 12.0);
     if (l == 0) {
-        launch_stencil(OpSmooth<true>{L.x2, L.rhs, L.x, kOmega}, L.d, partials_, st_);   // + r.z partials
+        launch_stencil(OpSmooth<true>{L.x2, L.rhs, L.x, kOmega}, L.d, partials_, st_, ks, 12.0);   // + r.z
     } else {
         launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
     }
@@ -522,17 +534,22 @@ int Solver::pcg(double tol, int max_it, double rr0) {
     int stall = 0;
     for (; it < max_it; ++it) {
         if (it == 0)
-            launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, 0.f}, F.d, partials_, st_);
+            launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, 0.f}, F.d, partials_, st_, WG_PROF_SWEEP,
+                           12.0);
         else {
             // beta is read on the host-visible copy after the last finalize
-            launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, (float)hsc_->beta}, F.d, partials_, st_);
+            launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, (float)hsc_->beta}, F.d, partials_, st_,
+                           WG_PROF_SWEEP, 16.0);
         }
         finalize(FIN_PQ, tb, 0);
-        if (it == 0)
-            k_cg_update<true><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
-        else
-            k_cg_update<false><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
-        WG_LAUNCH_CHECK();
+        {
+            prof::Scope ps(WG_PROF_CGUPDATE, st_, (it == 0 ? 20.0 : 24.0) * (double)N);
+            if (it == 0)
+                k_cg_update<true><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
+            else
+                k_cg_update<false><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
+            WG_LAUNCH_CHECK();
+        }
         finalize(FIN_RR, rb, 0);
         vcycle(0);   // z for the next direction
         finalize(FIN_RZ, tb, 0);   // beta = rz / rz_old
@@ -565,7 +582,7 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64{x, b, F.rhs}, F.d, partials_, st_);
+        launch_stencil(OpResid64{x, b, F.rhs}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;

@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "mc_table.inc"
+#include "prof.h"
 #include "surface.h"
 
 namespace wg {
@@ -668,6 +669,7 @@ void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
 uint32_t Surface::extract(const double *chi, const double *c) {
     NB nb{{nb_[0], nb_[1], nb_[2]}};
     const uint32_t nbr = (uint32_t)nbricks_pad_;
+    prof::Scope ps(WG_PROF_MC, st_, 8.0 * (double)d_.count());
     k_mc_count<<<cdiv(nbr, 4), 256, 0, st_>>>(chi, c, d_, nb, nbr, cnt_b_);
     WG_LAUNCH_CHECK();
     const uint32_t nblk = cdiv(nbr, kScanBlock);
@@ -712,6 +714,7 @@ void Surface::sdf(const double *chi, const double *c, double h, float *phi, int3
         lev.cnt[l] = level_cnt_[l];
     }
     const uint32_t tiles = cdiv(d_.nx, 4) * cdiv(d_.ny, 4) * cdiv(d_.nz, 4);
+    prof::Scope ps(WG_PROF_SDF, st_, (double)d_.count());
     k_sdf<<<cdiv(tiles, 4), 256, 0, st_>>>(chi, c, d_, h, box_, lev, active_, off_b_, cnt_b_, tri_, cnt_.n_tris, phi,
                                            argmin, err);
     WG_LAUNCH_CHECK();
@@ -727,6 +730,7 @@ void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const
 void launch_sample(const GridF &g, const float *phi, const float *q, int nq, float *out_phi, float *out_nrm,
                    hipStream_t s) {
     if (nq <= 0) return;
+    prof::Scope ps(WG_PROF_SAMPLE, s, 28.0 * (double)nq);
     k_sample<<<cdiv(nq, 256), 256, 0, s>>>(g, phi, q, nq, out_phi, out_nrm);
     WG_LAUNCH_CHECK();
 }
