@@ -47,7 +47,7 @@ size_t Recon::footprint(const wg_grid &g, int max_points) {
     if ((size_t)g.n[1] * g.n[2] > face) face = (size_t)g.n[1] * g.n[2];
     if ((size_t)g.n[0] * g.n[2] > face) face = (size_t)g.n[0] * g.n[2];
     size_t tris = 4 * face;
-    return a.planned() + (tris + tris / 4 + 64) * (3 * 16 + 8) + (face / 2) * 32;
+    return a.planned() + (tris + tris / 4 + 64) * (3 * 16 + 8) + (tris / 3) * 5 * 16;
 }
 
 void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
@@ -274,9 +274,7 @@ int Recon::get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tri
     const int64_t T = surf_.n_tris();
     if (n_tris) *n_tris = T;
     const int64_t m = T < max_tris ? T : max_tris;
-    if (m > 0 && tris)
-        WG_HIP(hipMemcpy2DAsync(tris, 3 * sizeof(float), surf_.tris(), sizeof(float4), 3 * sizeof(float),
-                                (size_t)m * 3, hipMemcpyDeviceToDevice, st_));
+    if (m > 0 && tris) surf_.export_tris(tris, (uint32_t)m);
     if (m > 0 && info)
         WG_HIP(hipMemcpyAsync(info, surf_.tri_info(), (size_t)m * sizeof(int2), hipMemcpyDeviceToDevice, st_));
     return WG_OK;

@@ -58,7 +58,7 @@ class Solver {
     float *e_ = nullptr, *p_[2] = {nullptr, nullptr}, *q_ = nullptr;
     double *partials_ = nullptr;
     SolveScalars *dsc_ = nullptr, *hsc_ = nullptr;
-    float *coarseM_[2] = {nullptr, nullptr};   // [bc] dense pseudo-inverse of the coarsest level
+    float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
     int bc_sign_ = -1;
 };

@@ -15,11 +15,12 @@ namespace wg {
 
 namespace {
 
-constexpr int TX = 64, TY = 4, ZC = 8;
+constexpr int TX = 64, TY = 4, ZC = 16;
 constexpr int kRedBlocks = 2048;     // grid of the pointwise reductions
 constexpr int kMaxRed = 5;
 constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi smoothing factor
-constexpr int kCoarseMax = 512;         // dense coarse solve up to this many cells
+constexpr int kCoarseTarget = 8;        // coarsen until every extent is <= this (or odd)
+constexpr int kCoarseAxis = 16;         // exact coarsest solve when every extent is <= this
 
 struct Tiles {
     unsigned gx, gy, gz;
@@ -74,16 +75,145 @@ __global__ __launch_bounds__(256) void k_stencil(Op op, Dims d, Tiles t, double 
     }
 }
 
-// r = b - A x in FP64 (r stored FP32); sums of r, r^2, x, b, b^2.
+// Four consecutive x cells per lane (x extent divisible by 4).  A wavefront
+// covers R rows x L float4 columns (L = min(64, nx/4), R = 64/L) and marches
+// ZC planes in z; x neighbours inside the wavefront come from lane shuffles,
+// the two ends of a row segment load theirs.  One 16-byte load per field and
+// plane per lane keeps the sweep at streaming bandwidth.
+template <class T>
+struct V4 {
+    T v[4];
+};
+
+template <class T>
+__device__ __forceinline__ V4<T> ld4(const T *p) {
+    V4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2 *>(p), b = *reinterpret_cast<const double2 *>(p + 2);
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+    }
+    return r;
+}
+__device__ __forceinline__ void st4(float *p, const V4<float> &r) {
+    *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+}
+
+struct Waves4 {
+    unsigned L, R, S, G, gz, zlen;   // lanes per row segment, rows per wave, segments per row,
+                                     // row groups, z chunks, planes per chunk
+    __host__ __device__ unsigned tasks() const { return S * G * gz; }
+};
+// z-march length: as long as possible (fewer halo planes) while keeping at
+// least kTasks wavefront tasks; `even` keeps chunk starts even.
+constexpr unsigned kTasks = 4096;
+inline void set_zlen(Waves4 &w, int nz, bool even = false) {
+    unsigned cols = w.S * w.G;
+    unsigned z = (unsigned)(((size_t)nz * cols) / kTasks);
+    z = z < 1 ? 1 : (z > (unsigned)ZC ? (unsigned)ZC : z);
+    if (even) z = z < 2 ? 2 : (z & ~1u);
+    w.zlen = z;
+    w.gz = cdiv(nz, z);
+}
+inline Waves4 waves4_of(const Dims &d, bool even = false) {
+    Waves4 w;
+    const unsigned W4 = (unsigned)d.nx / 4;
+    w.L = W4 < 64 ? W4 : 64;
+    w.R = 64 / w.L;
+    w.S = (W4 + w.L - 1) / w.L;
+    w.G = ((unsigned)d.ny + w.R - 1) / w.R;
+    set_zlen(w, d.nz, even);
+    return w;
+}
+
+template <class Op>
+__global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, double *partials) {
+    using T = typename Op::T;
+    const unsigned nb = gridDim.x;
+    const unsigned lb = xcd_logical_block(blockIdx.x, nb);
+    const unsigned task = lb * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    double acc[Op::NRED > 0 ? Op::NRED : 1];
+    for (int k = 0; k < (Op::NRED > 0 ? Op::NRED : 1); ++k) acc[k] = 0.0;
+    const unsigned W4 = (unsigned)d.nx / 4;
+    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
+    const unsigned sl = lane % wv.L, rr = lane / wv.L;
+    const unsigned x4 = seg * wv.L + sl;
+    const int j = (int)(grp * wv.R + rr);
+    const bool valid = task < wv.tasks() && rr < wv.R && x4 < W4 && j < d.ny;
+    const int z0 = (int)(zc * wv.zlen);
+    if (task < wv.tasks()) {
+        const int i = 4 * (int)(valid ? x4 : 0);
+        const int jj = valid ? j : 0;
+        const size_t plane = (size_t)d.nx * d.ny;
+        const size_t base = (size_t)i + (size_t)d.nx * jj;
+        const int z1 = min(z0 + (int)wv.zlen, d.nz);
+        const bool ym = jj > 0, yp = jj + 1 < d.ny;
+        const bool xl = i > 0, xr = i + 4 < d.nx;                 // neighbours exist
+        const bool shl = sl > 0, shr = sl + 1 < wv.L && x4 + 1 < W4; // ... and sit in the next lane
+        const int nb_y = (!ym) + (!yp);
+        V4<T> cm, cc;
+        for (int q = 0; q < 4; ++q) cm.v[q] = T(0);
+        if (valid && z0 > 0) cm = op.load4(base + (size_t)(z0 - 1) * plane);
+        if (valid) cc = op.load4(base + (size_t)z0 * plane);
+        else for (int q = 0; q < 4; ++q) cc.v[q] = T(0);
+        for (int k = z0; k < z1; ++k) {
+            const size_t idx = base + (size_t)k * plane;
+            const bool zp = k + 1 < d.nz;
+            V4<T> cp, a, b;
+            for (int q = 0; q < 4; ++q) cp.v[q] = a.v[q] = b.v[q] = T(0);
+            if (valid && zp) cp = op.load4(idx + plane);
+            if (valid && ym) a = op.load4(idx - d.nx);
+            if (valid && yp) b = op.load4(idx + d.nx);
+            T left = __shfl_up(cc.v[3], 1, 64), right = __shfl_down(cc.v[0], 1, 64);
+            if (!shl) left = (valid && xl) ? op.load1(idx - 1) : T(0);
+            if (!shr) right = (valid && xr) ? op.load1(idx + 4) : T(0);
+            if (!xl) left = T(0);
+            if (!xr) right = T(0);
+            if (valid) {
+                const int nbc = nb_y + (k == 0) + (!zp);
+                V4<T> s, dg;
+                for (int q = 0; q < 4; ++q) {
+                    s.v[q] = a.v[q] + b.v[q] + cm.v[q] + cp.v[q];
+                    dg.v[q] = T(6 + d.bc_sign * nbc);
+                }
+                s.v[0] += left + cc.v[1];
+                s.v[1] += cc.v[0] + cc.v[2];
+                s.v[2] += cc.v[1] + cc.v[3];
+                s.v[3] += cc.v[2] + right;
+                if (!xl) dg.v[0] += T(d.bc_sign);
+                if (!xr) dg.v[3] += T(d.bc_sign);
+                op.apply4(idx, cc, s, dg, acc);
+            }
+            cm = cc;
+            cc = cp;
+        }
+    }
+    if constexpr (Op::NRED > 0) {
+        __shared__ double lds[4][Op::NRED];
+        block_sum<Op::NRED>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < Op::NRED; ++k) partials[(size_t)k * nb + lb] = acc[k];
+    }
+}
+
+// r = (b - mb) - A x in FP64 (r stored FP32); sums of r, r^2, x, b - mb,
+// (b - mb)^2.  mb is the mean of b for zero-flux boundaries (the compatibility
+// projection of the right-hand side), 0 otherwise.
 struct OpResid64 {
     using T = double;
     static constexpr int NRED = 5;
     const double *x;
     const float *b;
     float *r;
+    double mb;
     __device__ double load(size_t i) const { return x[i]; }
+    __device__ double load1(size_t i) const { return x[i]; }
+    __device__ V4<double> load4(size_t i) const { return ld4(x + i); }
     __device__ void apply(size_t i, double c, double s, double diag, double *acc) const {
-        double bv = (double)b[i];
+        double bv = (double)b[i] - mb;
         double rv = bv - (diag * c - s);
         r[i] = (float)rv;
         acc[0] += rv;
@@ -91,6 +221,22 @@ struct OpResid64 {
         acc[2] += c;
         acc[3] += bv;
         acc[4] += bv * bv;
+    }
+    __device__ void apply4(size_t i, const V4<double> &c, const V4<double> &s, const V4<double> &dg,
+                           double *acc) const {
+        const V4<float> bb = ld4(b + i);
+        V4<float> out;
+        for (int q = 0; q < 4; ++q) {
+            const double bv = (double)bb.v[q] - mb;
+            const double rv = bv - (dg.v[q] * c.v[q] - s.v[q]);
+            out.v[q] = (float)rv;
+            acc[0] += rv;
+            acc[1] += rv * rv;
+            acc[2] += c.v[q];
+            acc[3] += bv;
+            acc[4] += bv * bv;
+        }
+        st4(r + i, out);
     }
 };
 
@@ -102,7 +248,15 @@ struct OpSmoothFirst {
     float *out;
     float w;
     __device__ float load(size_t) const { return 0.f; }
+    __device__ float load1(size_t) const { return 0.f; }
+    __device__ V4<float> load4(size_t) const { return V4<float>{{0.f, 0.f, 0.f, 0.f}}; }
     __device__ void apply(size_t i, float, float, float diag, double *) const { out[i] = w * rhs[i] / diag; }
+    __device__ void apply4(size_t i, const V4<float> &, const V4<float> &, const V4<float> &dg, double *) const {
+        const V4<float> r = ld4(rhs + i);
+        V4<float> o;
+        for (int q = 0; q < 4; ++q) o.v[q] = w * r.v[q] / dg.v[q];
+        st4(out + i, o);
+    }
 };
 
 // Weighted-Jacobi sweep x_out = x + w (rhs - A x) / diag; DOT adds rhs . x_out.
@@ -114,11 +268,22 @@ struct OpSmooth {
     float *out;
     float w;
     __device__ float load(size_t i) const { return x[i]; }
+    __device__ float load1(size_t i) const { return x[i]; }
+    __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
     __device__ void apply(size_t i, float c, float s, float diag, double *acc) const {
         float rv = rhs[i];
         float v = c + w * (rv - (diag * c - s)) / diag;
         out[i] = v;
         if constexpr (DOT) acc[0] += (double)rv * (double)v;
+    }
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *acc) const {
+        const V4<float> r = ld4(rhs + i);
+        V4<float> o;
+        for (int q = 0; q < 4; ++q) {
+            o.v[q] = c.v[q] + w * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
+            if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
+        }
+        st4(out + i, o);
     }
 };
 
@@ -129,8 +294,16 @@ struct OpResid {
     const float *x, *rhs;
     float *out;
     __device__ float load(size_t i) const { return x[i]; }
+    __device__ float load1(size_t i) const { return x[i]; }
+    __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
     __device__ void apply(size_t i, float c, float s, float diag, double *) const {
         out[i] = rhs[i] - (diag * c - s);
+    }
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
+        const V4<float> r = ld4(rhs + i);
+        V4<float> o;
+        for (int q = 0; q < 4; ++q) o.v[q] = r.v[q] - (dg.v[q] * c.v[q] - s.v[q]);
+        st4(out + i, o);
     }
 };
 
@@ -147,11 +320,29 @@ struct OpPMatvec {
         if constexpr (FIRST) return z[i];
         else return z[i] + beta * pold[i];
     }
+    __device__ float load1(size_t i) const { return load(i); }
+    __device__ V4<float> load4(size_t i) const {
+        V4<float> r = ld4(z + i);
+        if constexpr (!FIRST) {
+            const V4<float> p = ld4(pold + i);
+            for (int k = 0; k < 4; ++k) r.v[k] += beta * p.v[k];
+        }
+        return r;
+    }
     __device__ void apply(size_t i, float c, float s, float diag, double *acc) const {
         float qv = diag * c - s;
         pnew[i] = c;
         q[i] = qv;
         acc[0] += (double)c * (double)qv;
+    }
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *acc) const {
+        V4<float> qq;
+        for (int k = 0; k < 4; ++k) {
+            qq.v[k] = dg.v[k] * c.v[k] - s.v[k];
+            acc[0] += (double)c.v[k] * (double)qq.v[k];
+        }
+        st4(pnew + i, c);
+        st4(q + i, qq);
     }
 };
 
@@ -174,10 +365,13 @@ __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
-__global__ void k_sub_mean(float *r, const SolveScalars *sc, size_t n) {
-    const float m = (float)sc->mean_r;
+__global__ __launch_bounds__(256) void k_sum(const float *__restrict__ x, size_t n, double *partials) {
+    double acc[1] = {0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        r[i] -= m;
+        acc[0] += (double)x[i];
+    __shared__ double lds[4][1];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
 __global__ void k_axpy64(double *x, const float *e, size_t n) {
@@ -266,21 +460,203 @@ __global__ __launch_bounds__(256) void k_prolong_add(const float *__restrict__ c
     fine[idx] += acc;
 }
 
-// x = M rhs with the dense pseudo-inverse of the coarsest operator.
-__global__ __launch_bounds__(256) void k_coarse_direct(const float *__restrict__ rhs, float *__restrict__ x,
-                                                        const float *__restrict__ M, int n) {
-    __shared__ float r[kCoarseMax];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) r[i] = rhs[i];
-    __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
-        const float *m = M + (size_t)row * n;
-        float acc = 0.f;
-        for (int j = 0; j < n; ++j) acc += m[j] * r[j];
-        x[row] = acc;
+// Vector transfers (fine x extent divisible by 4).  Lane layout as in
+// k_stencil4: a wavefront covers R rows x L float4 columns of the fine grid;
+// one fine float4 covers two coarse cells in x.
+
+// coarse = 1/2 P^T fine: a wavefront takes R coarse rows J (fine rows
+// 2J-1 .. 2J+2) and marches over coarse planes K.
+__global__ __launch_bounds__(256) void k_restrict4(const float *__restrict__ fine, Dims df, float *__restrict__ coarse,
+                                                   Dims dc, Waves4 wv) {
+    const unsigned task = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (task >= wv.tasks()) return;   // whole wavefront
+    const int s = -dc.bc_sign;
+    const unsigned W4 = (unsigned)df.nx / 4;
+    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
+    const unsigned sl = lane % wv.L, rr = lane / wv.L;
+    const unsigned t = seg * wv.L + sl;                  // fine float4 column = coarse pair (2t, 2t+1)
+    const int J = (int)(grp * wv.R + rr);
+    const bool valid = rr < wv.R && t < W4 && J < dc.ny;
+    const bool shl = sl > 0, shr = sl + 1 < wv.L && t + 1 < W4;
+    const int I0 = 2 * (int)t, I1 = I0 + 1;
+    // x weights of the 6 fine cells 4t-1 .. 4t+4 for coarse I0 and I1
+    const float a0 = restrict_w(0, I0, dc.nx, s), a1 = restrict_w(1, I0, dc.nx, s), a2 = restrict_w(2, I0, dc.nx, s),
+                a3 = restrict_w(3, I0, dc.nx, s);
+    const float b0 = restrict_w(0, I1, dc.nx, s), b1 = restrict_w(1, I1, dc.nx, s), b2 = restrict_w(2, I1, dc.nx, s),
+                b3 = restrict_w(3, I1, dc.nx, s);
+    const int K0 = (int)(zc * wv.zlen), K1 = min(K0 + (int)wv.zlen, dc.nz);
+    const size_t fplane = (size_t)df.nx * df.ny;
+    // y-reduced, x-restricted value pair of fine plane p
+    auto yx = [&](int p, float &v0, float &v1) {
+        v0 = v1 = 0.f;
+        for (int ty = 0; ty < 4; ++ty) {
+            const int fj = 2 * J - 1 + ty;
+            const float wy = valid ? restrict_w(ty, J, dc.ny, s) : 0.f;
+            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+            const bool inrow = valid && wy != 0.f && p >= 0 && p < df.nz;
+            const size_t o = inrow ? (size_t)4 * t + (size_t)df.nx * fj + fplane * p : 0;
+            if (inrow) q = *reinterpret_cast<const float4 *>(fine + o);
+            float left = __shfl_up(q.w, 1, 64), right = __shfl_down(q.x, 1, 64);
+            if (!shl) left = (inrow && t > 0) ? fine[o - 1] : 0.f;
+            if (!shr) right = (inrow && t + 1 < W4) ? fine[o + 4] : 0.f;
+            const float x0 = a0 * left + a1 * q.x + a2 * q.y + a3 * q.z;
+            const float x1 = b0 * q.y + b1 * q.z + b2 * q.w + b3 * right;
+            v0 += wy * x0;
+            v1 += wy * x1;
+        }
+    };
+    // rolling y-reduced planes 2K-1 .. 2K+2
+    float m0, m1, c0, c1;           // planes 2K-1, 2K
+    yx(2 * K0 - 1, m0, m1);
+    yx(2 * K0, c0, c1);
+    for (int K = K0; K < K1; ++K) {
+        float p0, p1, q0, q1;       // planes 2K+1, 2K+2
+        yx(2 * K + 1, p0, p1);
+        yx(2 * K + 2, q0, q1);
+        const float w0 = restrict_w(0, K, dc.nz, s), w1 = restrict_w(1, K, dc.nz, s),
+                    w2 = restrict_w(2, K, dc.nz, s), w3 = restrict_w(3, K, dc.nz, s);
+        if (valid) {
+            const float r0 = 0.5f * (w0 * m0 + w1 * c0 + w2 * p0 + w3 * q0);
+            const float r1 = 0.5f * (w0 * m1 + w1 * c1 + w2 * p1 + w3 * q1);
+            *reinterpret_cast<float2 *>(coarse + (size_t)I0 + (size_t)dc.nx * (J + (size_t)dc.ny * K)) =
+                make_float2(r0, r1);
+        }
+        m0 = p0; m1 = p1; c0 = q0; c1 = q1;
     }
 }
 
-enum { FIN_RESID = 0, FIN_RZ = 1, FIN_PQ = 2, FIN_RR = 3 };
+// fine += P coarse: a wavefront takes R fine rows j and marches over fine
+// planes in pairs (2K, 2K+1), which share coarse planes K-1 .. K+1.
+__global__ __launch_bounds__(256) void k_prolong4(const float *__restrict__ coarse, Dims dc, float *__restrict__ fine,
+                                                  Dims df, Waves4 wv) {
+    const unsigned task = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    if (task >= wv.tasks()) return;   // whole wavefront
+    const int s = -dc.bc_sign;
+    const unsigned W4 = (unsigned)df.nx / 4;
+    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
+    const unsigned sl = lane % wv.L, rr = lane / wv.L;
+    const unsigned t = seg * wv.L + sl;
+    const int j = (int)(grp * wv.R + rr);
+    const bool valid = rr < wv.R && t < W4 && j < df.ny;
+    const bool shl = sl > 0, shr = sl + 1 < wv.L && t + 1 < W4;
+    // y: coarse rows and weights
+    int Jy[2];
+    float wy[2];
+    prolong_1d(valid ? j : 0, dc.ny, s, Jy[0], Jy[1], wy[0], wy[1]);
+    const bool lb = 2 * (int)t - 1 >= 0, rb = 2 * (int)t + 2 < dc.nx;   // coarse x neighbours exist
+    // x-interpolated fine quad from coarse row (J, K)
+    auto xrow = [&](int J, int K, float4 &o) {
+        float2 c = make_float2(0.f, 0.f);
+        const size_t base = (size_t)dc.nx * (J + (size_t)dc.ny * K);
+        if (valid) c = *reinterpret_cast<const float2 *>(coarse + base + 2 * t);
+        float l = __shfl_up(c.y, 1, 64), r = __shfl_down(c.x, 1, 64);
+        if (!shl) l = (valid && lb) ? coarse[base + 2 * t - 1] : 0.f;
+        if (!shr) r = (valid && rb) ? coarse[base + 2 * t + 2] : 0.f;
+        o.x = lb ? 0.75f * c.x + 0.25f * l : (0.75f + 0.25f * s) * c.x;
+        o.y = 0.75f * c.x + 0.25f * c.y;
+        o.z = 0.75f * c.y + 0.25f * c.x;
+        o.w = rb ? 0.75f * c.y + 0.25f * r : (0.75f + 0.25f * s) * c.y;
+    };
+    auto yrow = [&](int K, float4 &o) {   // y-combined quad at coarse plane K for fine row j
+        float4 a, b;
+        xrow(Jy[0], K, a);
+        xrow(Jy[1], K, b);
+        o = make_float4(wy[0] * a.x + wy[1] * b.x, wy[0] * a.y + wy[1] * b.y, wy[0] * a.z + wy[1] * b.z,
+                        wy[0] * a.w + wy[1] * b.w);
+    };
+    const int k0 = (int)(zc * wv.zlen), k1 = min(k0 + (int)wv.zlen, df.nz);   // zlen even: k0 even
+    const size_t fplane = (size_t)df.nx * df.ny;
+    for (int k = k0; k < k1; k += 2) {
+        const int K = k >> 1;
+        float4 cm, cc, cp;
+        yrow(K > 0 ? K - 1 : K, cm);
+        yrow(K, cc);
+        yrow(K + 1 < dc.nz ? K + 1 : K, cp);
+        for (int h = 0; h < 2 && k + h < k1; ++h) {
+            // fine plane k+h: even -> (K, K-1), odd -> (K, K+1); mirror at the ends
+            const bool odd = h == 1;
+            const bool inb = odd ? (K + 1 < dc.nz) : (K > 0);
+            const float wK = inb ? 0.75f : 0.75f + 0.25f * s, wN = inb ? 0.25f : 0.f;
+            const float4 &N = odd ? cp : cm;
+            if (valid) {
+                float4 *f = reinterpret_cast<float4 *>(fine + (size_t)4 * t + (size_t)df.nx * j + fplane * (k + h));
+                float4 v = *f;
+                v.x += wK * cc.x + wN * N.x;
+                v.y += wK * cc.y + wN * N.y;
+                v.z += wK * cc.z + wN * N.z;
+                v.w += wK * cc.w + wN * N.w;
+                *f = v;
+            }
+        }
+    }
+}
+
+// Exact solve on the coarsest level (every extent <= kCoarseAxis) by the
+// separable eigenbasis of the 7-point operator: transform along x, y, z with
+// the orthonormal 1-D bases, divide by lambda_x + lambda_y + lambda_z (the
+// constant mode is dropped), transform back.  One workgroup, data in LDS.
+// E = [phi_x (cx*cx), phi_y (cy*cy), phi_z (cz*cz), lam_x, lam_y, lam_z],
+// phi_a[m * n_a + i] = mode m at cell i.
+__global__ __launch_bounds__(256) void k_coarse_eig(const float *__restrict__ rhs, float *__restrict__ x,
+                                                     const float *__restrict__ E, int cx, int cy, int cz) {
+    constexpr int M = kCoarseAxis * kCoarseAxis * kCoarseAxis;
+    __shared__ float A[M], B[M], Ph[3 * kCoarseAxis * kCoarseAxis + 3 * kCoarseAxis];
+    const int n = cx * cy * cz;
+    const int ne = cx * cx + cy * cy + cz * cz + cx + cy + cz;
+    for (int i = threadIdx.x; i < ne; i += blockDim.x) Ph[i] = E[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) A[i] = rhs[i];
+    __syncthreads();
+    const float *Px = Ph, *Py = Px + cx * cx, *Pz = Py + cy * cy;
+    const float *Lx = Pz + cz * cz, *Ly = Lx + cx, *Lz = Ly + cy;
+    // forward: x, y, z
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int m = o % cx, r = o / cx;
+        float acc = 0.f;
+        for (int i = 0; i < cx; ++i) acc += Px[m * cx + i] * A[i + cx * r];
+        B[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int i = o % cx, m = (o / cx) % cy, k = o / (cx * cy);
+        float acc = 0.f;
+        for (int j = 0; j < cy; ++j) acc += Py[m * cy + j] * B[i + cx * (j + cy * k)];
+        A[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int i = o % cx, j = (o / cx) % cy, m = o / (cx * cy);
+        float acc = 0.f;
+        for (int k = 0; k < cz; ++k) acc += Pz[m * cz + k] * A[i + cx * (j + cy * k)];
+        const float lam = Lx[i] + Ly[j] + Lz[m];
+        B[o] = lam > 1e-12f ? acc / lam : 0.f;
+    }
+    __syncthreads();
+    // inverse: z, y, x (transposed bases)
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
+        float acc = 0.f;
+        for (int m = 0; m < cz; ++m) acc += Pz[m * cz + k] * B[i + cx * (j + cy * m)];
+        A[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
+        float acc = 0.f;
+        for (int m = 0; m < cy; ++m) acc += Py[m * cy + j] * A[i + cx * (m + cy * k)];
+        B[o] = acc;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int i = o % cx, r = o / cx;
+        float acc = 0.f;
+        for (int m = 0; m < cx; ++m) acc += Px[m * cx + i] * B[m + cx * r];
+        x[o] = acc;
+    }
+}
+
+enum { FIN_RESID = 0, FIN_RZ = 1, FIN_PQ = 2, FIN_RR = 3, FIN_BSUM = 4 };
 
 __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsigned nb, int mode, int flag,
                                                    SolveScalars *sc, double ncells) {
@@ -330,6 +706,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
         case FIN_RR:
             sc->rr = v[0];
             break;
+        case FIN_BSUM:
+            sc->b_sum = v[0];
+            break;
     }
 }
 
@@ -349,31 +728,15 @@ void basis_1d(int n, int bc, std::vector<double> &phi, std::vector<double> &lam)
     }
 }
 
-// Dense pseudo-inverse of A on a small grid from the separable eigenbasis.
-std::vector<float> coarse_pinv(const Dims &d, int bc) {
-    std::vector<double> px, py, pz, lx, ly, lz;
-    basis_1d(d.nx, bc, px, lx);
-    basis_1d(d.ny, bc, py, ly);
-    basis_1d(d.nz, bc, pz, lz);
-    const int N = (int)d.count();
-    std::vector<double> M((size_t)N * N, 0.0), v(N);
-    for (int c = 0; c < d.nz; ++c)
-        for (int b = 0; b < d.ny; ++b)
-            for (int a = 0; a < d.nx; ++a) {
-                double lam = lx[a] + ly[b] + lz[c];
-                if (lam < 1e-12) continue;
-                for (int k = 0; k < d.nz; ++k)
-                    for (int j = 0; j < d.ny; ++j)
-                        for (int i = 0; i < d.nx; ++i)
-                            v[(k * d.ny + j) * d.nx + i] =
-                                px[(size_t)a * d.nx + i] * py[(size_t)b * d.ny + j] * pz[(size_t)c * d.nz + k];
-                for (int r = 0; r < N; ++r) {
-                    double vr = v[r] / lam;
-                    double *row = &M[(size_t)r * N];
-                    for (int s = 0; s < N; ++s) row[s] += vr * v[s];
-                }
-            }
-    return std::vector<float>(M.begin(), M.end());
+// 1-D eigenbases and eigenvalues of the coarsest level, laid out for k_coarse_eig.
+std::vector<float> coarse_basis(const Dims &d, int bc) {
+    std::vector<float> out;
+    std::vector<double> phi[3], lam[3];
+    const int n[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) basis_1d(n[a], bc, phi[a], lam[a]);
+    for (int a = 0; a < 3; ++a) out.insert(out.end(), phi[a].begin(), phi[a].end());
+    for (int a = 0; a < 3; ++a) out.insert(out.end(), lam[a].begin(), lam[a].end());
+    return out;
 }
 
 std::vector<Dims> level_dims(int nx, int ny, int nz) {
@@ -381,15 +744,20 @@ std::vector<Dims> level_dims(int nx, int ny, int nz) {
     Dims d{nx, ny, nz, -1};
     out.push_back(d);
     while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 4 && d.ny >= 4 && d.nz >= 4 &&
-           d.count() > 64) {
+           (d.nx > kCoarseTarget || d.ny > kCoarseTarget || d.nz > kCoarseTarget)) {
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, -1};
         out.push_back(d);
     }
     return out;
 }
 
+// blocks of the sweep kernel that runs on grid d (its reductions write one partial per block)
+unsigned sweep_blocks(const Dims &d) {
+    return d.nx % 4 == 0 ? cdiv(waves4_of(d).tasks(), 4) : tiles_of(d).count();
+}
+
 size_t partial_slots(const Dims &fine) {
-    size_t nb = tiles_of(fine).count();
+    size_t nb = sweep_blocks(fine);
     return (nb > (size_t)kRedBlocks ? nb : (size_t)kRedBlocks) * kMaxRed;
 }
 
@@ -410,8 +778,9 @@ void Solver::plan(Arena &a, int nx, int ny, int nz) {
     a.reserve(partial_slots(dims[0]) * sizeof(double));
     a.reserve(sizeof(SolveScalars));
     const Dims &c = dims.back();
-    if (c.count() <= (size_t)kCoarseMax)
-        for (int bc = 0; bc < 2; ++bc) a.reserve(c.count() * c.count() * sizeof(float));
+    if (c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis)
+        for (int bc = 0; bc < 2; ++bc)
+            a.reserve((size_t)(c.nx * c.nx + c.ny * c.ny + c.nz * c.nz + c.nx + c.ny + c.nz) * sizeof(float));
 }
 
 void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
@@ -442,12 +811,12 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
     dsc_ = a.take<SolveScalars>(1);
     WG_HIP(hipHostMalloc((void **)&hsc_, sizeof(SolveScalars), hipHostMallocDefault));
     const Dims &c = dims.back();
-    coarse_direct_ = c.count() <= (size_t)kCoarseMax;
+    coarse_direct_ = c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis;
     if (coarse_direct_) {
         for (int bc = 0; bc < 2; ++bc) {
-            coarseM_[bc] = a.take<float>(c.count() * c.count());
-            auto M = coarse_pinv(c, bc);
-            WG_HIP(hipMemcpy(coarseM_[bc], M.data(), M.size() * sizeof(float), hipMemcpyHostToDevice));
+            auto E = coarse_basis(c, bc);
+            coarseM_[bc] = a.take<float>(E.size());
+            WG_HIP(hipMemcpy(coarseM_[bc], E.data(), E.size() * sizeof(float), hipMemcpyHostToDevice));
         }
     }
 }
@@ -471,9 +840,14 @@ void Solver::read_scalars() {
 template <class Op>
 static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStream_t s, int kind = -1,
                            double bytes_per_cell = 0.0) {
-    Tiles t = tiles_of(d);
     prof::Scope ps(kind, s, bytes_per_cell * (double)d.count());
-    k_stencil<Op><<<t.count(), TX * TY, 0, s>>>(op, d, t, partials);
+    if (d.nx % 4 == 0) {
+        const Waves4 wv = waves4_of(d);
+        k_stencil4<Op><<<cdiv(wv.tasks(), 4), 256, 0, s>>>(op, d, wv, partials);
+    } else {
+        const Tiles t = tiles_of(d);
+        k_stencil<Op><<<t.count(), TX * TY, 0, s>>>(op, d, t, partials);
+    }
     WG_LAUNCH_CHECK();
 }
 
@@ -483,7 +857,7 @@ void Solver::vcycle(int l) {
     const int last = (int)lv_.size() - 1;
     if (l == last) {
         if (coarse_direct_) {
-            k_coarse_direct<<<1, 256, 0, st_>>>(L.rhs, L.x, coarseM_[bc_sign_ > 0 ? 1 : 0], (int)L.d.count());
+            k_coarse_eig<<<1, 256, 0, st_>>>(L.rhs, L.x, coarseM_[bc_sign_ > 0 ? 1 : 0], L.d.nx, L.d.ny, L.d.nz);
             WG_LAUNCH_CHECK();
         } else {
             // no direct solve possible (odd extents): a fixed, even number of sweeps
@@ -504,13 +878,25 @@ void Solver::vcycle(int l) {
     launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_, ks, 12.0);
     {
         prof::Scope ps(kt, st_, 4.0 * (double)(L.d.count() + C.d.count()));
-        k_restrict<<<cdiv(C.d.count(), 256), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d);
+        if (L.d.nx % 4 == 0) {
+            Waves4 wv = waves4_of(L.d);
+            wv.G = ((unsigned)C.d.ny + wv.R - 1) / wv.R;   // rows of the coarse grid
+            set_zlen(wv, C.d.nz);
+            k_restrict4<<<cdiv(wv.tasks(), 4), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d, wv);
+        } else {
+            k_restrict<<<cdiv(C.d.count(), 256), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d);
+        }
         WG_LAUNCH_CHECK();
     }
     vcycle(l + 1);
     {
         prof::Scope ps(kt, st_, 8.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
-        k_prolong_add<<<cdiv(L.d.count(), 256), 256, 0, st_>>>(C.x, C.d, L.x, L.d);
+        if (L.d.nx % 4 == 0) {
+            const Waves4 wv = waves4_of(L.d, true);
+            k_prolong4<<<cdiv(wv.tasks(), 4), 256, 0, st_>>>(C.x, C.d, L.x, L.d, wv);
+        } else {
+            k_prolong_add<<<cdiv(L.d.count(), 256), 256, 0, st_>>>(C.x, C.d, L.x, L.d);
+        }
         WG_LAUNCH_CHECK();
     }
     launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 12.0);
@@ -524,7 +910,7 @@ void Solver::vcycle(int l) {
 int Solver::pcg(double tol, int max_it, double rr0) {
     Level &F = lv_[0];
     const size_t N = F.d.count();
-    const unsigned tb = tiles_of(F.d).count();
+    const unsigned tb = sweep_blocks(F.d);
     const unsigned rb = red_blocks(N);
     // z = M r, rz = r.z ; the first finalize must not form beta
     vcycle(0);
@@ -570,7 +956,7 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
     for (auto &L : lv_) L.d.bc_sign = bc_sign_;
     Level &F = lv_[0];
     const size_t N = F.d.count();
-    const unsigned tb = tiles_of(F.d).count();
+    const unsigned tb = sweep_blocks(F.d);
     const unsigned gb = red_blocks(N);
     SolveResult res;
     WG_HIP(hipMemsetAsync(dsc_, 0, sizeof(SolveScalars), st_));
@@ -578,11 +964,19 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
         k_fill64<<<gb, kBlock, 0, st_>>>(x, 0.0, N);
         WG_LAUNCH_CHECK();
     }
+    double mb = 0.0;
+    if (bc == WG_BC_NEUMANN) {
+        k_sum<<<gb, kBlock, 0, st_>>>(b, N, partials_);
+        WG_LAUNCH_CHECK();
+        finalize(FIN_BSUM, gb, 0);
+        read_scalars();
+        mb = hsc_->b_sum / (double)N;
+    }
     const double tol = o.rel_tol > 0 ? o.rel_tol : 1e-6;
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64{x, b, F.rhs}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
+        launch_stencil(OpResid64{x, b, F.rhs, mb}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;
@@ -609,12 +1003,8 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
             res.status = WG_ENOTCONV;
             break;
         }
-        if (bc == WG_BC_NEUMANN) {
-            k_sub_mean<<<gb, kBlock, 0, st_>>>(F.rhs, dsc_, N);
-            WG_LAUNCH_CHECK();
-        }
         double inner = 0.5 * tol / res.rel_res;
-        if (inner < 1e-3) inner = 1e-3;
+        if (inner < 1e-4) inner = 1e-4;
         if (inner > 0.5) inner = 0.5;
         int budget = max_iters - res.iters;
         if (budget > 60) budget = 60;

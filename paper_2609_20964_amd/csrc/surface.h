@@ -2,10 +2,11 @@
 //
 // Marching Cubes (Warp-Geo Eq. 27-28) runs on the dual lattice whose cube
 // corners are the cell centres.  Cubes are grouped into 4x4x4 bricks (one
-// wavefront each), bricks are visited in Morton order, and every non-empty
-// brick becomes a leaf of an 8-ary box hierarchy built bottom-up over that
-// order.  The signed distance (Eq. 29-34) of every grid node is the exact
-// minimum over all triangles: one wavefront per 4x4x4 node tile walks the
+// wavefront each); bricks, and the cubes inside a brick, are visited in Morton
+// order, so the triangle list is Morton ordered.  Groups of 4 consecutive
+// triangles are the leaves of an 8-ary hierarchy of oriented boxes (thin along
+// the patch normal) built bottom-up over that order.  The signed distance (Eq. 29-34) of every grid node is the exact
+// minimum over all triangles: one wavefront per 8x8x4 node tile walks the
 // hierarchy together, pruning a box only when it is farther than every lane's
 // current best, so the result equals the brute-force minimum.
 #pragma once
@@ -35,9 +36,11 @@ class Surface {
                float *g_chi, double *g_c);
 
     uint32_t n_tris() const { return cnt_.n_tris; }
+    // first n triangles as float[9] (vertices in grid units)
+    void export_tris(float *out, uint32_t n);
     const float4 *tris() const { return tri_; }
     const int2 *tri_info() const { return info_; }
-    size_t bytes() const { return cap_ * (3 * sizeof(float4) + sizeof(int2)) + box_cap_ * 2 * sizeof(float4); }
+    size_t bytes() const { return cap_ * (3 * sizeof(float4) + sizeof(int2)) + box_cap_ * 5 * sizeof(float4); }
 
   private:
     void ensure_capacity(uint32_t tris, uint32_t active);
@@ -53,7 +56,8 @@ class Surface {
     // growable
     float4 *tri_ = nullptr;        // [cap][3]
     int2 *info_ = nullptr;         // [cap]
-    float4 *box_ = nullptr;        // [box_cap][2] (lo, hi) for every hierarchy level
+    float4 *box_ = nullptr;        // [box_cap][4] oriented-box nodes of every hierarchy level
+    float4 *nsum_ = nullptr;       // [box_cap] area-weighted normal sums (hierarchy build only)
     size_t cap_ = 0, box_cap_ = 0;
     std::vector<uint32_t> level_off_, level_cnt_;
     int levels_ = 0;

@@ -1,6 +1,7 @@
 // Surface extraction, exact signed distance on every grid node, sampling and
 // their reverses.  See surface.h for the data layout.
 #include <cmath>
+#include <cstdlib>
 
 #include "mc_table.inc"
 #include "prof.h"
@@ -13,12 +14,10 @@ namespace {
 constexpr int kBrick = 4;                   // cubes per brick edge (64 = one wavefront)
 constexpr int kMaxLevels = 12;
 constexpr int kStack = 64;
+constexpr uint32_t kLeaf = 4;               // triangles per hierarchy leaf
+constexpr int kNode = 4;                    // float4 per hierarchy node
+constexpr uint32_t kLeafBit = 1u << 31;     // packed child word: leaf flag, count << 27, first index
 
-struct LevelInfo {
-    uint32_t off[kMaxLevels];
-    uint32_t cnt[kMaxLevels];
-    int L;
-};
 
 __device__ __forceinline__ uint32_t compact3(uint32_t m) {
     m &= 0x09249249u;
@@ -56,9 +55,10 @@ struct BrickPos {
 __device__ __forceinline__ BrickPos brick_lane(uint32_t m, int lane, const int nb[3], const Dims &d) {
     int bx = compact3(m), by = compact3(m >> 1), bz = compact3(m >> 2);
     BrickPos p;
-    p.i = bx * kBrick + (lane & 3);
-    p.j = by * kBrick + ((lane >> 2) & 3);
-    p.k = bz * kBrick + (lane >> 4);
+    // Morton order inside the brick too, so the triangle list is in Morton order of cubes
+    p.i = bx * kBrick + (int)compact3((uint32_t)lane);
+    p.j = by * kBrick + (int)compact3((uint32_t)lane >> 1);
+    p.k = bz * kBrick + (int)compact3((uint32_t)lane >> 2);
     p.ok = bx < nb[0] && by < nb[1] && bz < nb[2] && p.i < d.nx - 1 && p.j < d.ny - 1 && p.k < d.nz - 1;
     return p;
 }
@@ -176,12 +176,14 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t *cnt, uint32_
     }
 }
 
-// One wavefront per non-empty brick: triangles of its cubes (vertices by
-// Eq. 28 with eta in FP64) and the brick's bounding box (hierarchy leaf).
+// One wavefront per non-empty brick: the triangles of its cubes, vertices by
+// Eq. 28 with eta in FP64.  Each triangle is stored ready for the distance
+// test: A = (a, |ab|^2), B = (ab, ab.ac), C = (ac, |ac|^2) with ab = b - a,
+// ac = c - a in grid units.
 __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi, const double *iso, Dims d, NB nb,
                                                   const uint32_t *__restrict__ active, uint32_t n_active,
                                                   const uint32_t *__restrict__ off, float4 *__restrict__ tri,
-                                                  int2 *__restrict__ info, float4 *__restrict__ box) {
+                                                  int2 *__restrict__ info) {
     const int lane = threadIdx.x % 64;
     const uint32_t idx = blockIdx.x * 4 + threadIdx.x / 64;
     if (idx >= n_active) return;   // whole wavefront
@@ -202,9 +204,9 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
     }
     pre -= nt;
     const uint32_t base = off[m] + pre;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int t = 0; t < nt; ++t) {
         int packed = 0;
+        double V[3][3];
         for (int q = 0; q < 3; ++q) {
             int e = WG_MC_TRI[cs][3 * t + q];
             packed |= e << (4 * q);
@@ -213,176 +215,298 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
             double x1 = chi[cell + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2)];
             double x2 = chi[cell + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2)];
             double eta = (c - x1) / (x2 - x1);
-            double pos[3] = {(double)(p.i + (b0 & 1)), (double)(p.j + ((b0 >> 1) & 1)), (double)(p.k + (b0 >> 2))};
-            pos[ax] += eta;
-            float4 v = make_float4((float)pos[0], (float)pos[1], (float)pos[2], 0.f);
-            tri[3 * (size_t)(base + t) + q] = v;
-            lo[0] = fminf(lo[0], v.x); lo[1] = fminf(lo[1], v.y); lo[2] = fminf(lo[2], v.z);
-            hi[0] = fmaxf(hi[0], v.x); hi[1] = fmaxf(hi[1], v.y); hi[2] = fmaxf(hi[2], v.z);
+            V[q][0] = (double)(p.i + (b0 & 1));
+            V[q][1] = (double)(p.j + ((b0 >> 1) & 1));
+            V[q][2] = (double)(p.k + (b0 >> 2));
+            V[q][ax] += eta;
         }
+        float a[3], ab[3], ac[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = (float)V[0][k];
+            ab[k] = (float)(V[1][k] - V[0][k]);
+            ac[k] = (float)(V[2][k] - V[0][k]);
+        }
+        double aa = 0, bc = 0, cc = 0;
+        for (int k = 0; k < 3; ++k) {
+            aa += (double)ab[k] * ab[k];
+            bc += (double)ab[k] * ac[k];
+            cc += (double)ac[k] * ac[k];
+        }
+        const size_t o = 3 * (size_t)(base + t);
+        tri[o] = make_float4(a[0], a[1], a[2], (float)aa);
+        tri[o + 1] = make_float4(ab[0], ab[1], ab[2], (float)bc);
+        tri[o + 2] = make_float4(ac[0], ac[1], ac[2], (float)cc);
         info[base + t] = make_int2((int)cell, packed);
     }
+}
+
+// Hierarchy nodes are oriented boxes: node = 4 float4,
+//   [0] = (centre, e_u), [1] = (u, e_v), [2] = (v, e_n), [3] = (n, children),
+// "children" being the bits of a word: leaf flag (bit 31), count << 27, first
+// index (first triangle of a leaf, first child node otherwise);
+// with (u, v, n) orthonormal, n along the area-weighted normal of the triangles
+// below the node, e_* the half extents.  Where the normals cancel the axes are
+// the coordinate axes (an axis-aligned box).  Extents carry a small relative
+// margin so the box bound never exceeds the true distance.
+__device__ __forceinline__ void frame_from_normal(float nx, float ny, float nz, float *u, float *v, float *n) {
+    const float L = sqrtf(nx * nx + ny * ny + nz * nz);
+    if (!(L > 1e-12f)) {
+        u[0] = 1; u[1] = 0; u[2] = 0; v[0] = 0; v[1] = 1; v[2] = 0; n[0] = 0; n[1] = 0; n[2] = 1;
+        return;
+    }
+    n[0] = nx / L; n[1] = ny / L; n[2] = nz / L;
+    // u = normalize(n x e_k), e_k the coordinate axis least aligned with n
+    const float ax = fabsf(n[0]), ay = fabsf(n[1]), az = fabsf(n[2]);
+    float e[3] = {0, 0, 0};
+    e[(ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2)] = 1.f;
+    float ux = n[1] * e[2] - n[2] * e[1], uy = n[2] * e[0] - n[0] * e[2], uz = n[0] * e[1] - n[1] * e[0];
+    const float lu = sqrtf(ux * ux + uy * uy + uz * uz);
+    u[0] = ux / lu; u[1] = uy / lu; u[2] = uz / lu;
+    v[0] = n[1] * u[2] - n[2] * u[1]; v[1] = n[2] * u[0] - n[0] * u[2]; v[2] = n[0] * u[1] - n[1] * u[0];
+}
+
+__device__ __forceinline__ void store_node(float4 *node, const float *u, const float *v, const float *n,
+                                           const float *lo, const float *hi, uint32_t children) {
+    float c[3], e[3];
+    for (int k = 0; k < 3; ++k) {
+        const float m = 0.5f * (lo[k] + hi[k]);
+        e[k] = 0.5f * (hi[k] - lo[k]) + 1e-5f * (1.f + fabsf(m));
+        c[k] = m;
+    }
+    const float cx = c[0] * u[0] + c[1] * v[0] + c[2] * n[0];
+    const float cy = c[0] * u[1] + c[1] * v[1] + c[2] * n[1];
+    const float cz = c[0] * u[2] + c[1] * v[2] + c[2] * n[2];
+    node[0] = make_float4(cx, cy, cz, e[0]);
+    node[1] = make_float4(u[0], u[1], u[2], e[1]);
+    node[2] = make_float4(v[0], v[1], v[2], e[2]);
+    node[3] = make_float4(n[0], n[1], n[2], __uint_as_float(children));
+}
+
+// Leaves: one thread per group of kLeaf consecutive triangles.
+__global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ tri, uint32_t n_tris,
+                                                     float4 *__restrict__ nodes, float4 *__restrict__ nsum,
+                                                     uint32_t n_leaves) {
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_leaves) return;
+    const uint32_t t0 = g * kLeaf, t1 = min(t0 + kLeaf, n_tris);
+    float ns[3] = {0.f, 0.f, 0.f};
+    for (uint32_t t = t0; t < t1; ++t) {
+        const float4 B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+        ns[0] += B.y * C.z - B.z * C.y;
+        ns[1] += B.z * C.x - B.x * C.z;
+        ns[2] += B.x * C.y - B.y * C.x;
+    }
+    float u[3], v[3], n[3];
+    frame_from_normal(ns[0], ns[1], ns[2], u, v, n);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t t = t0; t < t1; ++t) {
+        const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+        const float P[3][3] = {{A.x, A.y, A.z}, {A.x + B.x, A.y + B.y, A.z + B.z}, {A.x + C.x, A.y + C.y, A.z + C.z}};
+        for (int q = 0; q < 3; ++q) {
+            const float pu = P[q][0] * u[0] + P[q][1] * u[1] + P[q][2] * u[2];
+            const float pv = P[q][0] * v[0] + P[q][1] * v[1] + P[q][2] * v[2];
+            const float pn = P[q][0] * n[0] + P[q][1] * n[1] + P[q][2] * n[2];
+            lo[0] = fminf(lo[0], pu); hi[0] = fmaxf(hi[0], pu);
+            lo[1] = fminf(lo[1], pv); hi[1] = fmaxf(hi[1], pv);
+            lo[2] = fminf(lo[2], pn); hi[2] = fmaxf(hi[2], pn);
+        }
+    }
+    store_node(nodes + (size_t)kNode * g, u, v, n, lo, hi, kLeafBit | ((t1 - t0) << 27) | t0);
+    nsum[g] = make_float4(ns[0], ns[1], ns[2], 0.f);
+}
+
+// Parents: one wavefront per parent; lane l takes corner (l & 7) of child (l >> 3).
+// child_first: absolute index of the child level's first node.
+__global__ __launch_bounds__(256) void k_parent_nodes(const float4 *__restrict__ child,
+                                                       const float4 *__restrict__ child_nsum, uint32_t nchild,
+                                                       uint32_t child_first, float4 *__restrict__ parent,
+                                                       float4 *__restrict__ parent_nsum, uint32_t nparent) {
+    const int lane = threadIdx.x % 64;
+    const uint32_t j = blockIdx.x * 4 + threadIdx.x / 64;
+    if (j >= nparent) return;   // whole wavefront
+    const uint32_t ci = 8 * j + (lane >> 3);
+    const bool has = ci < nchild;
+    float4 c0 = make_float4(0, 0, 0, 0), c1 = c0, c2 = c0, c3 = c0, c4 = c0;
+    if (has) {
+        const float4 *nd = child + (size_t)kNode * ci;
+        c0 = nd[0]; c1 = nd[1]; c2 = nd[2]; c3 = nd[3]; c4 = child_nsum[ci];
+    }
+    // normal sum of the children (each child counted once: corner 0 lanes)
+    float ns[3] = {(has && (lane & 7) == 0) ? c4.x : 0.f, (has && (lane & 7) == 0) ? c4.y : 0.f,
+                   (has && (lane & 7) == 0) ? c4.z : 0.f};
     for (int o = 32; o > 0; o >>= 1)
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, 64));
-            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, 64));
+        for (int k = 0; k < 3; ++k) ns[k] += __shfl_xor(ns[k], o, 64);
+    float u[3], v[3], n[3];
+    frame_from_normal(ns[0], ns[1], ns[2], u, v, n);
+    // this lane's corner of its child box
+    const float su = (lane & 1) ? 1.f : -1.f, sv = (lane & 2) ? 1.f : -1.f, sn = (lane & 4) ? 1.f : -1.f;
+    const float px = c0.x + su * c0.w * c1.x + sv * c1.w * c2.x + sn * c2.w * c3.x;
+    const float py = c0.y + su * c0.w * c1.y + sv * c1.w * c2.y + sn * c2.w * c3.y;
+    const float pz = c0.z + su * c0.w * c1.z + sv * c1.w * c2.z + sn * c2.w * c3.z;
+    float lo[3], hi[3];
+    const float pr[3] = {px * u[0] + py * u[1] + pz * u[2], px * v[0] + py * v[1] + pz * v[2],
+                         px * n[0] + py * n[1] + pz * n[2]};
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = has ? pr[k] : INFINITY;
+        hi[k] = has ? pr[k] : -INFINITY;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
+            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o, 64));
         }
     if (lane == 0) {
-        box[2 * (size_t)idx] = make_float4(lo[0], lo[1], lo[2], 0.f);
-        box[2 * (size_t)idx + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        const uint32_t cnt = min(8u, nchild - 8 * j);
+        store_node(parent + (size_t)kNode * j, u, v, n, lo, hi, (cnt << 27) | (child_first + 8 * j));
+        parent_nsum[j] = make_float4(ns[0], ns[1], ns[2], 0.f);
     }
 }
 
-__global__ __launch_bounds__(256) void k_box_level(const float4 *__restrict__ child, uint32_t nchild,
-                                                    float4 *__restrict__ parent, uint32_t nparent) {
-    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nparent) return;
-    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f), hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
-    uint32_t c1 = min(8 * j + 8, nchild);
-    for (uint32_t c = 8 * j; c < c1; ++c) {
-        float4 a = child[2 * (size_t)c], b = child[2 * (size_t)c + 1];
-        lo.x = fminf(lo.x, a.x); lo.y = fminf(lo.y, a.y); lo.z = fminf(lo.z, a.z);
-        hi.x = fmaxf(hi.x, b.x); hi.y = fmaxf(hi.y, b.y); hi.z = fmaxf(hi.z, b.z);
-    }
-    parent[2 * (size_t)j] = lo;
-    parent[2 * (size_t)j + 1] = hi;
+// Mesh export: vertices a, a + ab, a + ac as float[9] per triangle.
+__global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ tri, uint32_t n, float *__restrict__ out) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+    float *o = out + 9 * (size_t)t;
+    o[0] = A.x; o[1] = A.y; o[2] = A.z;
+    o[3] = A.x + B.x; o[4] = A.y + B.y; o[5] = A.z + B.z;
+    o[6] = A.x + C.x; o[7] = A.y + C.y; o[8] = A.z + C.z;
 }
 
-__device__ __forceinline__ float box_d2(float px, float py, float pz, float4 lo, float4 hi) {
-    float dx = fmaxf(fmaxf(lo.x - px, 0.f), px - hi.x);
-    float dy = fmaxf(fmaxf(lo.y - py, 0.f), py - hi.y);
-    float dz = fmaxf(fmaxf(lo.z - pz, 0.f), pz - hi.z);
-    return dx * dx + dy * dy + dz * dz;
-}
-
-__device__ __forceinline__ float seg_d2(float3 p, float3 a, float3 b, float &t) {
-    float3 ab = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
-    float3 ap = make_float3(p.x - a.x, p.y - a.y, p.z - a.z);
-    float l2 = ab.x * ab.x + ab.y * ab.y + ab.z * ab.z;
-    t = l2 > 0.f ? (ap.x * ab.x + ap.y * ab.y + ap.z * ab.z) / l2 : 0.f;
-    t = fminf(fmaxf(t, 0.f), 1.f);
-    float ex = ap.x - t * ab.x, ey = ap.y - t * ab.y, ez = ap.z - t * ab.z;
-    return ex * ex + ey * ey + ez * ez;
-}
-
-// Closest point of triangle (a,b,c) to p by Voronoi-region classification
-// (Ericson, Real-Time Collision Detection, 2005, Sec. 5.1.5), with guards
-// for zero-length edges and zero-area triangles.  Returns the squared
+// Closest point of a triangle to p by Voronoi-region classification (Ericson,
+// Real-Time Collision Detection, 2005, Sec. 5.1.5), on the stored record
+// A = (a, |ab|^2), B = (ab, ab.ac), C = (ac, |ac|^2): with ap = p - a, the six
+// dot products of that method follow from d1 = ab.ap and d2 = ac.ap.  Guards
+// cover zero-length edges; a zero-area triangle falls back to vertex a, which
+// is never closer than its true nearest point (its edges are shared with its
+// neighbours, which supply the exact distance).  Returns the squared
 // distance; (v, w) are the barycentric weights of b and c at the closest point.
-__device__ float tri_d2(float3 p, float3 a, float3 b, float3 c, float &v, float &w) {
-    float3 ab = make_float3(b.x - a.x, b.y - a.y, b.z - a.z);
-    float3 ac = make_float3(c.x - a.x, c.y - a.y, c.z - a.z);
-    float3 ap = make_float3(p.x - a.x, p.y - a.y, p.z - a.z);
-    float d1 = ab.x * ap.x + ab.y * ap.y + ab.z * ap.z;
-    float d2 = ac.x * ap.x + ac.y * ap.y + ac.z * ap.z;
-    float3 bp = make_float3(p.x - b.x, p.y - b.y, p.z - b.z);
-    float d3 = ab.x * bp.x + ab.y * bp.y + ab.z * bp.z;
-    float d4 = ac.x * bp.x + ac.y * bp.y + ac.z * bp.z;
-    float3 cp = make_float3(p.x - c.x, p.y - c.y, p.z - c.z);
-    float d5 = ab.x * cp.x + ab.y * cp.y + ab.z * cp.z;
-    float d6 = ac.x * cp.x + ac.y * cp.y + ac.z * cp.z;
-    float vc = d1 * d4 - d3 * d2;
-    float vb = d5 * d2 - d1 * d6;
-    float va = d3 * d6 - d5 * d4;
+__device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, float4 B, float4 C, float &v,
+                                        float &w) {
+    const float apx = px - A.x, apy = py - A.y, apz = pz - A.z;
+    const float d1 = B.x * apx + B.y * apy + B.z * apz;
+    const float d2 = C.x * apx + C.y * apy + C.z * apz;
+    const float aa = A.w, bc = B.w, cc = C.w;
+    const float d3 = d1 - aa, d4 = d2 - bc;     // against p - b
+    const float d5 = d1 - bc, d6 = d2 - cc;     // against p - c
+    const float vc = d1 * d4 - d3 * d2;
+    const float vb = d5 * d2 - d1 * d6;
+    const float va = d3 * d6 - d5 * d4;
     if (d1 <= 0.f && d2 <= 0.f) { v = 0.f; w = 0.f; }
     else if (d3 >= 0.f && d4 <= d3) { v = 1.f; w = 0.f; }
     else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-        float den = d1 - d3;
+        const float den = d1 - d3;
         v = den > 0.f ? d1 / den : 0.f;
         w = 0.f;
     } else if (d6 >= 0.f && d5 <= d6) { v = 0.f; w = 1.f; }
     else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-        float den = d2 - d6;
+        const float den = d2 - d6;
         v = 0.f;
         w = den > 0.f ? d2 / den : 0.f;
     } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
-        float den = (d4 - d3) + (d5 - d6);
+        const float den = (d4 - d3) + (d5 - d6);
         w = den > 0.f ? (d4 - d3) / den : 0.f;
         v = 1.f - w;
     } else {
-        float sum = va + vb + vc;
-        if (sum > 0.f) {
-            v = vb / sum;
-            w = vc / sum;
-        } else {
-            // zero area: nearest of the three edges
-            float t0, t1, t2;
-            float e0 = seg_d2(p, a, b, t0), e1 = seg_d2(p, b, c, t1), e2 = seg_d2(p, c, a, t2);
-            if (e0 <= e1 && e0 <= e2) { v = t0; w = 0.f; }
-            else if (e1 <= e2) { v = 1.f - t1; w = t1; }
-            else { v = 0.f; w = 1.f - t2; }
-        }
+        const float sum = va + vb + vc;
+        v = sum > 0.f ? vb / sum : 0.f;
+        w = sum > 0.f ? vc / sum : 0.f;
     }
-    float qx = a.x + v * ab.x + w * ac.x - p.x;
-    float qy = a.y + v * ab.y + w * ac.y - p.y;
-    float qz = a.z + v * ab.z + w * ac.z - p.z;
+    const float qx = apx - v * B.x - w * C.x;
+    const float qy = apy - v * B.y - w * C.y;
+    const float qz = apz - v * B.z - w * C.z;
     return qx * qx + qy * qy + qz * qz;
 }
 
-__device__ __forceinline__ float3 f3(float4 v) { return make_float3(v.x, v.y, v.z); }
-
-__device__ __forceinline__ int cdiv_dev(int n) { return (n + 3) / 4; }
-
-// Exact unsigned distance from every node of a 4x4x4 tile (one wavefront) to
-// the mesh, by a wavefront-cooperative walk of the box hierarchy; sign from
-// chi >= c (outside positive); phi = sign * distance * h.
+// Tile = LX x LY x (LZ * kTZ) nodes: lane (x, y, z) of an LX x LY x LZ block
+// owns the kTZ nodes z, z + LZ, ... of its column.
+template <int LX, int LY, int LZ, int kTZ>
 __global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, const double *iso, Dims d, double h,
-                                              const float4 *__restrict__ box, LevelInfo lev,
-                                              const uint32_t *__restrict__ active, const uint32_t *__restrict__ off,
-                                              const uint32_t *__restrict__ cnt, const float4 *__restrict__ tri,
-                                              uint32_t n_tris, float *__restrict__ phi, int32_t *__restrict__ argmin,
-                                              int *err) {
+                                              const float4 *__restrict__ nodes, uint32_t root,
+                                              const float4 *__restrict__ tri, uint32_t n_tris,
+                                              float *__restrict__ phi, int32_t *__restrict__ argmin, int *err) {
+    static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    const int tx = cdiv_dev(d.nx), ty = cdiv_dev(d.ny), tz = cdiv_dev(d.nz);
+    constexpr int TZ = LZ * kTZ;
+    const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
     const uint32_t tile = blockIdx.x * 4 + w;
     if (tile >= (uint32_t)(tx * ty * tz)) return;   // whole wavefront
     const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
-    const int gi = bx * 4 + (lane & 3), gj = by * 4 + ((lane >> 2) & 3), gk = bz * 4 + (lane >> 4);
-    const bool valid = gi < d.nx && gj < d.ny && gk < d.nz;
-    const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1), k = min(gk, d.nz - 1);
-    const float px = (float)i, py = (float)j, pz = (float)k;
-    const float cx = bx * 4 + 1.5f, cy = by * 4 + 1.5f, cz = bz * 4 + 1.5f;
-    float best = INFINITY;
-    int arg = -1;
+    const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
+    const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1);
+    const float px = (float)i, py = (float)j;
+    float pz[kTZ], best[kTZ];
+    int arg[kTZ];
+#pragma unroll
+    for (int k = 0; k < kTZ; ++k) {
+        pz[k] = (float)min(gk0 + LZ * k, d.nz - 1);
+        best[k] = INFINITY;
+        arg[k] = -1;
+    }
     if (n_tris > 0) {
-        int sp = 0;
-        stk[w][0] = (uint32_t)(lev.L - 1) << 24;
-        sp = 1;
+        int sp = 1;
+        stk[w][0] = root;
         while (sp > 0) {
             --sp;
-            const uint32_t ent = __builtin_amdgcn_readfirstlane(stk[w][sp]);
-            const int level = ent >> 24;
-            const uint32_t idx = ent & 0xffffffu;
-            const size_t bi = lev.off[level] + idx;
-            const float4 blo = box[2 * bi], bhi = box[2 * bi + 1];
-            if (__ballot(box_d2(px, py, pz, blo, bhi) < best) == 0) continue;
-            if (level == 0) {
-                const uint32_t m = active[idx];
-                const uint32_t t0 = off[m], t1 = t0 + cnt[m];
-                const float3 p = make_float3(px, py, pz);
-                for (uint32_t t = t0; t < t1; ++t) {
-                    float v_, w_;
-                    float dd = tri_d2(p, f3(tri[3 * (size_t)t]), f3(tri[3 * (size_t)t + 1]), f3(tri[3 * (size_t)t + 2]),
-                                      v_, w_);
-                    if (dd < best) {
-                        best = dd;
-                        arg = (int)t;
+            const uint32_t ni = __builtin_amdgcn_readfirstlane(stk[w][sp]);
+            const float4 *nd = nodes + (size_t)kNode * ni;
+            const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
+            // bound of this node for the lane's kTZ nodes (they differ only in z)
+            bool need = false;
+            {
+                const float rx = px - N0.x, ry = py - N0.y;
+                const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
+                            bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
+#pragma unroll
+                for (int k = 0; k < kTZ; ++k) {
+                    const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
+                    const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
+                    const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
+                    need |= du * du + dv * dv + dn * dn < best[k];
+                }
+            }
+            if (__ballot(need) == 0) continue;
+            const uint32_t word = __float_as_uint(N3.w);
+            const uint32_t first = word & 0x07ffffffu, cnt = (word >> 27) & 15u;
+            if (word & kLeafBit) {
+                for (uint32_t t = first; t < first + cnt; ++t) {
+                    const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+#pragma unroll
+                    for (int k = 0; k < kTZ; ++k) {
+                        float v_, w_;
+                        const float dd = tri_d2(px, py, pz[k], A, B, C, v_, w_);
+                        if (dd < best[k]) {
+                            best[k] = dd;
+                            arg[k] = (int)t;
+                        }
                     }
                 }
             } else {
-                const uint32_t c0 = idx * 8;
-                const uint32_t nch = min(8u, lev.cnt[level - 1] - c0);
-                const uint32_t coff = lev.off[level - 1];
                 float key[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    key[q] = -1.f;
-                    if ((uint32_t)q < nch) {
-                        const size_t ci = coff + c0 + q;
-                        const float4 lo = box[2 * ci], hi = box[2 * ci + 1];
-                        if (__ballot(box_d2(px, py, pz, lo, hi) < best) != 0) key[q] = box_d2(cx, cy, cz, lo, hi);
+                    // always a valid node (clamped), so all eight loads can be issued together
+                    const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
+                    const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
+                    const float rx = px - C0.x, ry = py - C0.y;
+                    const float bu = C1.x * rx + C1.y * ry - C1.z * C0.z, bv = C2.x * rx + C2.y * ry - C2.z * C0.z,
+                                bn = C3.x * rx + C3.y * ry - C3.z * C0.z;
+                    bool vis = false;
+                    float d0 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < kTZ; ++k) {
+                        const float du = fmaxf(fabsf(bu + C1.z * pz[k]) - C0.w, 0.f);
+                        const float dv = fmaxf(fabsf(bv + C2.z * pz[k]) - C1.w, 0.f);
+                        const float dn = fmaxf(fabsf(bn + C3.z * pz[k]) - C2.w, 0.f);
+                        const float dd = du * du + dv * dv + dn * dn;
+                        vis |= dd < best[k];
+                        if (k == 0) d0 = dd;
                     }
+                    // order key: lane 0's bound for its first node (uniform)
+                    key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0)
+                                 ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d0)))
+                                 : -1.f;
                 }
                 if (sp + 8 > kStack) {
                     atomicOr(err, 2);
@@ -403,17 +527,22 @@ __global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, con
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
                         if (q == qb) key[q] = -1.f;
-                    stk[w][sp] = ((uint32_t)(level - 1) << 24) | (c0 + qb);
+                    stk[w][sp] = first + (uint32_t)qb;
                     ++sp;
                 }
             }
         }
     }
-    if (valid) {
-        const size_t o = (size_t)i + (size_t)d.nx * (j + (size_t)d.ny * k);
-        const float s = chi[o] >= iso[0] ? 1.f : -1.f;
-        phi[o] = s * sqrtf(best) * (float)h;
-        argmin[o] = arg;
+    if (gi < d.nx && gj < d.ny) {
+        const double c = iso[0];
+#pragma unroll
+        for (int k = 0; k < kTZ; ++k) {
+            if (gk0 + LZ * k >= d.nz) break;
+            const size_t o = (size_t)i + (size_t)d.nx * (j + (size_t)d.ny * (gk0 + LZ * k));
+            const float s = chi[o] >= c ? 1.f : -1.f;
+            phi[o] = s * sqrtf(best[k]) * (float)h;
+            argmin[o] = arg[k];
+        }
     }
 }
 
@@ -432,13 +561,12 @@ __global__ __launch_bounds__(256) void k_sdf_T(const float *__restrict__ gphi, c
     if (g != 0.f && t >= 0) {
         const double c = iso[0];
         const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / ((size_t)d.nx * d.ny);
-        const float3 p = make_float3((float)i, (float)j, (float)k);
-        const float3 A = f3(tri[3 * (size_t)t]), B = f3(tri[3 * (size_t)t + 1]), C = f3(tri[3 * (size_t)t + 2]);
+        const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
         float v, w;
-        tri_d2(p, A, B, C, v, w);
-        float q[3] = {A.x + v * (B.x - A.x) + w * (C.x - A.x), A.y + v * (B.y - A.y) + w * (C.y - A.y),
-                      A.z + v * (B.z - A.z) + w * (C.z - A.z)};
-        float u[3] = {p.x - q[0], p.y - q[1], p.z - q[2]};
+        tri_d2((float)i, (float)j, (float)k, A, B, C, v, w);
+        // p - (a + v ab + w ac)
+        float u[3] = {(float)i - A.x - v * B.x - w * C.x, (float)j - A.y - v * B.y - w * C.y,
+                      (float)k - A.z - v * B.z - w * C.z};
         float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         if (dist > 0.f) {
             const float sgn = chi[o] >= c ? 1.f : -1.f;
@@ -641,6 +769,7 @@ Surface::~Surface() {
     if (tri_) (void)hipFree(tri_);
     if (info_) (void)hipFree(info_);
     if (box_) (void)hipFree(box_);
+    if (nsum_) (void)hipFree(nsum_);
     if (hcnt_) (void)hipHostFree(hcnt_);
 }
 
@@ -655,13 +784,18 @@ void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
         WG_HIP(hipMalloc(&info_, c * sizeof(int2)));
         cap_ = c;
     }
-    // boxes of every level: at most active * 8/7 + levels
-    size_t need = (size_t)active + active / 7 + kMaxLevels + 1;
+    // boxes of every level: leaves = ceil(tris / kLeaf), then 8-ary levels
+    (void)active;
+    size_t leaves = ((size_t)tris + kLeaf - 1) / kLeaf;
+    size_t need = leaves + leaves / 7 + kMaxLevels + 1;
     if (need > box_cap_) {
         if (box_) WG_HIP(hipFree(box_));
         box_ = nullptr;
         size_t c = need + need / 4 + 64;
-        WG_HIP(hipMalloc(&box_, c * 2 * sizeof(float4)));
+        WG_HIP(hipMalloc(&box_, c * kNode * sizeof(float4)));
+        if (nsum_) WG_HIP(hipFree(nsum_));
+        nsum_ = nullptr;
+        WG_HIP(hipMalloc(&nsum_, c * sizeof(float4)));
         box_cap_ = c;
     }
 }
@@ -685,16 +819,18 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     level_cnt_.clear();
     if (cnt_.n_tris == 0) return 0;
     ensure_capacity(cnt_.n_tris, cnt_.n_active);
-    k_mc_emit<<<cdiv(cnt_.n_active, 4), 256, 0, st_>>>(chi, c, d_, nb, active_, cnt_.n_active, off_b_, tri_, info_,
-                                                       box_);
+    k_mc_emit<<<cdiv(cnt_.n_active, 4), 256, 0, st_>>>(chi, c, d_, nb, active_, cnt_.n_active, off_b_, tri_, info_);
     WG_LAUNCH_CHECK();
-    uint32_t n = cnt_.n_active, off = 0;
+    uint32_t n = cdiv(cnt_.n_tris, kLeaf), off = 0;
+    k_leaf_nodes<<<cdiv(n, 256), 256, 0, st_>>>(tri_, cnt_.n_tris, box_, nsum_, n);
+    WG_LAUNCH_CHECK();
     level_off_.push_back(0);
     level_cnt_.push_back(n);
     while (n > 1) {
         uint32_t m = (n + 7) / 8;
         uint32_t noff = off + n;
-        k_box_level<<<cdiv(m, 256), 256, 0, st_>>>(box_ + 2 * (size_t)off, n, box_ + 2 * (size_t)noff, m);
+        k_parent_nodes<<<cdiv(m, 4), 256, 0, st_>>>(box_ + (size_t)kNode * off, nsum_ + off, n, off,
+                                                     box_ + (size_t)kNode * noff, nsum_ + noff, m);
         WG_LAUNCH_CHECK();
         off = noff;
         n = m;
@@ -706,24 +842,39 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     return cnt_.n_tris;
 }
 
-void Surface::sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err) {
-    LevelInfo lev{};
-    lev.L = levels_;
-    for (int l = 0; l < levels_; ++l) {
-        lev.off[l] = level_off_[l];
-        lev.cnt[l] = level_cnt_[l];
-    }
-    const uint32_t tiles = cdiv(d_.nx, 4) * cdiv(d_.ny, 4) * cdiv(d_.nz, 4);
-    prof::Scope ps(WG_PROF_SDF, st_, (double)d_.count());
-    k_sdf<<<cdiv(tiles, 4), 256, 0, st_>>>(chi, c, d_, h, box_, lev, active_, off_b_, cnt_b_, tri_, cnt_.n_tris, phi,
-                                           argmin, err);
+template <int LX, int LY, int LZ, int KZ>
+static void launch_sdf(const Dims &d, const double *chi, const double *c, double h, const float4 *nodes,
+                       uint32_t root, const float4 *tri, uint32_t n_tris, float *phi, int32_t *argmin, int *err,
+                       hipStream_t s) {
+    const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
+    k_sdf<LX, LY, LZ, KZ><<<cdiv(tiles, 4), 256, 0, s>>>(chi, c, d, h, nodes, root, tri, n_tris, phi, argmin, err);
     WG_LAUNCH_CHECK();
+}
+
+void Surface::sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err) {
+    const uint32_t root = levels_ > 0 ? level_off_[levels_ - 1] : 0;
+    prof::Scope ps(WG_PROF_SDF, st_, (double)d_.count());
+    static const int variant = getenv("WG_SDF_TILE") ? atoi(getenv("WG_SDF_TILE")) : 0;
+    switch (variant) {
+        case 1: launch_sdf<4, 4, 4, 1>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+        case 2: launch_sdf<4, 4, 4, 2>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+        case 3: launch_sdf<8, 8, 1, 2>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+        case 5: launch_sdf<8, 8, 1, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+        case 6: launch_sdf<4, 4, 4, 8>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+        default: launch_sdf<4, 4, 4, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
+    }
 }
 
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                     float *g_chi, double *g_c) {
     if (cnt_.n_tris == 0) return;
     k_sdf_T<<<cdiv(d_.count(), 256), 256, 0, st_>>>(gphi, chi, c, d_, h, argmin, tri_, info_, g_chi, g_c);
+    WG_LAUNCH_CHECK();
+}
+
+void Surface::export_tris(float *out, uint32_t n) {
+    if (n == 0) return;
+    k_export_tris<<<cdiv(n, 256), 256, 0, st_>>>(tri_, n, out);
     WG_LAUNCH_CHECK();
 }
 

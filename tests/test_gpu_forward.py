@@ -51,8 +51,24 @@ def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=Non
     assert _rel(chi, ref.chi) <= 1e-5
     # F5: iso-value
     assert abs(st["iso_c"] - ref.c) <= 1e-5 * np.abs(ref.chi).max()
-    # F6: same surface size
+    # F6: same triangles (matched by cube and local edges), vertices within 1e-5 cells
     assert abs(st["n_tris"] - len(ref.mesh)) <= max(2, 1e-3 * len(ref.mesh))
+    tris, info = r.mesh()
+    tris, info = tris.cpu().numpy().astype(np.float64), info.cpu().numpy()
+    nx, ny, _ = grid.n
+    cube_ref = ref.mesh.cube[:, 0] + nx * (ref.mesh.cube[:, 1] + ny * ref.mesh.cube[:, 2])
+    e = ref.mesh.edge
+    key_ref = {(int(c), int(a), int(b_), int(d)): i for i, (c, (a, b_, d)) in enumerate(zip(cube_ref, e))}
+    matched = 0
+    worst = 0.0
+    for t in range(len(tris)):
+        k = (int(info[t, 0]), int(info[t, 1] & 15), int((info[t, 1] >> 4) & 15), int((info[t, 1] >> 8) & 15))
+        i = key_ref.get(k)
+        if i is not None:
+            matched += 1
+            worst = max(worst, float(np.abs(tris[t] - ref.mesh.xyz[i]).max()))
+    assert matched >= len(ref.mesh) - max(2, 1e-3 * len(ref.mesh))
+    assert worst <= 1e-5 * max(grid.n)
     # F7: signed distance on nodes
     phi = f["phi"].cpu().numpy().astype(np.float64)
     if full_phi:
@@ -183,9 +199,11 @@ def test_warm_start_reaches_same_field():
     chi_w = r.fields()["chi"].cpu().numpy()
     st_c = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=False)
     chi_c = r.fields()["chi"].cpu().numpy()
-    # both solves stop at rel. residual 1e-10; the field error is then bounded by
-    # kappa(A) * 1e-10 each, kappa ~ 12 n^2 / pi^2 on the zero-mean subspace
+    # both solves stop at rel. residual 1e-10, so each field is within
+    # kappa(A) * 1e-10 of the exact one (kappa ~ 12 n^2 / pi^2 on the zero-mean
+    # subspace); the two passes also re-splat b with FP32 atomics in a
+    # different order, which moves b (and chi) by ~1e-7 relative
     kappa = 12 * 32 ** 2 / math.pi ** 2
-    assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10
+    assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10 + 1e-6
     assert st_w["iters"] <= st_c["iters"]
     r.close()
