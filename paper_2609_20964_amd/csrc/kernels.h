@@ -12,9 +12,28 @@ struct GridF {
     double h;
 };
 
+// Points are binned into kTile^3-cell tiles for the splat.
+constexpr int kTile = 8;
+constexpr uint32_t kChunk = 256;   // points per splat workgroup pass
+struct TileDims {
+    int tx, ty, tz;
+    __host__ __device__ int count() const { return tx * ty * tz; }
+};
+inline TileDims tile_dims(const Dims &d) {
+    return {(d.nx + kTile - 1) / kTile, (d.ny + kTile - 1) / kTile, (d.nz + kTile - 1) / kTile};
+}
+
 // ---- splat.hip -------------------------------------------------------------
-__global__ void k_splat_div(const float *xyz, const float *nrm, int npts, GridF g, float *b, int32_t *keys,
-                            float *xyz_c, float *nrm_c, int *err);
+__global__ void k_bin_points(const float *xyz, const float *nrm, int npts, GridF g, TileDims td, int32_t *keys,
+                             float *xyz_c, float *nrm_c, int32_t *tile_of, uint32_t *rank, uint32_t *tile_cnt,
+                             int *err);
+__global__ void k_tile_scatter(const int32_t *tile_of, const uint32_t *rank, const uint32_t *tile_off, int npts,
+                               uint32_t *perm);
+__global__ void k_chunk_counts(const uint32_t *tile_cnt, uint32_t ntiles, uint32_t *ch_cnt);
+__global__ void k_chunk_tiles(const uint32_t *ch_cnt, const uint32_t *ch_off, uint32_t ntiles, uint32_t *chunk_tile);
+__global__ void k_splat_chunks(const uint32_t *perm, const uint32_t *tile_off, const uint32_t *tile_cnt,
+                               const uint32_t *ch_off, const uint32_t *chunk_tile, const uint32_t *n_chunks,
+                               const float *xyz_c, const float *nrm_c, GridF g, TileDims td, float *b);
 __global__ void k_iso_partial(const float *xyz, int npts, GridF g, const double *chi, double *partials);
 __global__ void k_iso_finalize(const double *partials, int nb, int npts, double *out);
 __global__ void k_iso_T(const float *xyz, int npts, GridF g, const double *g_c, float *g_chi);

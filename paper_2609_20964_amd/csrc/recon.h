@@ -41,7 +41,11 @@ class Recon {
     Surface surf_;
     float *b_ = nullptr, *phi_ = nullptr, *gphi_ = nullptr, *gchi_ = nullptr;
     double *chi_ = nullptr, *lam_ = nullptr, *iso_part_ = nullptr, *scal_ = nullptr;
-    int32_t *argmin_ = nullptr, *keys_ = nullptr;
+    int32_t *argmin_ = nullptr, *keys_ = nullptr, *tile_of_ = nullptr;
+    uint32_t *rank_ = nullptr, *perm_ = nullptr, *tile_cnt_ = nullptr, *tile_off_ = nullptr, *tile_act_ = nullptr;
+    uint32_t *tile_blk_ = nullptr, *tile_tot_ = nullptr, *ch_cnt_ = nullptr, *ch_off_ = nullptr, *ch_act_ = nullptr;
+    uint32_t *ch_blk_ = nullptr, *ch_tot_ = nullptr, *chunk_tile_ = nullptr;
+    TileDims td_{};
     float *xyz_ = nullptr, *nrm_ = nullptr;
     int *err_ = nullptr, *herr_ = nullptr;
     double *hscal_ = nullptr;

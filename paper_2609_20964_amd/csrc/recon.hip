@@ -1,11 +1,13 @@
 // Reconstruction handle: resident device state and the forward / reverse
 // drivers behind the C ABI (include/wgeo.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 
 #include "prof.h"
 #include "recon.h"
+#include "scan.h"
 
 namespace wg {
 
@@ -63,6 +65,16 @@ void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
     a.reserve((size_t)max_points * 3 * sizeof(float));       // points
     a.reserve((size_t)max_points * 3 * sizeof(float));       // normals
     a.reserve((size_t)max_points * sizeof(int32_t));          // keys
+    a.reserve((size_t)max_points * sizeof(int32_t));          // tile of each point
+    a.reserve((size_t)max_points * sizeof(uint32_t));         // rank inside the tile
+    a.reserve((size_t)max_points * sizeof(uint32_t));         // points ordered by tile
+    const size_t nt = (size_t)tile_dims(d).count();
+    for (int k = 0; k < 6; ++k) a.reserve(nt * sizeof(uint32_t));   // tile and chunk counts, offsets, lists
+    for (int k = 0; k < 2; ++k) {
+        a.reserve(2 * (size_t)cdiv(nt, scan::kScanBlock) * sizeof(uint32_t));
+        a.reserve(2 * sizeof(uint32_t));
+    }
+    a.reserve((nt + (size_t)max_points / kChunk + 1) * sizeof(uint32_t));   // tile of each chunk
     a.reserve(kIsoBlocks * sizeof(double));
     a.reserve(8 * sizeof(double));       // scalars: c, c_shifted, g_c
     a.reserve(4 * sizeof(int));          // error flags
@@ -92,6 +104,22 @@ Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_po
     xyz_ = arena_.take<float>((size_t)max_points * 3);
     nrm_ = arena_.take<float>((size_t)max_points * 3);
     keys_ = arena_.take<int32_t>((size_t)max_points);
+    tile_of_ = arena_.take<int32_t>((size_t)max_points);
+    rank_ = arena_.take<uint32_t>((size_t)max_points);
+    perm_ = arena_.take<uint32_t>((size_t)max_points);
+    td_ = tile_dims(d_);
+    const size_t nt = (size_t)td_.count();
+    tile_cnt_ = arena_.take<uint32_t>(nt);
+    tile_off_ = arena_.take<uint32_t>(nt);
+    tile_act_ = arena_.take<uint32_t>(nt);
+    ch_cnt_ = arena_.take<uint32_t>(nt);
+    ch_off_ = arena_.take<uint32_t>(nt);
+    ch_act_ = arena_.take<uint32_t>(nt);
+    tile_blk_ = arena_.take<uint32_t>(2 * (size_t)cdiv(nt, scan::kScanBlock));
+    tile_tot_ = arena_.take<uint32_t>(2);
+    ch_blk_ = arena_.take<uint32_t>(2 * (size_t)cdiv(nt, scan::kScanBlock));
+    ch_tot_ = arena_.take<uint32_t>(2);
+    chunk_tile_ = arena_.take<uint32_t>(nt + (size_t)max_points / kChunk + 1);
     iso_part_ = arena_.take<double>(kIsoBlocks);
     scal_ = arena_.take<double>(8);
     err_ = arena_.take<int>(4);
@@ -128,9 +156,25 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
     WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
     if (npts > 0) {
-        // per point: 24 B read, 24 B copied, 4 B key, 81 four-byte atomic adds into b
+        // per point: 24 B read, 24 B copied, 4 B key, tile bookkeeping, 81 contributions to b
         prof::Scope ps(WG_PROF_SPLAT, st_, 376.0 * npts);
-        k_splat_div<<<cdiv(npts, 256), 256, 0, st_>>>(xyz, nrm, npts, gf_, b_, keys_, xyz_, nrm_, err_);
+        const uint32_t nt = (uint32_t)td_.count();
+        WG_HIP(hipMemsetAsync(tile_cnt_, 0, nt * sizeof(uint32_t), st_));
+        k_bin_points<<<cdiv(npts, 256), 256, 0, st_>>>(xyz, nrm, npts, gf_, td_, keys_, xyz_, nrm_, tile_of_, rank_,
+                                                      tile_cnt_, err_);
+        const uint32_t nblk = cdiv(nt, scan::kScanBlock);
+        scan::k_scan_partial<<<nblk, 256, 0, st_>>>(tile_cnt_, nt, tile_blk_);
+        scan::k_scan_top<<<1, 256, 0, st_>>>(tile_blk_, nblk, tile_tot_);
+        scan::k_scan_final<<<nblk, 256, 0, st_>>>(tile_cnt_, nt, tile_blk_, tile_off_, tile_act_);
+        k_tile_scatter<<<cdiv(npts, 256), 256, 0, st_>>>(tile_of_, rank_, tile_off_, npts, perm_);
+        k_chunk_counts<<<cdiv(nt, 256), 256, 0, st_>>>(tile_cnt_, nt, ch_cnt_);
+        scan::k_scan_partial<<<nblk, 256, 0, st_>>>(ch_cnt_, nt, ch_blk_);
+        scan::k_scan_top<<<1, 256, 0, st_>>>(ch_blk_, nblk, ch_tot_);
+        scan::k_scan_final<<<nblk, 256, 0, st_>>>(ch_cnt_, nt, ch_blk_, ch_off_, ch_act_);
+        k_chunk_tiles<<<cdiv(nt, 256), 256, 0, st_>>>(ch_cnt_, ch_off_, nt, chunk_tile_);
+        const unsigned grid = std::min<unsigned>(2048u, nt + cdiv(npts, kChunk));
+        k_splat_chunks<<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_, chunk_tile_, ch_tot_, xyz_, nrm_,
+                                              gf_, td_, b_);
         WG_LAUNCH_CHECK();
     }
     check_err("splat");

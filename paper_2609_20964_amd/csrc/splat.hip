@@ -6,7 +6,8 @@
 // b = -h^2 D_h V straight into b.  With face values F = (V_i + V_{i+1})/2 on
 // interior faces and 0 on the outer faces, a point whose weights cover the
 // 3x3x3 block around its cell touches the 81 cells of that block widened by
-// one along each axis; each of those gets one atomic add.
+// one along each axis.  Points are binned into 8^3-cell tiles; a workgroup
+// accumulates one tile's points in LDS and adds the window to b once.
 #include <cmath>
 
 #include "kernels.h"
@@ -52,33 +53,15 @@ __device__ __forceinline__ bool in_range(int k, int o, int n) { return k + o >= 
 
 }  // namespace
 
-// F1 + F2 + F3.  b must be zero on entry.  Copies the points into the handle
-// (xyz_c, nrm_c) and records each point's linear central-cell key.  A point
-// outside the grid sets *err and contributes nothing.
-__global__ __launch_bounds__(256) void k_splat_div(const float *__restrict__ xyz, const float *__restrict__ nrm,
-                                                    int npts, GridF g, float *__restrict__ b,
-                                                    int32_t *__restrict__ keys, float *__restrict__ xyz_c,
-                                                    float *__restrict__ nrm_c, int *err) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
-    const float x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
-    const float n0 = nrm[3 * i], n1 = nrm[3 * i + 1], n2 = nrm[3 * i + 2];
-    xyz_c[3 * i] = x0; xyz_c[3 * i + 1] = x1; xyz_c[3 * i + 2] = x2;
-    nrm_c[3 * i] = n0; nrm_c[3 * i + 1] = n1; nrm_c[3 * i + 2] = n2;
-    const float inv4h = (float)(0.25 / g.h);
-    AxisW X, Y, Z;
-    if (!bin_axis(x0, g.lo[0], g.h, g.d.nx, X, inv4h) || !bin_axis(x1, g.lo[1], g.h, g.d.ny, Y, inv4h) ||
-        !bin_axis(x2, g.lo[2], g.h, g.d.nz, Z, inv4h)) {
-        keys[i] = -1;
-        atomicOr(err, 1);
-        return;
-    }
-    keys[i] = X.k + g.d.nx * (Y.k + g.d.ny * Z.k);
+// Contributions of one point to b: calls emit(cx, cy, cz, value) for every
+// cell k + (cx, cy, cz) of the 81-cell support (|c| <= 2, at most one |c| = 2)
+// inside the grid.  value = -(h/2) h^-3 / S * sum_xi n_xi (face terms).
+template <class Emit>
+__device__ __forceinline__ void point_divergence(const AxisW &X, const AxisW &Y, const AxisW &Z, float n0, float n1,
+                                                 float n2, const GridF &g, Emit &&emit) {
     const float Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
     const float S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + 0.5f;     // Eq. 24 normaliser
     const float coef = -0.5f * (float)g.h * (float)(1.0 / (g.h * g.h * g.h)) / S;
-    const size_t sx = 1, sy = (size_t)g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
-    const size_t c0 = (size_t)X.k + sy * Y.k + sz * Z.k;
 #pragma unroll
     for (int cz = -2; cz <= 2; ++cz)
 #pragma unroll
@@ -90,18 +73,118 @@ __global__ __launch_bounds__(256) void k_splat_div(const float *__restrict__ xyz
                     continue;
                 const float r0 = raw_w(X, Y, Z, cx, cy, cz);
                 float acc = 0.f;
-                // x faces
                 if (in_range(X.k, cx + 1, g.d.nx)) acc += n0 * (r0 + raw_w(X, Y, Z, cx + 1, cy, cz));
                 if (in_range(X.k, cx - 1, g.d.nx)) acc -= n0 * (raw_w(X, Y, Z, cx - 1, cy, cz) + r0);
                 if (in_range(Y.k, cy + 1, g.d.ny)) acc += n1 * (r0 + raw_w(X, Y, Z, cx, cy + 1, cz));
                 if (in_range(Y.k, cy - 1, g.d.ny)) acc -= n1 * (raw_w(X, Y, Z, cx, cy - 1, cz) + r0);
                 if (in_range(Z.k, cz + 1, g.d.nz)) acc += n2 * (r0 + raw_w(X, Y, Z, cx, cy, cz + 1));
                 if (in_range(Z.k, cz - 1, g.d.nz)) acc -= n2 * (raw_w(X, Y, Z, cx, cy, cz - 1) + r0);
-                if (acc != 0.f)
-                    unsafeAtomicAdd(b + c0 + (ptrdiff_t)cx * (ptrdiff_t)sx + (ptrdiff_t)cy * (ptrdiff_t)sy +
-                                        (ptrdiff_t)cz * (ptrdiff_t)sz,
-                                    coef * acc);
+                if (acc != 0.f) emit(cx, cy, cz, coef * acc);
             }
+}
+
+// F1: central cell of each point (FP64 floor), copies of the points into the
+// handle, the linear cell key, and a histogram of points per kTile^3 tile.
+// rank[i] is the point's slot inside its tile.  A point outside the grid sets
+// *err and gets key -1, tile -1.
+__global__ __launch_bounds__(256) void k_bin_points(const float *__restrict__ xyz, const float *__restrict__ nrm,
+                                                     int npts, GridF g, TileDims td, int32_t *__restrict__ keys,
+                                                     float *__restrict__ xyz_c, float *__restrict__ nrm_c,
+                                                     int32_t *__restrict__ tile_of, uint32_t *__restrict__ rank,
+                                                     uint32_t *__restrict__ tile_cnt, int *err) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const float x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
+    xyz_c[3 * i] = x0; xyz_c[3 * i + 1] = x1; xyz_c[3 * i + 2] = x2;
+    nrm_c[3 * i] = nrm[3 * i]; nrm_c[3 * i + 1] = nrm[3 * i + 1]; nrm_c[3 * i + 2] = nrm[3 * i + 2];
+    AxisW X, Y, Z;
+    if (!bin_axis(x0, g.lo[0], g.h, g.d.nx, X, 0.f) || !bin_axis(x1, g.lo[1], g.h, g.d.ny, Y, 0.f) ||
+        !bin_axis(x2, g.lo[2], g.h, g.d.nz, Z, 0.f)) {
+        keys[i] = -1;
+        tile_of[i] = -1;
+        atomicOr(err, 1);
+        return;
+    }
+    keys[i] = X.k + g.d.nx * (Y.k + g.d.ny * Z.k);
+    const int t = X.k / kTile + td.tx * (Y.k / kTile + td.ty * (Z.k / kTile));
+    tile_of[i] = t;
+    rank[i] = atomicAdd(tile_cnt + t, 1u);
+}
+
+// Points ordered by tile: perm[tile_off[t] + rank[i]] = i.
+__global__ __launch_bounds__(256) void k_tile_scatter(const int32_t *__restrict__ tile_of,
+                                                       const uint32_t *__restrict__ rank,
+                                                       const uint32_t *__restrict__ tile_off, int npts,
+                                                       uint32_t *__restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const int t = tile_of[i];
+    if (t >= 0) perm[tile_off[t] + rank[i]] = (uint32_t)i;
+}
+
+// Chunks of at most kChunk points of one tile: chunk counts per tile ...
+__global__ __launch_bounds__(256) void k_chunk_counts(const uint32_t *__restrict__ tile_cnt, uint32_t ntiles,
+                                                       uint32_t *__restrict__ ch_cnt) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) ch_cnt[t] = (tile_cnt[t] + kChunk - 1) / kChunk;
+}
+
+// ... and the tile of every chunk.
+__global__ __launch_bounds__(256) void k_chunk_tiles(const uint32_t *__restrict__ ch_cnt,
+                                                      const uint32_t *__restrict__ ch_off, uint32_t ntiles,
+                                                      uint32_t *__restrict__ chunk_tile) {
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    for (uint32_t c = 0; c < ch_cnt[t]; ++c) chunk_tile[ch_off[t] + c] = t;
+}
+
+// F2 + F3: a workgroup takes chunks (at most kChunk points of one tile); the
+// points add their divergence contributions into a (kTile + 4)^3 window in
+// LDS (the support reaches two cells out), then each touched cell of the
+// window gets one atomic add into b.  b must be zero on entry.  The grid
+// strides over the chunks; their count is read on the device.
+__global__ __launch_bounds__(256) void k_splat_chunks(const uint32_t *__restrict__ perm,
+                                                       const uint32_t *__restrict__ tile_off,
+                                                       const uint32_t *__restrict__ tile_cnt,
+                                                       const uint32_t *__restrict__ ch_off,
+                                                       const uint32_t *__restrict__ chunk_tile,
+                                                       const uint32_t *__restrict__ n_chunks,
+                                                       const float *__restrict__ xyz_c, const float *__restrict__ nrm_c,
+                                                       GridF g, TileDims td, float *__restrict__ b) {
+    constexpr int W = kTile + 4;
+    __shared__ float win[W * W * W];
+    const uint32_t total = n_chunks[0];
+    for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+        const uint32_t tile = chunk_tile[ch];
+        const uint32_t c = ch - ch_off[tile];
+        const uint32_t p0 = c * kChunk, p1 = min(p0 + kChunk, tile_cnt[tile]);
+        for (int l = threadIdx.x; l < W * W * W; l += blockDim.x) win[l] = 0.f;
+        __syncthreads();
+        const int T0x = (int)(tile % td.tx) * kTile, T0y = (int)((tile / td.tx) % td.ty) * kTile,
+                  T0z = (int)(tile / (td.tx * td.ty)) * kTile;
+        const uint32_t off = tile_off[tile];
+        for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+            const uint32_t i = perm[off + p];
+            AxisW X, Y, Z;
+            bin_axis(xyz_c[3 * i], g.lo[0], g.h, g.d.nx, X, 0.f);
+            bin_axis(xyz_c[3 * i + 1], g.lo[1], g.h, g.d.ny, Y, 0.f);
+            bin_axis(xyz_c[3 * i + 2], g.lo[2], g.h, g.d.nz, Z, 0.f);
+            const int lx = X.k - T0x + 2, ly = Y.k - T0y + 2, lz = Z.k - T0z + 2;
+            point_divergence(X, Y, Z, nrm_c[3 * i], nrm_c[3 * i + 1], nrm_c[3 * i + 2], g,
+                             [&](int cx, int cy, int cz, float v) {
+                                 atomicAdd(win + (lx + cx) + W * ((ly + cy) + W * (lz + cz)), v);
+                             });
+        }
+        __syncthreads();
+        for (int l = threadIdx.x; l < W * W * W; l += blockDim.x) {
+            const float v = win[l];
+            if (v == 0.f) continue;
+            const int gx = T0x - 2 + l % W, gy = T0y - 2 + (l / W) % W, gz = T0z - 2 + l / (W * W);
+            // contributions only ever target cells inside the grid
+            unsafeAtomicAdd(b + (size_t)gx + (size_t)g.d.nx * (gy + (size_t)g.d.ny * gz), v);
+        }
+        __syncthreads();
+    }
 }
 
 namespace {

@@ -4,6 +4,7 @@
 #include <cstdlib>
 
 #include "mc_table.inc"
+#include "scan.h"
 #include "prof.h"
 #include "surface.h"
 
@@ -81,99 +82,6 @@ __global__ __launch_bounds__(256) void k_mc_count(const double *__restrict__ chi
     }
     for (int o = 32; o > 0; o >>= 1) nt += __shfl_xor(nt, o, 64);
     if (lane == 0) cnt[m] = nt;
-}
-
-// Exclusive block scan of (count, nonzero-flag) pairs over 256 threads.
-__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t f, uint32_t &ea, uint32_t &ef, uint32_t &ta,
-                                            uint32_t &tf) {
-    __shared__ uint32_t wa[4], wf[4];
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    uint32_t xa = a, xf = f;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t ya = __shfl_up(xa, o, 64), yf = __shfl_up(xf, o, 64);
-        if (lane >= o) {
-            xa += ya;
-            xf += yf;
-        }
-    }
-    if (lane == 63) {
-        wa[w] = xa;
-        wf[w] = xf;
-    }
-    __syncthreads();
-    uint32_t pa = 0, pf = 0;
-    for (int k = 0; k < w; ++k) {
-        pa += wa[k];
-        pf += wf[k];
-    }
-    ta = wa[0] + wa[1] + wa[2] + wa[3];
-    tf = wf[0] + wf[1] + wf[2] + wf[3];
-    ea = pa + xa - a;
-    ef = pf + xf - f;
-    __syncthreads();
-}
-
-constexpr int kScanPer = 4;      // entries per thread
-constexpr int kScanBlock = 256 * kScanPer;
-
-__global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *cnt, uint32_t n, uint32_t *blk) {
-    uint32_t a = 0, f = 0;
-    for (int q = 0; q < kScanPer; ++q) {
-        uint32_t idx = blockIdx.x * kScanBlock + threadIdx.x * kScanPer + q;
-        if (idx < n) {
-            a += cnt[idx];
-            f += cnt[idx] != 0;
-        }
-    }
-    uint32_t ea, ef, ta, tf;
-    block_scan2(a, f, ea, ef, ta, tf);
-    if (threadIdx.x == 0) {
-        blk[2 * blockIdx.x] = ta;
-        blk[2 * blockIdx.x + 1] = tf;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t *blk, uint32_t nblk, SurfaceCounts *out) {
-    uint32_t carry_a = 0, carry_f = 0;
-    for (uint32_t base = 0; base < nblk; base += 256) {
-        uint32_t idx = base + threadIdx.x;
-        uint32_t a = idx < nblk ? blk[2 * idx] : 0, f = idx < nblk ? blk[2 * idx + 1] : 0;
-        uint32_t ea, ef, ta, tf;
-        block_scan2(a, f, ea, ef, ta, tf);
-        if (idx < nblk) {
-            blk[2 * idx] = carry_a + ea;
-            blk[2 * idx + 1] = carry_f + ef;
-        }
-        carry_a += ta;
-        carry_f += tf;
-    }
-    if (threadIdx.x == 0) {
-        out->n_tris = carry_a;
-        out->n_active = carry_f;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_scan_final(const uint32_t *cnt, uint32_t n, const uint32_t *blk,
-                                                     uint32_t *off, uint32_t *active) {
-    uint32_t v[kScanPer];
-    uint32_t a = 0, f = 0;
-    for (int q = 0; q < kScanPer; ++q) {
-        uint32_t idx = blockIdx.x * kScanBlock + threadIdx.x * kScanPer + q;
-        v[q] = idx < n ? cnt[idx] : 0;
-        a += v[q];
-        f += v[q] != 0;
-    }
-    uint32_t ea, ef, ta, tf;
-    block_scan2(a, f, ea, ef, ta, tf);
-    uint32_t oa = blk[2 * blockIdx.x] + ea, of = blk[2 * blockIdx.x + 1] + ef;
-    for (int q = 0; q < kScanPer; ++q) {
-        uint32_t idx = blockIdx.x * kScanBlock + threadIdx.x * kScanPer + q;
-        if (idx < n) {
-            off[idx] = oa;
-            if (v[q]) active[of++] = idx;
-            oa += v[q];
-        }
-    }
 }
 
 // One wavefront per non-empty brick: the triangles of its cubes, vertices by
@@ -743,7 +651,7 @@ void Surface::plan(Arena &a, const Dims &d) {
     size_t pad;
     brick_geometry(d, nb, bits, pad);
     for (int k = 0; k < 3; ++k) a.reserve(pad * sizeof(uint32_t));   // counts, offsets, active
-    a.reserve(2 * (size_t)cdiv(pad, kScanBlock) * sizeof(uint32_t));
+    a.reserve(2 * (size_t)cdiv(pad, scan::kScanBlock) * sizeof(uint32_t));
     a.reserve(sizeof(SurfaceCounts));
 }
 
@@ -755,7 +663,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     cnt_b_ = a.take<uint32_t>(nbricks_pad_);
     off_b_ = a.take<uint32_t>(nbricks_pad_);
     active_ = a.take<uint32_t>(nbricks_pad_);
-    blk_ = a.take<uint32_t>(2 * (size_t)cdiv(nbricks_pad_, kScanBlock));
+    blk_ = a.take<uint32_t>(2 * (size_t)cdiv(nbricks_pad_, scan::kScanBlock));
     dcnt_ = a.take<SurfaceCounts>(1);
     WG_HIP(hipHostMalloc((void **)&hcnt_, sizeof(SurfaceCounts), hipHostMallocDefault));
     // a first guess at the triangle capacity: ~4 per cube over a few slices
@@ -806,10 +714,10 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     prof::Scope ps(WG_PROF_MC, st_, 8.0 * (double)d_.count());
     k_mc_count<<<cdiv(nbr, 4), 256, 0, st_>>>(chi, c, d_, nb, nbr, cnt_b_);
     WG_LAUNCH_CHECK();
-    const uint32_t nblk = cdiv(nbr, kScanBlock);
-    k_scan_partial<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_);
-    k_scan_top<<<1, 256, 0, st_>>>(blk_, nblk, dcnt_);
-    k_scan_final<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_, off_b_, active_);
+    const uint32_t nblk = cdiv(nbr, scan::kScanBlock);
+    scan::k_scan_partial<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_);
+    scan::k_scan_top<<<1, 256, 0, st_>>>(blk_, nblk, reinterpret_cast<uint32_t *>(dcnt_));
+    scan::k_scan_final<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_, off_b_, active_);
     WG_LAUNCH_CHECK();
     WG_HIP(hipMemcpyAsync(hcnt_, dcnt_, sizeof(SurfaceCounts), hipMemcpyDeviceToHost, st_));
     WG_HIP(hipStreamSynchronize(st_));
