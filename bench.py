@@ -88,10 +88,23 @@ def gpu_run(args):
     _lib.profile_enable([])
     prof = _lib.profile_read(dominant)
     elapsed = t1 - t0
+
+    # two more (untimed) steps with every kind profiled: the solver's kernels as a group
+    _lib.profile_reset()
+    _lib.profile_enable(kinds)
+    solve_ms = []
+    for k in range(2):
+        t = args.warmup + args.steps - 2 + k
+        st2 = r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
+        solve_ms.append(st2["ms"][1])
+    torch.cuda.synchronize()
+    _lib.profile_enable([])
+    solver_kinds = {k: _lib.profile_read(k) for k in SOLVER_KINDS}
+    _lib.profile_reset()
     last_t = args.warmup + args.steps - 1
     fields = r.fields()
     gpu_last = {"chi": fields["chi"].cpu().numpy(), "phi": fields["phi"].cpu().numpy(),
-                "iso_c": stats[-1]["iso_c"], "phi_q": phi.cpu().numpy(), "t": last_t}
+                "iso_c": st2["iso_c"], "phi_q": phi.cpu().numpy(), "t": last_t}
 
     # reverse pass at the same size: L = mean phi(q)^2
     adj_ms = []
@@ -107,7 +120,7 @@ def gpu_run(args):
     r.close()
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
-            "q": q.cpu().numpy(), "adj_ms": adj_ms}
+            "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -119,6 +132,29 @@ KIND_KERNEL = {"sweep": "k_stencil<OpPMatvec>", "smooth": "k_stencil<OpSmooth>",
                "transfer": "k_restrict/k_prolong_add", "cgupdate": "k_cg_update", "sample": "k_sample"}
 
 
+SOLVER_KINDS = ("sweep", "smooth", "resid64", "transfer", "cgupdate")
+
+
+def solver_hbm(res):
+    """HBM roofline of the Poisson solve taken as a whole: algorithmic bytes of
+    its bandwidth-bound kernels over (a) their own event-timed duration and
+    (b) the whole solve phase (reductions, coarse solve and host waits
+    included)."""
+    kinds = res["solver_kinds"]
+    units = sum(v["units"] for v in kinds.values())
+    ms = sum(v["ms"] for v in kinds.values())
+    if ms <= 0:
+        return None
+    phase_ms = sum(res["solve_ms"])
+    per = {k: {"GB_s": v["units"] / (v["ms"] * 1e6) if v["ms"] > 0 else None, "launches": v["launches"],
+               "ms": v["ms"] / len(res["solve_ms"])} for k, v in kinds.items()}
+    return {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "kernels_GB_s": units / (ms * 1e6), "kernels_frac": units / (ms * 1e6) / HBM_PEAK_GBS,
+            "phase_GB_s": units / (phase_ms * 1e6), "phase_frac": units / (phase_ms * 1e6) / HBM_PEAK_GBS,
+            "bytes_per_solve": units / len(res["solve_ms"]), "phase_ms": phase_ms / len(res["solve_ms"]),
+            "per_kind": per}
+
+
 def roofline(res):
     p = res["prof"]
     kind = res["dominant"]
@@ -126,34 +162,39 @@ def roofline(res):
         return None
     avg_s = p["ms"] / p["launches"] / 1e3
     per_launch = p["units"] / p["launches"]
-    traffic = load_traffic(kind)
+    pmc = load_pmc(kind)
+    traffic = pmc.get("traffic_bytes_per_launch")
     if KIND_BOUND[kind] == "hbm":
         achieved = per_launch / avg_s / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     else:
-        # distance walk: nodes per second against the node rate the FP32 vector
-        # peak allows for the per-node triangle tests it performed
-        achieved = per_launch / avg_s / 1e9
-        out = {"bound": "alu", "achieved": achieved, "peak": None, "unit": "Gnodes/s", "frac": None,
-               "traffic": traffic}
+        # distance walk: FP32 operations per node (counted once with rocprofv3
+        # for this workload) x nodes per launch / event-timed launch duration
+        fpn = pmc.get("fp32_flops_per_unit")
+        achieved = fpn * per_launch / avg_s / 1e12 if fpn else None
+        out = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+               "frac": achieved / FP32_VALU_TFLOPS if achieved else None, "traffic": traffic,
+               "nodes_per_s": per_launch / avg_s}
+        if pmc.get("valu_issue_frac") is not None:
+            out["valu_issue_frac"] = pmc["valu_issue_frac"]
     out.update({"kernel": KIND_KERNEL[kind], "launches": p["launches"], "avg_launch_us": avg_s * 1e6,
                 "units_per_launch": per_launch})
     return out
 
 
-def load_traffic(kind):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if one
-    exists for this kernel and workload (else null)."""
+def load_pmc(kind):
+    """Per-launch figures from the committed rocprofv3 counter summary for this
+    kernel and workload (`key value` lines), if one exists."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kind}_flapping256.txt")
-    if not os.path.exists(path):
-        return None
     vals = {}
-    for line in open(path):
-        parts = line.split()
-        if len(parts) == 2 and parts[0] in ("traffic_bytes_per_launch", "source_sha"):
-            vals[parts[0]] = parts[1]
-    return float(vals["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in vals else None
+    if os.path.exists(path):
+        for line in open(path):
+            parts = line.split()
+            if len(parts) == 2 and parts[0] in ("traffic_bytes_per_launch", "fp32_flops_per_unit",
+                                                 "valu_issue_frac"):
+                vals[parts[0]] = float(parts[1])
+    return vals
 
 
 def cpu_baseline(res, n, sample_nodes):
@@ -179,7 +220,7 @@ def cpu_baseline(res, n, sample_nodes):
     chi_ref = ref.chi
     err = {
         "chi_rel_l2": float(np.linalg.norm(g["chi"] - chi_ref) / np.linalg.norm(chi_ref)),
-        "iso_c_abs": float(abs(g["iso_c"] - ref.c)),
+        "iso_c_rel": float(abs(g["iso_c"] - ref.c) / np.abs(chi_ref).max()),
         "phi_max_abs_over_h": float(np.abs(g["phi"].reshape(-1)[nodes].astype(np.float64) - phi_ref).max() * n),
         "nodes_compared": int(sample_nodes),
         "step": int(g["t"]),
@@ -192,21 +233,35 @@ def cpu_baseline(res, n, sample_nodes):
     return base, err
 
 
-def serving_run(n_requests, max_inflight, budget_gb, reqs=None):
+def serving_run(n_requests, max_inflight, budget_gb):
+    """The request stream replayed twice: at its own Poisson arrival times
+    (latency at the offered load) and with every request arriving at once
+    (throughput at saturation); each as continuous batching and one at a time."""
+    import torch
+
+    from paper_2609_20964_amd import synth
+
+    reqs = []
+    for rq in synth.request_stream(n_requests):
+        x, nrm = rq.cloud()
+        reqs.append((rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(),
+                     torch.from_numpy(rq.queries()).cuda()))
+    out = {"offered_load": replay(reqs, max_inflight, budget_gb, 1.0),
+           "saturated": replay(reqs, max_inflight, budget_gb, 0.0)}
+    out["workload"] = (f"{len(reqs)} requests, Poisson arrivals 50/s, grids 64/128/256 (0.5/0.3/0.2), "
+                       "log-normal points (median 50k), 30% with gradient, rel. res 1e-6; "
+                       "saturated = all requests at t=0")
+    return out
+
+
+def replay(reqs, max_inflight, budget_gb, time_scale):
     import threading
 
     import torch
 
-    from paper_2609_20964_amd import synth
     from paper_2609_20964_amd.serving import Server
 
-    if reqs is None:
-        stream = synth.request_stream(n_requests)
-        reqs = []
-        for rq in stream:
-            x, nrm = rq.cloud()
-            reqs.append((rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(),
-                         torch.from_numpy(rq.queries()).cuda()))
+    arrival = [rq.arrival_s * time_scale for rq, *_ in reqs]
     out = {}
     for mode, inflight in (("batched", max_inflight), ("plain", 1)):
         srv = Server(int(budget_gb * (1 << 30)), max_inflight=inflight)
@@ -215,7 +270,7 @@ def serving_run(n_requests, max_inflight, budget_gb, reqs=None):
 
         def client():
             for i, (rq, x, nrm, q) in enumerate(reqs):
-                delay = rq.arrival_s - (time.perf_counter() - start)
+                delay = arrival[i] - (time.perf_counter() - start)
                 if delay > 0:
                     time.sleep(delay)
                 gphi = torch.full((q.shape[0],), 1.0 / q.shape[0], device="cuda") if rq.want_grad else None
@@ -233,8 +288,8 @@ def serving_run(n_requests, max_inflight, budget_gb, reqs=None):
                     done[i] = (res, time.perf_counter() - start)
             time.sleep(0.0005)
         th.join()
-        lat = np.array([done[i][1] - reqs[i][0].arrival_s for i in range(len(reqs))])
-        span = max(d[1] for d in done.values()) - reqs[0][0].arrival_s
+        lat = np.array([done[i][1] - arrival[i] for i in range(len(reqs))])
+        span = max(d[1] for d in done.values()) - arrival[0]
         ok = sum(1 for d in done.values() if d[0][0] in (0, -3))
         cells = sum(rq.n ** 3 for rq, *_ in reqs)
         out[mode] = {"max_inflight": inflight, "req_per_s": len(reqs) / span, "cells_per_s": cells / span,
@@ -242,9 +297,40 @@ def serving_run(n_requests, max_inflight, budget_gb, reqs=None):
                      "ok": ok, "requests": len(reqs),
                      "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
         srv.close()
-    out["workload"] = (f"{len(reqs)} requests, Poisson arrivals 50/s, grids 64/128/256 (0.5/0.3/0.2), "
-                       "log-normal points (median 50k), 30% with gradient, rel. res 1e-6")
     return out
+
+
+def copy_probe():
+    import torch
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
+
+
+def pmc_summary(path):
+    """Mean counter value per dispatch, by kernel name (first 60 chars)."""
+    import csv
+    from collections import defaultdict
+
+    acc = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    with open(path) as f:
+        rows = csv.DictReader(f)
+        if "Kernel_Name" not in (rows.fieldnames or []) or "Counter_Name" not in rows.fieldnames:
+            raise SystemExit(f"unexpected columns in {path}: {rows.fieldnames}")
+        for row in rows:
+            name = row["Kernel_Name"][:60]
+            acc[name][row["Counter_Name"]] += float(row["Counter_Value"])
+            disp[name].add(row["Dispatch_Id"])
+    for name in sorted(acc, key=lambda k: -len(disp[k])):
+        n = len(disp[name])
+        vals = " ".join(f"{c}={v / n:.6g}" for c, v in sorted(acc[name].items()))
+        print(f"{name} | dispatches={n} | {vals}")
 
 
 def main():
@@ -260,7 +346,17 @@ def main():
     ap.add_argument("--serving", type=int, default=40, help="requests in the serving replay (0: skip)")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 counter_collection.csv: mean per dispatch by kernel")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs one reconstruction per device and has no "
               "multi-GPU path (sharding is described in DESIGN.md); run it with --gpus 1.", file=sys.stderr)
@@ -287,6 +383,7 @@ def main():
                                f"rel res {args.tol:g}, {args.queries} queries sampled per step",
                    "grid": args.n, "points": args.points, "queries": args.queries, "rel_tol": args.tol},
         "roofline": roofline(res),
+        "solver_roofline": solver_hbm(res),
         "solver": {"iters_mean": float(np.mean([s["iters"] for s in st])),
                    "refinements_mean": float(np.mean([s["refinements"] for s in st])),
                    "rel_res_max": float(max(s["rel_res"] for s in st)),

@@ -762,15 +762,8 @@ static void launch_sdf(const Dims &d, const double *chi, const double *c, double
 void Surface::sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err) {
     const uint32_t root = levels_ > 0 ? level_off_[levels_ - 1] : 0;
     prof::Scope ps(WG_PROF_SDF, st_, (double)d_.count());
-    static const int variant = getenv("WG_SDF_TILE") ? atoi(getenv("WG_SDF_TILE")) : 0;
-    switch (variant) {
-        case 1: launch_sdf<4, 4, 4, 1>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-        case 2: launch_sdf<4, 4, 4, 2>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-        case 3: launch_sdf<8, 8, 1, 2>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-        case 5: launch_sdf<8, 8, 1, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-        case 6: launch_sdf<4, 4, 4, 8>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-        default: launch_sdf<4, 4, 4, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_); break;
-    }
+    // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
+    launch_sdf<4, 4, 4, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_);
 }
 
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
