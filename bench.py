@@ -312,8 +312,25 @@ def copy_probe():
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
 
 
+def short_kernel_name(name):
+    for ns in ("wg::scan::(anonymous namespace)::", "wg::(anonymous namespace)::", "wg::"):
+        name = name.replace(ns, "")
+    if name.startswith("void "):
+        name = name[5:]
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
 def pmc_summary(path):
-    """Mean counter value per dispatch, by kernel name (first 60 chars)."""
+    """Mean counter value per dispatch, by kernel name (namespaces and
+    argument lists dropped)."""
     import csv
     from collections import defaultdict
 
@@ -324,7 +341,7 @@ def pmc_summary(path):
         if "Kernel_Name" not in (rows.fieldnames or []) or "Counter_Name" not in rows.fieldnames:
             raise SystemExit(f"unexpected columns in {path}: {rows.fieldnames}")
         for row in rows:
-            name = row["Kernel_Name"][:60]
+            name = short_kernel_name(row["Kernel_Name"])
             acc[name][row["Counter_Name"]] += float(row["Counter_Value"])
             disp[name].add(row["Dispatch_Id"])
     for name in sorted(acc, key=lambda k: -len(disp[k])):

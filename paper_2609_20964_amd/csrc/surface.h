@@ -6,7 +6,7 @@
 // order, so the triangle list is Morton ordered.  Groups of 4 consecutive
 // triangles are the leaves of an 8-ary hierarchy of oriented boxes (thin along
 // the patch normal) built bottom-up over that order.  The signed distance (Eq. 29-34) of every grid node is the exact
-// minimum over all triangles: one wavefront per 8x8x4 node tile walks the
+// minimum over all triangles: one wavefront per 4x4x16 node tile walks the
 // hierarchy together, pruning a box only when it is farther than every lane's
 // current best, so the result equals the brute-force minimum.
 #pragma once
@@ -40,7 +40,7 @@ class Surface {
     void export_tris(float *out, uint32_t n);
     const float4 *tris() const { return tri_; }
     const int2 *tri_info() const { return info_; }
-    size_t bytes() const { return cap_ * (3 * sizeof(float4) + sizeof(int2)) + box_cap_ * 5 * sizeof(float4); }
+    size_t bytes() const { return cap_ * (4 * sizeof(float4) + sizeof(int2)) + box_cap_ * 5 * sizeof(float4); }
 
   private:
     void ensure_capacity(uint32_t tris, uint32_t active);
@@ -54,7 +54,7 @@ class Surface {
     SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
     SurfaceCounts cnt_{};
     // growable
-    float4 *tri_ = nullptr;        // [cap][3]
+    float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)
     int2 *info_ = nullptr;         // [cap]
     float4 *box_ = nullptr;        // [box_cap][4] oriented-box nodes of every hierarchy level
     float4 *nsum_ = nullptr;       // [box_cap] area-weighted normal sums (hierarchy build only)

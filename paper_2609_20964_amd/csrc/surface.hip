@@ -17,6 +17,7 @@ constexpr int kMaxLevels = 12;
 constexpr int kStack = 64;
 constexpr uint32_t kLeaf = 4;               // triangles per hierarchy leaf
 constexpr int kNode = 4;                    // float4 per hierarchy node
+constexpr int kTri = 4;                     // float4 per triangle record
 constexpr uint32_t kLeafBit = 1u << 31;     // packed child word: leaf flag, count << 27, first index
 
 
@@ -134,16 +135,24 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
             ab[k] = (float)(V[1][k] - V[0][k]);
             ac[k] = (float)(V[2][k] - V[0][k]);
         }
-        double aa = 0, bc = 0, cc = 0;
+        double aa = 0, bc = 0, cc = 0, ee = 0;
         for (int k = 0; k < 3; ++k) {
             aa += (double)ab[k] * ab[k];
             bc += (double)ab[k] * ac[k];
             cc += (double)ac[k] * ac[k];
+            const double e = (double)ac[k] - ab[k];
+            ee += e * e;
         }
-        const size_t o = 3 * (size_t)(base + t);
+        const double nx = (double)ab[1] * ac[2] - (double)ab[2] * ac[1];
+        const double ny = (double)ab[2] * ac[0] - (double)ab[0] * ac[2];
+        const double nz = (double)ab[0] * ac[1] - (double)ab[1] * ac[0];
+        const double det = nx * nx + ny * ny + nz * nz;   // |ab x ac|^2 = aa cc - bc^2
+        const size_t o = kTri * (size_t)(base + t);
         tri[o] = make_float4(a[0], a[1], a[2], (float)aa);
         tri[o + 1] = make_float4(ab[0], ab[1], ab[2], (float)bc);
         tri[o + 2] = make_float4(ac[0], ac[1], ac[2], (float)cc);
+        tri[o + 3] = make_float4(aa > 0 ? (float)(1.0 / aa) : 0.f, cc > 0 ? (float)(1.0 / cc) : 0.f,
+                                 ee > 0 ? (float)(1.0 / ee) : 0.f, det > 0 ? (float)(1.0 / det) : 0.f);
         info[base + t] = make_int2((int)cell, packed);
     }
 }
@@ -199,7 +208,7 @@ __global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ t
     const uint32_t t0 = g * kLeaf, t1 = min(t0 + kLeaf, n_tris);
     float ns[3] = {0.f, 0.f, 0.f};
     for (uint32_t t = t0; t < t1; ++t) {
-        const float4 B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+        const float4 B = tri[kTri * (size_t)t + 1], C = tri[kTri * (size_t)t + 2];
         ns[0] += B.y * C.z - B.z * C.y;
         ns[1] += B.z * C.x - B.x * C.z;
         ns[2] += B.x * C.y - B.y * C.x;
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ t
     frame_from_normal(ns[0], ns[1], ns[2], u, v, n);
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t t = t0; t < t1; ++t) {
-        const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+        const float4 A = tri[kTri * (size_t)t], B = tri[kTri * (size_t)t + 1], C = tri[kTri * (size_t)t + 2];
         const float P[3][3] = {{A.x, A.y, A.z}, {A.x + B.x, A.y + B.y, A.z + B.z}, {A.x + C.x, A.y + C.y, A.z + C.z}};
         for (int q = 0; q < 3; ++q) {
             const float pu = P[q][0] * u[0] + P[q][1] * u[1] + P[q][2] * u[2];
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(256) void k_parent_nodes(const float4 *__restrict__
 __global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ tri, uint32_t n, float *__restrict__ out) {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+    float4 A = tri[kTri * (size_t)t], B = tri[kTri * (size_t)t + 1], C = tri[kTri * (size_t)t + 2];
     float *o = out + 9 * (size_t)t;
     o[0] = A.x; o[1] = A.y; o[2] = A.z;
     o[3] = A.x + B.x; o[4] = A.y + B.y; o[5] = A.z + B.z;
@@ -283,47 +292,45 @@ __global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ 
 
 // Closest point of a triangle to p by Voronoi-region classification (Ericson,
 // Real-Time Collision Detection, 2005, Sec. 5.1.5), on the stored record
-// A = (a, |ab|^2), B = (ab, ab.ac), C = (ac, |ac|^2): with ap = p - a, the six
-// dot products of that method follow from d1 = ab.ap and d2 = ac.ap.  Guards
-// cover zero-length edges; a zero-area triangle falls back to vertex a, which
-// is never closer than its true nearest point (its edges are shared with its
-// neighbours, which supply the exact distance).  Returns the squared
-// distance; (v, w) are the barycentric weights of b and c at the closest point.
-__device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, float4 B, float4 C, float &v,
-                                        float &w) {
+// A = (a, |ab|^2), B = (ab, ab.ac), C = (ac, |ac|^2),
+// R = (1/|ab|^2, 1/|ac|^2, 1/|bc|^2, 1/|ab x ac|^2) (0 where the length is 0).
+// With ap = p - a, every dot product of that method follows from d1 = ab.ap
+// and d2 = ac.ap, and each of its divisions is by one of the four constants in
+// R, so a region costs one or two multiplications.  The regions are tested in
+// the method's order (vertices, edges, face interior); neighbouring nodes of a
+// wavefront mostly share a region, so the branches rarely diverge.  A
+// zero-area triangle falls back to vertex a in the interior case, never closer
+// than its true nearest point (its edges are shared with neighbours, which
+// supply the exact distance).  Returns the squared distance; (v, w) are the
+// barycentric weights of b and c at the closest point.
+__device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, float4 B, float4 C, float4 R,
+                                        float &v, float &w) {
     const float apx = px - A.x, apy = py - A.y, apz = pz - A.z;
     const float d1 = B.x * apx + B.y * apy + B.z * apz;
     const float d2 = C.x * apx + C.y * apy + C.z * apz;
-    const float aa = A.w, bc = B.w, cc = C.w;
-    const float d3 = d1 - aa, d4 = d2 - bc;     // against p - b
-    const float d5 = d1 - bc, d6 = d2 - cc;     // against p - c
+    const float d3 = d1 - A.w, d4 = d2 - B.w;   // against p - b
+    const float d5 = d1 - B.w, d6 = d2 - C.w;   // against p - c
     const float vc = d1 * d4 - d3 * d2;
     const float vb = d5 * d2 - d1 * d6;
     const float va = d3 * d6 - d5 * d4;
     if (d1 <= 0.f && d2 <= 0.f) { v = 0.f; w = 0.f; }
     else if (d3 >= 0.f && d4 <= d3) { v = 1.f; w = 0.f; }
-    else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-        const float den = d1 - d3;
-        v = den > 0.f ? d1 / den : 0.f;
-        w = 0.f;
-    } else if (d6 >= 0.f && d5 <= d6) { v = 0.f; w = 1.f; }
-    else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-        const float den = d2 - d6;
-        v = 0.f;
-        w = den > 0.f ? d2 / den : 0.f;
-    } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
-        const float den = (d4 - d3) + (d5 - d6);
-        w = den > 0.f ? (d4 - d3) / den : 0.f;
-        v = 1.f - w;
-    } else {
-        const float sum = va + vb + vc;
-        v = sum > 0.f ? vb / sum : 0.f;
-        w = sum > 0.f ? vc / sum : 0.f;
-    }
+    else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) { v = d1 * R.x; w = 0.f; }
+    else if (d6 >= 0.f && d5 <= d6) { v = 0.f; w = 1.f; }
+    else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) { v = 0.f; w = d2 * R.y; }
+    else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) { w = (d4 - d3) * R.z; v = 1.f - w; }
+    else { v = vb * R.w; w = vc * R.w; }
     const float qx = apx - v * B.x - w * C.x;
     const float qy = apy - v * B.y - w * C.y;
     const float qz = apz - v * B.z - w * C.z;
     return qx * qx + qy * qy + qz * qz;
+}
+
+// Descending compare-exchange of two wave-uniform keys.
+__device__ __forceinline__ void cx_desc(uint32_t &a, uint32_t &b) {
+    const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    a = hi;
+    b = lo;
 }
 
 // Tile = LX x LY x (LZ * kTZ) nodes: lane (x, y, z) of an LX x LY x LZ block
@@ -379,11 +386,12 @@ __global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, con
             const uint32_t first = word & 0x07ffffffu, cnt = (word >> 27) & 15u;
             if (word & kLeafBit) {
                 for (uint32_t t = first; t < first + cnt; ++t) {
-                    const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+                    const float4 *tr = tri + kTri * (size_t)t;
+                    const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
 #pragma unroll
                     for (int k = 0; k < kTZ; ++k) {
                         float v_, w_;
-                        const float dd = tri_d2(px, py, pz[k], A, B, C, v_, w_);
+                        const float dd = tri_d2(px, py, pz[k], A, B, C, R, v_, w_);
                         if (dd < best[k]) {
                             best[k] = dd;
                             arg[k] = (int)t;
@@ -391,7 +399,10 @@ __global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, con
                     }
                 }
             } else {
-                float key[8];
+                // sort key of a child: bit 31 = to be visited, then the bound of
+                // lane 0's first node (a non-negative float, so its bits order
+                // like integers) with the child's index in the low 3 bits
+                uint32_t key[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     // always a valid node (clamped), so all eight loads can be issued together
@@ -411,31 +422,25 @@ __global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, con
                         vis |= dd < best[k];
                         if (k == 0) d0 = dd;
                     }
-                    // order key: lane 0's bound for its first node (uniform)
-                    key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0)
-                                 ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d0)))
-                                 : -1.f;
+                    const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
+                    key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q) : 0u;
                 }
                 if (sp + 8 > kStack) {
                     atomicOr(err, 2);
                     continue;
                 }
-                // push farthest first so the nearest child is popped next
+                // 19-comparator sorting network, descending: the farthest child is
+                // pushed first so the nearest is popped next
+                cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
+                cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
+                cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
+                cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
+                cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
+                cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
-                    int qb = -1;
-                    float kb = -0.5f;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (key[q] > kb) {
-                            kb = key[q];
-                            qb = q;
-                        }
-                    if (qb < 0) break;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (q == qb) key[q] = -1.f;
-                    stk[w][sp] = first + (uint32_t)qb;
+                    if (key[r] == 0u) break;
+                    stk[w][sp] = first + (key[r] & 7u);
                     ++sp;
                 }
             }
@@ -469,9 +474,10 @@ __global__ __launch_bounds__(256) void k_sdf_T(const float *__restrict__ gphi, c
     if (g != 0.f && t >= 0) {
         const double c = iso[0];
         const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / ((size_t)d.nx * d.ny);
-        const float4 A = tri[3 * (size_t)t], B = tri[3 * (size_t)t + 1], C = tri[3 * (size_t)t + 2];
+        const float4 *tr = tri + kTri * (size_t)t;
+        const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
         float v, w;
-        tri_d2((float)i, (float)j, (float)k, A, B, C, v, w);
+        tri_d2((float)i, (float)j, (float)k, A, B, C, R, v, w);
         // p - (a + v ab + w ac)
         float u[3] = {(float)i - A.x - v * B.x - w * C.x, (float)j - A.y - v * B.y - w * C.y,
                       (float)k - A.z - v * B.z - w * C.z};
@@ -688,7 +694,7 @@ void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
         tri_ = nullptr;
         info_ = nullptr;
         size_t c = (size_t)tris + tris / 4 + 64;
-        WG_HIP(hipMalloc(&tri_, c * 3 * sizeof(float4)));
+        WG_HIP(hipMalloc(&tri_, c * kTri * sizeof(float4)));
         WG_HIP(hipMalloc(&info_, c * sizeof(int2)));
         cap_ = c;
     }
