@@ -57,7 +57,8 @@ class Solver {
     std::vector<Level> lv_;
     float *e_ = nullptr, *p_[2] = {nullptr, nullptr}, *q_ = nullptr;
     double *partials_ = nullptr;
-    SolveScalars *dsc_ = nullptr, *hsc_ = nullptr;
+    SolveScalars *dsc_ = nullptr;
+    SolveScalars *hsc_ = nullptr, *hsc_dev_ = nullptr;   // host-mapped copy (host / device address)
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
     int bc_sign_ = -1;

@@ -19,7 +19,7 @@ constexpr int TX = 64, TY = 4, ZC = 16;
 constexpr int kRedBlocks = 2048;     // grid of the pointwise reductions
 constexpr int kMaxRed = 5;
 constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi smoothing factor
-constexpr int kCoarseTarget = 8;        // coarsen until every extent is <= this (or odd)
+constexpr int kCoarseTarget = 16;       // coarsen until every extent is <= this (or odd)
 constexpr int kCoarseAxis = 16;         // exact coarsest solve when every extent is <= this
 
 struct Tiles {
@@ -259,6 +259,32 @@ struct OpSmoothFirst {
     }
 };
 
+// The two pre-smoothing sweeps of the V-cycle from a zero guess, in one pass
+// over rhs: x1 = wd rhs (a sweep with the constant diagonal 1/wd = 6/w), then
+// x2 = x1 + w (rhs - A x1) / diag.  A x1 is a 7-point stencil on rhs, so only
+// rhs is read.  The last post-smoothing sweep uses the same constant diagonal
+// (OpSmoothC), which keeps the V-cycle symmetric; 2 (6 / w) I - A stays
+// positive definite (the 7-point rows sum to at most 12 < 14), so both sweeps
+// are A-norm contractions for either boundary condition.
+struct OpSmooth2 {
+    using T = float;
+    static constexpr int NRED = 0;
+    const float *rhs;
+    float *out;
+    float w, wd;
+    __device__ float load(size_t i) const { return rhs[i]; }
+    __device__ float load1(size_t i) const { return rhs[i]; }
+    __device__ V4<float> load4(size_t i) const { return ld4(rhs + i); }
+    __device__ void apply(size_t i, float c, float s, float diag, double *) const {
+        out[i] = wd * c + w * (c - wd * (diag * c - s)) / diag;
+    }
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
+        V4<float> o;
+        for (int q = 0; q < 4; ++q) o.v[q] = wd * c.v[q] + w * (c.v[q] - wd * (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
+        st4(out + i, o);
+    }
+};
+
 // Weighted-Jacobi sweep x_out = x + w (rhs - A x) / diag; DOT adds rhs . x_out.
 template <bool DOT>
 struct OpSmooth {
@@ -281,6 +307,35 @@ struct OpSmooth {
         V4<float> o;
         for (int q = 0; q < 4; ++q) {
             o.v[q] = c.v[q] + w * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
+            if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
+        }
+        st4(out + i, o);
+    }
+};
+
+// Last post-smoothing sweep, constant diagonal: x_out = x + wd (rhs - A x);
+// DOT adds rhs . x_out.
+template <bool DOT>
+struct OpSmoothC {
+    using T = float;
+    static constexpr int NRED = DOT ? 1 : 0;
+    const float *x, *rhs;
+    float *out;
+    float wd;
+    __device__ float load(size_t i) const { return x[i]; }
+    __device__ float load1(size_t i) const { return x[i]; }
+    __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
+    __device__ void apply(size_t i, float c, float s, float diag, double *acc) const {
+        float rv = rhs[i];
+        float v = c + wd * (rv - (diag * c - s));
+        out[i] = v;
+        if constexpr (DOT) acc[0] += (double)rv * (double)v;
+    }
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *acc) const {
+        const V4<float> r = ld4(rhs + i);
+        V4<float> o;
+        for (int q = 0; q < 4; ++q) {
+            o.v[q] = c.v[q] + wd * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q]));
             if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
         }
         st4(out + i, o);
@@ -593,73 +648,108 @@ __global__ __launch_bounds__(256) void k_prolong4(const float *__restrict__ coar
     }
 }
 
-// Exact solve on the coarsest level (every extent <= kCoarseAxis) by the
+// Exact solve on the coarsest level (every extent <= kCoarseAxis = 16) by the
 // separable eigenbasis of the 7-point operator: transform along x, y, z with
 // the orthonormal 1-D bases, divide by lambda_x + lambda_y + lambda_z (the
-// constant mode is dropped), transform back.  One workgroup, data in LDS.
-// E = [phi_x (cx*cx), phi_y (cy*cy), phi_z (cz*cz), lam_x, lam_y, lam_z],
-// phi_a[m * n_a + i] = mode m at cell i.
+// constant mode is dropped), transform back.  One workgroup of 16 x 16
+// threads; the field sits in LDS as [k][j][i] (row length padded to 17 so the
+// strided line reads are free of bank conflicts), each thread transforms whole
+// lines held in registers, and the bases sit in LDS zero-padded to 16 x 16
+// (every lane reads the same entry: a broadcast).  E = [phi_x (cx*cx),
+// phi_y (cy*cy), phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] =
+// mode m at cell i.
+constexpr int kEigPad = kCoarseAxis + 1;
+constexpr int kEigB = kCoarseAxis * kCoarseAxis;
+
+// out[m] = sum_i P[m][i] in[i] (FWD) or sum_i P[i][m] in[i] (inverse), P padded 16 x 16
+template <bool FWD>
+__device__ __forceinline__ void eig_line(const float *P, const float (&in)[kCoarseAxis], float (&out)[kCoarseAxis]) {
+#pragma unroll
+    for (int m = 0; m < kCoarseAxis; ++m) out[m] = 0.f;
+#pragma unroll
+    for (int i = 0; i < kCoarseAxis; ++i) {
+#pragma unroll
+        for (int m = 0; m < kCoarseAxis; ++m) out[m] += P[FWD ? m * kCoarseAxis + i : i * kCoarseAxis + m] * in[i];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_coarse_eig(const float *__restrict__ rhs, float *__restrict__ x,
                                                      const float *__restrict__ E, int cx, int cy, int cz) {
-    constexpr int M = kCoarseAxis * kCoarseAxis * kCoarseAxis;
-    __shared__ float A[M], B[M], Ph[3 * kCoarseAxis * kCoarseAxis + 3 * kCoarseAxis];
+    __shared__ float L[kCoarseAxis * kCoarseAxis * kEigPad];
+    __shared__ float Pm[3 * kEigB + 3 * kCoarseAxis];
     const int n = cx * cy * cz;
-    const int ne = cx * cx + cy * cy + cz * cz + cx + cy + cz;
-    for (int i = threadIdx.x; i < ne; i += blockDim.x) Ph[i] = E[i];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) A[i] = rhs[i];
-    __syncthreads();
-    const float *Px = Ph, *Py = Px + cx * cx, *Pz = Py + cy * cy;
-    const float *Lx = Pz + cz * cz, *Ly = Lx + cx, *Lz = Ly + cy;
-    // forward: x, y, z
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int m = o % cx, r = o / cx;
-        float acc = 0.f;
-        for (int i = 0; i < cx; ++i) acc += Px[m * cx + i] * A[i + cx * r];
-        B[o] = acc;
+    const int ext[3] = {cx, cy, cz};
+    {
+        const float *src = E;
+        for (int a = 0; a < 3; ++a) {
+            const int na = ext[a];
+            for (int o = threadIdx.x; o < kEigB; o += blockDim.x) {
+                const int m = o / kCoarseAxis, i = o % kCoarseAxis;
+                Pm[a * kEigB + o] = (m < na && i < na) ? src[m * na + i] : 0.f;
+            }
+            src += na * na;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const int na = ext[a];
+            for (int o = threadIdx.x; o < kCoarseAxis; o += blockDim.x) Pm[3 * kEigB + a * kCoarseAxis + o] = o < na ? src[o] : 0.f;
+            src += na;
+        }
     }
-    __syncthreads();
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, m = (o / cx) % cy, k = o / (cx * cy);
-        float acc = 0.f;
-        for (int j = 0; j < cy; ++j) acc += Py[m * cy + j] * B[i + cx * (j + cy * k)];
-        A[o] = acc;
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, j = (o / cx) % cy, m = o / (cx * cy);
-        float acc = 0.f;
-        for (int k = 0; k < cz; ++k) acc += Pz[m * cz + k] * A[i + cx * (j + cy * k)];
-        const float lam = Lx[i] + Ly[j] + Lz[m];
-        B[o] = lam > 1e-12f ? acc / lam : 0.f;
-    }
-    __syncthreads();
-    // inverse: z, y, x (transposed bases)
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
-        float acc = 0.f;
-        for (int m = 0; m < cz; ++m) acc += Pz[m * cz + k] * B[i + cx * (j + cy * m)];
-        A[o] = acc;
-    }
+    const float *Px = Pm, *Py = Pm + kEigB, *Pz = Pm + 2 * kEigB;
+    const float *Lx = Pm + 3 * kEigB, *Ly = Lx + kCoarseAxis, *Lz = Ly + kCoarseAxis;
+    auto at = [](int i, int j, int k) { return i + kEigPad * (j + kCoarseAxis * k); };
+    for (int o = threadIdx.x; o < kCoarseAxis * kCoarseAxis * kEigPad; o += blockDim.x) L[o] = 0.f;
     __syncthreads();
     for (int o = threadIdx.x; o < n; o += blockDim.x) {
         const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
-        float acc = 0.f;
-        for (int m = 0; m < cy; ++m) acc += Py[m * cy + j] * A[i + cx * (m + cy * k)];
-        B[o] = acc;
+        L[at(i, j, k)] = rhs[o];
     }
     __syncthreads();
+    const int u = threadIdx.x % kCoarseAxis, v = threadIdx.x / kCoarseAxis;
+    float in[kCoarseAxis], out[kCoarseAxis];
+    // forward x: line (j, k) = (u, v)
+    for (int i = 0; i < kCoarseAxis; ++i) in[i] = L[at(i, u, v)];
+    eig_line<true>(Px, in, out);
+    for (int i = 0; i < kCoarseAxis; ++i) L[at(i, u, v)] = out[i];
+    __syncthreads();
+    // forward y: line (i, k) = (u, v)
+    for (int j = 0; j < kCoarseAxis; ++j) in[j] = L[at(u, j, v)];
+    eig_line<true>(Py, in, out);
+    for (int j = 0; j < kCoarseAxis; ++j) L[at(u, j, v)] = out[j];
+    __syncthreads();
+    // forward z, divide by the eigenvalue (0 for the constant mode and the padding), inverse z: line (i, j)
+    for (int k = 0; k < kCoarseAxis; ++k) in[k] = L[at(u, v, k)];
+    eig_line<true>(Pz, in, out);
+    for (int k = 0; k < kCoarseAxis; ++k) {
+        const float lam = Lx[u] + Ly[v] + Lz[k];
+        in[k] = (u < cx && v < cy && k < cz && lam > 1e-12f) ? out[k] / lam : 0.f;
+    }
+    eig_line<false>(Pz, in, out);
+    for (int k = 0; k < kCoarseAxis; ++k) L[at(u, v, k)] = out[k];
+    __syncthreads();
+    // inverse y
+    for (int j = 0; j < kCoarseAxis; ++j) in[j] = L[at(u, j, v)];
+    eig_line<false>(Py, in, out);
+    for (int j = 0; j < kCoarseAxis; ++j) L[at(u, j, v)] = out[j];
+    __syncthreads();
+    // inverse x
+    for (int i = 0; i < kCoarseAxis; ++i) in[i] = L[at(i, u, v)];
+    eig_line<false>(Px, in, out);
+    for (int i = 0; i < kCoarseAxis; ++i) L[at(i, u, v)] = out[i];
+    __syncthreads();
     for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, r = o / cx;
-        float acc = 0.f;
-        for (int m = 0; m < cx; ++m) acc += Px[m * cx + i] * B[m + cx * r];
-        x[o] = acc;
+        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
+        x[o] = L[at(i, j, k)];
     }
 }
 
 enum { FIN_RESID = 0, FIN_RZ = 1, FIN_PQ = 2, FIN_RR = 3, FIN_BSUM = 4 };
 
+// Final stage of a two-stage reduction: sums the per-block partials in a
+// fixed order, updates the solver scalars and copies them to `mirror`, a
+// host-mapped buffer the host reads after synchronising the stream.
 __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsigned nb, int mode, int flag,
-                                                   SolveScalars *sc, double ncells) {
+                                                   SolveScalars *sc, double ncells, SolveScalars *mirror) {
     const int nred = mode == FIN_RESID ? 5 : 1;
     double v[5] = {0, 0, 0, 0, 0};
     for (int k = 0; k < nred; ++k) {
@@ -710,6 +800,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
             sc->b_sum = v[0];
             break;
     }
+    *mirror = *sc;
 }
 
 // Orthonormal 1-D eigenbasis of the 7-point operator along one axis.
@@ -809,7 +900,8 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
     }
     partials_ = a.take<double>(partial_slots(dims[0]));
     dsc_ = a.take<SolveScalars>(1);
-    WG_HIP(hipHostMalloc((void **)&hsc_, sizeof(SolveScalars), hipHostMallocDefault));
+    WG_HIP(hipHostMalloc((void **)&hsc_, sizeof(SolveScalars), hipHostMallocMapped | hipHostMallocCoherent));
+    WG_HIP(hipHostGetDevicePointer((void **)&hsc_dev_, hsc_, 0));
     const Dims &c = dims.back();
     coarse_direct_ = c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis;
     if (coarse_direct_) {
@@ -826,12 +918,12 @@ Solver::~Solver() {
 }
 
 void Solver::finalize(int mode, unsigned nb, int flag) {
-    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count());
+    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count(), hsc_dev_);
     WG_LAUNCH_CHECK();
 }
 
 void Solver::read_scalars() {
-    WG_HIP(hipMemcpyAsync(hsc_, dsc_, sizeof(SolveScalars), hipMemcpyDeviceToHost, st_));
+    // the last finalize wrote the host-mapped copy
     WG_HIP(hipStreamSynchronize(st_));
 }
 
@@ -857,7 +949,7 @@ void Solver::vcycle(int l) {
     const int last = (int)lv_.size() - 1;
     if (l == last) {
         if (coarse_direct_) {
-            k_coarse_eig<<<1, 256, 0, st_>>>(L.rhs, L.x, coarseM_[bc_sign_ > 0 ? 1 : 0], L.d.nx, L.d.ny, L.d.nz);
+            k_coarse_eig<<<1, kCoarseAxis * kCoarseAxis, 0, st_>>>(L.rhs, L.x, coarseM_[bc_sign_ > 0 ? 1 : 0], L.d.nx, L.d.ny, L.d.nz);
             WG_LAUNCH_CHECK();
         } else {
             // no direct solve possible (odd extents): a fixed, even number of sweeps
@@ -873,8 +965,7 @@ void Solver::vcycle(int l) {
     Level &C = lv_[l + 1];
     C.d.bc_sign = bc_sign_;
     const int ks = l == 0 ? WG_PROF_SMOOTH : -1, kt = l == 0 ? WG_PROF_TRANSFER : -1;
-    launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 8.0);
-    launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_, ks, 12.0);
+    launch_stencil(OpSmooth2{L.rhs, L.x, kOmega, kOmega / 6.f}, L.d, nullptr, st_, ks, 8.0);
     launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_, ks, 12.0);
     {
         prof::Scope ps(kt, st_, 4.0 * (double)(L.d.count() + C.d.count()));
@@ -901,9 +992,9 @@ void Solver::vcycle(int l) {
     }
     launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 12.0);
     if (l == 0) {
-        launch_stencil(OpSmooth<true>{L.x2, L.rhs, L.x, kOmega}, L.d, partials_, st_, ks, 12.0);   // + r.z
+        launch_stencil(OpSmoothC<true>{L.x2, L.rhs, L.x, kOmega / 6.f}, L.d, partials_, st_, ks, 12.0);   // + r.z
     } else {
-        launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
+        launch_stencil(OpSmoothC<false>{L.x2, L.rhs, L.x, kOmega / 6.f}, L.d, nullptr, st_);
     }
 }
 
