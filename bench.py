@@ -7,7 +7,9 @@ flapping ellipsoid (semi-axes 0.30, 0.12, 0.08) under a travelling-wave shear,
 solve warm-started from the previous step to FP64 relative residual 1e-6,
 surface + signed distance on every grid node, then SDF and normals sampled at
 65,536 query points.  Inputs for every step are resident in HBM before the
-timed region.  Metric: reconstructions per second.
+timed region.  Metric: reconstructions per second.  Steps run through the
+pipelined entry point (a step's distance walk and sampling overlap the next
+step's splat and solve); the same loop without pipelining is reported too.
 
 Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic bytes (or nodes) per launch
@@ -50,7 +52,7 @@ def gpu_run(args):
 
     n, npts, nq = args.n, args.points, args.queries
     fl = synth.Flapping(n_points=npts)
-    total = args.warmup + args.steps + args.adjoint_steps
+    total = args.warmup + args.steps + args.adjoint_steps + 1
     log(f"generating {total} steps of {npts} points")
     clouds = []
     for t in range(total):
@@ -64,9 +66,9 @@ def gpu_run(args):
     for t in range(args.warmup):
         if t == max(args.warmup - 3, 0):
             _lib.profile_enable(kinds)
-        st = r.forward(*clouds[t], rel_tol=args.tol, warm_start=t > 0)
-        r.sample(q)
+        st, _, _ = r.step(*clouds[t], q, rel_tol=args.tol, warm_start=t > 0)
         log(f"warmup {t}: iters {st['iters']} rel_res {st['rel_res']:.2e} ms {[round(v, 2) for v in st['ms'][:5]]}")
+    r.wait()
     torch.cuda.synchronize()
     per_kind = {k: _lib.profile_read(k) for k in kinds}
     dominant = max(per_kind, key=lambda k: per_kind[k]["ms"])
@@ -75,19 +77,32 @@ def gpu_run(args):
     _lib.profile_reset()
     _lib.profile_enable([dominant])
 
+    # timed: pipelined steps (each step's distance walk and sampling overlap the
+    # next step's splat and solve), all outputs complete at the final synchronise
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         t = args.warmup + k
-        st = r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
-        phi, nq_out = r.sample(q)
+        st, phi, nq_out = r.step(*clouds[t], q, rel_tol=args.tol, warm_start=True)
         stats.append(st)
+    r.wait()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     _lib.profile_enable([])
     prof = _lib.profile_read(dominant)
     elapsed = t1 - t0
+
+    # the same loop without pipelining (forward, then sample), for reference
+    plain_steps = min(args.steps, 10)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for k in range(plain_steps):
+        t = args.warmup + args.steps - plain_steps + k
+        r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
+        r.sample(q)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - p0) / plain_steps * 1e3
 
     # two more (untimed) steps with every kind profiled: the solver's kernels as a group
     _lib.profile_reset()
@@ -106,9 +121,9 @@ def gpu_run(args):
     gpu_last = {"chi": fields["chi"].cpu().numpy(), "phi": fields["phi"].cpu().numpy(),
                 "iso_c": st2["iso_c"], "phi_q": phi.cpu().numpy(), "t": last_t}
 
-    # reverse pass at the same size: L = mean phi(q)^2
+    # reverse pass at the same size: L = mean phi(q)^2 (one untimed warm-up call first)
     adj_ms = []
-    for k in range(args.adjoint_steps):
+    for k in range(args.adjoint_steps + 1 if args.adjoint_steps else 0):
         t = args.warmup + args.steps + k
         r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
         phi, _ = r.sample(q, normals=False)
@@ -116,11 +131,13 @@ def gpu_run(args):
         a0 = time.perf_counter()
         r.backward(q, (2.0 / nq) * phi, rel_tol=args.tol)
         torch.cuda.synchronize()
-        adj_ms.append((time.perf_counter() - a0) * 1e3)
+        if k > 0:
+            adj_ms.append((time.perf_counter() - a0) * 1e3)
     r.close()
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
-            "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms}
+            "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
+            "plain_ms": plain_ms, "plain_steps": plain_steps}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -405,8 +422,10 @@ def main():
                    "refinements_mean": float(np.mean([s["refinements"] for s in st])),
                    "rel_res_max": float(max(s["rel_res"] for s in st)),
                    "n_tris_mean": float(np.mean([s["n_tris"] for s in st]))},
+        "unpipelined": {"ms_per_step": res["plain_ms"], "recons_per_s": 1e3 / res["plain_ms"],
+                        "steps": res["plain_steps"]},
         "phase_ms_mean": {k: float(np.mean([s["ms"][i] for s in st]))
-                          for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
+                          for i, k in enumerate(["splat", "solve", "iso", "surface"])},
         "kernel_ms_per_step_warmup": {k: v["ms"] / 3 for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
     }

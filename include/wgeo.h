@@ -114,6 +114,26 @@ int wg_recon_forward(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_
  * Queries outside the grid's cell-centre box are clamped to it. */
 int wg_sample_sdf_normals(wg_recon *r, const float *d_q, int n_q, float *d_phi, float *d_nrm_out);
 
+/* Forward reconstruction followed by sampling at d_q, pipelined with the next
+ * call on the same handle (a moving-boundary loop, Sec. 3.2).  Computes what
+ * wg_recon_forward then wg_sample_sdf_normals compute, but returns once the
+ * surface is extracted: the distance walk and the sampling of this call run
+ * on the handle's second stream while the next wg_recon_step bins, splats and
+ * solves (the walk reads neither the field nor the point buffers that step
+ * overwrites).  d_phi / d_nrm_out of a call are complete once a later
+ * wg_recon_wait(r) has been reached on the handle's stream (or the device has
+ * been synchronised); every other call on r orders itself after them.  d_q
+ * must stay valid until then.  Errors and statistics are those of
+ * wg_recon_forward; stats->ms[4] (the walk) is reported as 0. */
+int wg_recon_step(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_points,
+                  const float *d_q, int n_q, float *d_phi, float *d_nrm_out,
+                  const wg_solve_opts *opts, wg_stats *stats);
+
+/* Orders the handle's stream after all work r has left running on its second
+ * stream (the last wg_recon_step's walk and sampling).  Does not block the
+ * host. */
+int wg_recon_wait(wg_recon *r);
+
 /* Reverse pass (Sec. 2.5, Eq. 35-39) of the last forward + sampling at d_q:
  * given dL/dphi(q) (d_gphi, [n_q]) and optionally dL/dn(q) (d_gnrm, [n_q][3]
  * or NULL), writes dL/dx (d_gxyz, [n_points][3]) and dL/dn_i (d_gnrm_pts,

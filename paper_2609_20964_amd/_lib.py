@@ -66,6 +66,9 @@ SIGNATURES = {
     "wg_recon_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
                                    C.POINTER(WgStats)]),
     "wg_sample_sdf_normals": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "wg_recon_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                C.c_void_p, C.POINTER(WgSolveOpts), C.POINTER(WgStats)]),
+    "wg_recon_wait": (C.c_int, [C.c_void_p]),
     "wg_recon_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.POINTER(WgSolveOpts), C.POINTER(WgStats)]),
     "wg_poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),

@@ -14,8 +14,15 @@ class Recon {
     ~Recon();
     static size_t footprint(const wg_grid &g, int max_points);
 
-    int forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st);
-    int sample(const float *q, int nq, float *phi, float *nrm);
+    // pipelined: leave the distance walk running on the second stream (it
+    // overlaps the splat and solve of the next forward); otherwise the handle
+    // stream waits for it before returning.
+    int forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st,
+                bool pipelined = false);
+    // pipelined: sample on the second stream right behind the distance walk.
+    int sample(const float *q, int nq, float *phi, float *nrm, bool pipelined = false);
+    // Order the handle stream after everything enqueued on the second stream.
+    void join();
     int backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
                  float *gq, const wg_solve_opts &o, wg_stats *st);
     int poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st);
@@ -30,6 +37,7 @@ class Recon {
   private:
     static void plan(Arena &a, const wg_grid &g, int max_points);
     void check_err(const char *what);
+    void wait_sdf();
 
     wg_grid grid_;
     int max_points_;
@@ -51,6 +59,11 @@ class Recon {
     double *hscal_ = nullptr;
     int n_points_ = 0;
     bool have_forward_ = false;
+    // second stream: the distance walk (and pipelined sampling)
+    hipStream_t sdf_st_ = nullptr;
+    hipEvent_t ev_mc_ = nullptr, ev_sdf_ = nullptr, ev_tail_ = nullptr;
+    bool sdf_pending_ = false;   // ev_sdf_ recorded and not yet waited for on st_
+    bool tail_pending_ = false;  // work after ev_sdf_ on sdf_st_ (pipelined sampling)
     double chi_mean_ = 0.0, iso_c_ = 0.0;
 };
 

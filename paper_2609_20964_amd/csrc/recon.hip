@@ -127,25 +127,55 @@ Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_po
     surf_.bind(arena_, d_, st_);
     WG_HIP(hipHostMalloc((void **)&herr_, 4 * sizeof(int), hipHostMallocDefault));
     WG_HIP(hipHostMalloc((void **)&hscal_, 8 * sizeof(double), hipHostMallocDefault));
+    WG_HIP(hipStreamCreateWithFlags(&sdf_st_, hipStreamNonBlocking));
+    WG_HIP(hipEventCreateWithFlags(&ev_mc_, hipEventDisableTiming));
+    WG_HIP(hipEventCreateWithFlags(&ev_sdf_, hipEventDisableTiming));
+    WG_HIP(hipEventCreateWithFlags(&ev_tail_, hipEventDisableTiming));
     WG_HIP(hipMemsetAsync(chi_, 0, N * sizeof(double), st_));
+    WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
     WG_HIP(hipStreamSynchronize(st_));
 }
 
 Recon::~Recon() {
+    if (sdf_st_) (void)hipStreamSynchronize(sdf_st_);
+    if (ev_mc_) (void)hipEventDestroy(ev_mc_);
+    if (ev_sdf_) (void)hipEventDestroy(ev_sdf_);
+    if (ev_tail_) (void)hipEventDestroy(ev_tail_);
+    if (sdf_st_) (void)hipStreamDestroy(sdf_st_);
     if (herr_) (void)hipHostFree(herr_);
     if (hscal_) (void)hipHostFree(hscal_);
 }
 
+// The handle stream waits (on the device) for the last distance walk.
+void Recon::wait_sdf() {
+    if (sdf_pending_) {
+        WG_HIP(hipStreamWaitEvent(st_, ev_sdf_, 0));
+        sdf_pending_ = false;
+    }
+}
+
+void Recon::join() {
+    wait_sdf();
+    if (tail_pending_) {
+        WG_HIP(hipStreamWaitEvent(st_, ev_tail_, 0));
+        tail_pending_ = false;
+    }
+}
+
 size_t Recon::bytes_resident() const { return arena_.planned() + surf_.bytes(); }
 
+// err_[0]: splat flags (bit 0: a point outside the grid); err_[1]: distance
+// walk flags (bit 1: stack overflow), read only once that walk is known to be
+// complete on the handle stream.
 void Recon::check_err(const char *what) {
     WG_HIP(hipMemcpyAsync(herr_, err_, 4 * sizeof(int), hipMemcpyDeviceToHost, st_));
     WG_HIP(hipStreamSynchronize(st_));
     if (herr_[0] & 1) throw Error(WG_EINVAL, std::string(what) + ": a point lies outside the grid");
-    if (herr_[0] & 2) throw Error(WG_EDEVICE, std::string(what) + ": distance traversal stack overflow");
+    if (!sdf_pending_ && (herr_[1] & 2)) throw Error(WG_EDEVICE, "distance traversal stack overflow");
 }
 
-int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st) {
+int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st,
+                   bool pipelined) {
     require(npts >= 0 && npts <= max_points_, WG_EINVAL, "n_points outside [0, max_points]");
     require(npts == 0 || (xyz && nrm), WG_EINVAL, "null point or normal pointer");
     require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
@@ -154,7 +184,7 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     Timer tm(st_);
     tm.mark(0);
     WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
-    WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
+    WG_HIP(hipMemsetAsync(err_, 0, sizeof(int), st_));
     if (npts > 0) {
         // per point: 24 B read, 24 B copied, 4 B key, tile bookkeeping, 81 contributions to b
         prof::Scope ps(WG_PROF_SPLAT, st_, 376.0 * npts);
@@ -196,9 +226,23 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     }
     WG_LAUNCH_CHECK();
     tm.mark(3);
-    surf_.extract(chi_, scal_);
+    // the previous distance walk (and pipelined sampling) reads the triangle
+    // records, the hierarchy, the node sides and phi that follow: wait for it
+    join();
+    WG_HIP(hipMemcpyAsync(herr_ + 1, err_ + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
+    surf_.extract(chi_, scal_);   // host-synchronising: the previous walk has finished
+    if (herr_[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
+    surf_.signs(chi_, scal_);
+    WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
     tm.mark(4);
-    surf_.sdf(chi_, scal_, grid_.h, phi_, argmin_, err_);
+    // distance walk on the second stream: it reads neither chi nor anything
+    // the next splat and solve write, so it may overlap them
+    WG_HIP(hipEventRecord(ev_mc_, st_));
+    WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
+    surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_);
+    WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
+    sdf_pending_ = true;
+    if (!pipelined) wait_sdf();
     tm.mark(5);
     WG_HIP(hipMemcpyAsync(hscal_, scal_, sizeof(double), hipMemcpyDeviceToHost, st_));
     check_err("sdf");
@@ -214,15 +258,25 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         st->n_tris = surf_.n_tris();
         st->status = sr.status;
         for (int k = 0; k < 5; ++k) st->ms[k] = tm.between(k, k + 1);
+        if (pipelined) st->ms[4] = 0.f;   // the walk is still running
         st->bytes_resident = bytes_resident();
     }
     return sr.status;
 }
 
-int Recon::sample(const float *q, int nq, float *phi, float *nrm) {
+int Recon::sample(const float *q, int nq, float *phi, float *nrm, bool pipelined) {
     require(have_forward_, WG_ESTATE, "sample before a successful forward");
     require(nq >= 0 && (nq == 0 || (q && phi)), WG_EINVAL, "bad query arguments");
-    launch_sample(gf_, phi_, q, nq, phi, nrm, st_);
+    if (pipelined) {
+        // behind the walk on the second stream; q was ready on the handle stream
+        // when the walk's start event was recorded after it
+        launch_sample(gf_, phi_, q, nq, phi, nrm, sdf_st_);
+        WG_HIP(hipEventRecord(ev_tail_, sdf_st_));
+        tail_pending_ = true;
+    } else {
+        join();
+        launch_sample(gf_, phi_, q, nq, phi, nrm, st_);
+    }
     return WG_OK;
 }
 
@@ -233,6 +287,7 @@ int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gn
     require(n_points_ == 0 || (gxyz && gnrm_pts), WG_EINVAL, "null point-gradient outputs");
     require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
     const size_t N = d_.count();
+    join();
     Timer tm(st_);
     tm.mark(0);
     WG_HIP(hipMemsetAsync(gphi_, 0, N * sizeof(float), st_));
@@ -301,6 +356,7 @@ int Recon::poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg
 
 int Recon::get_fields(float *b, double *chi, float *phi, int32_t *keys) {
     require(have_forward_, WG_ESTATE, "no forward result");
+    join();
     const size_t N = d_.count();
     if (b) WG_HIP(hipMemcpyAsync(b, b_, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
     if (chi) {
@@ -315,6 +371,7 @@ int Recon::get_fields(float *b, double *chi, float *phi, int32_t *keys) {
 
 int Recon::get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tris) {
     require(have_forward_, WG_ESTATE, "no forward result");
+    join();
     const int64_t T = surf_.n_tris();
     if (n_tris) *n_tris = T;
     const int64_t m = T < max_tris ? T : max_tris;
@@ -410,6 +467,25 @@ int wg_sample_sdf_normals(wg_recon *r, const float *d_q, int n_q, float *d_phi, 
     return guarded([&] {
         wg::require(r, WG_EINVAL, "null handle");
         return r->impl->sample(d_q, n_q, d_phi, d_nrm_out);
+    });
+}
+
+int wg_recon_step(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_points, const float *d_q, int n_q,
+                  float *d_phi, float *d_nrm_out, const wg_solve_opts *opts, wg_stats *stats) {
+    return guarded([&] {
+        wg::require(r && opts, WG_EINVAL, "null argument");
+        wg::require(n_q >= 0 && (n_q == 0 || (d_q && d_phi)), WG_EINVAL, "bad query arguments");
+        const int rc = r->impl->forward(d_xyz, d_nrm, n_points, *opts, stats, true);
+        r->impl->sample(d_q, n_q, d_phi, d_nrm_out, true);
+        return rc;
+    });
+}
+
+int wg_recon_wait(wg_recon *r) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        r->impl->join();
+        return WG_OK;
     });
 }
 

@@ -29,8 +29,12 @@ class Surface {
     // Extract the mesh of {chi = *c} (c on the device).  Host-synchronising:
     // returns the triangle count.
     uint32_t extract(const double *chi, const double *c);
-    // phi and the nearest-triangle index on every node.
-    void sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err);
+    // Side of every node against the extracted surface (chi >= c: outside), on
+    // the surface's stream; the distance walk reads these bits, not chi.
+    void signs(const double *chi, const double *c);
+    // phi and the nearest-triangle index on every node, on stream s (after
+    // extract and signs have completed there).
+    void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s);
     // reverse of sdf through the vertices: g_chi, g_c (+=)
     void sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                float *g_chi, double *g_c);
@@ -52,6 +56,9 @@ class Surface {
     size_t nbricks_pad_ = 0;       // (2^mbits)^3
     uint32_t *cnt_b_ = nullptr, *off_b_ = nullptr, *active_ = nullptr, *blk_ = nullptr;
     SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
+    uint32_t *sign_ = nullptr;     // [ceil(N / 32)] node sides
+    uint32_t *next_tile_ = nullptr;   // work counter of the persistent distance walk
+    unsigned sdf_blocks_ = 0;
     SurfaceCounts cnt_{};
     // growable
     float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)

@@ -333,128 +333,150 @@ __device__ __forceinline__ void cx_desc(uint32_t &a, uint32_t &b) {
     b = lo;
 }
 
+// Side of every node: bit (o & 31) of word o >> 5 is set where chi >= c
+// (outside, Eq. 31: the mesh separates exactly the nodes with chi >= c from
+// the others).  One node per lane; a wavefront writes two words.
+__global__ __launch_bounds__(256) void k_sign_bits(const double *__restrict__ chi, const double *iso, size_t n,
+                                                    uint32_t *__restrict__ sign) {
+    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t base = o - threadIdx.x % 64;
+    if (base >= n) return;   // whole wavefront
+    const double c = iso[0];
+    const uint64_t bits = __ballot(o < n && chi[o] >= c);
+    if (threadIdx.x % 64 == 0) {
+        sign[base >> 5] = (uint32_t)bits;
+        if (base + 32 < n) sign[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+    }
+}
+
 // Tile = LX x LY x (LZ * kTZ) nodes: lane (x, y, z) of an LX x LY x LZ block
 // owns the kTZ nodes z, z + LZ, ... of its column.
 template <int LX, int LY, int LZ, int kTZ>
-__global__ __launch_bounds__(256) void k_sdf(const double *__restrict__ chi, const double *iso, Dims d, double h,
+__global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, Dims d, double h,
                                               const float4 *__restrict__ nodes, uint32_t root,
                                               const float4 *__restrict__ tri, uint32_t n_tris,
-                                              float *__restrict__ phi, int32_t *__restrict__ argmin, int *err) {
+                                              float *__restrict__ phi, int32_t *__restrict__ argmin, int *err,
+                                              uint32_t *next_tile) {
     static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     constexpr int TZ = LZ * kTZ;
     const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
-    const uint32_t tile = blockIdx.x * 4 + w;
-    if (tile >= (uint32_t)(tx * ty * tz)) return;   // whole wavefront
-    const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
-    const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
-    const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1);
-    const float px = (float)i, py = (float)j;
-    float pz[kTZ], best[kTZ];
-    int arg[kTZ];
+    const uint32_t n_tiles = (uint32_t)(tx * ty * tz);
+    // persistent: each wavefront takes the next tile until none is left
+    for (;;) {
+        uint32_t tile = 0;
+        if (lane == 0) tile = atomicAdd(next_tile, 1u);
+        tile = __builtin_amdgcn_readfirstlane(tile);
+        if (tile >= n_tiles) break;   // whole wavefront
+        const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
+        const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
+        const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1);
+        const float px = (float)i, py = (float)j;
+        float pz[kTZ], best[kTZ];
+        int arg[kTZ];
 #pragma unroll
-    for (int k = 0; k < kTZ; ++k) {
-        pz[k] = (float)min(gk0 + LZ * k, d.nz - 1);
-        best[k] = INFINITY;
-        arg[k] = -1;
-    }
-    if (n_tris > 0) {
-        int sp = 1;
-        stk[w][0] = root;
-        while (sp > 0) {
-            --sp;
-            const uint32_t ni = __builtin_amdgcn_readfirstlane(stk[w][sp]);
-            const float4 *nd = nodes + (size_t)kNode * ni;
-            const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
-            // bound of this node for the lane's kTZ nodes (they differ only in z)
-            bool need = false;
-            {
-                const float rx = px - N0.x, ry = py - N0.y;
-                const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
-                            bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
-#pragma unroll
-                for (int k = 0; k < kTZ; ++k) {
-                    const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
-                    const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
-                    const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
-                    need |= du * du + dv * dv + dn * dn < best[k];
-                }
-            }
-            if (__ballot(need) == 0) continue;
-            const uint32_t word = __float_as_uint(N3.w);
-            const uint32_t first = word & 0x07ffffffu, cnt = (word >> 27) & 15u;
-            if (word & kLeafBit) {
-                for (uint32_t t = first; t < first + cnt; ++t) {
-                    const float4 *tr = tri + kTri * (size_t)t;
-                    const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
+        for (int k = 0; k < kTZ; ++k) {
+            pz[k] = (float)min(gk0 + LZ * k, d.nz - 1);
+            best[k] = INFINITY;
+            arg[k] = -1;
+        }
+        if (n_tris > 0) {
+            int sp = 1;
+            stk[w][0] = root;
+            while (sp > 0) {
+                --sp;
+                const uint32_t ni = __builtin_amdgcn_readfirstlane(stk[w][sp]);
+                const float4 *nd = nodes + (size_t)kNode * ni;
+                const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
+                // bound of this node for the lane's kTZ nodes (they differ only in z)
+                bool need = false;
+                {
+                    const float rx = px - N0.x, ry = py - N0.y;
+                    const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
+                                bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
 #pragma unroll
                     for (int k = 0; k < kTZ; ++k) {
-                        float v_, w_;
-                        const float dd = tri_d2(px, py, pz[k], A, B, C, R, v_, w_);
-                        if (dd < best[k]) {
-                            best[k] = dd;
-                            arg[k] = (int)t;
+                        const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
+                        const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
+                        const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
+                        need |= du * du + dv * dv + dn * dn < best[k];
+                    }
+                }
+                if (__ballot(need) == 0) continue;
+                const uint32_t word = __float_as_uint(N3.w);
+                const uint32_t first = word & 0x07ffffffu, cnt = (word >> 27) & 15u;
+                if (word & kLeafBit) {
+                    for (uint32_t t = first; t < first + cnt; ++t) {
+                        const float4 *tr = tri + kTri * (size_t)t;
+                        const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
+#pragma unroll
+                        for (int k = 0; k < kTZ; ++k) {
+                            float v_, w_;
+                            const float dd = tri_d2(px, py, pz[k], A, B, C, R, v_, w_);
+                            if (dd < best[k]) {
+                                best[k] = dd;
+                                arg[k] = (int)t;
+                            }
                         }
                     }
-                }
-            } else {
-                // sort key of a child: bit 31 = to be visited, then the bound of
-                // lane 0's first node (a non-negative float, so its bits order
-                // like integers) with the child's index in the low 3 bits
-                uint32_t key[8];
+                } else {
+                    // sort key of a child: bit 31 = to be visited, then the bound of
+                    // lane 0's first node (a non-negative float, so its bits order
+                    // like integers) with the child's index in the low 3 bits
+                    uint32_t key[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    // always a valid node (clamped), so all eight loads can be issued together
-                    const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
-                    const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
-                    const float rx = px - C0.x, ry = py - C0.y;
-                    const float bu = C1.x * rx + C1.y * ry - C1.z * C0.z, bv = C2.x * rx + C2.y * ry - C2.z * C0.z,
-                                bn = C3.x * rx + C3.y * ry - C3.z * C0.z;
-                    bool vis = false;
-                    float d0 = 0.f;
+                    for (int q = 0; q < 8; ++q) {
+                        // always a valid node (clamped), so all eight loads can be issued together
+                        const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
+                        const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
+                        const float rx = px - C0.x, ry = py - C0.y;
+                        const float bu = C1.x * rx + C1.y * ry - C1.z * C0.z, bv = C2.x * rx + C2.y * ry - C2.z * C0.z,
+                                    bn = C3.x * rx + C3.y * ry - C3.z * C0.z;
+                        bool vis = false;
+                        float d0 = 0.f;
 #pragma unroll
-                    for (int k = 0; k < kTZ; ++k) {
-                        const float du = fmaxf(fabsf(bu + C1.z * pz[k]) - C0.w, 0.f);
-                        const float dv = fmaxf(fabsf(bv + C2.z * pz[k]) - C1.w, 0.f);
-                        const float dn = fmaxf(fabsf(bn + C3.z * pz[k]) - C2.w, 0.f);
-                        const float dd = du * du + dv * dv + dn * dn;
-                        vis |= dd < best[k];
-                        if (k == 0) d0 = dd;
+                        for (int k = 0; k < kTZ; ++k) {
+                            const float du = fmaxf(fabsf(bu + C1.z * pz[k]) - C0.w, 0.f);
+                            const float dv = fmaxf(fabsf(bv + C2.z * pz[k]) - C1.w, 0.f);
+                            const float dn = fmaxf(fabsf(bn + C3.z * pz[k]) - C2.w, 0.f);
+                            const float dd = du * du + dv * dv + dn * dn;
+                            vis |= dd < best[k];
+                            if (k == 0) d0 = dd;
+                        }
+                        const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
+                        key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q) : 0u;
                     }
-                    const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
-                    key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q) : 0u;
-                }
-                if (sp + 8 > kStack) {
-                    atomicOr(err, 2);
-                    continue;
-                }
-                // 19-comparator sorting network, descending: the farthest child is
-                // pushed first so the nearest is popped next
-                cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
-                cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
-                cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
-                cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
-                cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
-                cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
+                    if (sp + 8 > kStack) {
+                        atomicOr(err, 2);
+                        continue;
+                    }
+                    // 19-comparator sorting network, descending: the farthest child is
+                    // pushed first so the nearest is popped next
+                    cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
+                    cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
+                    cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
+                    cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
+                    cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
+                    cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    if (key[r] == 0u) break;
-                    stk[w][sp] = first + (key[r] & 7u);
-                    ++sp;
+                    for (int r = 0; r < 8; ++r) {
+                        if (key[r] == 0u) break;
+                        stk[w][sp] = first + (key[r] & 7u);
+                        ++sp;
+                    }
                 }
             }
         }
-    }
-    if (gi < d.nx && gj < d.ny) {
-        const double c = iso[0];
+        if (gi < d.nx && gj < d.ny) {
 #pragma unroll
-        for (int k = 0; k < kTZ; ++k) {
-            if (gk0 + LZ * k >= d.nz) break;
-            const size_t o = (size_t)i + (size_t)d.nx * (j + (size_t)d.ny * (gk0 + LZ * k));
-            const float s = chi[o] >= c ? 1.f : -1.f;
-            phi[o] = s * sqrtf(best[k]) * (float)h;
-            argmin[o] = arg[k];
+            for (int k = 0; k < kTZ; ++k) {
+                if (gk0 + LZ * k >= d.nz) break;
+                const size_t o = (size_t)i + (size_t)d.nx * (j + (size_t)d.ny * (gk0 + LZ * k));
+                const float s = ((sign[o >> 5] >> (o & 31)) & 1u) ? 1.f : -1.f;
+                phi[o] = s * sqrtf(best[k]) * (float)h;
+                argmin[o] = arg[k];
+            }
         }
     }
 }
@@ -659,6 +681,8 @@ void Surface::plan(Arena &a, const Dims &d) {
     for (int k = 0; k < 3; ++k) a.reserve(pad * sizeof(uint32_t));   // counts, offsets, active
     a.reserve(2 * (size_t)cdiv(pad, scan::kScanBlock) * sizeof(uint32_t));
     a.reserve(sizeof(SurfaceCounts));
+    a.reserve(cdiv(d.count(), 32) * sizeof(uint32_t));   // node sides
+    a.reserve(sizeof(uint32_t));                          // tile counter of the walk
 }
 
 void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
@@ -671,6 +695,14 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     active_ = a.take<uint32_t>(nbricks_pad_);
     blk_ = a.take<uint32_t>(2 * (size_t)cdiv(nbricks_pad_, scan::kScanBlock));
     dcnt_ = a.take<SurfaceCounts>(1);
+    sign_ = a.take<uint32_t>(cdiv(d.count(), 32));
+    next_tile_ = a.take<uint32_t>(1);
+    // the persistent walk launches as many workgroups as can be resident at once
+    int dev = 0, cus = 0, per_cu = 0;
+    WG_HIP(hipGetDevice(&dev));
+    WG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    WG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sdf<4, 4, 4, 4>, 256, 0));
+    sdf_blocks_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
     WG_HIP(hipHostMalloc((void **)&hcnt_, sizeof(SurfaceCounts), hipHostMallocDefault));
     // a first guess at the triangle capacity: ~4 per cube over a few slices
     size_t face = (size_t)d.nx * d.ny;
@@ -757,19 +789,28 @@ uint32_t Surface::extract(const double *chi, const double *c) {
 }
 
 template <int LX, int LY, int LZ, int KZ>
-static void launch_sdf(const Dims &d, const double *chi, const double *c, double h, const float4 *nodes,
-                       uint32_t root, const float4 *tri, uint32_t n_tris, float *phi, int32_t *argmin, int *err,
-                       hipStream_t s) {
+static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes, uint32_t root,
+                       const float4 *tri, uint32_t n_tris, float *phi, int32_t *argmin, int *err, uint32_t *next_tile,
+                       unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
-    k_sdf<LX, LY, LZ, KZ><<<cdiv(tiles, 4), 256, 0, s>>>(chi, c, d, h, nodes, root, tri, n_tris, phi, argmin, err);
+    if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
+    WG_HIP(hipMemsetAsync(next_tile, 0, sizeof(uint32_t), s));
+    k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, root, tri, n_tris, phi, argmin, err, next_tile);
     WG_LAUNCH_CHECK();
 }
 
-void Surface::sdf(const double *chi, const double *c, double h, float *phi, int32_t *argmin, int *err) {
+void Surface::signs(const double *chi, const double *c) {
+    const size_t n = d_.count();
+    k_sign_bits<<<cdiv(n, 256), 256, 0, st_>>>(chi, c, n, sign_);
+    WG_LAUNCH_CHECK();
+}
+
+void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
     const uint32_t root = levels_ > 0 ? level_off_[levels_ - 1] : 0;
-    prof::Scope ps(WG_PROF_SDF, st_, (double)d_.count());
+    prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
-    launch_sdf<4, 4, 4, 4>(d_, chi, c, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, st_);
+    launch_sdf<4, 4, 4, 4>(d_, sign_, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, next_tile_,
+                           sdf_blocks_, s);
 }
 
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,

@@ -52,6 +52,7 @@ class Recon:
         self.generation = 0
         self.n_points = 0
         self.last_stats = None
+        self._pending = None
 
     @staticmethod
     def footprint(n, max_points, lo=(0.0, 0.0, 0.0), h=None):
@@ -106,6 +107,39 @@ class Recon:
         L.check(L.lib().wg_sample_sdf_normals(self._alive(), pq, nq, C.c_void_p(phi.data_ptr()),
                                               C.c_void_p(nrm.data_ptr()) if nrm is not None else None))
         return phi, nrm
+
+    def step(self, xyz, nrm, q, rel_tol=1e-6, max_iters=500, warm_start=True, normals=True):
+        """Pipelined forward + sampling for moving-boundary loops (wg_recon_step):
+        returns (stats, phi [Q], nrm [Q,3] or None) once the surface is extracted;
+        the distance walk and the sampling finish on the handle's second stream
+        while the next step splats and solves.  The outputs are complete after
+        wait() (or a device synchronisation), or once the next step returns."""
+        npts, nq = int(xyz.shape[0]), int(q.shape[0])
+        if nrm.shape[0] != npts:
+            raise ValueError("xyz and nrm differ in length")
+        px, pn = _dev(xyz, torch.float32, 3, "xyz"), _dev(nrm, torch.float32, 3, "nrm")
+        pq = _dev(q, torch.float32, 3, "q")
+        phi = torch.empty(nq, dtype=torch.float32, device=q.device)
+        nout = torch.empty((nq, 3), dtype=torch.float32, device=q.device) if normals else None
+        st = L.WgStats()
+        o = L.make_opts(rel_tol, max_iters, warm_start)
+        rc = L.check(L.lib().wg_recon_step(self._alive(), px, pn, npts, pq, nq, C.c_void_p(phi.data_ptr()),
+                                           C.c_void_p(nout.data_ptr()) if nout is not None else None,
+                                           C.byref(o), C.byref(st)), allow=(L.WG_OK, L.WG_ENOTCONV))
+        if rc == L.WG_ENOTCONV:
+            warnings.warn(f"Poisson solve stopped at rel. residual {st.rel_res:.3e}")
+        # the library writes these on its second stream: keep them (and q) alive
+        # until that work is ordered before any reuse of their memory
+        self._pending = (q, phi, nout)
+        self.generation += 1
+        self.n_points = npts
+        self.last_stats = st.as_dict()
+        return self.last_stats, phi, nout
+
+    def wait(self):
+        """Order the handle's stream after the last step's distance walk and sampling."""
+        L.check(L.lib().wg_recon_wait(self._alive()))
+        self._pending = None
 
     # -- reverse ---------------------------------------------------------------
     def backward(self, q, gphi, gnrm=None, want_gq=False, rel_tol=1e-6, max_iters=500):

@@ -207,3 +207,39 @@ def test_warm_start_reaches_same_field():
     assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10 + 1e-6
     assert st_w["iters"] <= st_c["iters"]
     r.close()
+
+
+def test_pipelined_steps_match_plain():
+    """wg_recon_step (distance walk and sampling overlapping the next step's
+    splat and solve) gives what forward + sample give, step by step, on a
+    moving-boundary sequence; other calls order themselves after it."""
+    from paper_2609_20964_amd.recon import Recon
+    n = 64
+    fl = synth.Flapping(n_points=40000)
+    q = _cuda(synth.uniform_queries(5000, 71))
+    a, b = Recon(n, fl.n_points), Recon(n, fl.n_points)
+    outs = []
+    for t in range(6):
+        x, nrm = (_cuda(v) for v in fl.step(3 * t))
+        st, phi, nq = a.step(x, nrm, q, rel_tol=1e-8, warm_start=t > 0)
+        sb = b.forward(x, nrm, rel_tol=1e-8, warm_start=t > 0)
+        pb, nb = b.sample(q)
+        assert st["status"] == 0 and abs(st["n_tris"] - sb["n_tris"]) <= 2
+        outs.append((phi, nq, pb, nb))
+    a.wait()
+    torch.cuda.synchronize()
+    h = 1.0 / n
+    for phi, nq, pb, nb in outs:
+        assert np.abs(phi.cpu().numpy() - pb.cpu().numpy()).max() <= 1e-4 * h
+        assert np.abs(nq.cpu().numpy() - nb.cpu().numpy()).max() <= 1e-3
+    # a plain call after a pipelined step sees the finished walk
+    x, nrm = (_cuda(v) for v in fl.step(20))
+    a.step(x, nrm, q, rel_tol=1e-8, warm_start=True)
+    b.forward(x, nrm, rel_tol=1e-8, warm_start=True)
+    fa, fb = a.fields(), b.fields()
+    assert np.abs(fa["phi"].cpu().numpy() - fb["phi"].cpu().numpy()).max() <= 1e-4 * h
+    pa, _ = a.sample(q)
+    pb, _ = b.sample(q)
+    assert np.abs(pa.cpu().numpy() - pb.cpu().numpy()).max() <= 1e-4 * h
+    a.close()
+    b.close()
