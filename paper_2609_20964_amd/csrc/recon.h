@@ -23,6 +23,8 @@ class Recon {
     int sample(const float *q, int nq, float *phi, float *nrm, bool pipelined = false);
     // Order the handle stream after everything enqueued on the second stream.
     void join();
+    // distance walk as a persistent kernel (default) or one workgroup per 4 tiles
+    void set_persistent(bool on) { surf_.set_persistent(on); }
     int backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
                  float *gq, const wg_solve_opts &o, wg_stats *st);
     int poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st);

@@ -127,10 +127,6 @@ Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_po
     surf_.bind(arena_, d_, st_);
     WG_HIP(hipHostMalloc((void **)&herr_, 4 * sizeof(int), hipHostMallocDefault));
     WG_HIP(hipHostMalloc((void **)&hscal_, 8 * sizeof(double), hipHostMallocDefault));
-    WG_HIP(hipStreamCreateWithFlags(&sdf_st_, hipStreamNonBlocking));
-    WG_HIP(hipEventCreateWithFlags(&ev_mc_, hipEventDisableTiming));
-    WG_HIP(hipEventCreateWithFlags(&ev_sdf_, hipEventDisableTiming));
-    WG_HIP(hipEventCreateWithFlags(&ev_tail_, hipEventDisableTiming));
     WG_HIP(hipMemsetAsync(chi_, 0, N * sizeof(double), st_));
     WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
     WG_HIP(hipStreamSynchronize(st_));
@@ -235,14 +231,24 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     surf_.signs(chi_, scal_);
     WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
     tm.mark(4);
-    // distance walk on the second stream: it reads neither chi nor anything
-    // the next splat and solve write, so it may overlap them
-    WG_HIP(hipEventRecord(ev_mc_, st_));
-    WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
-    surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_);
-    WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
-    sdf_pending_ = true;
-    if (!pipelined) wait_sdf();
+    if (pipelined) {
+        // distance walk on the second stream (created on first use): it reads
+        // neither chi nor anything the next splat and solve write, so it may
+        // overlap them
+        if (!sdf_st_) {
+            WG_HIP(hipStreamCreateWithFlags(&sdf_st_, hipStreamNonBlocking));
+            WG_HIP(hipEventCreateWithFlags(&ev_mc_, hipEventDisableTiming));
+            WG_HIP(hipEventCreateWithFlags(&ev_sdf_, hipEventDisableTiming));
+            WG_HIP(hipEventCreateWithFlags(&ev_tail_, hipEventDisableTiming));
+        }
+        WG_HIP(hipEventRecord(ev_mc_, st_));
+        WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_);
+        WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
+        sdf_pending_ = true;
+    } else {
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_);
+    }
     tm.mark(5);
     WG_HIP(hipMemcpyAsync(hscal_, scal_, sizeof(double), hipMemcpyDeviceToHost, st_));
     check_err("sdf");
@@ -267,7 +273,7 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
 int Recon::sample(const float *q, int nq, float *phi, float *nrm, bool pipelined) {
     require(have_forward_, WG_ESTATE, "sample before a successful forward");
     require(nq >= 0 && (nq == 0 || (q && phi)), WG_EINVAL, "bad query arguments");
-    if (pipelined) {
+    if (pipelined && sdf_st_) {
         // behind the walk on the second stream; q was ready on the handle stream
         // when the walk's start event was recorded after it
         launch_sample(gf_, phi_, q, nq, phi, nrm, sdf_st_);

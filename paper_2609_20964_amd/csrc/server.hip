@@ -67,6 +67,7 @@ class Server {
         WG_HIP(hipSetDevice(device_));
         WG_HIP(hipStreamCreateWithFlags(&ingest_, hipStreamNonBlocking));
         t0_ = std::chrono::steady_clock::now();
+        n_workers_ = max_inflight;
         for (int k = 0; k < max_inflight; ++k) workers_.emplace_back([this] { worker(); });
     }
 
@@ -183,6 +184,8 @@ class Server {
                 try {
                     WG_HIP(hipStreamCreateWithFlags(&h.s, hipStreamNonBlocking));
                     h.r = new Recon(g, k.cap, h.s);
+                    // concurrent handles: let their walks interleave by workgroup
+                    h.r->set_persistent(n_workers_ == 1);
                 } catch (...) {
                     if (h.s) (void)hipStreamDestroy(h.s);
                     lk.lock();
@@ -273,6 +276,7 @@ class Server {
     std::map<uint64_t, std::unique_ptr<Job>> jobs_;
     std::list<Handle> idle_;
     std::vector<std::thread> workers_;
+    int n_workers_ = 1;
     size_t resident_ = 0;
     uint64_t next_ticket_ = 0, clock_ = 0;
     int running_ = 0;

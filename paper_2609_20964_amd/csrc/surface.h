@@ -42,6 +42,11 @@ class Surface {
     uint32_t n_tris() const { return cnt_.n_tris; }
     // first n triangles as float[9] (vertices in grid units)
     void export_tris(float *out, uint32_t n);
+    // persistent = true (default): the distance walk runs as many workgroups
+    // as fit on the device at once, each taking tiles from a queue (no tail).
+    // false: one workgroup per 4 tiles, so the walks of concurrent handles
+    // interleave workgroup by workgroup.
+    void set_persistent(bool on);
     const float4 *tris() const { return tri_; }
     const int2 *tri_info() const { return info_; }
     size_t bytes() const { return cap_ * (4 * sizeof(float4) + sizeof(int2)) + box_cap_ * 5 * sizeof(float4); }
@@ -58,7 +63,7 @@ class Surface {
     SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
     uint32_t *sign_ = nullptr;     // [ceil(N / 32)] node sides
     uint32_t *next_tile_ = nullptr;   // work counter of the persistent distance walk
-    unsigned sdf_blocks_ = 0;
+    unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
     SurfaceCounts cnt_{};
     // growable
     float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)

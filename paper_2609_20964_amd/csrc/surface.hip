@@ -702,7 +702,8 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     WG_HIP(hipGetDevice(&dev));
     WG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sdf<4, 4, 4, 4>, 256, 0));
-    sdf_blocks_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
+    sdf_blocks_full_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
+    sdf_blocks_ = sdf_blocks_full_;
     WG_HIP(hipHostMalloc((void **)&hcnt_, sizeof(SurfaceCounts), hipHostMallocDefault));
     // a first guess at the triangle capacity: ~4 per cube over a few slices
     size_t face = (size_t)d.nx * d.ny;
@@ -710,6 +711,8 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     if ((size_t)d.nx * d.nz > face) face = (size_t)d.nx * d.nz;
     ensure_capacity((uint32_t)(4 * face), (uint32_t)(face / 4 + 16));
 }
+
+void Surface::set_persistent(bool on) { sdf_blocks_ = on ? sdf_blocks_full_ : ~0u; }
 
 Surface::~Surface() {
     if (tri_) (void)hipFree(tri_);
