@@ -49,7 +49,7 @@ size_t Recon::footprint(const wg_grid &g, int max_points) {
     if ((size_t)g.n[1] * g.n[2] > face) face = (size_t)g.n[1] * g.n[2];
     if ((size_t)g.n[0] * g.n[2] > face) face = (size_t)g.n[0] * g.n[2];
     size_t tris = 4 * face;
-    return a.planned() + (tris + tris / 4 + 64) * (4 * 16 + 8) + (tris / 3) * 5 * 16;
+    return a.planned() + (tris + tris / 4 + 64) * (4 * 16 + 8) + (tris / 3) * 6 * 16;
 }
 
 void Recon::plan(Arena &a, const wg_grid &g, int max_points) {

@@ -4,8 +4,9 @@
 // corners are the cell centres.  Cubes are grouped into 4x4x4 bricks (one
 // wavefront each); bricks, and the cubes inside a brick, are visited in Morton
 // order, so the triangle list is Morton ordered.  Groups of 4 consecutive
-// triangles are the leaves of an 8-ary hierarchy of oriented boxes (thin along
-// the patch normal) built bottom-up over that order.  The signed distance (Eq. 29-34) of every grid node is the exact
+// triangles are the leaves of an 8-ary hierarchy built bottom-up over that
+// order: oriented boxes (thin along the patch normal) at the leaves,
+// axis-aligned boxes above.  The signed distance (Eq. 29-34) of every grid node is the exact
 // minimum over all triangles: one wavefront per 4x4x16 node tile walks the
 // hierarchy together, pruning a box only when it is farther than every lane's
 // current best, so the result equals the brute-force minimum.
@@ -49,7 +50,7 @@ class Surface {
     void set_persistent(bool on);
     const float4 *tris() const { return tri_; }
     const int2 *tri_info() const { return info_; }
-    size_t bytes() const { return cap_ * (4 * sizeof(float4) + sizeof(int2)) + box_cap_ * 5 * sizeof(float4); }
+    size_t bytes() const { return cap_ * (4 * sizeof(float4) + sizeof(int2)) + box_cap_ * 6 * sizeof(float4); }
 
   private:
     void ensure_capacity(uint32_t tris, uint32_t active);
@@ -69,7 +70,7 @@ class Surface {
     float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)
     int2 *info_ = nullptr;         // [cap]
     float4 *box_ = nullptr;        // [box_cap][4] oriented-box nodes of every hierarchy level
-    float4 *nsum_ = nullptr;       // [box_cap] area-weighted normal sums (hierarchy build only)
+    float4 *aabb_ = nullptr;       // [box_cap][2] axis-aligned box of every node (hierarchy build only)
     size_t cap_ = 0, box_cap_ = 0;
     std::vector<uint32_t> level_off_, level_cnt_;
     int levels_ = 0;

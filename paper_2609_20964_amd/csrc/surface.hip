@@ -18,7 +18,11 @@ constexpr int kStack = 64;
 constexpr uint32_t kLeaf = 4;               // triangles per hierarchy leaf
 constexpr int kNode = 4;                    // float4 per hierarchy node
 constexpr int kTri = 4;                     // float4 per triangle record
-constexpr uint32_t kLeafBit = 1u << 31;     // packed child word: leaf flag, count << 27, first index
+// packed node word: (count - 1) << 27 | first index (first triangle of a
+// leaf, absolute index of the first child node otherwise), bit 30 set on an
+// internal node whose children are leaves
+constexpr uint32_t kKidsLeaves = 1u << 30;
+constexpr uint32_t kLeafEntry = 1u << 31;   // traversal stack entry: the node is a leaf
 
 
 __device__ __forceinline__ uint32_t compact3(uint32_t m) {
@@ -157,14 +161,16 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
     }
 }
 
-// Hierarchy nodes are oriented boxes: node = 4 float4,
-//   [0] = (centre, e_u), [1] = (u, e_v), [2] = (v, e_n), [3] = (n, children),
-// "children" being the bits of a word: leaf flag (bit 31), count << 27, first
-// index (first triangle of a leaf, first child node otherwise);
-// with (u, v, n) orthonormal, n along the area-weighted normal of the triangles
-// below the node, e_* the half extents.  Where the normals cancel the axes are
-// the coordinate axes (an axis-aligned box).  Extents carry a small relative
-// margin so the box bound never exceeds the true distance.
+// Hierarchy nodes take kNode float4 each.  A leaf (kLeaf consecutive
+// triangles) is an oriented box:
+//   [0] = (centre, e_u), [1] = (u, e_v), [2] = (v, e_n), [3] = (n, word),
+// with (u, v, n) orthonormal, n along the area-weighted normal of its
+// triangles, e_* the half extents; where the normals cancel the axes are the
+// coordinate axes.  An internal node (up to 8 consecutive children) is an
+// axis-aligned box: [0] = (lo, word), [1] = (hi, 0).  Over curved patches of
+// many triangles the axis-aligned box is the tighter (and cheaper) bound; over
+// a few triangles of one patch the oriented box is.  Extents carry a small
+// relative margin so a bound never exceeds the true distance.
 __device__ __forceinline__ void frame_from_normal(float nx, float ny, float nz, float *u, float *v, float *n) {
     const float L = sqrtf(nx * nx + ny * ny + nz * nz);
     if (!(L > 1e-12f)) {
@@ -182,26 +188,12 @@ __device__ __forceinline__ void frame_from_normal(float nx, float ny, float nz, 
     v[0] = n[1] * u[2] - n[2] * u[1]; v[1] = n[2] * u[0] - n[0] * u[2]; v[2] = n[0] * u[1] - n[1] * u[0];
 }
 
-__device__ __forceinline__ void store_node(float4 *node, const float *u, const float *v, const float *n,
-                                           const float *lo, const float *hi, uint32_t children) {
-    float c[3], e[3];
-    for (int k = 0; k < 3; ++k) {
-        const float m = 0.5f * (lo[k] + hi[k]);
-        e[k] = 0.5f * (hi[k] - lo[k]) + 1e-5f * (1.f + fabsf(m));
-        c[k] = m;
-    }
-    const float cx = c[0] * u[0] + c[1] * v[0] + c[2] * n[0];
-    const float cy = c[0] * u[1] + c[1] * v[1] + c[2] * n[1];
-    const float cz = c[0] * u[2] + c[1] * v[2] + c[2] * n[2];
-    node[0] = make_float4(cx, cy, cz, e[0]);
-    node[1] = make_float4(u[0], u[1], u[2], e[1]);
-    node[2] = make_float4(v[0], v[1], v[2], e[2]);
-    node[3] = make_float4(n[0], n[1], n[2], __uint_as_float(children));
-}
+__device__ __forceinline__ float box_margin(float m) { return 1e-5f * (1.f + fabsf(m)); }
 
-// Leaves: one thread per group of kLeaf consecutive triangles.
+// Leaves: one thread per group of kLeaf consecutive triangles.  Also writes
+// the leaf's axis-aligned box to aabb[2 g], aabb[2 g + 1] for the parents.
 __global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ tri, uint32_t n_tris,
-                                                     float4 *__restrict__ nodes, float4 *__restrict__ nsum,
+                                                     float4 *__restrict__ nodes, float4 *__restrict__ aabb,
                                                      uint32_t n_leaves) {
     uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_leaves) return;
@@ -216,6 +208,7 @@ __global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ t
     float u[3], v[3], n[3];
     frame_from_normal(ns[0], ns[1], ns[2], u, v, n);
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float alo[3] = {INFINITY, INFINITY, INFINITY}, ahi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t t = t0; t < t1; ++t) {
         const float4 A = tri[kTri * (size_t)t], B = tri[kTri * (size_t)t + 1], C = tri[kTri * (size_t)t + 2];
         const float P[3][3] = {{A.x, A.y, A.z}, {A.x + B.x, A.y + B.y, A.z + B.z}, {A.x + C.x, A.y + C.y, A.z + C.z}};
@@ -226,57 +219,53 @@ __global__ __launch_bounds__(256) void k_leaf_nodes(const float4 *__restrict__ t
             lo[0] = fminf(lo[0], pu); hi[0] = fmaxf(hi[0], pu);
             lo[1] = fminf(lo[1], pv); hi[1] = fmaxf(hi[1], pv);
             lo[2] = fminf(lo[2], pn); hi[2] = fmaxf(hi[2], pn);
+            for (int k = 0; k < 3; ++k) {
+                alo[k] = fminf(alo[k], P[q][k]);
+                ahi[k] = fmaxf(ahi[k], P[q][k]);
+            }
         }
     }
-    store_node(nodes + (size_t)kNode * g, u, v, n, lo, hi, kLeafBit | ((t1 - t0) << 27) | t0);
-    nsum[g] = make_float4(ns[0], ns[1], ns[2], 0.f);
+    float c[3], e[3];
+    for (int k = 0; k < 3; ++k) {
+        const float m = 0.5f * (lo[k] + hi[k]);
+        e[k] = 0.5f * (hi[k] - lo[k]) + box_margin(m);
+        c[k] = m;
+    }
+    float4 *nd = nodes + (size_t)kNode * g;
+    nd[0] = make_float4(c[0] * u[0] + c[1] * v[0] + c[2] * n[0], c[0] * u[1] + c[1] * v[1] + c[2] * n[1],
+                        c[0] * u[2] + c[1] * v[2] + c[2] * n[2], e[0]);
+    nd[1] = make_float4(u[0], u[1], u[2], e[1]);
+    nd[2] = make_float4(v[0], v[1], v[2], e[2]);
+    nd[3] = make_float4(n[0], n[1], n[2], __uint_as_float(((t1 - t0 - 1) << 27) | t0));
+    for (int k = 0; k < 3; ++k) {
+        alo[k] -= box_margin(alo[k]);
+        ahi[k] += box_margin(ahi[k]);
+    }
+    aabb[2 * (size_t)g] = make_float4(alo[0], alo[1], alo[2], 0.f);
+    aabb[2 * (size_t)g + 1] = make_float4(ahi[0], ahi[1], ahi[2], 0.f);
 }
 
-// Parents: one wavefront per parent; lane l takes corner (l & 7) of child (l >> 3).
-// child_first: absolute index of the child level's first node.
-__global__ __launch_bounds__(256) void k_parent_nodes(const float4 *__restrict__ child,
-                                                       const float4 *__restrict__ child_nsum, uint32_t nchild,
-                                                       uint32_t child_first, float4 *__restrict__ parent,
-                                                       float4 *__restrict__ parent_nsum, uint32_t nparent) {
-    const int lane = threadIdx.x % 64;
-    const uint32_t j = blockIdx.x * 4 + threadIdx.x / 64;
-    if (j >= nparent) return;   // whole wavefront
-    const uint32_t ci = 8 * j + (lane >> 3);
-    const bool has = ci < nchild;
-    float4 c0 = make_float4(0, 0, 0, 0), c1 = c0, c2 = c0, c3 = c0, c4 = c0;
-    if (has) {
-        const float4 *nd = child + (size_t)kNode * ci;
-        c0 = nd[0]; c1 = nd[1]; c2 = nd[2]; c3 = nd[3]; c4 = child_nsum[ci];
+// Parents: one thread per parent; its box is the union of its (up to 8)
+// children's axis-aligned boxes.  child_first: absolute index of the child
+// level's first node; aabb holds every level's boxes at absolute indices.
+__global__ __launch_bounds__(256) void k_parent_nodes(float4 *__restrict__ nodes, float4 *__restrict__ aabb,
+                                                       uint32_t child_first, uint32_t nchild, uint32_t parent_first,
+                                                       uint32_t nparent, uint32_t kids_leaves) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nparent) return;
+    const uint32_t c0 = child_first + 8 * j, cnt = min(8u, nchild - 8 * j);
+    float4 lo = aabb[2 * (size_t)c0], hi = aabb[2 * (size_t)c0 + 1];
+    for (uint32_t q = 1; q < cnt; ++q) {
+        const float4 a = aabb[2 * (size_t)(c0 + q)], b = aabb[2 * (size_t)(c0 + q) + 1];
+        lo.x = fminf(lo.x, a.x); lo.y = fminf(lo.y, a.y); lo.z = fminf(lo.z, a.z);
+        hi.x = fmaxf(hi.x, b.x); hi.y = fmaxf(hi.y, b.y); hi.z = fmaxf(hi.z, b.z);
     }
-    // normal sum of the children (each child counted once: corner 0 lanes)
-    float ns[3] = {(has && (lane & 7) == 0) ? c4.x : 0.f, (has && (lane & 7) == 0) ? c4.y : 0.f,
-                   (has && (lane & 7) == 0) ? c4.z : 0.f};
-    for (int o = 32; o > 0; o >>= 1)
-        for (int k = 0; k < 3; ++k) ns[k] += __shfl_xor(ns[k], o, 64);
-    float u[3], v[3], n[3];
-    frame_from_normal(ns[0], ns[1], ns[2], u, v, n);
-    // this lane's corner of its child box
-    const float su = (lane & 1) ? 1.f : -1.f, sv = (lane & 2) ? 1.f : -1.f, sn = (lane & 4) ? 1.f : -1.f;
-    const float px = c0.x + su * c0.w * c1.x + sv * c1.w * c2.x + sn * c2.w * c3.x;
-    const float py = c0.y + su * c0.w * c1.y + sv * c1.w * c2.y + sn * c2.w * c3.y;
-    const float pz = c0.z + su * c0.w * c1.z + sv * c1.w * c2.z + sn * c2.w * c3.z;
-    float lo[3], hi[3];
-    const float pr[3] = {px * u[0] + py * u[1] + pz * u[2], px * v[0] + py * v[1] + pz * v[2],
-                         px * n[0] + py * n[1] + pz * n[2]};
-    for (int k = 0; k < 3; ++k) {
-        lo[k] = has ? pr[k] : INFINITY;
-        hi[k] = has ? pr[k] : -INFINITY;
-    }
-    for (int o = 32; o > 0; o >>= 1)
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
-            hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o, 64));
-        }
-    if (lane == 0) {
-        const uint32_t cnt = min(8u, nchild - 8 * j);
-        store_node(parent + (size_t)kNode * j, u, v, n, lo, hi, (cnt << 27) | (child_first + 8 * j));
-        parent_nsum[j] = make_float4(ns[0], ns[1], ns[2], 0.f);
-    }
+    const uint32_t p = parent_first + j;
+    aabb[2 * (size_t)p] = lo;
+    aabb[2 * (size_t)p + 1] = hi;
+    float4 *nd = nodes + (size_t)kNode * p;
+    nd[0] = make_float4(lo.x, lo.y, lo.z, __uint_as_float(kids_leaves | ((cnt - 1) << 27) | c0));
+    nd[1] = make_float4(hi.x, hi.y, hi.z, 0.f);
 }
 
 // Mesh export: vertices a, a + ab, a + ac as float[9] per triangle.
@@ -333,6 +322,46 @@ __device__ __forceinline__ void cx_desc(uint32_t &a, uint32_t &b) {
     b = lo;
 }
 
+// Squared distance bounds of a box for a lane's kTZ nodes (same x, y; z in
+// pz): `need` is set if any of them is below that node's best; returns the
+// bound of the first node.  Oriented box record (N0..N3) and axis-aligned
+// box record (lo in A0, hi in A1).
+template <int kTZ>
+__device__ __forceinline__ float obb_bound(float4 N0, float4 N1, float4 N2, float4 N3, float px, float py,
+                                           const float (&pz)[kTZ], const float (&best)[kTZ], bool &need) {
+    const float rx = px - N0.x, ry = py - N0.y;
+    const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
+                bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
+    float d0 = 0.f;
+#pragma unroll
+    for (int k = 0; k < kTZ; ++k) {
+        const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
+        const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
+        const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
+        const float dd = du * du + dv * dv + dn * dn;
+        need |= dd < best[k];
+        if (k == 0) d0 = dd;
+    }
+    return d0;
+}
+
+template <int kTZ>
+__device__ __forceinline__ float aabb_bound(float4 A0, float4 A1, float px, float py, const float (&pz)[kTZ],
+                                            const float (&best)[kTZ], bool &need) {
+    const float dx = fmaxf(fmaxf(A0.x - px, px - A1.x), 0.f);
+    const float dy = fmaxf(fmaxf(A0.y - py, py - A1.y), 0.f);
+    const float dxy = dx * dx + dy * dy;
+    float d0 = 0.f;
+#pragma unroll
+    for (int k = 0; k < kTZ; ++k) {
+        const float dz = fmaxf(fmaxf(A0.z - pz[k], pz[k] - A1.z), 0.f);
+        const float dd = dz * dz + dxy;
+        need |= dd < best[k];
+        if (k == 0) d0 = dd;
+    }
+    return d0;
+}
+
 // Side of every node: bit (o & 31) of word o >> 5 is set where chi >= c
 // (outside, Eq. 31: the mesh separates exactly the nodes with chi >= c from
 // the others).  One node per lane; a wavefront writes two words.
@@ -386,27 +415,16 @@ __global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, 
             stk[w][0] = root;
             while (sp > 0) {
                 --sp;
-                const uint32_t ni = __builtin_amdgcn_readfirstlane(stk[w][sp]);
-                const float4 *nd = nodes + (size_t)kNode * ni;
-                const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
-                // bound of this node for the lane's kTZ nodes (they differ only in z)
-                bool need = false;
-                {
-                    const float rx = px - N0.x, ry = py - N0.y;
-                    const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
-                                bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
-#pragma unroll
-                    for (int k = 0; k < kTZ; ++k) {
-                        const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
-                        const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
-                        const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
-                        need |= du * du + dv * dv + dn * dn < best[k];
-                    }
-                }
-                if (__ballot(need) == 0) continue;
-                const uint32_t word = __float_as_uint(N3.w);
-                const uint32_t first = word & 0x07ffffffu, cnt = (word >> 27) & 15u;
-                if (word & kLeafBit) {
+                const uint32_t ent = __builtin_amdgcn_readfirstlane(stk[w][sp]);
+                const float4 *nd = nodes + (size_t)kNode * (ent & ~kLeafEntry);
+                if (ent & kLeafEntry) {
+                    // leaf: recheck its oriented box against the current bests, then its triangles
+                    const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
+                    bool need = false;
+                    obb_bound<kTZ>(N0, N1, N2, N3, px, py, pz, best, need);
+                    if (__ballot(need) == 0) continue;
+                    const uint32_t word = __float_as_uint(N3.w);
+                    const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
                     for (uint32_t t = first; t < first + cnt; ++t) {
                         const float4 *tr = tri + kTri * (size_t)t;
                         const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
@@ -420,51 +438,64 @@ __global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, 
                             }
                         }
                     }
-                } else {
-                    // sort key of a child: bit 31 = to be visited, then the bound of
-                    // lane 0's first node (a non-negative float, so its bits order
-                    // like integers) with the child's index in the low 3 bits
-                    uint32_t key[8];
+                    continue;
+                }
+                // internal node: recheck its axis-aligned box, then order its children
+                const float4 A0 = nd[0], A1 = nd[1];
+                {
+                    bool need = false;
+                    aabb_bound<kTZ>(A0, A1, px, py, pz, best, need);
+                    if (__ballot(need) == 0) continue;
+                }
+                const uint32_t word = __float_as_uint(A0.w);
+                const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
+                const bool kids_leaves = (word & kKidsLeaves) != 0;
+                // sort key of a child: bit 31 = to be visited, then the bound of
+                // lane 0's first node (a non-negative float, so its bits order
+                // like integers) with the child's index in the low 3 bits
+                uint32_t key[8];
+                if (kids_leaves) {
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         // always a valid node (clamped), so all eight loads can be issued together
                         const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
                         const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
-                        const float rx = px - C0.x, ry = py - C0.y;
-                        const float bu = C1.x * rx + C1.y * ry - C1.z * C0.z, bv = C2.x * rx + C2.y * ry - C2.z * C0.z,
-                                    bn = C3.x * rx + C3.y * ry - C3.z * C0.z;
                         bool vis = false;
-                        float d0 = 0.f;
-#pragma unroll
-                        for (int k = 0; k < kTZ; ++k) {
-                            const float du = fmaxf(fabsf(bu + C1.z * pz[k]) - C0.w, 0.f);
-                            const float dv = fmaxf(fabsf(bv + C2.z * pz[k]) - C1.w, 0.f);
-                            const float dn = fmaxf(fabsf(bn + C3.z * pz[k]) - C2.w, 0.f);
-                            const float dd = du * du + dv * dv + dn * dn;
-                            vis |= dd < best[k];
-                            if (k == 0) d0 = dd;
-                        }
+                        const float d0 = obb_bound<kTZ>(C0, C1, C2, C3, px, py, pz, best, vis);
                         const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
-                        key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q) : 0u;
+                        key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q)
+                                                                             : 0u;
                     }
-                    if (sp + 8 > kStack) {
-                        atomicOr(err, 2);
-                        continue;
-                    }
-                    // 19-comparator sorting network, descending: the farthest child is
-                    // pushed first so the nearest is popped next
-                    cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
-                    cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
-                    cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
-                    cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
-                    cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
-                    cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
+                } else {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) {
-                        if (key[r] == 0u) break;
-                        stk[w][sp] = first + (key[r] & 7u);
-                        ++sp;
+                    for (int q = 0; q < 8; ++q) {
+                        const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
+                        const float4 C0 = cd[0], C1 = cd[1];
+                        bool vis = false;
+                        const float d0 = aabb_bound<kTZ>(C0, C1, px, py, pz, best, vis);
+                        const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
+                        key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q)
+                                                                             : 0u;
                     }
+                }
+                if (sp + 8 > kStack) {
+                    atomicOr(err, 2);
+                    continue;
+                }
+                // 19-comparator sorting network, descending: the farthest child is
+                // pushed first so the nearest is popped next
+                cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
+                cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
+                cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
+                cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
+                cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
+                cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
+                const uint32_t flag = kids_leaves ? kLeafEntry : 0u;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    if (key[r] == 0u) break;
+                    stk[w][sp] = (first + (key[r] & 7u)) | flag;
+                    ++sp;
                 }
             }
         }
@@ -697,12 +728,16 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     dcnt_ = a.take<SurfaceCounts>(1);
     sign_ = a.take<uint32_t>(cdiv(d.count(), 32));
     next_tile_ = a.take<uint32_t>(1);
-    // the persistent walk launches as many workgroups as can be resident at once
+    // the persistent walk stays one workgroup per compute unit below full
+    // residency: its workgroups only retire when the tile queue is empty, and
+    // work on the handle's other stream (the next step's splat and solve, host
+    // copies) needs free slots meanwhile
     int dev = 0, cus = 0, per_cu = 0;
     WG_HIP(hipGetDevice(&dev));
     WG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sdf<4, 4, 4, 4>, 256, 0));
-    sdf_blocks_full_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)(per_cu > 0 ? per_cu : 1);
+    per_cu = per_cu > 1 ? per_cu - 1 : 1;
+    sdf_blocks_full_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)per_cu;
     sdf_blocks_ = sdf_blocks_full_;
     WG_HIP(hipHostMalloc((void **)&hcnt_, sizeof(SurfaceCounts), hipHostMallocDefault));
     // a first guess at the triangle capacity: ~4 per cube over a few slices
@@ -718,7 +753,7 @@ Surface::~Surface() {
     if (tri_) (void)hipFree(tri_);
     if (info_) (void)hipFree(info_);
     if (box_) (void)hipFree(box_);
-    if (nsum_) (void)hipFree(nsum_);
+    if (aabb_) (void)hipFree(aabb_);
     if (hcnt_) (void)hipHostFree(hcnt_);
 }
 
@@ -742,9 +777,9 @@ void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
         box_ = nullptr;
         size_t c = need + need / 4 + 64;
         WG_HIP(hipMalloc(&box_, c * kNode * sizeof(float4)));
-        if (nsum_) WG_HIP(hipFree(nsum_));
-        nsum_ = nullptr;
-        WG_HIP(hipMalloc(&nsum_, c * sizeof(float4)));
+        if (aabb_) WG_HIP(hipFree(aabb_));
+        aabb_ = nullptr;
+        WG_HIP(hipMalloc(&aabb_, c * 2 * sizeof(float4)));
         box_cap_ = c;
     }
 }
@@ -771,15 +806,15 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     k_mc_emit<<<cdiv(cnt_.n_active, 4), 256, 0, st_>>>(chi, c, d_, nb, active_, cnt_.n_active, off_b_, tri_, info_);
     WG_LAUNCH_CHECK();
     uint32_t n = cdiv(cnt_.n_tris, kLeaf), off = 0;
-    k_leaf_nodes<<<cdiv(n, 256), 256, 0, st_>>>(tri_, cnt_.n_tris, box_, nsum_, n);
+    k_leaf_nodes<<<cdiv(n, 256), 256, 0, st_>>>(tri_, cnt_.n_tris, box_, aabb_, n);
     WG_LAUNCH_CHECK();
     level_off_.push_back(0);
     level_cnt_.push_back(n);
     while (n > 1) {
-        uint32_t m = (n + 7) / 8;
-        uint32_t noff = off + n;
-        k_parent_nodes<<<cdiv(m, 4), 256, 0, st_>>>(box_ + (size_t)kNode * off, nsum_ + off, n, off,
-                                                     box_ + (size_t)kNode * noff, nsum_ + noff, m);
+        const uint32_t m = (n + 7) / 8;
+        const uint32_t noff = off + n;
+        k_parent_nodes<<<cdiv(m, 256), 256, 0, st_>>>(box_, aabb_, off, n, noff, m,
+                                                       level_off_.size() == 1 ? kKidsLeaves : 0u);
         WG_LAUNCH_CHECK();
         off = noff;
         n = m;
@@ -809,7 +844,8 @@ void Surface::signs(const double *chi, const double *c) {
 }
 
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
-    const uint32_t root = levels_ > 0 ? level_off_[levels_ - 1] : 0;
+    // a one-level hierarchy is a single leaf
+    const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
     prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<4, 4, 4, 4>(d_, sign_, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, next_tile_,
