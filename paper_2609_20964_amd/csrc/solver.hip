@@ -1095,7 +1095,8 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
             break;
         }
         double inner = 0.5 * tol / res.rel_res;
-        if (inner < 1e-4) inner = 1e-4;
+        // FP32 vectors reach about 1e-7 relative: aim no lower than 1e-6 per inner solve
+        if (inner < 1e-6) inner = 1e-6;
         if (inner > 0.5) inner = 0.5;
         int budget = max_iters - res.iters;
         if (budget > 60) budget = 60;
