@@ -393,7 +393,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs one reconstruction per device and has no "
-              "multi-GPU path (sharding is described in DESIGN.md); run it with --gpus 1.", file=sys.stderr)
+              "multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     res = gpu_run(args)

@@ -1,6 +1,6 @@
 """GPU parity of the forward path (through the C ABI) against the FP64 oracle.
 
-Tolerances (written here, derived in the design doc): Poisson field 1e-5 relative
+Tolerances: Poisson field 1e-5 relative
 (both zero-mean, GPU solved to rel. residual 1e-10); SDF 1e-4 h absolute;
 point-to-cell keys bit-exact; right-hand side 1e-5 relative (FP32 atomics).
 """
