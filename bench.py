@@ -21,7 +21,9 @@ Also reported on the same JSON line:
   oracle_error  GPU vs oracle on the last timed step;
   adjoint       the reverse pass (adjoint solve included) at the same size;
   serving       a replayed Poisson-arrival request stream, continuous batching
-                vs one request at a time.
+                vs one request at a time;
+  secondary     the 128^3 torus (1e6 queries) and the 16-coefficient gradient
+                (forward + backward against 32 finite-difference forwards).
 """
 from __future__ import annotations
 
@@ -250,6 +252,76 @@ def cpu_baseline(res, n, sample_nodes):
     return base, err
 
 
+def secondary_run():
+    """The two 128^3 workloads: the noisy torus (200,000 points, 1,000,000
+    queries, rel. res 1e-6, cold solve) and the differentiable superellipsoid
+    (100,000 points, 65,536 targets): forward + backward against the 32
+    forward evaluations a central finite-difference gradient in 16
+    coefficients needs."""
+    import torch
+
+    from paper_2609_20964_amd import synth
+    from paper_2609_20964_amd.recon import Recon
+
+    out = {}
+    x, nrm = synth.torus(200_000)
+    q = torch.from_numpy(synth.uniform_queries(1_000_000, 204)).cuda()
+    xd, nd = torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda()
+    r = Recon(128, len(x))
+    r.forward(xd, nd, rel_tol=1e-6)
+    r.sample(q)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.forward(xd, nd, rel_tol=1e-6)
+        r.sample(q)
+    torch.cuda.synchronize()
+    t_rec = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.sample(q)
+    torch.cuda.synchronize()
+    t_q = (time.perf_counter() - t0) / reps
+    r.close()
+    out["torus_128"] = {"recons_per_s": 1.0 / t_rec, "ms_per_recon": t_rec * 1e3,
+                        "queries_per_s": q.shape[0] / t_q, "workload": "torus R 0.3 r 0.1, 200000 noisy points, "
+                        "128^3, cold solve to rel res 1e-6, SDF and normals at 1e6 queries"}
+
+    case = synth.diff_case()
+    xs, ns = synth.star(case.shape.coeffs, 100_000, 302)
+    xd, nd = torch.from_numpy(xs).cuda(), torch.from_numpy(ns).cuda()
+    tq = torch.from_numpy(case.targets).cuda()
+    T = tq.shape[0]
+    r = Recon(128, len(xs))
+
+    def fwd():
+        r.forward(xd, nd, rel_tol=1e-6)
+        phi, _ = r.sample(tq, normals=False)
+        return phi
+
+    phi = fwd()
+    r.backward(tq, (2.0 / T) * phi, rel_tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        phi = fwd()
+        r.backward(tq, (2.0 / T) * phi, rel_tol=1e-6)
+    torch.cuda.synchronize()
+    t_ad = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(32):
+        fwd()
+    torch.cuda.synchronize()
+    t_fd = time.perf_counter() - t0
+    r.close()
+    out["superellipsoid_128_gradient"] = {"forward_backward_ms": t_ad * 1e3, "fd_32_forwards_ms": t_fd * 1e3,
+                                          "fd_over_adjoint": t_fd / t_ad,
+                                          "workload": "16-coefficient superellipsoid, 100000 points, 128^3, "
+                                          "loss mean phi^2 at 65536 targets, rel res 1e-6"}
+    return out
+
+
 def serving_run(n_requests, max_inflight, budget_gb):
     """The request stream replayed twice: at its own Poisson arrival times
     (latency at the offered load) and with every request arriving at once
@@ -380,6 +452,7 @@ def main():
     ap.add_argument("--serving", type=int, default=40, help="requests in the serving replay (0: skip)")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", metavar="CSV",
@@ -435,6 +508,8 @@ def main():
         line["oracle_error"] = err
     if args.serving > 0:
         line["serving"] = serving_run(args.serving, 4, 64.0)
+    if not args.no_secondary:
+        line["secondary"] = secondary_run()
     print(json.dumps(line), flush=True)
 
 
