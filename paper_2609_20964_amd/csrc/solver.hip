@@ -18,7 +18,7 @@ namespace {
 constexpr int TX = 64, TY = 4, ZC = 16;
 constexpr int kRedBlocks = 2048;     // grid of the pointwise reductions
 constexpr int kMaxRed = 5;
-constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi smoothing factor
+constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi factor of the sweeps on an odd-sized coarsest level
 constexpr int kCoarseTarget = 16;       // coarsen until every extent is <= this (or odd)
 constexpr int kCoarseAxis = 16;         // exact coarsest solve when every extent is <= this
 
@@ -259,28 +259,36 @@ struct OpSmoothFirst {
     }
 };
 
-// The two pre-smoothing sweeps of the V-cycle from a zero guess, in one pass
-// over rhs: x1 = wd rhs (a sweep with the constant diagonal 1/wd = 6/w), then
-// x2 = x1 + w (rhs - A x1) / diag.  A x1 is a 7-point stencil on rhs, so only
-// rhs is read.  The last post-smoothing sweep uses the same constant diagonal
-// (OpSmoothC), which keeps the V-cycle symmetric; 2 (6 / w) I - A stays
-// positive definite (the 7-point rows sum to at most 12 < 14), so both sweeps
-// are A-norm contractions for either boundary condition.
+// Smoothing: a degree-2 Chebyshev polynomial in A/6 on [kChebLo, 2] (the
+// spectrum of A/6 lies in [0, 2]: the rows of A sum to at most 12), applied as
+// two Richardson sweeps x <- x + w_k (rhs - A x) with w_k = 1 / (6 lambda_k),
+// lambda_k the polynomial's roots.  The factor |s(lambda)| stays below 1 on
+// (0, 2] and below 1/T_2((2 + lo) / (2 - lo)) on [lo, 2]; both sweeps are
+// polynomials in the same matrix, so pre- and post-smoothing commute and the
+// V-cycle is a symmetric preconditioner.  From a zero guess the first sweep is
+// pointwise, x1 = wa rhs, so the two pre-smoothing sweeps are one pass over
+// rhs: x2 = x1 + wb (rhs - A x1), a 7-point stencil of rhs.
+constexpr double kChebLo = 0.25;
+constexpr double kChebL1 = (2.0 + kChebLo) / 2 - (2.0 - kChebLo) / 2 * 0.70710678118654752;
+constexpr double kChebL2 = (2.0 + kChebLo) / 2 + (2.0 - kChebLo) / 2 * 0.70710678118654752;
+constexpr float kChebWa = (float)(1.0 / (6.0 * kChebL1));
+constexpr float kChebWb = (float)(1.0 / (6.0 * kChebL2));
+
 struct OpSmooth2 {
     using T = float;
     static constexpr int NRED = 0;
     const float *rhs;
     float *out;
-    float w, wd;
+    float wa, wb;
     __device__ float load(size_t i) const { return rhs[i]; }
     __device__ float load1(size_t i) const { return rhs[i]; }
     __device__ V4<float> load4(size_t i) const { return ld4(rhs + i); }
     __device__ void apply(size_t i, float c, float s, float diag, double *) const {
-        out[i] = wd * c + w * (c - wd * (diag * c - s)) / diag;
+        out[i] = wa * c + wb * (c - wa * (diag * c - s));
     }
     __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
         V4<float> o;
-        for (int q = 0; q < 4; ++q) o.v[q] = wd * c.v[q] + w * (c.v[q] - wd * (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
+        for (int q = 0; q < 4; ++q) o.v[q] = wa * c.v[q] + wb * (c.v[q] - wa * (dg.v[q] * c.v[q] - s.v[q]));
         st4(out + i, o);
     }
 };
@@ -313,7 +321,7 @@ struct OpSmooth {
     }
 };
 
-// Last post-smoothing sweep, constant diagonal: x_out = x + wd (rhs - A x);
+// Post-smoothing sweep with the constant diagonal: x_out = x + wd (rhs - A x);
 // DOT adds rhs . x_out.
 template <bool DOT>
 struct OpSmoothC {
@@ -965,7 +973,7 @@ void Solver::vcycle(int l) {
     Level &C = lv_[l + 1];
     C.d.bc_sign = bc_sign_;
     const int ks = l == 0 ? WG_PROF_SMOOTH : -1, kt = l == 0 ? WG_PROF_TRANSFER : -1;
-    launch_stencil(OpSmooth2{L.rhs, L.x, kOmega, kOmega / 6.f}, L.d, nullptr, st_, ks, 8.0);
+    launch_stencil(OpSmooth2{L.rhs, L.x, kChebWa, kChebWb}, L.d, nullptr, st_, ks, 8.0);
     launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_, ks, 12.0);
     {
         prof::Scope ps(kt, st_, 4.0 * (double)(L.d.count() + C.d.count()));
@@ -990,11 +998,11 @@ void Solver::vcycle(int l) {
         }
         WG_LAUNCH_CHECK();
     }
-    launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_, ks, 12.0);
+    launch_stencil(OpSmoothC<false>{L.x, L.rhs, L.x2, kChebWb}, L.d, nullptr, st_, ks, 12.0);
     if (l == 0) {
-        launch_stencil(OpSmoothC<true>{L.x2, L.rhs, L.x, kOmega / 6.f}, L.d, partials_, st_, ks, 12.0);   // + r.z
+        launch_stencil(OpSmoothC<true>{L.x2, L.rhs, L.x, kChebWa}, L.d, partials_, st_, ks, 12.0);   // + r.z
     } else {
-        launch_stencil(OpSmoothC<false>{L.x2, L.rhs, L.x, kOmega / 6.f}, L.d, nullptr, st_);
+        launch_stencil(OpSmoothC<false>{L.x2, L.rhs, L.x, kChebWa}, L.d, nullptr, st_);
     }
 }
 
