@@ -243,3 +243,38 @@ def test_pipelined_steps_match_plain():
     assert np.abs(pa.cpu().numpy() - pb.cpu().numpy()).max() <= 1e-4 * h
     a.close()
     b.close()
+
+
+def test_degenerate_clouds_on_faces_coincident_zero_normals():
+    """Points exactly on cell faces and on the grid's lower faces, many
+    coincident points, zero normals: keys bit-exact, b, the field and every
+    node's SDF against the oracle."""
+    n = 32
+    g = D.Grid.unit(n)
+    rng = np.random.default_rng(61)
+    x, nrm = synth.sphere(2000, seed=62)
+    x = x.astype(np.float64)
+    # 300 points moved onto cell faces (k / n exactly, representable in FP32), some on x = 0
+    idx = rng.choice(len(x), 300, replace=False)
+    ax = rng.integers(0, 3, 300)
+    x[idx, ax] = np.round(x[idx, ax] * n) / n
+    x[idx[:20], 0] = 0.0
+    # 200 copies of one point with different normals, and 100 zero normals
+    x[-200:] = x[0]
+    nrm = nrm.astype(np.float64)
+    nrm[-200:] = synth.unit_sphere_dirs(np.random.default_rng(63), 200)
+    nrm[1000:1100] = 0.0
+    x, nrm = x.astype(np.float32), nrm.astype(np.float32)
+    q = synth.uniform_queries(3000, 64)
+    _forward_parity(g, x, nrm, q)
+
+
+def test_two_million_points_128():
+    """The largest point count of the serving stream (2,000,000) on a 128^3 grid:
+    the field in full, sampled nodes and queries against the oracle."""
+    g = D.Grid.unit(128)
+    x, nrm = synth.sphere(2_000_000, radius=0.3, seed=65)
+    q = synth.uniform_queries(2000, 66)
+    rng = np.random.default_rng(67)
+    nodes = rng.choice(128 ** 3, 2000, replace=False)
+    _forward_parity(g, x, nrm, q, full_phi=False, node_sample=nodes)
