@@ -28,8 +28,9 @@ hipEvent_t take_event() {
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (no cache writeback at the marker)
     hipEvent_t e;
-    WG_HIP(hipEventCreate(&e));
+    WG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
 }
 

@@ -26,7 +26,8 @@ struct Timer {
     hipEvent_t ev[9];
     hipStream_t s;
     explicit Timer(hipStream_t st) : s(st) {
-        for (auto &e : ev) WG_HIP(hipEventCreate(&e));
+        // timing only: no system-scope fence (no cache writeback at the marker)
+        for (auto &e : ev) WG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     ~Timer() {
         for (auto &e : ev) (void)hipEventDestroy(e);
