@@ -102,3 +102,53 @@ def test_differentiable_case_16_coefficients_128():
     print("dL/dc gpu", grad_gpu.numpy(), "\noracle", grad_ref.numpy(), flush=True)
     assert _close(grad_gpu.numpy(), grad_ref.numpy())
     r.close()
+
+
+def test_adjoint_against_central_differences_on_the_gpu():
+    """Directional derivatives of L = mean phi(q)^2 from the GPU adjoint
+    against central finite differences of GPU forwards (no oracle): along
+    random normal perturbations (b is linear in the normals), and along random
+    position perturbations that keep every point in its central cell (the
+    splat weights are smooth inside a cell)."""
+    from paper_2609_20964_amd.recon import Recon
+    n = 64
+    g = D.Grid.unit(n)
+    c = synth.draw_star_coeffs(81)
+    x, nrm = synth.star(c, 20000, 82)
+    q = synth.star(c + 0.01, 2000, 83)[0]
+    rng = np.random.default_rng(84)
+    r = Recon(n, len(x))
+
+    def loss(xx, nn):
+        r.forward(_cuda(xx), _cuda(nn), rel_tol=1e-11, max_iters=5000)
+        phi, _ = r.sample(_cuda(q), normals=False)
+        return float((phi.double() ** 2).mean())
+
+    loss(x, nrm)
+    phi, _ = r.sample(_cuda(q), normals=False)
+    gx, gn, _ = r.backward(_cuda(q), (2.0 / len(q)) * phi, rel_tol=1e-11, max_iters=5000)
+    gx, gn = gx.cpu().double().numpy(), gn.cpu().double().numpy()
+    # normals
+    dn = rng.standard_normal(nrm.shape)
+    eps = 1e-3
+    fd = (loss(x, nrm + eps * dn) - loss(x, nrm - eps * dn)) / (2 * eps)
+    ad = float((gn * dn).sum())
+    print(f"normals: adjoint {ad:.6e} fd {fd:.6e}", flush=True)
+    assert abs(ad - fd) <= 1e-2 * abs(fd)
+    # positions, restricted to points that stay in their cells at +-eps
+    dx = rng.standard_normal(x.shape)
+    eps = 2e-2 * g.h
+    k0 = D.cell_keys(g, x)[0]
+    stay = np.ones(len(x), bool)
+    for s in (1, -1):
+        xs = (x.astype(np.float64) + s * eps * dx).astype(np.float32)
+        stay &= (D.cell_keys(g, xs)[0] == k0).all(1)
+    dx[~stay] = 0.0
+    xp = (x.astype(np.float64) + eps * dx).astype(np.float32)
+    xm = (x.astype(np.float64) - eps * dx).astype(np.float32)
+    step = (xp.astype(np.float64) - xm.astype(np.float64)) / 2   # the perturbation FP32 actually applies
+    fd = (loss(xp, nrm) - loss(xm, nrm)) / 1.0
+    ad = float((gx * (2 * step)).sum())
+    print(f"positions ({stay.mean():.3f} of points moved): adjoint {ad:.6e} fd {fd:.6e}", flush=True)
+    assert abs(ad - fd) <= 2e-2 * abs(fd)
+    r.close()
