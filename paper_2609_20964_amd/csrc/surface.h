@@ -70,7 +70,7 @@ class Surface {
     float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)
     int2 *info_ = nullptr;         // [cap]
     float4 *box_ = nullptr;        // [box_cap][4] oriented-box nodes of every hierarchy level
-    float4 *aabb_ = nullptr;       // [box_cap][2] axis-aligned box of every node (hierarchy build only)
+    float4 *aabb_ = nullptr;       // [box_cap][2] axis-aligned box of every node (the walk reads the leaves')
     size_t cap_ = 0, box_cap_ = 0;
     std::vector<uint32_t> level_off_, level_cnt_;
     int levels_ = 0;

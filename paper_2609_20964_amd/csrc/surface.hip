@@ -382,7 +382,8 @@ __global__ __launch_bounds__(256) void k_sign_bits(const double *__restrict__ ch
 // owns the kTZ nodes z, z + LZ, ... of its column.
 template <int LX, int LY, int LZ, int kTZ>
 __global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, Dims d, double h,
-                                              const float4 *__restrict__ nodes, uint32_t root,
+                                              const float4 *__restrict__ nodes, const float4 *__restrict__ leaf_aabb,
+                                              uint32_t root,
                                               const float4 *__restrict__ tri, uint32_t n_tris,
                                               float *__restrict__ phi, int32_t *__restrict__ argmin, int *err,
                                               uint32_t *next_tile) {
@@ -455,16 +456,28 @@ __global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, 
                 // like integers) with the child's index in the low 3 bits
                 uint32_t key[8];
                 if (kids_leaves) {
+                    // leaves: their axis-aligned boxes first (cheaper, looser), the
+                    // oriented box only for the leaves some lane still needs
+                    uint32_t pass = 0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        // always a valid node (clamped), so all eight loads can be issued together
-                        const float4 *cd = nodes + (size_t)kNode * (first + min((uint32_t)q, cnt - 1));
-                        const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
+                        // always a valid leaf (clamped), so all eight loads can be issued together
+                        const float4 *ab = leaf_aabb + 2 * (size_t)(first + min((uint32_t)q, cnt - 1));
                         bool vis = false;
-                        const float d0 = obb_bound<kTZ>(C0, C1, C2, C3, px, py, pz, best, vis);
-                        const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
-                        key[q] = ((uint32_t)q < cnt && __ballot(vis) != 0) ? (0x80000000u | (kb & 0x7ffffff8u) | q)
-                                                                             : 0u;
+                        aabb_bound<kTZ>(ab[0], ab[1], px, py, pz, best, vis);
+                        if ((uint32_t)q < cnt && __ballot(vis) != 0) pass |= 1u << q;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        key[q] = 0u;
+                        if (pass & (1u << q)) {
+                            const float4 *cd = nodes + (size_t)kNode * (first + q);
+                            const float4 C0 = cd[0], C1 = cd[1], C2 = cd[2], C3 = cd[3];
+                            bool vis = false;
+                            const float d0 = obb_bound<kTZ>(C0, C1, C2, C3, px, py, pz, best, vis);
+                            const uint32_t kb = __builtin_amdgcn_readfirstlane(__float_as_uint(d0));
+                            if (__ballot(vis) != 0) key[q] = 0x80000000u | (kb & 0x7ffffff8u) | q;
+                        }
                     }
                 } else {
 #pragma unroll
@@ -827,13 +840,14 @@ uint32_t Surface::extract(const double *chi, const double *c) {
 }
 
 template <int LX, int LY, int LZ, int KZ>
-static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes, uint32_t root,
-                       const float4 *tri, uint32_t n_tris, float *phi, int32_t *argmin, int *err, uint32_t *next_tile,
-                       unsigned blocks, hipStream_t s) {
+static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
+                       const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
+                       int32_t *argmin, int *err, uint32_t *next_tile, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, sizeof(uint32_t), s));
-    k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, root, tri, n_tris, phi, argmin, err, next_tile);
+    k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
+                                                 next_tile);
     WG_LAUNCH_CHECK();
 }
 
@@ -848,7 +862,7 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
     prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
-    launch_sdf<4, 4, 4, 4>(d_, sign_, h, box_, root, tri_, cnt_.n_tris, phi, argmin, err, next_tile_,
+    launch_sdf<4, 4, 4, 4>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin, err, next_tile_,
                            sdf_blocks_, s);
 }
 
