@@ -146,9 +146,9 @@ def gpu_run(args):
 KIND_BOUND = {"splat": "hbm", "sweep": "hbm", "smooth": "hbm", "resid64": "hbm", "transfer": "hbm",
               "cgupdate": "hbm", "mc": "hbm", "sample": "hbm", "sdf": "alu"}
 # kernel names as rocprofv3 lists them
-KIND_KERNEL = {"sweep": "k_stencil<OpPMatvec>", "smooth": "k_stencil<OpSmooth>", "resid64": "k_stencil<OpResid64>",
-               "sdf": "k_sdf", "splat": "k_splat_div", "mc": "k_mc_count/k_mc_emit",
-               "transfer": "k_restrict/k_prolong_add", "cgupdate": "k_cg_update", "sample": "k_sample"}
+KIND_KERNEL = {"sweep": "k_stencil4<OpPMatvec>", "smooth": "k_vc_pre", "resid64": "k_stencil4<OpResid64>",
+               "sdf": "k_sdf", "splat": "k_splat_chunks", "mc": "k_mc_count/k_mc_emit",
+               "transfer": "k_vc_post", "cgupdate": "k_cg_update", "sample": "k_sample"}
 
 
 SOLVER_KINDS = ("sweep", "smooth", "resid64", "transfer", "cgupdate")

@@ -154,6 +154,17 @@ int wg_recon_backward(wg_recon *r, const float *d_q, int n_q, const float *d_gph
 int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc,
                      const wg_solve_opts *opts, wg_stats *stats);
 
+/* One application z = M r of the multigrid preconditioner that the Poisson
+ * solves (Eq. 20-21 operator, Sec. 2.5's iterative solve) use on r's grid:
+ * a V-cycle with cell-centred trilinear prolongation P, restriction P^T / 2,
+ * degree-2 Chebyshev smoothing before and after the coarse correction and an
+ * exact solve on the coarsest level.  M is symmetric and linear.  d_r, d_z:
+ * float32 [N] on the device (distinct; d_r is not modified); bc as for
+ * wg_poisson_solve.  Runs on the handle's stream without blocking the host;
+ * shares the solver's work buffers with forward/backward/poisson calls on r,
+ * which the stream orders. */
+int wg_mg_apply(wg_recon *r, const float *d_r, float *d_z, int bc);
+
 /* Copies of resident fields from the last forward: d_b float32 [N] (the
  * right-hand side), d_chi float64 [N] (zero mean), d_phi float32 [N],
  * d_keys int32 [n_points] (linear central-cell index i + n0 (j + n1 k)).
@@ -222,10 +233,12 @@ void wg_server_destroy(wg_server *s);
  * ------------------------------------------------------------------------- */
 
 /* Kernel kinds: the fused splat + divergence; the finest-level PCG direction
- * update fused with the 7-point operator; the finest-level weighted-Jacobi
- * sweeps; the FP64 residual of the refinement; the multigrid transfers; the
- * CG vector update; Marching Cubes (count, scan, emit, boxes); the distance
- * walk; query sampling.  "units" accumulate the algorithmic bytes each launch
+ * update fused with the 7-point operator; the finest-level V-cycle pass
+ * before the coarse correction (pre-smoothing, residual and restriction in one
+ * kernel); the FP64 residual of the refinement; the finest-level pass after
+ * it (prolongation and post-smoothing in one kernel); the CG vector update;
+ * Marching Cubes (count, scan, emit, boxes); the distance walk; query
+ * sampling.  "units" accumulate the algorithmic bytes each launch
  * must move (the bytes per cell, point or query of that kernel times the
  * cells, points or queries it processes), except for the distance walk, whose
  * units are grid nodes. */

@@ -73,6 +73,7 @@ SIGNATURES = {
                                     C.c_void_p, C.c_void_p, C.POINTER(WgSolveOpts), C.POINTER(WgStats)]),
     "wg_poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
                                    C.POINTER(WgStats)]),
+    "wg_mg_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "wg_get_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "wg_get_mesh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "wg_recon_destroy": (None, [C.c_void_p]),

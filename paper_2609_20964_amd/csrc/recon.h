@@ -28,6 +28,7 @@ class Recon {
     int backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
                  float *gq, const wg_solve_opts &o, wg_stats *st);
     int poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st);
+    int mg_apply(const float *r, float *z, int bc);
     int get_fields(float *b, double *chi, float *phi, int32_t *keys);
     int get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tris);
 

@@ -361,6 +361,12 @@ int Recon::poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg
     return sr.status;
 }
 
+int Recon::mg_apply(const float *r, float *z, int bc) {
+    require(r && z, WG_EINVAL, "null pointer");
+    solver_.mg_apply(r, z, bc);
+    return WG_OK;
+}
+
 int Recon::get_fields(float *b, double *chi, float *phi, int32_t *keys) {
     require(have_forward_, WG_ESTATE, "no forward result");
     join();
@@ -510,6 +516,14 @@ int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc, const w
         wg::require(r && opts, WG_EINVAL, "null argument");
         wg::require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
         return r->impl->poisson(d_b, d_x, bc, *opts, stats);
+    });
+}
+
+int wg_mg_apply(wg_recon *r, const float *d_r, float *d_z, int bc) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        wg::require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
+        return r->impl->mg_apply(d_r, d_z, bc);
     });
 }
 

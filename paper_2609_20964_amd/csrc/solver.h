@@ -43,12 +43,18 @@ class Solver {
     // x -= mean (FP64), used where a zero-mean field is promised.
     void shift(double *x, double by);
 
+    // z = M r: one V-cycle of the preconditioner with boundary condition bc
+    // (r, z: FP32 on the device, on the solver's stream).
+    void mg_apply(const float *r, float *z, int bc);
+
   private:
     struct Level {
         Dims d;
-        float *rhs, *x, *x2, *tmp;
+        float *rhs, *x, *x2;
     };
     void vcycle(int l);
+    void precond();
+    unsigned rz_blocks() const;
     int pcg(double tol, int max_it, double rr0);
     void finalize(int mode, unsigned nb, int flag);
     void read_scalars();
@@ -61,6 +67,7 @@ class Solver {
     SolveScalars *hsc_ = nullptr, *hsc_dev_ = nullptr;   // host-mapped copy (host / device address)
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
+    unsigned post_blocks_ = 0;   // workgroups of the finest post-smoothing pass (partials of r.z)
     int bc_sign_ = -1;
 };
 

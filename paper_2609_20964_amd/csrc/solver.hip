@@ -1,9 +1,12 @@
 // Matrix-free multigrid-preconditioned CG for the grid Poisson problem.
 //
-// Hot kernels are 2.5-D sweeps: a 64 x 4 workgroup tile of (x, y) columns
-// marches ZC planes in z, keeping the z-1, z, z+1 values in registers and
-// reading x/y neighbours through the caches; x is the fastest (coalesced)
-// axis.  Blocks are remapped so that each XCD sweeps one contiguous slab.
+// The single-operator sweeps (the CG direction update with A, the FP64
+// residual) are 2.5-D: a wavefront takes rows of float4 columns and marches
+// z planes, keeping the z-1, z, z+1 values in registers and reading x/y
+// neighbours through the caches; x is the fastest (coalesced) axis.  Each
+// V-cycle level is two fused passes that stage haloed tiles in LDS (see
+// k_vc_pre / k_vc_post).  Blocks are remapped so that each XCD sweeps one
+// contiguous slab.
 // Every reduction is two-stage and deterministic: one FP64 partial per block
 // (fixed block order), summed by a single-block finalize kernel.
 #include <cmath>
@@ -274,25 +277,6 @@ constexpr double kChebL2 = (2.0 + kChebLo) / 2 + (2.0 - kChebLo) / 2 * 0.7071067
 constexpr float kChebWa = (float)(1.0 / (6.0 * kChebL1));
 constexpr float kChebWb = (float)(1.0 / (6.0 * kChebL2));
 
-struct OpSmooth2 {
-    using T = float;
-    static constexpr int NRED = 0;
-    const float *rhs;
-    float *out;
-    float wa, wb;
-    __device__ float load(size_t i) const { return rhs[i]; }
-    __device__ float load1(size_t i) const { return rhs[i]; }
-    __device__ V4<float> load4(size_t i) const { return ld4(rhs + i); }
-    __device__ void apply(size_t i, float c, float s, float diag, double *) const {
-        out[i] = wa * c + wb * (c - wa * (diag * c - s));
-    }
-    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
-        V4<float> o;
-        for (int q = 0; q < 4; ++q) o.v[q] = wa * c.v[q] + wb * (c.v[q] - wa * (dg.v[q] * c.v[q] - s.v[q]));
-        st4(out + i, o);
-    }
-};
-
 // Weighted-Jacobi sweep x_out = x + w (rhs - A x) / diag; DOT adds rhs . x_out.
 template <bool DOT>
 struct OpSmooth {
@@ -317,55 +301,6 @@ struct OpSmooth {
             o.v[q] = c.v[q] + w * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
             if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
         }
-        st4(out + i, o);
-    }
-};
-
-// Post-smoothing sweep with the constant diagonal: x_out = x + wd (rhs - A x);
-// DOT adds rhs . x_out.
-template <bool DOT>
-struct OpSmoothC {
-    using T = float;
-    static constexpr int NRED = DOT ? 1 : 0;
-    const float *x, *rhs;
-    float *out;
-    float wd;
-    __device__ float load(size_t i) const { return x[i]; }
-    __device__ float load1(size_t i) const { return x[i]; }
-    __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
-    __device__ void apply(size_t i, float c, float s, float diag, double *acc) const {
-        float rv = rhs[i];
-        float v = c + wd * (rv - (diag * c - s));
-        out[i] = v;
-        if constexpr (DOT) acc[0] += (double)rv * (double)v;
-    }
-    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *acc) const {
-        const V4<float> r = ld4(rhs + i);
-        V4<float> o;
-        for (int q = 0; q < 4; ++q) {
-            o.v[q] = c.v[q] + wd * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q]));
-            if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
-        }
-        st4(out + i, o);
-    }
-};
-
-// out = rhs - A x.
-struct OpResid {
-    using T = float;
-    static constexpr int NRED = 0;
-    const float *x, *rhs;
-    float *out;
-    __device__ float load(size_t i) const { return x[i]; }
-    __device__ float load1(size_t i) const { return x[i]; }
-    __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
-    __device__ void apply(size_t i, float c, float s, float diag, double *) const {
-        out[i] = rhs[i] - (diag * c - s);
-    }
-    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
-        const V4<float> r = ld4(rhs + i);
-        V4<float> o;
-        for (int q = 0; q < 4; ++q) o.v[q] = r.v[q] - (dg.v[q] * c.v[q] - s.v[q]);
         st4(out + i, o);
     }
 };
@@ -463,197 +398,444 @@ __device__ __forceinline__ float restrict_w(int t, int C, int nc, int s) {
     }
 }
 
-// coarse = 1/2 P^T fine (P = cell-centred trilinear prolongation).
-__global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ fine, Dims df,
-                                                   float *__restrict__ coarse, Dims dc) {
-    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= dc.count()) return;
-    int I = idx % dc.nx, J = (idx / dc.nx) % dc.ny, K = idx / ((size_t)dc.nx * dc.ny);
-    const int s = -dc.bc_sign;    // mirror sign: +1 Neumann, -1 Dirichlet
-    float acc = 0.f;
-    for (int tz = 0; tz < 4; ++tz) {
-        float wz = restrict_w(tz, K, dc.nz, s);
-        if (wz == 0.f) continue;
-        int fk = 2 * K - 1 + tz;
-        for (int ty = 0; ty < 4; ++ty) {
-            float wy = restrict_w(ty, J, dc.ny, s);
-            if (wy == 0.f) continue;
-            int fj = 2 * J - 1 + ty;
-            const float *row = fine + ((size_t)fk * df.ny + fj) * df.nx;
-            float ax = 0.f;
-            for (int tx = 0; tx < 4; ++tx) {
-                float wx = restrict_w(tx, I, dc.nx, s);
-                if (wx != 0.f) ax += wx * row[2 * I - 1 + tx];
+// 1-D trilinear prolongation weights of fine cell f: coarse cells a = f / 2
+// (3/4) and its neighbour b on f's side (1/4); past a boundary the missing
+// neighbour mirrors onto a with sign s.
+struct Prolong1 {
+    int a, b;
+    float wa, wb;
+};
+__device__ __forceinline__ Prolong1 prolong_w(int f, int nc, int s) {
+    Prolong1 r;
+    r.a = f >> 1;
+    r.b = (f & 1) ? r.a + 1 : r.a - 1;
+    r.wa = 0.75f;
+    r.wb = 0.25f;
+    if (r.b < 0 || r.b >= nc) {
+        r.wa = 0.75f + 0.25f * s;
+        r.wb = 0.f;
+        r.b = r.a;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Fused V-cycle kernels.  Each level of the V-cycle is two passes over the
+// fine field instead of six:
+//   pre:  x = S rhs (both Chebyshev sweeps from a zero guess), r = rhs - A x,
+//         coarse rhs = 1/2 P^T r;
+//   post: x <- x + P e (e: the coarse correction), then the two Chebyshev
+//         sweeps in reverse order, and at the finest level the sum rhs . x.
+// A workgroup takes a tile of up to kVTX x kVTY fine (x, y) columns plus a
+// halo (3 cells for pre: r is needed one cell beyond the tile for the
+// restriction, x two, rhs three; 2 for post) and marches a chunk of z planes.
+// Each thread owns fixed columns of the haloed tile and keeps their z
+// neighbours in registers; the in-plane neighbours of the plane being worked
+// on come through LDS.  Values outside the grid are 0, which is what the
+// boundary rows of A assume (their diagonal carries the missing faces).
+// Halo cells are recomputed by every tile that needs them; each output is
+// written by its owner tile only.
+constexpr int kVB = 512;                  // threads per workgroup
+constexpr int kVTX = 64, kVTY = 16;       // largest fine tile
+constexpr int kPreH = 3, kPostH = 2;
+// the four corner cells of a haloed tile feed no 7-point stencil: no slot holds them
+constexpr int kPreCols = (kVTX + 2 * kPreH) * (kVTY + 2 * kPreH) - 4;
+constexpr int kPostCols = (kVTX + 2 * kPostH) * (kVTY + 2 * kPostH) - 4;
+constexpr int kPreCPT = (kPreCols + kVB - 1) / kVB;
+constexpr int kPostCPT = (kPostCols + kVB - 1) / kVB;
+
+struct VTile {
+    int tx, ty, zc;   // fine tile extents (even) and fine planes per chunk (even)
+    int gx, gy, gz;   // tiles per axis
+    __host__ __device__ unsigned count() const { return (unsigned)gx * (unsigned)gy * (unsigned)gz; }
+};
+
+// tiles of a level with a coarser level below it (every extent even)
+VTile vtile_of(const Dims &d) {
+    VTile t;
+    t.tx = d.nx < kVTX ? d.nx : kVTX;
+    t.ty = d.ny < kVTY ? d.ny : kVTY;
+    t.gx = (int)cdiv(d.nx, t.tx);
+    t.gy = (int)cdiv(d.ny, t.ty);
+    // longest chunk (fewest recomputed halo planes) that still gives >= 512 workgroups
+    for (t.zc = 16;; t.zc /= 2) {
+        t.gz = (int)cdiv(d.nz, t.zc);
+        if (t.zc == 2 || (size_t)t.gx * t.gy * t.gz >= 512) break;
+    }
+    return t;
+}
+
+// One owned column of the haloed tile.  Slots past the tile's columns (the
+// last thread rows) and columns off the grid compute with in = 0, so every
+// value they produce is 0 and no lane branches.
+struct VCol {
+    int c;       // index in the tile
+    unsigned off;   // i + nx j (0 off the grid: a valid address, masked at use)
+    float in;    // 1 on the grid, else 0
+    float dxy;   // 6 + bc_sign * (missing x/y faces)
+    bool own;    // an output cell of this tile
+};
+
+__device__ __forceinline__ VCol vcol(int k, int W, int Ht, int H, int X0, int Y0, int tx, int ty, const Dims &d,
+                                      int &i, int &j) {
+    // slot k -> tile cell c, skipping cells 0, W-1, (Ht-1) W and Ht W - 1
+    int c = k + 1;
+    c += c >= W - 1;
+    c += c >= (Ht - 1) * W;
+    c += c >= Ht * W - 1;
+    VCol r;
+    r.c = c;
+    r.off = 0;
+    r.in = 0.f;
+    r.dxy = 6.f;
+    r.own = false;
+    const int u = c % W, v = c / W;
+    i = X0 - H + u;
+    j = Y0 - H + v;
+    if (v < Ht && i >= 0 && i < d.nx && j >= 0 && j < d.ny) {
+        r.off = (unsigned)(i + d.nx * j);
+        r.in = 1.f;
+        r.dxy = (float)(6 + d.bc_sign * ((i == 0) + (i == d.nx - 1) + (j == 0) + (j == d.ny - 1)));
+        r.own = u >= H && u < H + tx && v >= H && v < H + ty;
+    } else {
+        i = j = 0;
+    }
+    return r;
+}
+
+// The LDS planes carry a pad of one tile row plus one on each side, so the
+// four in-plane neighbours of every slot are plain offsets; a value that
+// reads past the tile (or a pad) is never used.
+__device__ __forceinline__ float vnbr(const float *s, int c, int W) {
+    return (s[c - 1] + s[c + 1]) + (s[c - W] + s[c + W]);
+}
+
+// z-face part of the diagonal on plane z (uniform)
+__device__ __forceinline__ float vdz(int z, const Dims &d) {
+    return (float)(d.bc_sign * ((z == 0) + (z == d.nz - 1)));
+}
+
+// LDS planes: the tile's cells at [pad, pad + slots + 4), a pad of one tile
+// row plus a few cells on each side, so the four in-plane neighbours of every
+// slot are plain offsets.  Pads and the four corner cells are zeroed once.
+constexpr int kPrePad = kVTX + 2 * kPreH + 4, kPreLds = 2 * kPrePad + kPreCPT * kVB + 4;
+constexpr int kPostPad = kVTX + 2 * kPostH + 4, kPostLds = 2 * kPostPad + kPostCPT * kVB + 4;
+
+template <int N, int PAD>
+__device__ __forceinline__ void zero_pads(float *s, int W, int Ht) {
+    for (int k = threadIdx.x; k < PAD; k += kVB) {
+        s[k] = 0.f;
+        s[N - 1 - k] = 0.f;
+    }
+    if (threadIdx.x == 0) {
+        s[PAD] = 0.f;
+        s[PAD + W - 1] = 0.f;
+        s[PAD + (Ht - 1) * W] = 0.f;
+        s[PAD + Ht * W - 1] = 0.f;
+    }
+}
+
+// pre: xo = x2 of the pre-smoothing from a zero guess, crhs = 1/2 P^T (rhs - A xo).
+__global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, float *__restrict__ xo,
+                                                 float *__restrict__ crhs, Dims df, Dims dc, VTile vt, float wa,
+                                                 float wb) {
+    constexpr int H = kPreH, CPT = kPreCPT;
+    __shared__ float sR[2][kPreLds];
+    __shared__ float sX[2][kPreLds];
+    __shared__ float sr[kPreLds];
+    const unsigned lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % (unsigned)vt.gx), by = (int)((lb / (unsigned)vt.gx) % (unsigned)vt.gy),
+              bz = (int)(lb / ((unsigned)vt.gx * (unsigned)vt.gy));
+    const int X0 = bx * vt.tx, Y0 = by * vt.ty;
+    const int W = vt.tx + 2 * H, Ht = vt.ty + 2 * H;
+    zero_pads<kPreLds, kPrePad>(sR[0], W, Ht);
+    zero_pads<kPreLds, kPrePad>(sR[1], W, Ht);
+    zero_pads<kPreLds, kPrePad>(sX[0], W, Ht);
+    zero_pads<kPreLds, kPrePad>(sX[1], W, Ht);
+    zero_pads<kPreLds, kPrePad>(sr, W, Ht);
+    const int K0 = bz * (vt.zc / 2), K1 = min(K0 + vt.zc / 2, dc.nz);
+    const size_t plane = (size_t)df.nx * df.ny;
+    VCol col[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        int i, j;
+        col[q] = vcol((int)threadIdx.x + kVB * q, W, Ht, H, X0, Y0, vt.tx, vt.ty, df, i, j);
+        col[q].c += kPrePad;
+    }
+    // rhs is fetched two planes ahead into two buffers that the unrolled
+    // loop below uses in turn.  Fetches are unconditional (a plane outside
+    // [0, nz) is fetched clamped and scaled by 0), so a buffer keeps its
+    // registers across iterations and no fetch is waited for early.
+    const int s0 = 2 * K0 - 3, s1 = 2 * K1 + 2;   // s0 odd
+    auto load = [&](int s, float(&buf)[CPT], float &sc) {
+        sc = (s >= 0 && s < df.nz) ? 1.f : 0.f;
+        const float *rp = rhs + (size_t)min(max(s, 0), df.nz - 1) * plane;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) buf[q] = rp[col[q].off];
+    };
+    float bA[CPT], bB[CPT], sa, sb;
+    load(s0, bA, sa);
+    load(s0 + 1, bB, sb);
+    // coarse cell of this thread in the restriction (x fastest)
+    const int ctx = vt.tx / 2, cty = vt.ty / 2;
+    const int ca = (int)threadIdx.x % ctx, cb = (int)threadIdx.x / ctx;
+    const int I = X0 / 2 + ca, J = Y0 / 2 + cb;
+    const bool cown = cb < cty && I < dc.nx && J < dc.ny;
+    const int ms = -dc.bc_sign;   // mirror sign: +1 Neumann, -1 Dirichlet
+    float wx[4], wy[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        wx[t] = cown ? restrict_w(t, I, dc.nx, ms) : 0.f;
+        wy[t] = cown ? restrict_w(t, J, dc.ny, ms) : 0.f;
+    }
+    // fine cells 2I-1 .. 2I+2 sit at tile columns 2 ca + 2 .. 2 ca + 5 (H = 3)
+    const int rbase = kPrePad + W * (2 * cb + 2) + 2 * ca + 2;
+    float z0 = 0.f, z1 = 0.f, z2 = 0.f, z3 = 0.f;   // x/y-restricted r of fine planes t-3 .. t
+    // z rings: rhs on planes s-2, s-1, s; x on planes s-3, s-2, s-1
+    float h0[CPT], h1[CPT], h2[CPT], x0[CPT], x1[CPT], x2[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) h0[q] = h1[q] = h2[q] = x0[q] = x1[q] = x2[q] = 0.f;
+    // One z step; par = s & 1 (a constant at every call).
+    auto step = [&](int s, int par, float(&buf)[CPT], float &bsc) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            h0[q] = h1[q];
+            h1[q] = h2[q];
+            h2[q] = buf[q] * (col[q].in * bsc);
+        }
+        load(s + 2, buf, bsc);
+        float *R = sR[par];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) R[col[q].c] = h2[q];
+        __syncthreads();
+        // pre-smoothed x on plane p = s - 1: x1 = wa rhs, x2 = x1 + wb (rhs - A x1)
+        const int p = s - 1;
+        const bool pin = p >= 0 && p < df.nz;
+        const float pm = pin ? 1.f : 0.f, dzp = vdz(p, df);
+        const float *Rp = sR[par ^ 1];
+        float *X = sX[par ^ 1];
+        float *xop = xo + (size_t)(pin ? p : 0) * plane;
+        const bool pout = p >= 2 * K0 && p < 2 * K1;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const float nb = vnbr(Rp, col[q].c, W) + (h0[q] + h2[q]);
+            const float c = h1[q];
+            const float v = (wa * c + wb * (c - wa * ((col[q].dxy + dzp) * c - nb))) * (col[q].in * pm);
+            if (pout && col[q].own) xop[col[q].off] = v;
+            x0[q] = x1[q];
+            x1[q] = x2[q];
+            x2[q] = v;
+            X[col[q].c] = v;
+        }
+        __syncthreads();
+        // residual on plane t = s - 2, restricted in x and y
+        const int t = s - 2;
+        if (t >= 2 * K0 - 1) {
+            const float tm = (t >= 0 && t < df.nz) ? 1.f : 0.f, dzt = vdz(t, df);
+            const float *Xt = sX[par];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const float nb = vnbr(Xt, col[q].c, W) + (x0[q] + x2[q]);
+                sr[col[q].c] = (h0[q] - ((col[q].dxy + dzt) * x1[q] - nb)) * (col[q].in * tm);
             }
-            acc += wz * wy * ax;
-        }
-    }
-    coarse[idx] = 0.5f * acc;
-}
-
-__device__ __forceinline__ void prolong_1d(int f, int nc, int s, int &I, int &J, float &wI, float &wJ) {
-    I = f >> 1;
-    J = (f & 1) ? I + 1 : I - 1;
-    wI = 0.75f;
-    wJ = 0.25f;
-    if (J < 0 || J >= nc) {
-        wI += 0.25f * s;
-        wJ = 0.f;
-        J = I;
-    }
-}
-
-// fine += P coarse.
-__global__ __launch_bounds__(256) void k_prolong_add(const float *__restrict__ coarse, Dims dc,
-                                                      float *__restrict__ fine, Dims df) {
-    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= df.count()) return;
-    int i = idx % df.nx, j = (idx / df.nx) % df.ny, k = idx / ((size_t)df.nx * df.ny);
-    const int s = -dc.bc_sign;
-    int I[2], Jy[2], K[2];
-    float wx[2], wy[2], wz[2];
-    prolong_1d(i, dc.nx, s, I[0], I[1], wx[0], wx[1]);
-    prolong_1d(j, dc.ny, s, Jy[0], Jy[1], wy[0], wy[1]);
-    prolong_1d(k, dc.nz, s, K[0], K[1], wz[0], wz[1]);
-    float acc = 0.f;
-    for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a)
-                acc += wz[c] * wy[b] * wx[a] * coarse[((size_t)K[c] * dc.ny + Jy[b]) * dc.nx + I[a]];
-    fine[idx] += acc;
-}
-
-// Vector transfers (fine x extent divisible by 4).  Lane layout as in
-// k_stencil4: a wavefront covers R rows x L float4 columns of the fine grid;
-// one fine float4 covers two coarse cells in x.
-
-// coarse = 1/2 P^T fine: a wavefront takes R coarse rows J (fine rows
-// 2J-1 .. 2J+2) and marches over coarse planes K.
-__global__ __launch_bounds__(256) void k_restrict4(const float *__restrict__ fine, Dims df, float *__restrict__ coarse,
-                                                   Dims dc, Waves4 wv) {
-    const unsigned task = blockIdx.x * 4 + threadIdx.x / 64;
-    const int lane = threadIdx.x % 64;
-    if (task >= wv.tasks()) return;   // whole wavefront
-    const int s = -dc.bc_sign;
-    const unsigned W4 = (unsigned)df.nx / 4;
-    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
-    const unsigned sl = lane % wv.L, rr = lane / wv.L;
-    const unsigned t = seg * wv.L + sl;                  // fine float4 column = coarse pair (2t, 2t+1)
-    const int J = (int)(grp * wv.R + rr);
-    const bool valid = rr < wv.R && t < W4 && J < dc.ny;
-    const bool shl = sl > 0, shr = sl + 1 < wv.L && t + 1 < W4;
-    const int I0 = 2 * (int)t, I1 = I0 + 1;
-    // x weights of the 6 fine cells 4t-1 .. 4t+4 for coarse I0 and I1
-    const float a0 = restrict_w(0, I0, dc.nx, s), a1 = restrict_w(1, I0, dc.nx, s), a2 = restrict_w(2, I0, dc.nx, s),
-                a3 = restrict_w(3, I0, dc.nx, s);
-    const float b0 = restrict_w(0, I1, dc.nx, s), b1 = restrict_w(1, I1, dc.nx, s), b2 = restrict_w(2, I1, dc.nx, s),
-                b3 = restrict_w(3, I1, dc.nx, s);
-    const int K0 = (int)(zc * wv.zlen), K1 = min(K0 + (int)wv.zlen, dc.nz);
-    const size_t fplane = (size_t)df.nx * df.ny;
-    // y-reduced, x-restricted value pair of fine plane p
-    auto yx = [&](int p, float &v0, float &v1) {
-        v0 = v1 = 0.f;
-        for (int ty = 0; ty < 4; ++ty) {
-            const int fj = 2 * J - 1 + ty;
-            const float wy = valid ? restrict_w(ty, J, dc.ny, s) : 0.f;
-            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-            const bool inrow = valid && wy != 0.f && p >= 0 && p < df.nz;
-            const size_t o = inrow ? (size_t)4 * t + (size_t)df.nx * fj + fplane * p : 0;
-            if (inrow) q = *reinterpret_cast<const float4 *>(fine + o);
-            float left = __shfl_up(q.w, 1, 64), right = __shfl_down(q.x, 1, 64);
-            if (!shl) left = (inrow && t > 0) ? fine[o - 1] : 0.f;
-            if (!shr) right = (inrow && t + 1 < W4) ? fine[o + 4] : 0.f;
-            const float x0 = a0 * left + a1 * q.x + a2 * q.y + a3 * q.z;
-            const float x1 = b0 * q.y + b1 * q.z + b2 * q.w + b3 * right;
-            v0 += wy * x0;
-            v1 += wy * x1;
-        }
-    };
-    // rolling y-reduced planes 2K-1 .. 2K+2
-    float m0, m1, c0, c1;           // planes 2K-1, 2K
-    yx(2 * K0 - 1, m0, m1);
-    yx(2 * K0, c0, c1);
-    for (int K = K0; K < K1; ++K) {
-        float p0, p1, q0, q1;       // planes 2K+1, 2K+2
-        yx(2 * K + 1, p0, p1);
-        yx(2 * K + 2, q0, q1);
-        const float w0 = restrict_w(0, K, dc.nz, s), w1 = restrict_w(1, K, dc.nz, s),
-                    w2 = restrict_w(2, K, dc.nz, s), w3 = restrict_w(3, K, dc.nz, s);
-        if (valid) {
-            const float r0 = 0.5f * (w0 * m0 + w1 * c0 + w2 * p0 + w3 * q0);
-            const float r1 = 0.5f * (w0 * m1 + w1 * c1 + w2 * p1 + w3 * q1);
-            *reinterpret_cast<float2 *>(coarse + (size_t)I0 + (size_t)dc.nx * (J + (size_t)dc.ny * K)) =
-                make_float2(r0, r1);
-        }
-        m0 = p0; m1 = p1; c0 = q0; c1 = q1;
-    }
-}
-
-// fine += P coarse: a wavefront takes R fine rows j and marches over fine
-// planes in pairs (2K, 2K+1), which share coarse planes K-1 .. K+1.
-__global__ __launch_bounds__(256) void k_prolong4(const float *__restrict__ coarse, Dims dc, float *__restrict__ fine,
-                                                  Dims df, Waves4 wv) {
-    const unsigned task = blockIdx.x * 4 + threadIdx.x / 64;
-    const int lane = threadIdx.x % 64;
-    if (task >= wv.tasks()) return;   // whole wavefront
-    const int s = -dc.bc_sign;
-    const unsigned W4 = (unsigned)df.nx / 4;
-    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
-    const unsigned sl = lane % wv.L, rr = lane / wv.L;
-    const unsigned t = seg * wv.L + sl;
-    const int j = (int)(grp * wv.R + rr);
-    const bool valid = rr < wv.R && t < W4 && j < df.ny;
-    const bool shl = sl > 0, shr = sl + 1 < wv.L && t + 1 < W4;
-    // y: coarse rows and weights
-    int Jy[2];
-    float wy[2];
-    prolong_1d(valid ? j : 0, dc.ny, s, Jy[0], Jy[1], wy[0], wy[1]);
-    const bool lb = 2 * (int)t - 1 >= 0, rb = 2 * (int)t + 2 < dc.nx;   // coarse x neighbours exist
-    // x-interpolated fine quad from coarse row (J, K)
-    auto xrow = [&](int J, int K, float4 &o) {
-        float2 c = make_float2(0.f, 0.f);
-        const size_t base = (size_t)dc.nx * (J + (size_t)dc.ny * K);
-        if (valid) c = *reinterpret_cast<const float2 *>(coarse + base + 2 * t);
-        float l = __shfl_up(c.y, 1, 64), r = __shfl_down(c.x, 1, 64);
-        if (!shl) l = (valid && lb) ? coarse[base + 2 * t - 1] : 0.f;
-        if (!shr) r = (valid && rb) ? coarse[base + 2 * t + 2] : 0.f;
-        o.x = lb ? 0.75f * c.x + 0.25f * l : (0.75f + 0.25f * s) * c.x;
-        o.y = 0.75f * c.x + 0.25f * c.y;
-        o.z = 0.75f * c.y + 0.25f * c.x;
-        o.w = rb ? 0.75f * c.y + 0.25f * r : (0.75f + 0.25f * s) * c.y;
-    };
-    auto yrow = [&](int K, float4 &o) {   // y-combined quad at coarse plane K for fine row j
-        float4 a, b;
-        xrow(Jy[0], K, a);
-        xrow(Jy[1], K, b);
-        o = make_float4(wy[0] * a.x + wy[1] * b.x, wy[0] * a.y + wy[1] * b.y, wy[0] * a.z + wy[1] * b.z,
-                        wy[0] * a.w + wy[1] * b.w);
-    };
-    const int k0 = (int)(zc * wv.zlen), k1 = min(k0 + (int)wv.zlen, df.nz);   // zlen even: k0 even
-    const size_t fplane = (size_t)df.nx * df.ny;
-    for (int k = k0; k < k1; k += 2) {
-        const int K = k >> 1;
-        float4 cm, cc, cp;
-        yrow(K > 0 ? K - 1 : K, cm);
-        yrow(K, cc);
-        yrow(K + 1 < dc.nz ? K + 1 : K, cp);
-        for (int h = 0; h < 2 && k + h < k1; ++h) {
-            // fine plane k+h: even -> (K, K-1), odd -> (K, K+1); mirror at the ends
-            const bool odd = h == 1;
-            const bool inb = odd ? (K + 1 < dc.nz) : (K > 0);
-            const float wK = inb ? 0.75f : 0.75f + 0.25f * s, wN = inb ? 0.25f : 0.f;
-            const float4 &N = odd ? cp : cm;
-            if (valid) {
-                float4 *f = reinterpret_cast<float4 *>(fine + (size_t)4 * t + (size_t)df.nx * j + fplane * (k + h));
-                float4 v = *f;
-                v.x += wK * cc.x + wN * N.x;
-                v.y += wK * cc.y + wN * N.y;
-                v.z += wK * cc.z + wN * N.z;
-                v.w += wK * cc.w + wN * N.w;
-                *f = v;
+            __syncthreads();
+            if (cown) {
+                float acc = 0.f;
+#pragma unroll
+                for (int ty = 0; ty < 4; ++ty) {
+                    const float *row = sr + rbase + W * ty;
+                    acc += wy[ty] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+                }
+                z0 = z1;
+                z1 = z2;
+                z2 = z3;
+                z3 = acc;
+                if (t >= 2 * K0 + 2 && !(t & 1)) {   // t = 2K + 2: fine planes 2K-1 .. 2K+2 are in
+                    const int K = t / 2 - 1;
+                    crhs[(size_t)I + (size_t)dc.nx * ((size_t)J + (size_t)dc.ny * K)] =
+                        0.5f * (restrict_w(0, K, dc.nz, ms) * z0 + restrict_w(1, K, dc.nz, ms) * z1 +
+                                restrict_w(2, K, dc.nz, ms) * z2 + restrict_w(3, K, dc.nz, ms) * z3);
+                }
             }
         }
+    };
+    // two steps per iteration (s0 odd, s1 even: an even number of steps)
+    for (int s = s0; s <= s1; s += 2) {
+        step(s, 1, bA, sa);
+        step(s + 1, 0, bB, sb);
     }
+}
+
+// post: u = x + P e, v = u + wb (rhs - A u), xo = v + wa (rhs - A v); DOT adds
+// rhs . xo to the block's partial.
+template <bool DOT>
+__global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x, const float *__restrict__ rhs,
+                                                     const float *__restrict__ e, float *__restrict__ xo, Dims df,
+                                                     Dims dc, VTile vt, float wb, float wa, double *partials) {
+    constexpr int H = kPostH, CPT = kPostCPT;
+    __shared__ float sU[2][kPostLds];
+    __shared__ float sV[2][kPostLds];
+    __shared__ float sQ[3][kPostLds];   // x/y-interpolated coarse planes, by coarse index mod 3
+    const unsigned lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % (unsigned)vt.gx), by = (int)((lb / (unsigned)vt.gx) % (unsigned)vt.gy),
+              bz = (int)(lb / ((unsigned)vt.gx * (unsigned)vt.gy));
+    const int X0 = bx * vt.tx, Y0 = by * vt.ty;
+    const int W = vt.tx + 2 * H, Ht = vt.ty + 2 * H;
+    zero_pads<kPostLds, kPostPad>(sU[0], W, Ht);
+    zero_pads<kPostLds, kPostPad>(sU[1], W, Ht);
+    zero_pads<kPostLds, kPostPad>(sV[0], W, Ht);
+    zero_pads<kPostLds, kPostPad>(sV[1], W, Ht);
+    const int k0 = bz * vt.zc, k1 = min(k0 + vt.zc, df.nz);
+    const size_t plane = (size_t)df.nx * df.ny, cplane = (size_t)dc.nx * dc.ny;
+    const int ms = -dc.bc_sign;
+    VCol col[CPT];
+    unsigned ij[CPT];   // i | j << 16 of the column (0 off the grid)
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        int i, j;
+        col[q] = vcol((int)threadIdx.x + kVB * q, W, Ht, H, X0, Y0, vt.tx, vt.ty, df, i, j);
+        col[q].c += kPostPad;
+        ij[q] = (unsigned)i | ((unsigned)j << 16);
+    }
+    // The x/y-interpolated coarse plane m at each column goes to sQ[m % 3]:
+    // its four coarse values are fetched two steps before they are mixed.
+    // Each thread reads back only its own columns, so no barrier is needed.
+    // Off the coarse grid the plane is 0 (its weight is 0 too); the fetch is
+    // then clamped and scaled by cscale = 0.
+    float c0[CPT], c1[CPT], c2[CPT], c3[CPT];
+    float cscale = 0.f;
+    auto qfetch = [&](int m) {
+        cscale = (m >= 0 && m < dc.nz) ? 1.f : 0.f;
+        const float *em = e + (size_t)min(max(m, 0), dc.nz - 1) * cplane;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const Prolong1 px = prolong_w((int)(ij[q] & 0xffffu), dc.nx, ms);
+            const Prolong1 py = prolong_w((int)(ij[q] >> 16), dc.ny, ms);
+            const unsigned ra = (unsigned)(dc.nx * py.a), rb = (unsigned)(dc.nx * py.b);
+            c0[q] = em[ra + (unsigned)px.a];
+            c1[q] = em[ra + (unsigned)px.b];
+            c2[q] = em[rb + (unsigned)px.a];
+            c3[q] = em[rb + (unsigned)px.b];
+        }
+    };
+    auto qstore = [&](int m) {   // m: the plane of the last qfetch
+        float *Q = sQ[(m + 3) % 3];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const Prolong1 px = prolong_w((int)(ij[q] & 0xffffu), dc.nx, ms);
+            const Prolong1 py = prolong_w((int)(ij[q] >> 16), dc.ny, ms);
+            Q[col[q].c] = cscale * (py.wa * (px.wa * c0[q] + px.wb * c1[q]) + py.wb * (px.wa * c2[q] + px.wb * c3[q]));
+        }
+    };
+    // x and rhs of the next plane, fetched one step ahead (unconditionally, so
+    // the buffers keep their registers across the loop).  A plane outside
+    // [0, nz) is fetched clamped:
+    // every value computed from it there is masked to 0, and rhs enters only
+    // the planes' own (in-range) updates.
+    auto load = [&](int s, float(&xb)[CPT], float(&hb)[CPT]) {
+        const size_t o = (size_t)min(max(s, 0), df.nz - 1) * plane;
+        const float *xp = x + o, *hp = rhs + o;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            xb[q] = xp[col[q].off];
+            hb[q] = hp[col[q].off];
+        }
+    };
+    const int s0 = k0 - 2, s1 = k1 + 1;   // k0 even: s0 even, s0 >> 1 >= -1
+    qfetch((s0 >> 1) - 1);
+    qstore((s0 >> 1) - 1);
+    qfetch(s0 >> 1);
+    qstore(s0 >> 1);
+    qfetch((s0 >> 1) + 1);
+    float xA[CPT], hA[CPT];
+    load(s0, xA, hA);
+    double acc[1] = {0.0};
+    // z rings: u on planes s-2 .. s, v on s-3 .. s-1, rhs on s-2 .. s
+    float u0[CPT], u1[CPT], u2[CPT], v0[CPT], v1[CPT], v2[CPT], h0[CPT], h1[CPT], h2[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) u0[q] = u1[q] = u2[q] = v0[q] = v1[q] = v2[q] = h0[q] = h1[q] = h2[q] = 0.f;
+    // One z step; par = s & 1.
+    auto step = [&](int s, int par, float(&xb)[CPT], float(&hb)[CPT]) {
+        const int K = s >> 1;
+        if (!par) {
+            // planes K-1 and K are in sQ; K+1 (first needed at s+1) arrived: mix it, fetch K+2
+            qstore(K + 1);
+            qfetch(K + 2);
+        }
+        float xc[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            xc[q] = xb[q];
+            h0[q] = h1[q];
+            h1[q] = h2[q];
+            h2[q] = hb[q];
+        }
+        load(s + 1, xb, hb);
+        // u on plane s; z prolongation: plane s takes coarse K (3/4) and K-1 (even s) or K+1 (odd s)
+        const int N = par ? K + 1 : K - 1;
+        const bool nin = N >= 0 && N < dc.nz;
+        const float wK = nin ? 0.75f : 0.75f + 0.25f * ms, wN = nin ? 0.25f : 0.f;
+        const float sm = (s >= 0 && s < df.nz) ? 1.f : 0.f;
+        const float *QK = sQ[(K + 3) % 3], *QN = sQ[(N + 3) % 3];
+        float *U = sU[par];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const float uv = (xc[q] + wK * QK[col[q].c] + wN * QN[col[q].c]) * (col[q].in * sm);
+            u0[q] = u1[q];
+            u1[q] = u2[q];
+            u2[q] = uv;
+            U[col[q].c] = uv;
+        }
+        __syncthreads();
+        const int p = s - 1;
+        if (p >= k0 - 1) {
+            const float pm = (p >= 0 && p < df.nz) ? 1.f : 0.f, dzp = vdz(p, df);
+            const float *Up = sU[par ^ 1];
+            float *V = sV[par ^ 1];
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const float nb = vnbr(Up, col[q].c, W) + (u0[q] + u2[q]);
+                const float vv = (u1[q] + wb * (h1[q] - ((col[q].dxy + dzp) * u1[q] - nb))) * (col[q].in * pm);
+                v0[q] = v1[q];
+                v1[q] = v2[q];
+                v2[q] = vv;
+                V[col[q].c] = vv;
+            }
+            __syncthreads();
+            const int t = s - 2;
+            if (t >= k0) {   // t < k1 holds: s <= k1 + 1
+                const float dzt = vdz(t, df);
+                const float *Vt = sV[par];
+                float *xop = xo + (size_t)t * plane;
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) {
+                    const float nb = vnbr(Vt, col[q].c, W) + (v0[q] + v2[q]);
+                    const float w = v1[q] + wa * (h0[q] - ((col[q].dxy + dzt) * v1[q] - nb));
+                    if (col[q].own) {
+                        xop[col[q].off] = w;
+                        if constexpr (DOT) acc[0] += (double)h0[q] * (double)w;
+                    }
+                }
+            }
+        }
+    };
+    for (int s = s0; s <= s1; ++s) step(s, s & 1, xA, hA);
+    if constexpr (DOT) {
+        __shared__ double lds[kVB / 64][1];
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) partials[lb] = acc[0];
+    }
+}
+
+// out = rhs . x summed per block (the r.z of a single-level hierarchy).
+__global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const float *__restrict__ b, size_t n,
+                                              double *partials) {
+    double acc[1] = {0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        acc[0] += (double)a[i] * (double)b[i];
+    __shared__ double lds[4][1];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
 // Exact solve on the coarsest level (every extent <= kCoarseAxis = 16) by the
@@ -855,8 +1037,13 @@ unsigned sweep_blocks(const Dims &d) {
     return d.nx % 4 == 0 ? cdiv(waves4_of(d).tasks(), 4) : tiles_of(d).count();
 }
 
-size_t partial_slots(const Dims &fine) {
-    size_t nb = sweep_blocks(fine);
+// blocks of the finest post-smoothing pass (0 for a single-level hierarchy)
+unsigned post_blocks(const std::vector<Dims> &dims) { return dims.size() > 1 ? vtile_of(dims[0]).count() : 0u; }
+
+size_t partial_slots(const std::vector<Dims> &dims) {
+    size_t nb = sweep_blocks(dims[0]);
+    const size_t pb = post_blocks(dims);
+    if (pb > nb) nb = pb;
     return (nb > (size_t)kRedBlocks ? nb : (size_t)kRedBlocks) * kMaxRed;
 }
 
@@ -870,11 +1057,11 @@ unsigned red_blocks(size_t n) {
 void Solver::plan(Arena &a, int nx, int ny, int nz) {
     auto dims = level_dims(nx, ny, nz);
     size_t N = dims[0].count();
-    // fine level: r, z, z2, t0, e, p0, p1, q
-    for (int k = 0; k < 8; ++k) a.reserve(N * sizeof(float));
+    // fine level: r, z, z2, e, p0, p1, q
+    for (int k = 0; k < 7; ++k) a.reserve(N * sizeof(float));
     for (size_t l = 1; l < dims.size(); ++l)
-        for (int k = 0; k < 4; ++k) a.reserve(dims[l].count() * sizeof(float));
-    a.reserve(partial_slots(dims[0]) * sizeof(double));
+        for (int k = 0; k < 3; ++k) a.reserve(dims[l].count() * sizeof(float));
+    a.reserve(partial_slots(dims) * sizeof(double));
     a.reserve(sizeof(SolveScalars));
     const Dims &c = dims.back();
     if (c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis)
@@ -892,7 +1079,6 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
     f.rhs = a.take<float>(N);   // the CG residual r
     f.x = a.take<float>(N);     // z = M r
     f.x2 = a.take<float>(N);
-    f.tmp = a.take<float>(N);
     e_ = a.take<float>(N);
     p_[0] = a.take<float>(N);
     p_[1] = a.take<float>(N);
@@ -904,9 +1090,9 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
         L.rhs = a.take<float>(n);
         L.x = a.take<float>(n);
         L.x2 = a.take<float>(n);
-        L.tmp = a.take<float>(n);
     }
-    partials_ = a.take<double>(partial_slots(dims[0]));
+    partials_ = a.take<double>(partial_slots(dims));
+    post_blocks_ = post_blocks(dims);
     dsc_ = a.take<SolveScalars>(1);
     WG_HIP(hipHostMalloc((void **)&hsc_, sizeof(SolveScalars), hipHostMallocMapped | hipHostMallocCoherent));
     WG_HIP(hipHostGetDevicePointer((void **)&hsc_dev_, hsc_, 0));
@@ -973,37 +1159,51 @@ void Solver::vcycle(int l) {
     Level &C = lv_[l + 1];
     C.d.bc_sign = bc_sign_;
     const int ks = l == 0 ? WG_PROF_SMOOTH : -1, kt = l == 0 ? WG_PROF_TRANSFER : -1;
-    launch_stencil(OpSmooth2{L.rhs, L.x, kChebWa, kChebWb}, L.d, nullptr, st_, ks, 8.0);
-    launch_stencil(OpResid{L.x, L.rhs, L.tmp}, L.d, nullptr, st_, ks, 12.0);
+    const VTile vt = vtile_of(L.d);
     {
-        prof::Scope ps(kt, st_, 4.0 * (double)(L.d.count() + C.d.count()));
-        if (L.d.nx % 4 == 0) {
-            Waves4 wv = waves4_of(L.d);
-            wv.G = ((unsigned)C.d.ny + wv.R - 1) / wv.R;   // rows of the coarse grid
-            set_zlen(wv, C.d.nz);
-            k_restrict4<<<cdiv(wv.tasks(), 4), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d, wv);
-        } else {
-            k_restrict<<<cdiv(C.d.count(), 256), 256, 0, st_>>>(L.tmp, L.d, C.rhs, C.d);
-        }
+        // rhs read, x written; 1/8 of a cell's bytes for the coarse rhs
+        prof::Scope ps(ks, st_, 8.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
+        k_vc_pre<<<vt.count(), kVB, 0, st_>>>(L.rhs, L.x, C.rhs, L.d, C.d, vt, kChebWa, kChebWb);
         WG_LAUNCH_CHECK();
     }
     vcycle(l + 1);
     {
-        prof::Scope ps(kt, st_, 8.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
-        if (L.d.nx % 4 == 0) {
-            const Waves4 wv = waves4_of(L.d, true);
-            k_prolong4<<<cdiv(wv.tasks(), 4), 256, 0, st_>>>(C.x, C.d, L.x, L.d, wv);
-        } else {
-            k_prolong_add<<<cdiv(L.d.count(), 256), 256, 0, st_>>>(C.x, C.d, L.x, L.d);
-        }
+        // x and rhs read, the result written, the coarse correction read
+        prof::Scope ps(kt, st_, 12.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
+        if (l == 0)   // + r.z
+            k_vc_post<true><<<vt.count(), kVB, 0, st_>>>(L.x, L.rhs, C.x, L.x2, L.d, C.d, vt, kChebWb, kChebWa,
+                                                           partials_);
+        else
+            k_vc_post<false><<<vt.count(), kVB, 0, st_>>>(L.x, L.rhs, C.x, L.x2, L.d, C.d, vt, kChebWb, kChebWa,
+                                                            nullptr);
+        WG_LAUNCH_CHECK();
+        std::swap(L.x, L.x2);
+    }
+}
+
+// z = M r with r.z summed into partials_ (rz_blocks() of them).
+void Solver::precond() {
+    vcycle(0);
+    if (lv_.size() == 1) {
+        // the coarsest solve alone forms no sum: one more pass
+        Level &F = lv_[0];
+        const size_t N = F.d.count();
+        k_dot<<<red_blocks(N), kBlock, 0, st_>>>(F.rhs, F.x, N, partials_);
         WG_LAUNCH_CHECK();
     }
-    launch_stencil(OpSmoothC<false>{L.x, L.rhs, L.x2, kChebWb}, L.d, nullptr, st_, ks, 12.0);
-    if (l == 0) {
-        launch_stencil(OpSmoothC<true>{L.x2, L.rhs, L.x, kChebWa}, L.d, partials_, st_, ks, 12.0);   // + r.z
-    } else {
-        launch_stencil(OpSmoothC<false>{L.x2, L.rhs, L.x, kChebWa}, L.d, nullptr, st_);
-    }
+}
+
+unsigned Solver::rz_blocks() const { return lv_.size() > 1 ? post_blocks_ : red_blocks(lv_[0].d.count()); }
+
+void Solver::mg_apply(const float *r, float *z, int bc) {
+    require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
+    bc_sign_ = bc == WG_BC_NEUMANN ? -1 : +1;
+    for (auto &L : lv_) L.d.bc_sign = bc_sign_;
+    Level &F = lv_[0];
+    const size_t N = F.d.count();
+    WG_HIP(hipMemcpyAsync(F.rhs, r, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    vcycle(0);
+    WG_HIP(hipMemcpyAsync(z, F.x, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
 }
 
 int Solver::pcg(double tol, int max_it, double rr0) {
@@ -1012,8 +1212,8 @@ int Solver::pcg(double tol, int max_it, double rr0) {
     const unsigned tb = sweep_blocks(F.d);
     const unsigned rb = red_blocks(N);
     // z = M r, rz = r.z ; the first finalize must not form beta
-    vcycle(0);
-    finalize(FIN_RZ, tb, 1);
+    precond();
+    finalize(FIN_RZ, rz_blocks(), 1);
     int cur = 0, it = 0;
     double best = rr0;
     int stall = 0;
@@ -1036,8 +1236,8 @@ int Solver::pcg(double tol, int max_it, double rr0) {
             WG_LAUNCH_CHECK();
         }
         finalize(FIN_RR, rb, 0);
-        vcycle(0);   // z for the next direction
-        finalize(FIN_RZ, tb, 0);   // beta = rz / rz_old
+        precond();   // z for the next direction
+        finalize(FIN_RZ, rz_blocks(), 0);   // beta = rz / rz_old
         read_scalars();
         const double rr = hsc_->rr;
         if (hsc_->bad || !std::isfinite(rr)) { ++it; break; }

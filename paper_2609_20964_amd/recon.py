@@ -166,6 +166,8 @@ class Recon:
     # -- standalone solve and exports ---------------------------------------------
     def poisson(self, b, x=None, bc="neumann", rel_tol=1e-10, max_iters=1000):
         """Solve A x = b on this grid (float32 b [N], float64 x [N])."""
+        if b.numel() != self.cells or (x is not None and x.numel() != self.cells):
+            raise ValueError(f"b and x must hold {self.cells} cells")
         if x is None:
             x = torch.zeros(self.cells, dtype=torch.float64, device=b.device)
             warm = False
@@ -178,6 +180,16 @@ class Recon:
                                               _dev(x, torch.float64, None, "x"), bcode, C.byref(o),
                                               C.byref(st)), allow=(L.WG_OK, L.WG_ENOTCONV))
         return x, st.as_dict()
+
+    def mg_apply(self, r, bc="neumann"):
+        """z = M r: one V-cycle of the solver's multigrid preconditioner (float32 [N])."""
+        if r.numel() != self.cells:
+            raise ValueError(f"r must hold {self.cells} cells")
+        z = torch.empty_like(r)
+        bcode = {"neumann": L.WG_BC_NEUMANN, "dirichlet": L.WG_BC_DIRICHLET}[bc]
+        L.check(L.lib().wg_mg_apply(self._alive(), _dev(r, torch.float32, None, "r"), C.c_void_p(z.data_ptr()),
+                                    bcode))
+        return z
 
     def fields(self):
         """Resident fields of the last forward: b, chi (zero mean), phi, keys."""

@@ -241,6 +241,18 @@ def test_pipelined_steps_match_plain():
     pa, _ = a.sample(q)
     pb, _ = b.sample(q)
     assert np.abs(pa.cpu().numpy() - pb.cpu().numpy()).max() <= 1e-4 * h
+    # the reverse pass straight after a pipelined step (no wait) sees its walk
+    x, nrm = (_cuda(v) for v in fl.step(23))
+    _, phi_a, _ = a.step(x, nrm, q, rel_tol=1e-8, warm_start=True)
+    b.forward(x, nrm, rel_tol=1e-8, warm_start=True)
+    gphi = torch.ones(q.shape[0], dtype=torch.float32, device=q.device) / q.shape[0]
+    ga = a.backward(q, gphi, rel_tol=1e-10, max_iters=2000)
+    gb = b.backward(q, gphi, rel_tol=1e-10, max_iters=2000)
+    for u, v in zip(ga[:2], gb[:2]):
+        u, v = u.cpu().numpy(), v.cpu().numpy()
+        assert np.linalg.norm(u - v) <= 1e-3 * np.linalg.norm(v)
+    pb, _ = b.sample(q)
+    assert np.abs(phi_a.cpu().numpy() - pb.cpu().numpy()).max() <= 1e-4 * h
     a.close()
     b.close()
 
