@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
     constexpr int H = kPreH, CPT = kPreCPT;
     __shared__ float sR[2][kPreLds];
     __shared__ float sX[2][kPreLds];
-    __shared__ float sr[kPreLds];
+    __shared__ float sr[2][kPreLds];
     const unsigned lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int bx = (int)(lb % (unsigned)vt.gx), by = (int)((lb / (unsigned)vt.gx) % (unsigned)vt.gy),
               bz = (int)(lb / ((unsigned)vt.gx * (unsigned)vt.gy));
@@ -552,7 +552,8 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
     zero_pads<kPreLds, kPrePad>(sR[1], W, Ht);
     zero_pads<kPreLds, kPrePad>(sX[0], W, Ht);
     zero_pads<kPreLds, kPrePad>(sX[1], W, Ht);
-    zero_pads<kPreLds, kPrePad>(sr, W, Ht);
+    zero_pads<kPreLds, kPrePad>(sr[0], W, Ht);
+    zero_pads<kPreLds, kPrePad>(sr[1], W, Ht);
     const int K0 = bz * (vt.zc / 2), K1 = min(K0 + vt.zc / 2, dc.nz);
     const size_t plane = (size_t)df.nx * df.ny;
     VCol col[CPT];
@@ -595,8 +596,13 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
     float h0[CPT], h1[CPT], h2[CPT], x0[CPT], x1[CPT], x2[CPT];
 #pragma unroll
     for (int q = 0; q < CPT; ++q) h0[q] = h1[q] = h2[q] = x0[q] = x1[q] = x2[q] = 0.f;
-    // One z step; par = s & 1 (a constant at every call).
+    // One z step (par = s & 1, a constant at every call), with one barrier:
+    // every LDS plane it reads was written in the previous step, and every
+    // plane it writes was last read in the previous step.
+    //   rhs(s) -> sR[s];  x(s-1) from sR[s-1] -> sX[s-1];
+    //   r(s-2) from sX[s-2] -> sr[s-2];  restriction of r(s-3) from sr[s-3].
     auto step = [&](int s, int par, float(&buf)[CPT], float &bsc) {
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             h0[q] = h1[q];
@@ -604,64 +610,70 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
             h2[q] = buf[q] * (col[q].in * bsc);
         }
         load(s + 2, buf, bsc);
-        float *R = sR[par];
+        {
+            float *R = sR[par];
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) R[col[q].c] = h2[q];
-        __syncthreads();
+            for (int q = 0; q < CPT; ++q) R[col[q].c] = h2[q];
+        }
         // pre-smoothed x on plane p = s - 1: x1 = wa rhs, x2 = x1 + wb (rhs - A x1)
         const int p = s - 1;
-        const bool pin = p >= 0 && p < df.nz;
-        const float pm = pin ? 1.f : 0.f, dzp = vdz(p, df);
-        const float *Rp = sR[par ^ 1];
-        float *X = sX[par ^ 1];
-        float *xop = xo + (size_t)(pin ? p : 0) * plane;
-        const bool pout = p >= 2 * K0 && p < 2 * K1;
+        {
+            const bool pin = p >= 0 && p < df.nz;
+            const float pm = pin ? 1.f : 0.f, dzp = vdz(p, df);
+            const float *Rp = sR[par ^ 1];
+            float *X = sX[par ^ 1];
+            float *xop = xo + (size_t)(pin ? p : 0) * plane;
+            const bool pout = p >= 2 * K0 && p < 2 * K1;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const float nb = vnbr(Rp, col[q].c, W) + (h0[q] + h2[q]);
-            const float c = h1[q];
-            const float v = (wa * c + wb * (c - wa * ((col[q].dxy + dzp) * c - nb))) * (col[q].in * pm);
-            if (pout && col[q].own) xop[col[q].off] = v;
-            x0[q] = x1[q];
-            x1[q] = x2[q];
-            x2[q] = v;
-            X[col[q].c] = v;
+            for (int q = 0; q < CPT; ++q) {
+                const float nb = vnbr(Rp, col[q].c, W) + (h0[q] + h2[q]);
+                const float c = h1[q];
+                const float v = (wa * c + wb * (c - wa * ((col[q].dxy + dzp) * c - nb))) * (col[q].in * pm);
+                if (pout && col[q].own) xop[col[q].off] = v;
+                x0[q] = x1[q];
+                x1[q] = x2[q];
+                x2[q] = v;
+                X[col[q].c] = v;
+            }
         }
-        __syncthreads();
-        // residual on plane t = s - 2, restricted in x and y
+        // residual on plane t = s - 2
         const int t = s - 2;
         if (t >= 2 * K0 - 1) {
             const float tm = (t >= 0 && t < df.nz) ? 1.f : 0.f, dzt = vdz(t, df);
             const float *Xt = sX[par];
+            float *r = sr[par];
 #pragma unroll
             for (int q = 0; q < CPT; ++q) {
                 const float nb = vnbr(Xt, col[q].c, W) + (x0[q] + x2[q]);
-                sr[col[q].c] = (h0[q] - ((col[q].dxy + dzt) * x1[q] - nb)) * (col[q].in * tm);
+                r[col[q].c] = (h0[q] - ((col[q].dxy + dzt) * x1[q] - nb)) * (col[q].in * tm);
             }
-            __syncthreads();
-            if (cown) {
-                float acc = 0.f;
+        }
+        // residual of plane t - 1, restricted in x and y
+        const int tr = s - 3;
+        if (tr >= 2 * K0 - 1 && cown) {
+            const float *r = sr[par ^ 1] + rbase;
+            float acc = 0.f;
 #pragma unroll
-                for (int ty = 0; ty < 4; ++ty) {
-                    const float *row = sr + rbase + W * ty;
-                    acc += wy[ty] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
-                }
-                z0 = z1;
-                z1 = z2;
-                z2 = z3;
-                z3 = acc;
-                if (t >= 2 * K0 + 2 && !(t & 1)) {   // t = 2K + 2: fine planes 2K-1 .. 2K+2 are in
-                    const int K = t / 2 - 1;
-                    crhs[(size_t)I + (size_t)dc.nx * ((size_t)J + (size_t)dc.ny * K)] =
-                        0.5f * (restrict_w(0, K, dc.nz, ms) * z0 + restrict_w(1, K, dc.nz, ms) * z1 +
-                                restrict_w(2, K, dc.nz, ms) * z2 + restrict_w(3, K, dc.nz, ms) * z3);
-                }
+            for (int ty = 0; ty < 4; ++ty) {
+                const float *row = r + W * ty;
+                acc += wy[ty] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+            }
+            z0 = z1;
+            z1 = z2;
+            z2 = z3;
+            z3 = acc;
+            if (tr >= 2 * K0 + 2 && !(tr & 1)) {   // tr = 2K + 2: fine planes 2K-1 .. 2K+2 are in
+                const int K = tr / 2 - 1;
+                crhs[(size_t)I + (size_t)dc.nx * ((size_t)J + (size_t)dc.ny * K)] =
+                    0.5f * (restrict_w(0, K, dc.nz, ms) * z0 + restrict_w(1, K, dc.nz, ms) * z1 +
+                            restrict_w(2, K, dc.nz, ms) * z2 + restrict_w(3, K, dc.nz, ms) * z3);
             }
         }
     };
-    // two steps per iteration (s0 odd, s1 even: an even number of steps)
-    for (int s = s0; s <= s1; s += 2) {
+    // the last restricted plane, 2 K1, is restricted at step 2 K1 + 3 = s1 + 1
+    for (int s = s0; s <= s1 + 1; s += 2) {
         step(s, 1, bA, sa);
+        if (s + 1 > s1 + 1) break;
         step(s + 1, 0, bB, sb);
     }
 }
@@ -754,8 +766,12 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
     float u0[CPT], u1[CPT], u2[CPT], v0[CPT], v1[CPT], v2[CPT], h0[CPT], h1[CPT], h2[CPT];
 #pragma unroll
     for (int q = 0; q < CPT; ++q) u0[q] = u1[q] = u2[q] = v0[q] = v1[q] = v2[q] = h0[q] = h1[q] = h2[q] = 0.f;
-    // One z step; par = s & 1.
+    // One z step (par = s & 1) with one barrier: every LDS plane it reads was
+    // written in the previous step, and every plane it writes was last read in
+    // the previous step.  sQ is read back only by the thread that wrote it.
+    //   u(s) -> sU[s];  v(s-1) from sU[s-1] -> sV[s-1];  xo(s-2) from sV[s-2].
     auto step = [&](int s, int par, float(&xb)[CPT], float(&hb)[CPT]) {
+        __syncthreads();
         const int K = s >> 1;
         if (!par) {
             // planes K-1 and K are in sQ; K+1 (first needed at s+1) arrived: mix it, fetch K+2
@@ -772,21 +788,22 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
         }
         load(s + 1, xb, hb);
         // u on plane s; z prolongation: plane s takes coarse K (3/4) and K-1 (even s) or K+1 (odd s)
-        const int N = par ? K + 1 : K - 1;
-        const bool nin = N >= 0 && N < dc.nz;
-        const float wK = nin ? 0.75f : 0.75f + 0.25f * ms, wN = nin ? 0.25f : 0.f;
-        const float sm = (s >= 0 && s < df.nz) ? 1.f : 0.f;
-        const float *QK = sQ[(K + 3) % 3], *QN = sQ[(N + 3) % 3];
-        float *U = sU[par];
+        {
+            const int N = par ? K + 1 : K - 1;
+            const bool nin = N >= 0 && N < dc.nz;
+            const float wK = nin ? 0.75f : 0.75f + 0.25f * ms, wN = nin ? 0.25f : 0.f;
+            const float sm = (s >= 0 && s < df.nz) ? 1.f : 0.f;
+            const float *QK = sQ[(K + 3) % 3], *QN = sQ[(N + 3) % 3];
+            float *U = sU[par];
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const float uv = (xc[q] + wK * QK[col[q].c] + wN * QN[col[q].c]) * (col[q].in * sm);
-            u0[q] = u1[q];
-            u1[q] = u2[q];
-            u2[q] = uv;
-            U[col[q].c] = uv;
+            for (int q = 0; q < CPT; ++q) {
+                const float uv = (xc[q] + wK * QK[col[q].c] + wN * QN[col[q].c]) * (col[q].in * sm);
+                u0[q] = u1[q];
+                u1[q] = u2[q];
+                u2[q] = uv;
+                U[col[q].c] = uv;
+            }
         }
-        __syncthreads();
         const int p = s - 1;
         if (p >= k0 - 1) {
             const float pm = (p >= 0 && p < df.nz) ? 1.f : 0.f, dzp = vdz(p, df);
@@ -801,20 +818,19 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
                 v2[q] = vv;
                 V[col[q].c] = vv;
             }
-            __syncthreads();
-            const int t = s - 2;
-            if (t >= k0) {   // t < k1 holds: s <= k1 + 1
-                const float dzt = vdz(t, df);
-                const float *Vt = sV[par];
-                float *xop = xo + (size_t)t * plane;
+        }
+        const int t = s - 2;
+        if (t >= k0) {   // t < k1 holds: s <= k1 + 1
+            const float dzt = vdz(t, df);
+            const float *Vt = sV[par];
+            float *xop = xo + (size_t)t * plane;
 #pragma unroll
-                for (int q = 0; q < CPT; ++q) {
-                    const float nb = vnbr(Vt, col[q].c, W) + (v0[q] + v2[q]);
-                    const float w = v1[q] + wa * (h0[q] - ((col[q].dxy + dzt) * v1[q] - nb));
-                    if (col[q].own) {
-                        xop[col[q].off] = w;
-                        if constexpr (DOT) acc[0] += (double)h0[q] * (double)w;
-                    }
+            for (int q = 0; q < CPT; ++q) {
+                const float nb = vnbr(Vt, col[q].c, W) + (v0[q] + v2[q]);
+                const float w = v1[q] + wa * (h0[q] - ((col[q].dxy + dzt) * v1[q] - nb));
+                if (col[q].own) {
+                    xop[col[q].off] = w;
+                    if constexpr (DOT) acc[0] += (double)h0[q] * (double)w;
                 }
             }
         }
