@@ -419,7 +419,8 @@ def short_kernel_name(name):
 
 def pmc_summary(path):
     """Mean counter value per dispatch, by kernel name (namespaces and
-    argument lists dropped)."""
+    argument lists dropped) and grid size (a kernel that runs on every
+    multigrid level gets one line per level)."""
     import csv
     from collections import defaultdict
 
@@ -431,6 +432,8 @@ def pmc_summary(path):
             raise SystemExit(f"unexpected columns in {path}: {rows.fieldnames}")
         for row in rows:
             name = short_kernel_name(row["Kernel_Name"])
+            if row.get("Grid_Size"):
+                name += f" [grid {row['Grid_Size']}]"
             acc[name][row["Counter_Name"]] += float(row["Counter_Value"])
             disp[name].add(row["Dispatch_Id"])
     for name in sorted(acc, key=lambda k: -len(disp[k])):
