@@ -23,7 +23,8 @@ Also reported on the same JSON line:
   serving       a replayed Poisson-arrival request stream, continuous batching
                 vs one request at a time;
   secondary     the 128^3 torus (1e6 queries) and the 16-coefficient gradient
-                (forward + backward against 32 finite-difference forwards).
+                (forward + backward against 32 finite-difference forwards),
+                each with its error against the oracle (with cpu_baseline).
 """
 from __future__ import annotations
 
@@ -283,6 +284,14 @@ def secondary_run():
         r.sample(q)
     torch.cuda.synchronize()
     t_q = (time.perf_counter() - t0) / reps
+    # kept for the oracle comparison of the cpu_baseline leg
+    rng = np.random.default_rng(205)
+    nodes = rng.choice(128 ** 3, 400, replace=False)
+    pq, nq = r.sample(q[:200])
+    f = r.fields()
+    cmp = {"torus": {"x": x, "nrm": nrm, "chi": f["chi"].cpu().numpy(), "nodes": nodes,
+                     "phi_nodes": f["phi"].reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy(),
+                     "q": q[:200].cpu().numpy(), "phi_q": pq.cpu().numpy(), "n_q": nq.cpu().numpy()}}
     r.close()
     out["torus_128"] = {"recons_per_s": 1.0 / t_rec, "ms_per_recon": t_rec * 1e3,
                         "queries_per_s": q.shape[0] / t_q, "workload": "torus R 0.3 r 0.1, 200000 noisy points, "
@@ -301,7 +310,9 @@ def secondary_run():
         return phi
 
     phi = fwd()
-    r.backward(tq, (2.0 / T) * phi, rel_tol=1e-6)
+    gx, gn, _ = r.backward(tq, (2.0 / T) * phi, rel_tol=1e-6)
+    cmp["superellipsoid"] = {"x": xs, "nrm": ns, "targets": case.targets, "g_xyz": gx.cpu().numpy(),
+                             "g_nrm": gn.cpu().numpy()}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -319,7 +330,36 @@ def secondary_run():
                                           "fd_over_adjoint": t_fd / t_ad,
                                           "workload": "16-coefficient superellipsoid, 100000 points, 128^3, "
                                           "loss mean phi^2 at 65536 targets, rel res 1e-6"}
-    return out
+    return out, cmp
+
+
+def secondary_oracle_error(cmp):
+    """Part of the cpu_baseline leg: the GPU results of the two 128^3
+    workloads against the FP64 oracle (the torus field, SDF on 400 random
+    nodes, SDF and normals at 200 queries; the superellipsoid's point
+    gradients, all 100,000 points)."""
+    from oracle import discretize as D
+    from oracle import pipeline as P
+
+    grid = D.Grid.unit(128)
+    t = cmp["torus"]
+    ref = P.Recon(grid, t["x"], t["nrm"])
+    vq, nq = ref.sample(t["q"])
+    ok = np.linalg.norm(nq, axis=1) > 0
+    ang = np.arccos(np.clip(np.sum(t["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+    torus = {"chi_rel_l2": float(np.linalg.norm(t["chi"] - ref.chi) / np.linalg.norm(ref.chi)),
+             "phi_nodes_max_abs_over_h": float(np.abs(t["phi_nodes"] - ref.phi_nodes(t["nodes"])).max() * 128),
+             "phi_queries_max_abs_over_h": float(np.abs(t["phi_q"] - vq).max() * 128),
+             "normal_angle_max_rad": float(ang.max()), "nodes_compared": len(t["nodes"]),
+             "queries_compared": len(t["q"])}
+    e = cmp["superellipsoid"]
+    ref = P.Recon(grid, e["x"], e["nrm"])
+    phi, _ = ref.sample(e["targets"])
+    gx, gn, _ = ref.backward(e["targets"], 2.0 * phi / len(phi))
+    want = np.concatenate([gx, gn]).reshape(-1)
+    got = np.concatenate([e["g_xyz"], e["g_nrm"]]).reshape(-1).astype(np.float64)
+    sup = {"grad_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)), "points": len(e["x"])}
+    return {"torus_128": torus, "superellipsoid_128_gradient": sup}
 
 
 def serving_run(n_requests, max_inflight, budget_gb):
@@ -512,7 +552,10 @@ def main():
     if args.serving > 0:
         line["serving"] = serving_run(args.serving, 4, 64.0)
     if not args.no_secondary:
-        line["secondary"] = secondary_run()
+        line["secondary"], cmp = secondary_run()
+        if not args.no_cpu_baseline:
+            for k, v in secondary_oracle_error(cmp).items():
+                line["secondary"][k]["oracle_error"] = v
     print(json.dumps(line), flush=True)
 
 

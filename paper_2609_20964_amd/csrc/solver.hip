@@ -436,7 +436,11 @@ __device__ __forceinline__ Prolong1 prolong_w(int f, int nc, int s) {
 // Halo cells are recomputed by every tile that needs them; each output is
 // written by its owner tile only.
 constexpr int kVB = 512;                  // threads per workgroup
-constexpr int kVTX = 64, kVTY = 16;       // largest fine tile
+#ifndef WG_VTX
+#define WG_VTX 64
+#define WG_VTY 16
+#endif
+constexpr int kVTX = WG_VTX, kVTY = WG_VTY;       // largest fine tile
 constexpr int kPreH = 3, kPostH = 2;
 // the four corner cells of a haloed tile feed no 7-point stencil: no slot holds them
 constexpr int kPreCols = (kVTX + 2 * kPreH) * (kVTY + 2 * kPreH) - 4;
@@ -457,8 +461,8 @@ VTile vtile_of(const Dims &d) {
     t.ty = d.ny < kVTY ? d.ny : kVTY;
     t.gx = (int)cdiv(d.nx, t.tx);
     t.gy = (int)cdiv(d.ny, t.ty);
-    // longest chunk (fewest recomputed halo planes) that still gives >= 512 workgroups
-    for (t.zc = 16;; t.zc /= 2) {
+    // longest chunk (fewest recomputed halo planes, at most 32) that still gives >= 512 workgroups
+    for (t.zc = 32;; t.zc /= 2) {
         t.gz = (int)cdiv(d.nz, t.zc);
         if (t.zc == 2 || (size_t)t.gx * t.gy * t.gz >= 512) break;
     }

@@ -1,9 +1,9 @@
 """The Poisson solver's multigrid preconditioner z = M r (wg_mg_apply)
 against the float64 numpy V-cycle of tests/mg_reference.py, element by
-element.  Grids cover several tiles and z chunks (256 x 256 x 128 runs the
-chunk length of the 256^3 solves), a partial x tile, odd coarse extents, the
-Jacobi coarsest level and a single-level hierarchy.  Bar: relative L2 error
-1e-5 (FP32 sweeps)."""
+element.  Grids cover several tiles and z chunks (256^3 in the launch
+configuration of the benchmark's solves), a partial x tile, odd coarse
+extents, the Jacobi coarsest level and a single-level hierarchy.  Bar:
+relative L2 error 1e-5 (FP32 sweeps)."""
 import numpy as np
 import pytest
 
@@ -20,7 +20,7 @@ def _rel(a, b):
 @pytest.mark.parametrize("n,bc", [((64, 64, 64), "neumann"), ((96, 64, 32), "dirichlet"),
                                   ((48, 40, 24), "neumann"), ((36, 20, 20), "dirichlet"),
                                   ((34, 18, 20), "neumann"), ((16, 16, 16), "neumann"),
-                                  ((256, 256, 128), "neumann")])
+                                  ((256, 256, 256), "neumann")])
 def test_vcycle_matches_definition(n, bc):
     from paper_2609_20964_amd.recon import Recon
     shape = (n[2], n[1], n[0])
