@@ -363,70 +363,72 @@ def secondary_oracle_error(cmp):
 
 
 def serving_run(n_requests, max_inflight, budget_gb):
-    """The request stream replayed twice: at its own Poisson arrival times
-    (latency at the offered load) and with every request arriving at once
-    (throughput at saturation); each as continuous batching and one at a time."""
+    """The request stream replayed on two resident servers, continuous
+    batching (max_inflight at once) and one request at a time: first once
+    untimed at saturation (the servers' handle pools fill, as a long-running
+    server's would), then at the stream's own Poisson arrival times (latency at
+    the offered load) and with every request arriving at once (throughput at
+    saturation)."""
     import torch
 
     from paper_2609_20964_amd import synth
+    from paper_2609_20964_amd.serving import Server
 
     reqs = []
     for rq in synth.request_stream(n_requests):
         x, nrm = rq.cloud()
         reqs.append((rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(),
                      torch.from_numpy(rq.queries()).cuda()))
-    out = {"offered_load": replay(reqs, max_inflight, budget_gb, 1.0),
-           "saturated": replay(reqs, max_inflight, budget_gb, 0.0)}
+    out = {"offered_load": {}, "saturated": {}}
+    for mode, inflight in (("batched", max_inflight), ("plain", 1)):
+        srv = Server(int(budget_gb * (1 << 30)), max_inflight=inflight)
+        replay(srv, reqs, 0.0)
+        out["offered_load"][mode] = dict(max_inflight=inflight, **replay(srv, reqs, 1.0))
+        out["saturated"][mode] = dict(max_inflight=inflight, **replay(srv, reqs, 0.0))
+        srv.close()
     out["workload"] = (f"{len(reqs)} requests, Poisson arrivals 50/s, grids 64/128/256 (0.5/0.3/0.2), "
                        "log-normal points (median 50k), 30% with gradient, rel. res 1e-6; "
-                       "saturated = all requests at t=0")
+                       "saturated = all requests at t=0; servers warmed by one untimed saturated pass")
     return out
 
 
-def replay(reqs, max_inflight, budget_gb, time_scale):
+def replay(srv, reqs, time_scale):
     import threading
 
     import torch
 
-    from paper_2609_20964_amd.serving import Server
-
     arrival = [rq.arrival_s * time_scale for rq, *_ in reqs]
-    out = {}
-    for mode, inflight in (("batched", max_inflight), ("plain", 1)):
-        srv = Server(int(budget_gb * (1 << 30)), max_inflight=inflight)
-        tickets = [None] * len(reqs)
-        start = time.perf_counter()
+    tickets = [None] * len(reqs)
+    start = time.perf_counter()
 
-        def client():
-            for i, (rq, x, nrm, q) in enumerate(reqs):
-                delay = arrival[i] - (time.perf_counter() - start)
-                if delay > 0:
-                    time.sleep(delay)
-                gphi = torch.full((q.shape[0],), 1.0 / q.shape[0], device="cuda") if rq.want_grad else None
-                tickets[i] = (srv.submit(rq.n, x, nrm, q, gphi=gphi, rel_tol=1e-6), time.perf_counter() - start)
+    def client():
+        for i, (rq, x, nrm, q) in enumerate(reqs):
+            delay = arrival[i] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            gphi = torch.full((q.shape[0],), 1.0 / q.shape[0], device="cuda") if rq.want_grad else None
+            tickets[i] = (srv.submit(rq.n, x, nrm, q, gphi=gphi, rel_tol=1e-6), time.perf_counter() - start)
 
-        th = threading.Thread(target=client)
-        th.start()
-        done = {}
-        while len(done) < len(reqs):
-            for i in range(len(reqs)):
-                if i in done or tickets[i] is None:
-                    continue
-                res = srv.poll(tickets[i][0])
-                if res is not None:
-                    done[i] = (res, time.perf_counter() - start)
-            time.sleep(0.0005)
-        th.join()
-        lat = np.array([done[i][1] - arrival[i] for i in range(len(reqs))])
-        span = max(d[1] for d in done.values()) - arrival[0]
-        ok = sum(1 for d in done.values() if d[0][0] in (0, -3))
-        cells = sum(rq.n ** 3 for rq, *_ in reqs)
-        out[mode] = {"max_inflight": inflight, "req_per_s": len(reqs) / span, "cells_per_s": cells / span,
-                     "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                     "ok": ok, "requests": len(reqs),
-                     "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
-        srv.close()
-    return out
+    th = threading.Thread(target=client)
+    th.start()
+    done = {}
+    while len(done) < len(reqs):
+        for i in range(len(reqs)):
+            if i in done or tickets[i] is None:
+                continue
+            res = srv.poll(tickets[i][0])
+            if res is not None:
+                done[i] = (res, time.perf_counter() - start)
+        time.sleep(0.0005)
+    th.join()
+    lat = np.array([done[i][1] - arrival[i] for i in range(len(reqs))])
+    span = max(d[1] for d in done.values()) - arrival[0]
+    ok = sum(1 for d in done.values() if d[0][0] in (0, -3))
+    cells = sum(rq.n ** 3 for rq, *_ in reqs)
+    return {"req_per_s": len(reqs) / span, "cells_per_s": cells / span,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "ok": ok, "requests": len(reqs),
+            "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
 
 
 def copy_probe():

@@ -10,7 +10,9 @@
 // bytes of all resident handles stay within the HBM budget; idle handles of
 // other classes are evicted (least recently used first) to make room, and a
 // worker waits when everything resident is busy.  Every handle owns its own
-// HIP stream, so the kernels of concurrent requests overlap on the device.
+// HIP stream, so the kernels of concurrent requests overlap on the device; a
+// request that starts alone runs its distance walk persistent, one that starts
+// beside others runs it as independent workgroups.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -67,7 +69,6 @@ class Server {
         WG_HIP(hipSetDevice(device_));
         WG_HIP(hipStreamCreateWithFlags(&ingest_, hipStreamNonBlocking));
         t0_ = std::chrono::steady_clock::now();
-        n_workers_ = max_inflight;
         for (int k = 0; k < max_inflight; ++k) workers_.emplace_back([this] { worker(); });
     }
 
@@ -184,8 +185,6 @@ class Server {
                 try {
                     WG_HIP(hipStreamCreateWithFlags(&h.s, hipStreamNonBlocking));
                     h.r = new Recon(g, k.cap, h.s);
-                    // concurrent handles: let their walks interleave by workgroup
-                    h.r->set_persistent(n_workers_ == 1);
                 } catch (...) {
                     if (h.s) (void)hipStreamDestroy(h.s);
                     lk.lock();
@@ -201,8 +200,13 @@ class Server {
         }
     }
 
-    void run(Job &j, Handle &h) {
+    // alone: no other request was running when this one started.  A lone
+    // request's distance walk runs persistent (fastest alone); with others
+    // running, walks go one workgroup per tile group so concurrent requests
+    // interleave instead of queueing behind a walk that holds every slot.
+    void run(Job &j, Handle &h, bool alone) {
         const wg_request &rq = j.req;
+        h.r->set_persistent(alone);
         wg_solve_opts o = rq.opts;
         o.warm_start = 0;   // a request's result must not depend on what ran before it
         int st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats);
@@ -242,9 +246,10 @@ class Server {
                 h = acquire(k, j->req.grid, lk);
                 have = true;
                 j->res.t_start = now();
+                const bool alone = running_ == 1;
                 lk.unlock();
                 try {
-                    run(*j, h);
+                    run(*j, h, alone);
                 } catch (const Error &e) {
                     set_error(e.what());
                     j->res.status = e.code;
@@ -276,7 +281,6 @@ class Server {
     std::map<uint64_t, std::unique_ptr<Job>> jobs_;
     std::list<Handle> idle_;
     std::vector<std::thread> workers_;
-    int n_workers_ = 1;
     size_t resident_ = 0;
     uint64_t next_ticket_ = 0, clock_ = 0;
     int running_ = 0;
