@@ -111,6 +111,19 @@ def test_ragged_grid_offset_origin():
     _forward_parity(g, x, n, q)
 
 
+def test_ragged_96_80_72_partial_tiles():
+    # x and y extents that leave partial tiles in the V-cycle passes (96 = 64 + 32);
+    # four levels, down to an exact solve on 12 x 10 x 9 (an odd extent)
+    g = D.Grid((96, 80, 72), (0.0, 0.0, 0.0), 1.0 / 96)
+    x, n = synth.sphere(20000, radius=0.22, seed=35)
+    x = (x.astype(np.float64) - 0.5 + np.array([0.48, 0.40, 0.36])).astype(np.float32)
+    rng = np.random.default_rng(36)
+    hi = np.array(g.n) * g.h
+    q = rng.uniform(0.0, hi, (3000, 3)).astype(np.float32)
+    nodes = rng.choice(96 * 80 * 72, 3000, replace=False)
+    _forward_parity(g, x, n, q, full_phi=False, node_sample=nodes)
+
+
 def test_torus_noisy_64():
     g = D.Grid.unit(64)
     x, n = synth.torus(20000)
@@ -131,7 +144,10 @@ def _mode(bc, shape, k):
 
 @pytest.mark.parametrize("bc,n", [("neumann", (32, 32, 32)), ("dirichlet", (32, 32, 32)),
                                   ("neumann", (64, 64, 64)), ("dirichlet", (64, 64, 64)),
-                                  ("neumann", (20, 24, 28)), ("dirichlet", (12, 40, 16))])
+                                  ("neumann", (20, 24, 28)), ("dirichlet", (12, 40, 16)),
+                                  # single-level hierarchies: the exact coarsest solve alone, and the
+                                  # Jacobi-swept odd level as the whole preconditioner
+                                  ("neumann", (16, 12, 16)), ("dirichlet", (17, 9, 11))])
 def test_poisson_manufactured(bc, n):
     from paper_2609_20964_amd.recon import Recon
     shape = (n[2], n[1], n[0])
