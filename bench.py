@@ -254,17 +254,38 @@ def cpu_baseline(res, n, sample_nodes):
 
 
 def secondary_run():
-    """The two 128^3 workloads: the noisy torus (200,000 points, 1,000,000
-    queries, rel. res 1e-6, cold solve) and the differentiable superellipsoid
-    (100,000 points, 65,536 targets): forward + backward against the 32
-    forward evaluations a central finite-difference gradient in 16
-    coefficients needs."""
+    """The smaller workloads: the 32^3 sphere (4,096 points and queries, rel.
+    res 1e-8), the noisy 128^3 torus (200,000 points, 1,000,000 queries, rel.
+    res 1e-6, cold solve) and the differentiable 128^3 superellipsoid (100,000
+    points, 65,536 targets): forward + backward, chained to the 16 shape
+    coefficients, against the 32 forward evaluations a central
+    finite-difference gradient needs."""
     import torch
 
     from paper_2609_20964_amd import synth
     from paper_2609_20964_amd.recon import Recon
 
     out = {}
+    reps = 5
+    x, nrm = synth.sphere()
+    q = torch.from_numpy(synth.uniform_queries(4096, 102)).cuda()
+    xd, nd = torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda()
+    r = Recon(32, len(x))
+    r.forward(xd, nd, rel_tol=1e-8)
+    r.sample(q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r.forward(xd, nd, rel_tol=1e-8)
+        pq, nq = r.sample(q)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / reps
+    cmp = {"sphere": {"x": x, "nrm": nrm, "phi": r.fields()["phi"].cpu().numpy(), "q": q.cpu().numpy(),
+                      "phi_q": pq.cpu().numpy(), "n_q": nq.cpu().numpy()}}
+    r.close()
+    out["sphere_32"] = {"recons_per_s": 1.0 / t_s, "ms_per_recon": t_s * 1e3,
+                        "workload": "sphere r 0.3, 4096 points, 32^3, rel res 1e-8, SDF and normals at 4096 queries"}
+
     x, nrm = synth.torus(200_000)
     q = torch.from_numpy(synth.uniform_queries(1_000_000, 204)).cuda()
     xd, nd = torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda()
@@ -272,7 +293,6 @@ def secondary_run():
     r.forward(xd, nd, rel_tol=1e-6)
     r.sample(q)
     torch.cuda.synchronize()
-    reps = 5
     t0 = time.perf_counter()
     for _ in range(reps):
         r.forward(xd, nd, rel_tol=1e-6)
@@ -289,16 +309,18 @@ def secondary_run():
     nodes = rng.choice(128 ** 3, 400, replace=False)
     pq, nq = r.sample(q[:200])
     f = r.fields()
-    cmp = {"torus": {"x": x, "nrm": nrm, "chi": f["chi"].cpu().numpy(), "nodes": nodes,
+    cmp["torus"] = {"x": x, "nrm": nrm, "chi": f["chi"].cpu().numpy(), "nodes": nodes,
                      "phi_nodes": f["phi"].reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy(),
-                     "q": q[:200].cpu().numpy(), "phi_q": pq.cpu().numpy(), "n_q": nq.cpu().numpy()}}
+                     "q": q[:200].cpu().numpy(), "phi_q": pq.cpu().numpy(), "n_q": nq.cpu().numpy()}
     r.close()
     out["torus_128"] = {"recons_per_s": 1.0 / t_rec, "ms_per_recon": t_rec * 1e3,
                         "queries_per_s": q.shape[0] / t_q, "workload": "torus R 0.3 r 0.1, 200000 noisy points, "
                         "128^3, cold solve to rel res 1e-6, SDF and normals at 1e6 queries"}
 
     case = synth.diff_case()
-    xs, ns = synth.star(case.shape.coeffs, 100_000, 302)
+    ct = torch.tensor(case.shape.coeffs, dtype=torch.float64, requires_grad=True)
+    xt, nt = synth.star_points_torch(case.shape, case.dirs, ct)
+    xs, ns = xt.detach().numpy().astype(np.float32), nt.detach().numpy().astype(np.float32)
     xd, nd = torch.from_numpy(xs).cuda(), torch.from_numpy(ns).cuda()
     tq = torch.from_numpy(case.targets).cuda()
     T = tq.shape[0]
@@ -311,8 +333,11 @@ def secondary_run():
 
     phi = fwd()
     gx, gn, _ = r.backward(tq, (2.0 / T) * phi, rel_tol=1e-6)
+    # dL/dc: the point gradients chained through the shape generator (torch autograd, FP64, CPU)
+    (dldc,) = torch.autograd.grad((xt * gx.cpu().double()).sum() + (nt * gn.cpu().double()).sum(), ct,
+                                  retain_graph=True)
     cmp["superellipsoid"] = {"x": xs, "nrm": ns, "targets": case.targets, "g_xyz": gx.cpu().numpy(),
-                             "g_nrm": gn.cpu().numpy()}
+                             "g_nrm": gn.cpu().numpy(), "dldc": dldc.numpy(), "xt": xt, "nt": nt, "ct": ct}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -334,13 +359,23 @@ def secondary_run():
 
 
 def secondary_oracle_error(cmp):
-    """Part of the cpu_baseline leg: the GPU results of the two 128^3
-    workloads against the FP64 oracle (the torus field, SDF on 400 random
-    nodes, SDF and normals at 200 queries; the superellipsoid's point
-    gradients, all 100,000 points)."""
+    """Part of the cpu_baseline leg: the GPU results of the smaller workloads
+    against the FP64 oracle (the sphere's SDF on every node and at every
+    query; the torus field, SDF on 400 random nodes, SDF and normals at 200
+    queries; the superellipsoid's point gradients, all 100,000 points, and
+    its dL/dc through the same shape generator)."""
     from oracle import discretize as D
     from oracle import pipeline as P
 
+    s = cmp["sphere"]
+    g32 = D.Grid.unit(32)
+    ref = P.Recon(g32, s["x"], s["nrm"])
+    vq, nq = ref.sample(s["q"])
+    ok = np.linalg.norm(nq, axis=1) > 0
+    ang = np.arccos(np.clip(np.sum(s["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+    sphere = {"phi_grid_max_abs_over_h": float(np.abs(s["phi"].astype(np.float64) - ref.phi_grid()).max() * 32),
+              "phi_queries_max_abs_over_h": float(np.abs(s["phi_q"] - vq).max() * 32),
+              "normal_angle_max_rad": float(ang.max()), "nodes_compared": 32 ** 3, "queries_compared": len(s["q"])}
     grid = D.Grid.unit(128)
     t = cmp["torus"]
     ref = P.Recon(grid, t["x"], t["nrm"])
@@ -358,8 +393,14 @@ def secondary_oracle_error(cmp):
     gx, gn, _ = ref.backward(e["targets"], 2.0 * phi / len(phi))
     want = np.concatenate([gx, gn]).reshape(-1)
     got = np.concatenate([e["g_xyz"], e["g_nrm"]]).reshape(-1).astype(np.float64)
-    sup = {"grad_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)), "points": len(e["x"])}
-    return {"torus_128": torus, "superellipsoid_128_gradient": sup}
+    import torch
+    (dldc_ref,) = torch.autograd.grad((e["xt"] * torch.from_numpy(gx)).sum() + (e["nt"] * torch.from_numpy(gn)).sum(),
+                                      e["ct"])
+    dldc_ref = dldc_ref.numpy()
+    sup = {"point_grad_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)), "points": len(e["x"]),
+           "dL_dc_rel_l2": float(np.linalg.norm(e["dldc"] - dldc_ref) / np.linalg.norm(dldc_ref)),
+           "dL_dc_max_rel": float(np.abs(e["dldc"] - dldc_ref).max() / np.abs(dldc_ref).max())}
+    return {"sphere_32": sphere, "torus_128": torus, "superellipsoid_128_gradient": sup}
 
 
 def serving_run(n_requests, max_inflight, budget_gb):
@@ -380,19 +421,56 @@ def serving_run(n_requests, max_inflight, budget_gb):
         reqs.append((rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(),
                      torch.from_numpy(rq.queries()).cuda()))
     out = {"offered_load": {}, "saturated": {}}
+    cmp = None
     for mode, inflight in (("batched", max_inflight), ("plain", 1)):
         srv = Server(int(budget_gb * (1 << 30)), max_inflight=inflight)
         replay(srv, reqs, 0.0)
-        out["offered_load"][mode] = dict(max_inflight=inflight, **replay(srv, reqs, 1.0))
-        out["saturated"][mode] = dict(max_inflight=inflight, **replay(srv, reqs, 0.0))
+        stats, done = replay(srv, reqs, 1.0, keep=True)
+        out["offered_load"][mode] = dict(max_inflight=inflight, **stats)
+        stats, _ = replay(srv, reqs, 0.0)
+        out["saturated"][mode] = dict(max_inflight=inflight, **stats)
         srv.close()
+        if mode == "batched":
+            # kept for the oracle comparison of the cpu_baseline leg: a seeded
+            # subset of the 64^3 requests and of the others, SDF and normals at
+            # their first 200 queries
+            rng = np.random.default_rng(506)
+            small = [i for i, (rq, *_) in enumerate(reqs) if rq.n == 64]
+            big = [i for i, (rq, *_) in enumerate(reqs) if rq.n != 64]
+            pick = sorted(rng.choice(small, min(8, len(small)), replace=False).tolist() +
+                          rng.choice(big, min(2, len(big)), replace=False).tolist())
+            cmp = []
+            for i in pick:
+                rq, x, nrm, q = reqs[i]
+                outs = done[i][0][1]
+                cmp.append({"n": rq.n, "x": x.cpu().numpy(), "nrm": nrm.cpu().numpy(), "q": q[:200].cpu().numpy(),
+                            "phi_q": outs["phi"][:200].cpu().numpy(), "n_q": outs["nrm"][:200].cpu().numpy()})
     out["workload"] = (f"{len(reqs)} requests, Poisson arrivals 50/s, grids 64/128/256 (0.5/0.3/0.2), "
                        "log-normal points (median 50k), 30% with gradient, rel. res 1e-6; "
                        "saturated = all requests at t=0; servers warmed by one untimed saturated pass")
-    return out
+    return out, cmp
 
 
-def replay(srv, reqs, time_scale):
+def serving_oracle_error(cmp):
+    """Part of the cpu_baseline leg: served results (batched, offered load)
+    against the FP64 oracle: SDF and normals at the first 200 queries of 8
+    seeded 64^3 requests and 2 seeded larger ones."""
+    from oracle import discretize as D
+    from oracle import pipeline as P
+
+    worst_phi, worst_ang = 0.0, 0.0
+    for c in cmp:
+        ref = P.Recon(D.Grid.unit(c["n"]), c["x"], c["nrm"])
+        vq, nq = ref.sample(c["q"])
+        worst_phi = max(worst_phi, float(np.abs(c["phi_q"] - vq).max() * c["n"]))
+        ok = np.linalg.norm(nq, axis=1) > 0
+        ang = np.arccos(np.clip(np.sum(c["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+        worst_ang = max(worst_ang, float(ang.max()) if ang.size else 0.0)
+    return {"phi_queries_max_abs_over_h": worst_phi, "normal_angle_max_rad": worst_ang,
+            "requests_compared": [c["n"] for c in cmp], "queries_per_request": 200}
+
+
+def replay(srv, reqs, time_scale, keep=False):
     import threading
 
     import torch
@@ -425,10 +503,11 @@ def replay(srv, reqs, time_scale):
     span = max(d[1] for d in done.values()) - arrival[0]
     ok = sum(1 for d in done.values() if d[0][0] in (0, -3))
     cells = sum(rq.n ** 3 for rq, *_ in reqs)
-    return {"req_per_s": len(reqs) / span, "cells_per_s": cells / span,
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "ok": ok, "requests": len(reqs),
-            "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
+    stats = {"req_per_s": len(reqs) / span, "cells_per_s": cells / span,
+             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+             "ok": ok, "requests": len(reqs),
+             "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
+    return stats, (done if keep else None)
 
 
 def copy_probe():
@@ -552,7 +631,9 @@ def main():
         line["cpu_baseline"] = base
         line["oracle_error"] = err
     if args.serving > 0:
-        line["serving"] = serving_run(args.serving, 4, 64.0)
+        line["serving"], scmp = serving_run(args.serving, 4, 64.0)
+        if not args.no_cpu_baseline:
+            line["serving"]["oracle_error"] = serving_oracle_error(scmp)
     if not args.no_secondary:
         line["secondary"], cmp = secondary_run()
         if not args.no_cpu_baseline:
