@@ -22,8 +22,8 @@ constexpr int TX = 64, TY = 4, ZC = 16;
 constexpr int kRedBlocks = 2048;     // grid of the pointwise reductions
 constexpr int kMaxRed = 5;
 constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi factor of the sweeps on an odd-sized coarsest level
-constexpr int kCoarseTarget = 16;       // coarsen until every extent is <= this (or odd)
-constexpr int kCoarseAxis = 16;         // exact coarsest solve when every extent is <= this
+constexpr int kCoarseTarget = 32;       // coarsen until every extent is <= this (or odd)
+constexpr int kCoarseAxis = 32;         // exact coarsest solve when every extent is <= this
 
 struct Tiles {
     unsigned gx, gy, gz;
@@ -277,30 +277,24 @@ constexpr double kChebL2 = (2.0 + kChebLo) / 2 + (2.0 - kChebLo) / 2 * 0.7071067
 constexpr float kChebWa = (float)(1.0 / (6.0 * kChebL1));
 constexpr float kChebWb = (float)(1.0 / (6.0 * kChebL2));
 
-// Weighted-Jacobi sweep x_out = x + w (rhs - A x) / diag; DOT adds rhs . x_out.
-template <bool DOT>
+// Weighted-Jacobi sweep x_out = x + w (rhs - A x) / diag (only on an
+// odd-sized coarsest level, where no exact solve applies).
 struct OpSmooth {
     using T = float;
-    static constexpr int NRED = DOT ? 1 : 0;
+    static constexpr int NRED = 0;
     const float *x, *rhs;
     float *out;
     float w;
     __device__ float load(size_t i) const { return x[i]; }
     __device__ float load1(size_t i) const { return x[i]; }
     __device__ V4<float> load4(size_t i) const { return ld4(x + i); }
-    __device__ void apply(size_t i, float c, float s, float diag, double *acc) const {
-        float rv = rhs[i];
-        float v = c + w * (rv - (diag * c - s)) / diag;
-        out[i] = v;
-        if constexpr (DOT) acc[0] += (double)rv * (double)v;
+    __device__ void apply(size_t i, float c, float s, float diag, double *) const {
+        out[i] = c + w * (rhs[i] - (diag * c - s)) / diag;
     }
-    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *acc) const {
+    __device__ void apply4(size_t i, const V4<float> &c, const V4<float> &s, const V4<float> &dg, double *) const {
         const V4<float> r = ld4(rhs + i);
         V4<float> o;
-        for (int q = 0; q < 4; ++q) {
-            o.v[q] = c.v[q] + w * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
-            if constexpr (DOT) acc[0] += (double)r.v[q] * (double)o.v[q];
-        }
+        for (int q = 0; q < 4; ++q) o.v[q] = c.v[q] + w * (r.v[q] - (dg.v[q] * c.v[q] - s.v[q])) / dg.v[q];
         st4(out + i, o);
     }
 };
@@ -436,11 +430,7 @@ __device__ __forceinline__ Prolong1 prolong_w(int f, int nc, int s) {
 // Halo cells are recomputed by every tile that needs them; each output is
 // written by its owner tile only.
 constexpr int kVB = 512;                  // threads per workgroup
-#ifndef WG_VTX
-#define WG_VTX 64
-#define WG_VTY 16
-#endif
-constexpr int kVTX = WG_VTX, kVTY = WG_VTY;       // largest fine tile
+constexpr int kVTX = 64, kVTY = 16;       // largest fine tile
 constexpr int kPreH = 3, kPostH = 2;
 // the four corner cells of a haloed tile feed no 7-point stencil: no slot holds them
 constexpr int kPreCols = (kVTX + 2 * kPreH) * (kVTY + 2 * kPreH) - 4;
@@ -858,98 +848,110 @@ __global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
-// Exact solve on the coarsest level (every extent <= kCoarseAxis = 16) by the
+// Exact solve on the coarsest level (every extent <= kCoarseAxis) by the
 // separable eigenbasis of the 7-point operator: transform along x, y, z with
 // the orthonormal 1-D bases, divide by lambda_x + lambda_y + lambda_z (the
-// constant mode is dropped), transform back.  One workgroup of 16 x 16
-// threads; the field sits in LDS as [k][j][i] (row length padded to 17 so the
-// strided line reads are free of bank conflicts), each thread transforms whole
-// lines held in registers, and the bases sit in LDS zero-padded to 16 x 16
-// (every lane reads the same entry: a broadcast).  E = [phi_x (cx*cx),
-// phi_y (cy*cy), phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] =
-// mode m at cell i.
-constexpr int kEigPad = kCoarseAxis + 1;
-constexpr int kEigB = kCoarseAxis * kCoarseAxis;
+// constant mode is dropped), transform back.  Three small kernels: the x and
+// y transforms of one z plane per workgroup, then the z transform, division
+// and inverse z transform of one y row of coefficients per workgroup, then
+// the inverse y and x transforms per z plane.  Each workgroup stages its
+// 32 x 32 slice and the bases in LDS (rows padded to 33 floats; the bases
+// stored so that a wavefront's lanes read consecutive or identical entries)
+// and computes four outputs per thread.  E = [phi_x (cx*cx), phi_y (cy*cy),
+// phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] = mode m at cell i.
+constexpr int kEigN = kCoarseAxis;
+static_assert(kEigN == 32, "the eigen-solve kernels assume 32 x 32 slices and 256 threads");
 
-// out[m] = sum_i P[m][i] in[i] (FWD) or sum_i P[i][m] in[i] (inverse), P padded 16 x 16
+// FWD: c[k][my][mx] = sum_j sum_i phi_y[my][j] phi_x[mx][i] f[k][j][i] for z plane k = blockIdx.x;
+// inverse: f[k][j][i] = sum_my sum_mx phi_y[my][j] phi_x[mx][i] c[k][my][mx].
 template <bool FWD>
-__device__ __forceinline__ void eig_line(const float *P, const float (&in)[kCoarseAxis], float (&out)[kCoarseAxis]) {
-#pragma unroll
-    for (int m = 0; m < kCoarseAxis; ++m) out[m] = 0.f;
-#pragma unroll
-    for (int i = 0; i < kCoarseAxis; ++i) {
-#pragma unroll
-        for (int m = 0; m < kCoarseAxis; ++m) out[m] += P[FWD ? m * kCoarseAxis + i : i * kCoarseAxis + m] * in[i];
+__global__ __launch_bounds__(256) void k_eig_plane(const float *__restrict__ src, float *__restrict__ dst,
+                                                   const float *__restrict__ E, int cx, int cy) {
+    __shared__ float T[kEigN][kEigN + 1];
+    __shared__ float U[kEigN][kEigN + 1];
+    __shared__ float Px[kEigN][kEigN + 1];   // Px[i][m] = phi_x[m][i]
+    __shared__ float Py[kEigN][kEigN + 1];   // Py[j][m] = phi_y[m][j]
+    const size_t plane = (size_t)cx * cy, k = blockIdx.x;
+    const float *ex = E, *ey = E + cx * cx;
+    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
+        const int r = o / kEigN, c = o % kEigN;
+        Px[r][c] = (r < cx && c < cx) ? ex[c * cx + r] : 0.f;
+        Py[r][c] = (r < cy && c < cy) ? ey[c * cy + r] : 0.f;
+        T[r][c] = (r < cy && c < cx) ? src[k * plane + (size_t)r * cx + c] : 0.f;
+    }
+    __syncthreads();
+    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;   // lane in a row, 8 row groups
+    if (FWD) {
+        for (int j = g; j < kEigN; j += 8) {   // along x: U[j][m] = sum_i phi_x[m][i] T[j][i]
+            float acc = 0.f;
+#pragma unroll 8
+            for (int i = 0; i < kEigN; ++i) acc += Px[i][a] * T[j][i];
+            U[j][a] = acc;
+        }
+        __syncthreads();
+        for (int my = g; my < kEigN; my += 8) {   // along y: T[my][m] = sum_j phi_y[my][j] U[j][m]
+            float acc = 0.f;
+#pragma unroll 8
+            for (int j = 0; j < kEigN; ++j) acc += Py[j][my] * U[j][a];
+            T[my][a] = acc;
+        }
+    } else {
+        for (int j = g; j < kEigN; j += 8) {   // along y: U[j][m] = sum_my phi_y[my][j] T[my][m]
+            float acc = 0.f;
+#pragma unroll 8
+            for (int my = 0; my < kEigN; ++my) acc += Py[j][my] * T[my][a];
+            U[j][a] = acc;
+        }
+        __syncthreads();
+        for (int j = g; j < kEigN; j += 8) {   // along x: T[j][i] = sum_m phi_x[m][i] U[j][m]
+            float acc = 0.f;
+#pragma unroll 8
+            for (int m = 0; m < kEigN; ++m) acc += Px[a][m] * U[j][m];
+            T[j][a] = acc;
+        }
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
+        const int r = o / kEigN, c = o % kEigN;
+        if (r < cy && c < cx) dst[k * plane + (size_t)r * cx + c] = T[r][c];
     }
 }
 
-__global__ __launch_bounds__(256) void k_coarse_eig(const float *__restrict__ rhs, float *__restrict__ x,
-                                                     const float *__restrict__ E, int cx, int cy, int cz) {
-    __shared__ float L[kCoarseAxis * kCoarseAxis * kEigPad];
-    __shared__ float Pm[3 * kEigB + 3 * kCoarseAxis];
-    const int n = cx * cy * cz;
-    const int ext[3] = {cx, cy, cz};
-    {
-        const float *src = E;
-        for (int a = 0; a < 3; ++a) {
-            const int na = ext[a];
-            for (int o = threadIdx.x; o < kEigB; o += blockDim.x) {
-                const int m = o / kCoarseAxis, i = o % kCoarseAxis;
-                Pm[a * kEigB + o] = (m < na && i < na) ? src[m * na + i] : 0.f;
-            }
-            src += na * na;
-        }
-        for (int a = 0; a < 3; ++a) {
-            const int na = ext[a];
-            for (int o = threadIdx.x; o < kCoarseAxis; o += blockDim.x) Pm[3 * kEigB + a * kCoarseAxis + o] = o < na ? src[o] : 0.f;
-            src += na;
-        }
+// In place on the coefficients of y mode my = blockIdx.x: transform along z,
+// divide by the eigenvalue (0 for the constant mode), transform back.
+__global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const float *__restrict__ E, int cx, int cy,
+                                               int cz) {
+    __shared__ float V[kEigN][kEigN + 1];
+    __shared__ float Wz[kEigN][kEigN + 1];
+    __shared__ float Pz[kEigN][kEigN + 1];   // Pz[k][n] = phi_z[n][k]
+    __shared__ float lx[kEigN], lz[kEigN];
+    const size_t plane = (size_t)cx * cy, my = blockIdx.x;
+    const float *ez = E + cx * cx + cy * cy, *lam = ez + cz * cz;
+    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
+        const int r = o / kEigN, c = o % kEigN;
+        Pz[r][c] = (r < cz && c < cz) ? ez[c * cz + r] : 0.f;
+        V[r][c] = (r < cz && c < cx) ? buf[(size_t)r * plane + my * cx + c] : 0.f;
     }
-    const float *Px = Pm, *Py = Pm + kEigB, *Pz = Pm + 2 * kEigB;
-    const float *Lx = Pm + 3 * kEigB, *Ly = Lx + kCoarseAxis, *Lz = Ly + kCoarseAxis;
-    auto at = [](int i, int j, int k) { return i + kEigPad * (j + kCoarseAxis * k); };
-    for (int o = threadIdx.x; o < kCoarseAxis * kCoarseAxis * kEigPad; o += blockDim.x) L[o] = 0.f;
-    __syncthreads();
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
-        L[at(i, j, k)] = rhs[o];
+    if (threadIdx.x < kEigN) {
+        lx[threadIdx.x] = threadIdx.x < cx ? lam[threadIdx.x] : 0.f;
+        lz[threadIdx.x] = threadIdx.x < cz ? lam[cx + cy + threadIdx.x] : 0.f;
     }
     __syncthreads();
-    const int u = threadIdx.x % kCoarseAxis, v = threadIdx.x / kCoarseAxis;
-    float in[kCoarseAxis], out[kCoarseAxis];
-    // forward x: line (j, k) = (u, v)
-    for (int i = 0; i < kCoarseAxis; ++i) in[i] = L[at(i, u, v)];
-    eig_line<true>(Px, in, out);
-    for (int i = 0; i < kCoarseAxis; ++i) L[at(i, u, v)] = out[i];
-    __syncthreads();
-    // forward y: line (i, k) = (u, v)
-    for (int j = 0; j < kCoarseAxis; ++j) in[j] = L[at(u, j, v)];
-    eig_line<true>(Py, in, out);
-    for (int j = 0; j < kCoarseAxis; ++j) L[at(u, j, v)] = out[j];
-    __syncthreads();
-    // forward z, divide by the eigenvalue (0 for the constant mode and the padding), inverse z: line (i, j)
-    for (int k = 0; k < kCoarseAxis; ++k) in[k] = L[at(u, v, k)];
-    eig_line<true>(Pz, in, out);
-    for (int k = 0; k < kCoarseAxis; ++k) {
-        const float lam = Lx[u] + Ly[v] + Lz[k];
-        in[k] = (u < cx && v < cy && k < cz && lam > 1e-12f) ? out[k] / lam : 0.f;
+    const float ly = lam[cx + my];
+    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;
+    for (int n = g; n < kEigN; n += 8) {   // along z and divide: W[n][m] = sum_k phi_z[n][k] V[k][m] / lambda
+        float acc = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < kEigN; ++k) acc += Pz[k][n] * V[k][a];
+        const float l = lx[a] + ly + lz[n];
+        Wz[n][a] = (a < cx && n < cz && l > 1e-12f) ? acc / l : 0.f;
     }
-    eig_line<false>(Pz, in, out);
-    for (int k = 0; k < kCoarseAxis; ++k) L[at(u, v, k)] = out[k];
     __syncthreads();
-    // inverse y
-    for (int j = 0; j < kCoarseAxis; ++j) in[j] = L[at(u, j, v)];
-    eig_line<false>(Py, in, out);
-    for (int j = 0; j < kCoarseAxis; ++j) L[at(u, j, v)] = out[j];
-    __syncthreads();
-    // inverse x
-    for (int i = 0; i < kCoarseAxis; ++i) in[i] = L[at(i, u, v)];
-    eig_line<false>(Px, in, out);
-    for (int i = 0; i < kCoarseAxis; ++i) L[at(i, u, v)] = out[i];
-    __syncthreads();
-    for (int o = threadIdx.x; o < n; o += blockDim.x) {
-        const int i = o % cx, j = (o / cx) % cy, k = o / (cx * cy);
-        x[o] = L[at(i, j, k)];
+    for (int k = g; k < cz; k += 8) {   // back along z: V[k][m] = sum_n phi_z[n][k] W[n][m]
+        float acc = 0.f;
+#pragma unroll 8
+        for (int n = 0; n < kEigN; ++n) acc += Pz[k][n] * Wz[n][a];
+        if (a < cx) buf[(size_t)k * plane + my * cx + a] = acc;
     }
 }
 
@@ -1029,7 +1031,7 @@ void basis_1d(int n, int bc, std::vector<double> &phi, std::vector<double> &lam)
     }
 }
 
-// 1-D eigenbases and eigenvalues of the coarsest level, laid out for k_coarse_eig.
+// 1-D eigenbases and eigenvalues of the coarsest level, laid out for the eigen-solve kernels.
 std::vector<float> coarse_basis(const Dims &d, int bc) {
     std::vector<float> out;
     std::vector<double> phi[3], lam[3];
@@ -1163,16 +1165,19 @@ void Solver::vcycle(int l) {
     const int last = (int)lv_.size() - 1;
     if (l == last) {
         if (coarse_direct_) {
-            k_coarse_eig<<<1, kCoarseAxis * kCoarseAxis, 0, st_>>>(L.rhs, L.x, coarseM_[bc_sign_ > 0 ? 1 : 0], L.d.nx, L.d.ny, L.d.nz);
+            const float *E = coarseM_[bc_sign_ > 0 ? 1 : 0];
+            k_eig_plane<true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny);
+            k_eig_z<<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz);
+            k_eig_plane<false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny);
             WG_LAUNCH_CHECK();
         } else {
             // no direct solve possible (odd extents): a fixed, even number of sweeps
             launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
             for (int k = 0; k < 15; ++k) {
-                launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
-                launch_stencil(OpSmooth<false>{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
+                launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
+                launch_stencil(OpSmooth{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
             }
-            launch_stencil(OpSmooth<false>{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
+            launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
         }
         return;
     }

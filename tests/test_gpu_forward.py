@@ -113,7 +113,7 @@ def test_ragged_grid_offset_origin():
 
 def test_ragged_96_80_72_partial_tiles():
     # x and y extents that leave partial tiles in the V-cycle passes (96 = 64 + 32);
-    # four levels, down to an exact solve on 12 x 10 x 9 (an odd extent)
+    # three levels, down to an exact solve on 24 x 20 x 18
     g = D.Grid((96, 80, 72), (0.0, 0.0, 0.0), 1.0 / 96)
     x, n = synth.sphere(20000, radius=0.22, seed=35)
     x = (x.astype(np.float64) - 0.5 + np.array([0.48, 0.40, 0.36])).astype(np.float32)
@@ -147,7 +147,7 @@ def _mode(bc, shape, k):
                                   ("neumann", (20, 24, 28)), ("dirichlet", (12, 40, 16)),
                                   # single-level hierarchies: the exact coarsest solve alone, and the
                                   # Jacobi-swept odd level as the whole preconditioner
-                                  ("neumann", (16, 12, 16)), ("dirichlet", (17, 9, 11))])
+                                  ("neumann", (16, 12, 16)), ("dirichlet", (33, 9, 11))])
 def test_poisson_manufactured(bc, n):
     from paper_2609_20964_amd.recon import Recon
     shape = (n[2], n[1], n[0])
