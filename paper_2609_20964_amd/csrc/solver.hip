@@ -860,7 +860,8 @@ __global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const 
 // and computes four outputs per thread.  E = [phi_x (cx*cx), phi_y (cy*cy),
 // phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] = mode m at cell i.
 constexpr int kEigN = kCoarseAxis;
-static_assert(kEigN == 32, "the eigen-solve kernels assume 32 x 32 slices and 256 threads");
+constexpr int kEigG = 256 / kEigN;   // row groups of a 256-thread workgroup
+static_assert(256 % kEigN == 0, "a row of the slice is a whole number of lanes");
 
 // FWD: c[k][my][mx] = sum_j sum_i phi_y[my][j] phi_x[mx][i] f[k][j][i] for z plane k = blockIdx.x;
 // inverse: f[k][j][i] = sum_my sum_mx phi_y[my][j] phi_x[mx][i] c[k][my][mx].
@@ -880,30 +881,30 @@ __global__ __launch_bounds__(256) void k_eig_plane(const float *__restrict__ src
         T[r][c] = (r < cy && c < cx) ? src[k * plane + (size_t)r * cx + c] : 0.f;
     }
     __syncthreads();
-    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;   // lane in a row, 8 row groups
+    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;   // lane in a row, kEigG row groups
     if (FWD) {
-        for (int j = g; j < kEigN; j += 8) {   // along x: U[j][m] = sum_i phi_x[m][i] T[j][i]
+        for (int j = g; j < kEigN; j += kEigG) {   // along x: U[j][m] = sum_i phi_x[m][i] T[j][i]
             float acc = 0.f;
 #pragma unroll 8
             for (int i = 0; i < kEigN; ++i) acc += Px[i][a] * T[j][i];
             U[j][a] = acc;
         }
         __syncthreads();
-        for (int my = g; my < kEigN; my += 8) {   // along y: T[my][m] = sum_j phi_y[my][j] U[j][m]
+        for (int my = g; my < kEigN; my += kEigG) {   // along y: T[my][m] = sum_j phi_y[my][j] U[j][m]
             float acc = 0.f;
 #pragma unroll 8
             for (int j = 0; j < kEigN; ++j) acc += Py[j][my] * U[j][a];
             T[my][a] = acc;
         }
     } else {
-        for (int j = g; j < kEigN; j += 8) {   // along y: U[j][m] = sum_my phi_y[my][j] T[my][m]
+        for (int j = g; j < kEigN; j += kEigG) {   // along y: U[j][m] = sum_my phi_y[my][j] T[my][m]
             float acc = 0.f;
 #pragma unroll 8
             for (int my = 0; my < kEigN; ++my) acc += Py[j][my] * T[my][a];
             U[j][a] = acc;
         }
         __syncthreads();
-        for (int j = g; j < kEigN; j += 8) {   // along x: T[j][i] = sum_m phi_x[m][i] U[j][m]
+        for (int j = g; j < kEigN; j += kEigG) {   // along x: T[j][i] = sum_m phi_x[m][i] U[j][m]
             float acc = 0.f;
 #pragma unroll 8
             for (int m = 0; m < kEigN; ++m) acc += Px[a][m] * U[j][m];
@@ -939,7 +940,7 @@ __global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const fl
     __syncthreads();
     const float ly = lam[cx + my];
     const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;
-    for (int n = g; n < kEigN; n += 8) {   // along z and divide: W[n][m] = sum_k phi_z[n][k] V[k][m] / lambda
+    for (int n = g; n < kEigN; n += kEigG) {   // along z and divide: W[n][m] = sum_k phi_z[n][k] V[k][m] / lambda
         float acc = 0.f;
 #pragma unroll 8
         for (int k = 0; k < kEigN; ++k) acc += Pz[k][n] * V[k][a];
@@ -947,7 +948,7 @@ __global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const fl
         Wz[n][a] = (a < cx && n < cz && l > 1e-12f) ? acc / l : 0.f;
     }
     __syncthreads();
-    for (int k = g; k < cz; k += 8) {   // back along z: V[k][m] = sum_n phi_z[n][k] W[n][m]
+    for (int k = g; k < cz; k += kEigG) {   // back along z: V[k][m] = sum_n phi_z[n][k] W[n][m]
         float acc = 0.f;
 #pragma unroll 8
         for (int n = 0; n < kEigN; ++n) acc += Pz[k][n] * Wz[n][a];
