@@ -63,7 +63,7 @@ class Surface {
     uint32_t *cnt_b_ = nullptr, *off_b_ = nullptr, *active_ = nullptr, *blk_ = nullptr;
     SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
     uint32_t *sign_ = nullptr;     // [ceil(N / 32)] node sides
-    uint32_t *next_tile_ = nullptr;   // work counter of the persistent distance walk
+    uint32_t *next_tile_ = nullptr;   // per-slab work counters of the distance walk
     unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
     SurfaceCounts cnt_{};
     // growable

@@ -23,6 +23,12 @@ constexpr int kTri = 4;                     // float4 per triangle record
 // internal node whose children are leaves
 constexpr uint32_t kKidsLeaves = 1u << 30;
 constexpr uint32_t kLeafEntry = 1u << 31;   // traversal stack entry: the node is a leaf
+// The distance walk's tiles are split into kWalkParts z slabs, one work queue
+// each; workgroup b starts on slab b % kWalkParts (the XCD it runs on, as
+// workgroups are dealt to the 8 XCDs in turn), so each XCD's L2 holds the part
+// of the hierarchy near its slab, and moves on to the other slabs' queues when
+// its own is empty.
+constexpr int kWalkParts = 8;
 
 
 __device__ __forceinline__ uint32_t compact3(uint32_t m) {
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(256) void k_sign_bits(const double *__restrict__ ch
 // Tile = LX x LY x (LZ * kTZ) nodes: lane (x, y, z) of an LX x LY x LZ block
 // owns the kTZ nodes z, z + LZ, ... of its column.
 template <int LX, int LY, int LZ, int kTZ>
-__global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, Dims d, double h,
+__global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sign, Dims d, double h,
                                               const float4 *__restrict__ nodes, const float4 *__restrict__ leaf_aabb,
                                               uint32_t root,
                                               const float4 *__restrict__ tri, uint32_t n_tris,
@@ -393,12 +399,22 @@ __global__ __launch_bounds__(256) void k_sdf(const uint32_t *__restrict__ sign, 
     constexpr int TZ = LZ * kTZ;
     const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
     const uint32_t n_tiles = (uint32_t)(tx * ty * tz);
-    // persistent: each wavefront takes the next tile until none is left
+    // persistent: each wavefront takes the next tile of its slab's queue, then
+    // of the following slabs', until every queue is empty (each queue is left
+    // once it runs dry, so every wavefront exits after at most kWalkParts
+    // failed takes)
+    int part = (int)(blockIdx.x % kWalkParts), visited = 0;
     for (;;) {
+        const uint32_t t0 = (uint32_t)((uint64_t)n_tiles * part / kWalkParts);
+        const uint32_t t1 = (uint32_t)((uint64_t)n_tiles * (part + 1) / kWalkParts);
         uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(next_tile, 1u);
+        if (lane == 0) tile = t0 + atomicAdd(next_tile + part, 1u);
         tile = __builtin_amdgcn_readfirstlane(tile);
-        if (tile >= n_tiles) break;   // whole wavefront
+        if (tile >= t1) {   // whole wavefront: this queue is empty
+            if (++visited == kWalkParts) break;
+            part = (part + 1) % kWalkParts;
+            continue;
+        }
         const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
         const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
         const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1);
@@ -726,7 +742,7 @@ void Surface::plan(Arena &a, const Dims &d) {
     a.reserve(2 * (size_t)cdiv(pad, scan::kScanBlock) * sizeof(uint32_t));
     a.reserve(sizeof(SurfaceCounts));
     a.reserve(cdiv(d.count(), 32) * sizeof(uint32_t));   // node sides
-    a.reserve(sizeof(uint32_t));                          // tile counter of the walk
+    a.reserve(kWalkParts * sizeof(uint32_t));             // tile counters of the walk
 }
 
 void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
@@ -740,7 +756,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     blk_ = a.take<uint32_t>(2 * (size_t)cdiv(nbricks_pad_, scan::kScanBlock));
     dcnt_ = a.take<SurfaceCounts>(1);
     sign_ = a.take<uint32_t>(cdiv(d.count(), 32));
-    next_tile_ = a.take<uint32_t>(1);
+    next_tile_ = a.take<uint32_t>(kWalkParts);
     // the persistent walk stays one workgroup per compute unit below full
     // residency: its workgroups only retire when the tile queue is empty, and
     // work on the handle's other stream (the next step's splat and solve, host
@@ -845,7 +861,7 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
                        int32_t *argmin, int *err, uint32_t *next_tile, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
-    WG_HIP(hipMemsetAsync(next_tile, 0, sizeof(uint32_t), s));
+    WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
     k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
                                                  next_tile);
     WG_LAUNCH_CHECK();
