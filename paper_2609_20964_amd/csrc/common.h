@@ -34,6 +34,25 @@ inline void require(bool ok, int code, const std::string &msg) {
     if (!ok) throw Error(code, msg);
 }
 
+// Wait until a kernel on stream s has stored `want` into the host-mapped word
+// *seq (after the data it publishes).  Polling returns as soon as the store
+// lands, without a stream synchronisation's completion round trip; the stream
+// is queried now and then so that an error, or a stream that drained without
+// publishing, ends the wait.
+inline void wait_published(const unsigned *seq, unsigned want, hipStream_t s) {
+    for (unsigned k = 1;; ++k) {
+        if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) return;
+        if ((k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(seq, __ATOMIC_ACQUIRE) == want) return;
+                throw Error(WG_EDEVICE, "a published result never arrived");
+            }
+            if (e != hipErrorNotReady) hip_check(e, "hipStreamQuery", __FILE__, __LINE__);
+        }
+    }
+}
+
 constexpr int kBlock = 256;   // threads per workgroup for 1-D kernels
 constexpr int kWave = 64;
 

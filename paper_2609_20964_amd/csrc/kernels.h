@@ -23,6 +23,51 @@ inline TileDims tile_dims(const Dims &d) {
     return {(d.nx + kTile - 1) / kTile, (d.ny + kTile - 1) / kTile, (d.nz + kTile - 1) / kTile};
 }
 
+// ---- recon.hip -------------------------------------------------------------
+// Copies n 32-bit words into host-mapped memory, then stores seq to *seq_dst.
+// One wavefront: it fits beside a resident persistent kernel, where the
+// runtime's copy kernels (several wavefronts per SIMD) wait until that
+// kernel's workgroups retire.
+__global__ void k_mirror_words(const uint32_t *src, uint32_t *dst, int n, unsigned *seq_dst, unsigned seq);
+
+// Host-mapped, coherent pinned memory for a small device record the host reads:
+// fetch() enqueues the copy, wait() returns once it has landed.
+template <class T> class HostMapped {
+  public:
+    HostMapped() = default;
+    HostMapped(const HostMapped &) = delete;
+    HostMapped &operator=(const HostMapped &) = delete;
+    ~HostMapped() {
+        if (host_) (void)hipHostFree(host_);
+    }
+    void alloc() {
+        WG_HIP(hipHostMalloc((void **)&host_, sizeof(Rec), hipHostMallocMapped | hipHostMallocCoherent));
+        WG_HIP(hipHostGetDevicePointer((void **)&dev_, host_, 0));
+        host_->seq = seq_;
+    }
+    void fetch(const void *src, hipStream_t s) {
+        static_assert(sizeof(T) % 4 == 0, "mirrored records are whole 32-bit words");
+        k_mirror_words<<<1, kWave, 0, s>>>(static_cast<const uint32_t *>(src), reinterpret_cast<uint32_t *>(&dev_->v),
+                                          (int)(sizeof(T) / 4), &dev_->seq, ++seq_);
+        WG_LAUNCH_CHECK();
+        s_ = s;
+    }
+    // the record of the last fetch()
+    const T &wait() const {
+        wait_published(&host_->seq, seq_, s_);
+        return host_->v;
+    }
+
+  private:
+    struct Rec {
+        T v;
+        unsigned seq;
+    };
+    Rec *host_ = nullptr, *dev_ = nullptr;
+    unsigned seq_ = 0;
+    hipStream_t s_ = nullptr;
+};
+
 // ---- splat.hip -------------------------------------------------------------
 __global__ void k_bin_points(const float *xyz, const float *nrm, int npts, GridF g, TileDims td, int32_t *keys,
                              float *xyz_c, float *nrm_c, int32_t *tile_of, uint32_t *rank, uint32_t *tile_cnt,

@@ -58,8 +58,14 @@ class Recon {
     uint32_t *ch_blk_ = nullptr, *ch_tot_ = nullptr, *chunk_tile_ = nullptr;
     TileDims td_{};
     float *xyz_ = nullptr, *nrm_ = nullptr;
-    int *err_ = nullptr, *herr_ = nullptr;
-    double *hscal_ = nullptr;
+    // scal_[0..7] (c, c shifted, g_c) and err_[0..3] are one device block,
+    // mirrored whole into hm_
+    int *err_ = nullptr;
+    struct Mirror {
+        double scal[8];
+        int err[4];
+    };
+    HostMapped<Mirror> hm_;
     int n_points_ = 0;
     bool have_forward_ = false;
     // second stream: the distance walk (and pipelined sampling)

@@ -11,6 +11,14 @@
 
 namespace wg {
 
+__global__ __launch_bounds__(kWave) void k_mirror_words(const uint32_t *src, uint32_t *dst, int n, unsigned *seq_dst,
+                                                          unsigned seq) {
+    for (int i = threadIdx.x; i < n; i += kWave) dst[i] = src[i];
+    // one wavefront: the fence orders every lane's stores before seq
+    __threadfence_system();
+    if (threadIdx.x == 0) __hip_atomic_store(seq_dst, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 namespace {
 
 constexpr int kIsoBlocks = 512;
@@ -77,8 +85,7 @@ void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
     }
     a.reserve((nt + (size_t)max_points / kChunk + 1) * sizeof(uint32_t));   // tile of each chunk
     a.reserve(kIsoBlocks * sizeof(double));
-    a.reserve(8 * sizeof(double));       // scalars: c, c_shifted, g_c
-    a.reserve(4 * sizeof(int));          // error flags
+    a.reserve(8 * sizeof(double) + 4 * sizeof(int));   // scalars (c, c_shifted, g_c), then error flags
     Solver::plan(a, d.nx, d.ny, d.nz);
     Surface::plan(a, d);
 }
@@ -122,12 +129,11 @@ Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_po
     ch_tot_ = arena_.take<uint32_t>(2);
     chunk_tile_ = arena_.take<uint32_t>(nt + (size_t)max_points / kChunk + 1);
     iso_part_ = arena_.take<double>(kIsoBlocks);
-    scal_ = arena_.take<double>(8);
-    err_ = arena_.take<int>(4);
+    scal_ = arena_.take<double>(10);
+    err_ = reinterpret_cast<int *>(scal_ + 8);
     solver_.bind(arena_, d_.nx, d_.ny, d_.nz, st_);
     surf_.bind(arena_, d_, st_);
-    WG_HIP(hipHostMalloc((void **)&herr_, 4 * sizeof(int), hipHostMallocDefault));
-    WG_HIP(hipHostMalloc((void **)&hscal_, 8 * sizeof(double), hipHostMallocDefault));
+    hm_.alloc();
     WG_HIP(hipMemsetAsync(chi_, 0, N * sizeof(double), st_));
     WG_HIP(hipMemsetAsync(err_, 0, 4 * sizeof(int), st_));
     WG_HIP(hipStreamSynchronize(st_));
@@ -139,8 +145,6 @@ Recon::~Recon() {
     if (ev_sdf_) (void)hipEventDestroy(ev_sdf_);
     if (ev_tail_) (void)hipEventDestroy(ev_tail_);
     if (sdf_st_) (void)hipStreamDestroy(sdf_st_);
-    if (herr_) (void)hipHostFree(herr_);
-    if (hscal_) (void)hipHostFree(hscal_);
 }
 
 // The handle stream waits (on the device) for the last distance walk.
@@ -165,10 +169,10 @@ size_t Recon::bytes_resident() const { return arena_.planned() + surf_.bytes(); 
 // walk flags (bit 1: stack overflow), read only once that walk is known to be
 // complete on the handle stream.
 void Recon::check_err(const char *what) {
-    WG_HIP(hipMemcpyAsync(herr_, err_, 4 * sizeof(int), hipMemcpyDeviceToHost, st_));
-    WG_HIP(hipStreamSynchronize(st_));
-    if (herr_[0] & 1) throw Error(WG_EINVAL, std::string(what) + ": a point lies outside the grid");
-    if (!sdf_pending_ && (herr_[1] & 2)) throw Error(WG_EDEVICE, "distance traversal stack overflow");
+    hm_.fetch(scal_, st_);
+    const Mirror &m = hm_.wait();
+    if (m.err[0] & 1) throw Error(WG_EINVAL, std::string(what) + ": a point lies outside the grid");
+    if (!sdf_pending_ && (m.err[1] & 2)) throw Error(WG_EDEVICE, "distance traversal stack overflow");
 }
 
 int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_opts &o, wg_stats *st,
@@ -226,9 +230,13 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     // the previous distance walk (and pipelined sampling) reads the triangle
     // records, the hierarchy, the node sides and phi that follow: wait for it
     join();
-    WG_HIP(hipMemcpyAsync(herr_ + 1, err_ + 1, sizeof(int), hipMemcpyDeviceToHost, st_));
-    surf_.extract(chi_, scal_);   // host-synchronising: the previous walk has finished
-    if (herr_[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
+    hm_.fetch(scal_, st_);        // c and the previous walk's flags
+    surf_.extract(chi_, scal_);   // waits for the triangle count
+    {
+        const Mirror &m = hm_.wait();
+        if (m.err[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
+        iso_c_ = m.scal[0];
+    }
     surf_.signs(chi_, scal_);
     WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
     tm.mark(4);
@@ -251,9 +259,8 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_);
     }
     tm.mark(5);
-    WG_HIP(hipMemcpyAsync(hscal_, scal_, sizeof(double), hipMemcpyDeviceToHost, st_));
-    check_err("sdf");
-    iso_c_ = hscal_[0];
+    if (!pipelined) check_err("sdf");
+    WG_HIP(hipEventSynchronize(tm.ev[5]));   // the timing events (a pipelined walk runs on the second stream)
     have_forward_ = true;
     if (st) {
         std::memset(st, 0, sizeof(*st));

@@ -25,6 +25,14 @@ struct SolveScalars {
     int pad;
 };
 
+// Host-mapped copy of the scalars: the finalize that writes it stores seq
+// last, and the host waits for the value it expects.
+struct PublishedScalars {
+    SolveScalars s;
+    unsigned seq;
+    unsigned pad;
+};
+
 struct SolveResult {
     int iters = 0, refinements = 0, status = WG_OK;
     double rel_res = 0.0, x_mean = 0.0;
@@ -64,7 +72,9 @@ class Solver {
     float *e_ = nullptr, *p_[2] = {nullptr, nullptr}, *q_ = nullptr;
     double *partials_ = nullptr;
     SolveScalars *dsc_ = nullptr;
-    SolveScalars *hsc_ = nullptr, *hsc_dev_ = nullptr;   // host-mapped copy (host / device address)
+    PublishedScalars *pub_ = nullptr, *pub_dev_ = nullptr;   // host-mapped copy (host / device address)
+    const SolveScalars *hsc_ = nullptr;                       // &pub_->s
+    unsigned seq_ = 0;                                        // sequence number of the last finalize
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
     unsigned post_blocks_ = 0;   // workgroups of the finest post-smoothing pass (partials of r.z)

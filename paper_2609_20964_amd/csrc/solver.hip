@@ -962,7 +962,8 @@ enum { FIN_RESID = 0, FIN_RZ = 1, FIN_PQ = 2, FIN_RR = 3, FIN_BSUM = 4 };
 // fixed order, updates the solver scalars and copies them to `mirror`, a
 // host-mapped buffer the host reads after synchronising the stream.
 __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsigned nb, int mode, int flag,
-                                                   SolveScalars *sc, double ncells, SolveScalars *mirror) {
+                                                   SolveScalars *sc, double ncells, PublishedScalars *mirror,
+                                                   unsigned seq) {
     const int nred = mode == FIN_RESID ? 5 : 1;
     double v[5] = {0, 0, 0, 0, 0};
     for (int k = 0; k < nred; ++k) {
@@ -1013,7 +1014,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
             sc->b_sum = v[0];
             break;
     }
-    *mirror = *sc;
+    mirror->s = *sc;
+    // the host reads the scalars once it sees seq: make them visible first
+    __threadfence_system();
+    __hip_atomic_store(&mirror->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Orthonormal 1-D eigenbasis of the 7-point operator along one axis.
@@ -1117,8 +1121,10 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
     partials_ = a.take<double>(partial_slots(dims));
     post_blocks_ = post_blocks(dims);
     dsc_ = a.take<SolveScalars>(1);
-    WG_HIP(hipHostMalloc((void **)&hsc_, sizeof(SolveScalars), hipHostMallocMapped | hipHostMallocCoherent));
-    WG_HIP(hipHostGetDevicePointer((void **)&hsc_dev_, hsc_, 0));
+    WG_HIP(hipHostMalloc((void **)&pub_, sizeof(PublishedScalars), hipHostMallocMapped | hipHostMallocCoherent));
+    WG_HIP(hipHostGetDevicePointer((void **)&pub_dev_, pub_, 0));
+    pub_->seq = seq_;
+    hsc_ = &pub_->s;
     const Dims &c = dims.back();
     coarse_direct_ = c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis;
     if (coarse_direct_) {
@@ -1131,18 +1137,16 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
 }
 
 Solver::~Solver() {
-    if (hsc_) (void)hipHostFree(hsc_);
+    if (pub_) (void)hipHostFree(pub_);
 }
 
 void Solver::finalize(int mode, unsigned nb, int flag) {
-    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count(), hsc_dev_);
+    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count(), pub_dev_, ++seq_);
     WG_LAUNCH_CHECK();
 }
 
-void Solver::read_scalars() {
-    // the last finalize wrote the host-mapped copy
-    WG_HIP(hipStreamSynchronize(st_));
-}
+// Wait until the last finalize has published its scalars.
+void Solver::read_scalars() { wait_published(&pub_->seq, seq_, st_); }
 
 // kind / bytes_per_cell: optional timing bracket (WG_PROF_*) and the sweep's
 // algorithmic bytes per cell.

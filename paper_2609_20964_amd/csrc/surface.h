@@ -61,7 +61,8 @@ class Surface {
     int mbits_ = 0;                // Morton bits per axis
     size_t nbricks_pad_ = 0;       // (2^mbits)^3
     uint32_t *cnt_b_ = nullptr, *off_b_ = nullptr, *active_ = nullptr, *blk_ = nullptr;
-    SurfaceCounts *dcnt_ = nullptr, *hcnt_ = nullptr;
+    SurfaceCounts *dcnt_ = nullptr;
+    HostMapped<SurfaceCounts> hcnt_;
     uint32_t *sign_ = nullptr;     // [ceil(N / 32)] node sides
     uint32_t *next_tile_ = nullptr;   // per-slab work counters of the distance walk
     unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;

@@ -768,7 +768,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     per_cu = per_cu > 1 ? per_cu - 1 : 1;
     sdf_blocks_full_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)per_cu;
     sdf_blocks_ = sdf_blocks_full_;
-    WG_HIP(hipHostMalloc((void **)&hcnt_, sizeof(SurfaceCounts), hipHostMallocDefault));
+    hcnt_.alloc();
     // a first guess at the triangle capacity: ~4 per cube over a few slices
     size_t face = (size_t)d.nx * d.ny;
     if ((size_t)d.ny * d.nz > face) face = (size_t)d.ny * d.nz;
@@ -783,7 +783,6 @@ Surface::~Surface() {
     if (info_) (void)hipFree(info_);
     if (box_) (void)hipFree(box_);
     if (aabb_) (void)hipFree(aabb_);
-    if (hcnt_) (void)hipHostFree(hcnt_);
 }
 
 void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
@@ -824,9 +823,8 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     scan::k_scan_top<<<1, 256, 0, st_>>>(blk_, nblk, reinterpret_cast<uint32_t *>(dcnt_));
     scan::k_scan_final<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_, off_b_, active_);
     WG_LAUNCH_CHECK();
-    WG_HIP(hipMemcpyAsync(hcnt_, dcnt_, sizeof(SurfaceCounts), hipMemcpyDeviceToHost, st_));
-    WG_HIP(hipStreamSynchronize(st_));
-    cnt_ = *hcnt_;
+    hcnt_.fetch(dcnt_, st_);
+    cnt_ = hcnt_.wait();
     levels_ = 0;
     level_off_.clear();
     level_cnt_.clear();
