@@ -65,6 +65,9 @@ class Surface {
     HostMapped<SurfaceCounts> hcnt_;
     uint32_t *sign_ = nullptr;     // [ceil(N / 32)] node sides
     uint32_t *next_tile_ = nullptr;   // per-slab work counters of the distance walk
+    uint32_t *tile_cost_ = nullptr;   // work per tile recorded by the last walk
+    uint32_t *walk_order_ = nullptr;  // tiles of each slab, costliest first
+    bool have_cost_ = false;
     unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
     SurfaceCounts cnt_{};
     // growable

@@ -29,6 +29,17 @@ constexpr uint32_t kLeafEntry = 1u << 31;   // traversal stack entry: the node i
 // of the hierarchy near its slab, and moves on to the other slabs' queues when
 // its own is empty.
 constexpr int kWalkParts = 8;
+// Tiles of the walk: 4 x 4 x 16 nodes (a wavefront of 4 x 4 x 4 lanes, 4 nodes each along z).
+constexpr int kWalkLX = 4, kWalkLY = 4, kWalkLZ = 4, kWalkKZ = 4;
+inline uint32_t walk_tiles(const Dims &d) {
+    return cdiv(d.nx, kWalkLX) * cdiv(d.ny, kWalkLY) * cdiv(d.nz, kWalkLZ * kWalkKZ);
+}
+// Work units a wavefront adds to its tile's cost per stack pop, per internal
+// node expanded and per leaf expanded (in proportion to their vector
+// instruction counts); the next walk takes each slab's tiles in decreasing
+// order of these costs.
+constexpr uint32_t kCostPop = 1, kCostInner = 50, kCostLeaf = 75;
+constexpr int kCostBuckets = 64;   // two per octave of cost
 
 
 __device__ __forceinline__ uint32_t compact3(uint32_t m) {
@@ -392,7 +403,8 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                                               uint32_t root,
                                               const float4 *__restrict__ tri, uint32_t n_tris,
                                               float *__restrict__ phi, int32_t *__restrict__ argmin, int *err,
-                                              uint32_t *next_tile) {
+                                              uint32_t *next_tile, const uint32_t *__restrict__ order,
+                                              uint32_t *__restrict__ tile_cost) {
     static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
@@ -407,14 +419,18 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
     for (;;) {
         const uint32_t t0 = (uint32_t)((uint64_t)n_tiles * part / kWalkParts);
         const uint32_t t1 = (uint32_t)((uint64_t)n_tiles * (part + 1) / kWalkParts);
-        uint32_t tile = 0;
-        if (lane == 0) tile = t0 + atomicAdd(next_tile + part, 1u);
-        tile = __builtin_amdgcn_readfirstlane(tile);
-        if (tile >= t1) {   // whole wavefront: this queue is empty
+        uint32_t slot = 0;
+        if (lane == 0) slot = t0 + atomicAdd(next_tile + part, 1u);
+        slot = __builtin_amdgcn_readfirstlane(slot);
+        if (slot >= t1) {   // whole wavefront: this queue is empty
             if (++visited == kWalkParts) break;
             part = (part + 1) % kWalkParts;
             continue;
         }
+        // longest tiles (by the previous walk's costs) first, so that the
+        // queues end on short ones
+        const uint32_t tile = order ? __builtin_amdgcn_readfirstlane(order[slot]) : slot;
+        uint32_t work = 0;
         const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
         const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
         const int i = min(gi, d.nx - 1), j = min(gj, d.ny - 1);
@@ -432,6 +448,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
             stk[w][0] = root;
             while (sp > 0) {
                 --sp;
+                work += kCostPop;
                 const uint32_t ent = __builtin_amdgcn_readfirstlane(stk[w][sp]);
                 const float4 *nd = nodes + (size_t)kNode * (ent & ~kLeafEntry);
                 if (ent & kLeafEntry) {
@@ -440,6 +457,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                     bool need = false;
                     obb_bound<kTZ>(N0, N1, N2, N3, px, py, pz, best, need);
                     if (__ballot(need) == 0) continue;
+                    work += kCostLeaf;
                     const uint32_t word = __float_as_uint(N3.w);
                     const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
                     for (uint32_t t = first; t < first + cnt; ++t) {
@@ -464,6 +482,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                     aabb_bound<kTZ>(A0, A1, px, py, pz, best, need);
                     if (__ballot(need) == 0) continue;
                 }
+                work += kCostInner;
                 const uint32_t word = __float_as_uint(A0.w);
                 const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
                 const bool kids_leaves = (word & kKidsLeaves) != 0;
@@ -528,6 +547,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                 }
             }
         }
+        if (lane == 0 && tile < n_tiles) tile_cost[tile] = work;
         if (gi < d.nx && gj < d.ny) {
 #pragma unroll
             for (int k = 0; k < kTZ; ++k) {
@@ -539,6 +559,37 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
             }
         }
     }
+}
+
+// One workgroup per slab: the slab's tiles in decreasing order of the costs
+// the previous walk recorded (a counting sort on two buckets per octave; the
+// order inside a bucket is arbitrary, and no result depends on it).
+__device__ __forceinline__ int cost_bucket(uint32_t c) {
+    if (c == 0) return 0;
+    const int e = 31 - __clz(c);
+    return 2 * e + (e > 0 ? (int)((c >> (e - 1)) & 1u) : 0);
+}
+
+__global__ __launch_bounds__(256) void k_walk_order(const uint32_t *__restrict__ cost, uint32_t n_tiles,
+                                                     uint32_t *__restrict__ order) {
+    __shared__ uint32_t pos[kCostBuckets];
+    const uint32_t p = blockIdx.x;
+    const uint32_t t0 = (uint32_t)((uint64_t)n_tiles * p / kWalkParts);
+    const uint32_t t1 = (uint32_t)((uint64_t)n_tiles * (p + 1) / kWalkParts);
+    if (threadIdx.x < kCostBuckets) pos[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) atomicAdd(&pos[cost_bucket(cost[t])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {   // exclusive offsets, the costliest bucket first
+        uint32_t s = t0;
+        for (int b = kCostBuckets - 1; b >= 0; --b) {
+            const uint32_t c = pos[b];
+            pos[b] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) order[atomicAdd(&pos[cost_bucket(cost[t])], 1u)] = t;
 }
 
 // Reverse of phi through the distance (envelope theorem on Eq. 33) and the
@@ -743,6 +794,8 @@ void Surface::plan(Arena &a, const Dims &d) {
     a.reserve(sizeof(SurfaceCounts));
     a.reserve(cdiv(d.count(), 32) * sizeof(uint32_t));   // node sides
     a.reserve(kWalkParts * sizeof(uint32_t));             // tile counters of the walk
+    a.reserve((size_t)walk_tiles(d) * sizeof(uint32_t));   // tile costs of the walk
+    a.reserve((size_t)walk_tiles(d) * sizeof(uint32_t));   // tile order of the walk
 }
 
 void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
@@ -757,6 +810,9 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     dcnt_ = a.take<SurfaceCounts>(1);
     sign_ = a.take<uint32_t>(cdiv(d.count(), 32));
     next_tile_ = a.take<uint32_t>(kWalkParts);
+    tile_cost_ = a.take<uint32_t>(walk_tiles(d));
+    walk_order_ = a.take<uint32_t>(walk_tiles(d));
+    have_cost_ = false;
     // the persistent walk stays one workgroup per compute unit below full
     // residency: its workgroups only retire when the tile queue is empty, and
     // work on the handle's other stream (the next step's splat and solve, host
@@ -856,12 +912,17 @@ uint32_t Surface::extract(const double *chi, const double *c) {
 template <int LX, int LY, int LZ, int KZ>
 static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
                        const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
-                       int32_t *argmin, int *err, uint32_t *next_tile, unsigned blocks, hipStream_t s) {
+                       int32_t *argmin, int *err, uint32_t *next_tile, uint32_t *order, uint32_t *tile_cost,
+                       bool have_cost, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
+    if (have_cost) {
+        k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost, tiles, order);
+        WG_LAUNCH_CHECK();
+    }
     k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
-                                                 next_tile);
+                                                 next_tile, have_cost ? order : nullptr, tile_cost);
     WG_LAUNCH_CHECK();
 }
 
@@ -876,8 +937,10 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
     prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
-    launch_sdf<4, 4, 4, 4>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin, err, next_tile_,
-                           sdf_blocks_, s);
+    launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
+                                                  err, next_tile_, walk_order_, tile_cost_, have_cost_, sdf_blocks_,
+                                                  s);
+    have_cost_ = true;   // every tile's cost is written by the walk just launched
 }
 
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
