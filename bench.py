@@ -98,11 +98,12 @@ def gpu_run(args):
 
     # the same loop without pipelining (forward, then sample), for reference
     plain_steps = min(args.steps, 10)
+    plain_stats = []
     torch.cuda.synchronize()
     p0 = time.perf_counter()
     for k in range(plain_steps):
         t = args.warmup + args.steps - plain_steps + k
-        r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
+        plain_stats.append(r.forward(*clouds[t], rel_tol=args.tol, warm_start=True))
         r.sample(q)
     torch.cuda.synchronize()
     plain_ms = (time.perf_counter() - p0) / plain_steps * 1e3
@@ -140,7 +141,7 @@ def gpu_run(args):
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
-            "plain_ms": plain_ms, "plain_steps": plain_steps}
+            "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -155,11 +156,11 @@ KIND_KERNEL = {"sweep": "k_stencil4<OpPMatvec>", "smooth": "k_vc_pre", "resid64"
 SOLVER_KINDS = ("sweep", "smooth", "resid64", "transfer", "cgupdate")
 
 
-def solver_hbm(res):
+def solver_hbm(res, copy_gbs=None):
     """HBM roofline of the Poisson solve taken as a whole: algorithmic bytes of
     its bandwidth-bound kernels over (a) their own event-timed duration and
     (b) the whole solve phase (reductions, coarse solve and host waits
-    included)."""
+    included); both also against a measured device copy."""
     kinds = res["solver_kinds"]
     units = sum(v["units"] for v in kinds.values())
     ms = sum(v["ms"] for v in kinds.values())
@@ -168,11 +169,15 @@ def solver_hbm(res):
     phase_ms = sum(res["solve_ms"])
     per = {k: {"GB_s": v["units"] / (v["ms"] * 1e6) if v["ms"] > 0 else None, "launches": v["launches"],
                "ms": v["ms"] / len(res["solve_ms"])} for k, v in kinds.items()}
-    return {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "kernels_GB_s": units / (ms * 1e6), "kernels_frac": units / (ms * 1e6) / HBM_PEAK_GBS,
-            "phase_GB_s": units / (phase_ms * 1e6), "phase_frac": units / (phase_ms * 1e6) / HBM_PEAK_GBS,
-            "bytes_per_solve": units / len(res["solve_ms"]), "phase_ms": phase_ms / len(res["solve_ms"]),
-            "per_kind": per}
+    out = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "kernels_GB_s": units / (ms * 1e6), "kernels_frac": units / (ms * 1e6) / HBM_PEAK_GBS,
+           "phase_GB_s": units / (phase_ms * 1e6), "phase_frac": units / (phase_ms * 1e6) / HBM_PEAK_GBS,
+           "bytes_per_solve": units / len(res["solve_ms"]), "phase_ms": phase_ms / len(res["solve_ms"]),
+           "per_kind": per}
+    if copy_gbs:
+        out.update({"copy_GB_s": copy_gbs, "kernels_frac_of_copy": out["kernels_GB_s"] / copy_gbs,
+                    "phase_frac_of_copy": out["phase_GB_s"] / copy_gbs})
+    return out
 
 
 def roofline(res):
@@ -510,6 +515,26 @@ def replay(srv, reqs, time_scale, keep=False):
     return stats, (done if keep else None)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (GB/s, read + write bytes) timed with events:
+    the bandwidth a streaming kernel reaches on this device."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def copy_probe():
     import torch
 
@@ -614,15 +639,16 @@ def main():
                                f"rel res {args.tol:g}, {args.queries} queries sampled per step",
                    "grid": args.n, "points": args.points, "queries": args.queries, "rel_tol": args.tol},
         "roofline": roofline(res),
-        "solver_roofline": solver_hbm(res),
+        "solver_roofline": solver_hbm(res, copy_bandwidth()),
         "solver": {"iters_mean": float(np.mean([s["iters"] for s in st])),
                    "refinements_mean": float(np.mean([s["refinements"] for s in st])),
                    "rel_res_max": float(max(s["rel_res"] for s in st)),
                    "n_tris_mean": float(np.mean([s["n_tris"] for s in st]))},
         "unpipelined": {"ms_per_step": res["plain_ms"], "recons_per_s": 1e3 / res["plain_ms"],
                         "steps": res["plain_steps"]},
-        "phase_ms_mean": {k: float(np.mean([s["ms"][i] for s in st]))
-                          for i, k in enumerate(["splat", "solve", "iso", "surface"])},
+        # phases of the steps run one after another (in pipelined steps they overlap)
+        "phase_ms_plain": {k: float(np.mean([s["ms"][i] for s in res["plain_stats"]]))
+                           for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
         "kernel_ms_per_step_warmup": {k: v["ms"] / 3 for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
     }

@@ -33,9 +33,13 @@ Tiles tiles_of(const Dims &d) { return {cdiv(d.nx, TX), cdiv(d.ny, TY), cdiv(d.n
 
 // Generic 7-point sweep.  Op::load(idx) yields the stencil input at a linear
 // index; Op::apply(idx, centre, neighbour_sum, diag, acc) consumes one cell.
+// Scalars an operator reads from device memory once per workgroup (none by default).
+template <class Op> __device__ __forceinline__ void fetch_scalars(Op &) {}
+
 template <class Op>
 __global__ __launch_bounds__(256) void k_stencil(Op op, Dims d, Tiles t, double *partials) {
     using T = typename Op::T;
+    fetch_scalars(op);
     const unsigned nb = t.count();
     const unsigned lb = xcd_logical_block(blockIdx.x, nb);
     const unsigned bx = lb % t.gx, by = (lb / t.gx) % t.gy, bz = lb / (t.gx * t.gy);
@@ -134,6 +138,7 @@ inline Waves4 waves4_of(const Dims &d, bool even = false) {
 template <class Op>
 __global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, double *partials) {
     using T = typename Op::T;
+    fetch_scalars(op);
     const unsigned nb = gridDim.x;
     const unsigned lb = xcd_logical_block(blockIdx.x, nb);
     const unsigned task = lb * 4 + threadIdx.x / 64;
@@ -307,6 +312,7 @@ struct OpPMatvec {
     static constexpr int NRED = 1;
     const float *z, *pold;
     float *pnew, *q;
+    const SolveScalars *sc;   // beta, formed on the device by the last finalize
     float beta;
     __device__ float load(size_t i) const {
         if constexpr (FIRST) return z[i];
@@ -337,6 +343,8 @@ struct OpPMatvec {
         st4(q + i, qq);
     }
 };
+
+__device__ __forceinline__ void fetch_scalars(OpPMatvec<false> &op) { op.beta = (float)op.sc->beta; }
 
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float *__restrict__ r,
@@ -1249,13 +1257,11 @@ int Solver::pcg(double tol, int max_it, double rr0) {
     int stall = 0;
     for (; it < max_it; ++it) {
         if (it == 0)
-            launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, 0.f}, F.d, partials_, st_, WG_PROF_SWEEP,
-                           12.0);
-        else {
-            // beta is read on the host-visible copy after the last finalize
-            launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, (float)hsc_->beta}, F.d, partials_, st_,
+            launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, F.d, partials_, st_,
+                           WG_PROF_SWEEP, 12.0);
+        else   // beta = rz / rz_old, formed by the last finalize, read on the device
+            launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, F.d, partials_, st_,
                            WG_PROF_SWEEP, 16.0);
-        }
         finalize(FIN_PQ, tb, 0);
         {
             prof::Scope ps(WG_PROF_CGUPDATE, st_, (it == 0 ? 20.0 : 24.0) * (double)N);
@@ -1266,14 +1272,15 @@ int Solver::pcg(double tol, int max_it, double rr0) {
             WG_LAUNCH_CHECK();
         }
         finalize(FIN_RR, rb, 0);
-        precond();   // z for the next direction
-        finalize(FIN_RZ, rz_blocks(), 0);   // beta = rz / rz_old
+        // test r.r before the preconditioner: the last iteration forms no z
         read_scalars();
         const double rr = hsc_->rr;
         if (hsc_->bad || !std::isfinite(rr)) { ++it; break; }
         if (rr <= tol * tol * rr0) { ++it; break; }
         if (rr < 0.5 * best) { best = rr; stall = 0; }
         else if (++stall >= 4) { ++it; break; }
+        precond();   // z for the next direction
+        finalize(FIN_RZ, rz_blocks(), 0);   // beta = rz / rz_old
         cur ^= 1;
     }
     return it;
