@@ -21,6 +21,7 @@ struct SolveScalars {
     double rz, rz_old, pq, alpha, beta, rr;
     double res_sum, res_sq, x_sum, b_sum, b_sq;
     double mean_r, res_norm2, b_norm2;
+    double mean_b;   // mean of the right-hand side (Neumann)
     int bad;
     int pad;
 };

@@ -216,6 +216,7 @@ struct OpResid64 {
     const double *x;
     const float *b;
     float *r;
+    const SolveScalars *sc;   // mean of b formed on the device (Neumann), or null (no shift)
     double mb;
     __device__ double load(size_t i) const { return x[i]; }
     __device__ double load1(size_t i) const { return x[i]; }
@@ -345,6 +346,7 @@ struct OpPMatvec {
 };
 
 __device__ __forceinline__ void fetch_scalars(OpPMatvec<false> &op) { op.beta = (float)op.sc->beta; }
+__device__ __forceinline__ void fetch_scalars(OpResid64 &op) { op.mb = op.sc ? op.sc->mean_b : 0.0; }
 
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float *__restrict__ r,
@@ -1020,6 +1022,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
             break;
         case FIN_BSUM:
             sc->b_sum = v[0];
+            sc->mean_b = v[0] / ncells;
             break;
     }
     mirror->s = *sc;
@@ -1300,19 +1303,19 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
         k_fill64<<<gb, kBlock, 0, st_>>>(x, 0.0, N);
         WG_LAUNCH_CHECK();
     }
-    double mb = 0.0;
+    // Neumann: the residual kernel subtracts the mean of b, formed on the device
+    const SolveScalars *mean_src = nullptr;
     if (bc == WG_BC_NEUMANN) {
         k_sum<<<gb, kBlock, 0, st_>>>(b, N, partials_);
         WG_LAUNCH_CHECK();
         finalize(FIN_BSUM, gb, 0);
-        read_scalars();
-        mb = hsc_->b_sum / (double)N;
+        mean_src = dsc_;
     }
     const double tol = o.rel_tol > 0 ? o.rel_tol : 1e-6;
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64{x, b, F.rhs, mb}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
+        launch_stencil(OpResid64{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;

@@ -273,6 +273,27 @@ def test_pipelined_steps_match_plain():
     b.close()
 
 
+def test_walk_tile_order_changes_no_result():
+    """A handle's second distance walk takes its tiles in the order of the first
+    walk's costs; on a different surface it must still write every node (a
+    skipped tile would keep the first surface's distances) and match a fresh
+    handle's walk in plain tile order at every node."""
+    from paper_2609_20964_amd.recon import Recon
+    n = 64
+    xs, ns = synth.sphere(n_points=20000, radius=0.3, seed=101)
+    xt, nt = synth.torus(n_points=40000)
+    a, b = Recon(n, 40000), Recon(n, 40000)
+    a.forward(_cuda(xs), _cuda(ns), rel_tol=1e-10, max_iters=2000)
+    sa = a.forward(_cuda(xt), _cuda(nt), rel_tol=1e-10, max_iters=2000)
+    sb = b.forward(_cuda(xt), _cuda(nt), rel_tol=1e-10, max_iters=2000)
+    assert sa["status"] == 0 and sb["status"] == 0 and sa["n_tris"] == sb["n_tris"]
+    fa, fb = a.fields(), b.fields()
+    pa, pb = fa["phi"].cpu().numpy(), fb["phi"].cpu().numpy()
+    assert np.abs(pa - pb).max() <= 1e-4 / n
+    a.close()
+    b.close()
+
+
 def test_degenerate_clouds_on_faces_coincident_zero_normals():
     """Points exactly on cell faces and on the grid's lower faces, many
     coincident points, zero normals: keys bit-exact, b, the field and every
