@@ -812,7 +812,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     next_tile_ = a.take<uint32_t>(kWalkParts);
     tile_cost_ = a.take<uint32_t>(walk_tiles(d));
     walk_order_ = a.take<uint32_t>(walk_tiles(d));
-    have_cost_ = false;
+    have_order_ = false;
     // the persistent walk stays one workgroup per compute unit below full
     // residency: its workgroups only retire when the tile queue is empty, and
     // work on the handle's other stream (the next step's splat and solve, host
@@ -913,16 +913,15 @@ template <int LX, int LY, int LZ, int KZ>
 static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
                        const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
                        int32_t *argmin, int *err, uint32_t *next_tile, uint32_t *order, uint32_t *tile_cost,
-                       bool have_cost, unsigned blocks, hipStream_t s) {
+                       bool have_order, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
-    if (have_cost) {
-        k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost, tiles, order);
-        WG_LAUNCH_CHECK();
-    }
     k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
-                                                 next_tile, have_cost ? order : nullptr, tile_cost);
+                                                 next_tile, have_order ? order : nullptr, tile_cost);
+    // the next walk's order, from this walk's costs (off the critical path of
+    // a pipelined step: it runs beside the next step's solve)
+    k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost, tiles, order);
     WG_LAUNCH_CHECK();
 }
 
@@ -938,9 +937,9 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
     prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
-                                                  err, next_tile_, walk_order_, tile_cost_, have_cost_, sdf_blocks_,
+                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, sdf_blocks_,
                                                   s);
-    have_cost_ = true;   // every tile's cost is written by the walk just launched
+    have_order_ = true;   // ordered by the costs of the walk just launched
 }
 
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
