@@ -237,7 +237,6 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         if (m.err[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
         iso_c_ = m.scal[0];
     }
-    surf_.signs(chi_, scal_);
     WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
     tm.mark(4);
     if (pipelined) {

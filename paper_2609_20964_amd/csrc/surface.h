@@ -27,14 +27,12 @@ class Surface {
     void bind(Arena &a, const Dims &d, hipStream_t s);
     ~Surface();
 
-    // Extract the mesh of {chi = *c} (c on the device).  Host-synchronising:
-    // returns the triangle count.
+    // Side of every node (chi >= c: outside) and the mesh of {chi = *c} (c on
+    // the device).  Host-synchronising: returns the triangle count.  The
+    // distance walk reads the node sides, not chi.
     uint32_t extract(const double *chi, const double *c);
-    // Side of every node against the extracted surface (chi >= c: outside), on
-    // the surface's stream; the distance walk reads these bits, not chi.
-    void signs(const double *chi, const double *c);
     // phi and the nearest-triangle index on every node, on stream s (after
-    // extract and signs have completed there).
+    // extract has completed there).
     void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s);
     // reverse of sdf through the vertices: g_chi, g_c (+=)
     void sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,

@@ -1,5 +1,6 @@
 // Surface extraction, exact signed distance on every grid node, sampling and
 // their reverses.  See surface.h for the data layout.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -90,20 +91,53 @@ struct NB {
     int v[3];
 };
 
-__global__ __launch_bounds__(256) void k_mc_count(const double *__restrict__ chi, const double *iso, Dims d, NB nb,
+// Triangles per brick, from the node sides (k_sign_bits runs first: a corner
+// is inside, chi < c, where its side bit is clear).  A wavefront takes a brick
+// at a time (grid-stride over bricks): lanes 0..24 each read one row of the
+// brick's 5 x 5 x 5 corner nodes (5 consecutive bits), and each lane gathers
+// its cube's four rows from them by shuffles.  Reading chi at eight corners
+// per lane instead made the kernel bound by cache-line requests.
+__global__ __launch_bounds__(256) void k_mc_count(const uint32_t *__restrict__ side, Dims d, NB nb,
                                                    uint32_t nbricks, uint32_t *__restrict__ cnt) {
+    constexpr int E = kBrick + 1;
+    __shared__ unsigned char ntri[256];   // triangles per cube case
+    ntri[threadIdx.x] = WG_MC_NTRI[threadIdx.x];
+    __syncthreads();
     const int lane = threadIdx.x % 64;
-    const uint32_t m = blockIdx.x * 4 + threadIdx.x / 64;
-    if (m >= nbricks) return;   // whole wavefront
-    const double c = iso[0];
-    BrickPos p = brick_lane(m, lane, nb.v, d);
-    int nt = 0;
-    if (p.ok) {
-        const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
-        nt = WG_MC_NTRI[cube_case(chi, p.i + sy * p.j + sz * p.k, sy, sz, c)];
+    const size_t n_words = ((size_t)d.count() + 31) / 32;
+    // the lane's cube inside a brick (Morton order, as in brick_lane)
+    const int dx = (int)compact3((uint32_t)lane), dy = (int)compact3((uint32_t)lane >> 1),
+              dz = (int)compact3((uint32_t)lane >> 2);
+    const int r0 = dy + E * dz;   // its four corner rows: r0, r0 + 1, r0 + E, r0 + E + 1
+    for (uint32_t m = blockIdx.x * 4 + threadIdx.x / 64; m < nbricks; m += gridDim.x * 4) {
+        const int bx = (int)compact3(m), by = (int)compact3(m >> 1), bz = (int)compact3(m >> 2);
+        uint32_t row = 0;   // bit x: side of node (4 bx + x, row's y, row's z); rows past the grid are clamped
+        if (lane < E * E && bx < nb.v[0] && by < nb.v[1] && bz < nb.v[2]) {
+            const int gj = min(by * kBrick + lane % E, d.ny - 1), gk = min(bz * kBrick + lane / E, d.nz - 1);
+            const size_t o = (size_t)bx * kBrick + (size_t)d.nx * ((size_t)gj + (size_t)d.ny * gk);
+            const size_t w = o >> 5;
+            const int sh = (int)(o & 31);
+            uint64_t v = side[w];
+            if (sh + E > 32 && w + 1 < n_words) v |= (uint64_t)side[w + 1] << 32;
+            row = (uint32_t)(v >> sh) & ((1u << E) - 1u);
+        }
+        const uint32_t q00 = __shfl(row, r0, 64), q10 = __shfl(row, r0 + 1, 64);
+        const uint32_t q01 = __shfl(row, r0 + E, 64), q11 = __shfl(row, r0 + E + 1, 64);
+        const int i = bx * kBrick + dx, j = by * kBrick + dy, k = bz * kBrick + dz;
+        const bool ok = bx < nb.v[0] && by < nb.v[1] && bz < nb.v[2] && i < d.nx - 1 && j < d.ny - 1 && k < d.nz - 1;
+        int nt = 0;
+        if (ok) {
+            // corner b = dx' + 2 dy' + 4 dz' is inside where its side bit is clear
+            const uint32_t q[4] = {q00, q10, q01, q11};
+            int cs = 0;
+            for (int b = 0; b < 8; ++b) cs |= (int)(((q[b >> 1] >> (dx + (b & 1))) & 1u) ^ 1u) << b;
+            nt = ntri[cs];
+        }
+        // nt <= 5 (three bits): the wavefront's sum from three ballots
+        const uint32_t sum = (uint32_t)__popcll(__ballot(nt & 1)) + 2u * (uint32_t)__popcll(__ballot(nt & 2)) +
+                             4u * (uint32_t)__popcll(__ballot(nt & 4));
+        if (lane == 0) cnt[m] = sum;
     }
-    for (int o = 32; o > 0; o >>= 1) nt += __shfl_xor(nt, o, 64);
-    if (lane == 0) cnt[m] = nt;
 }
 
 // One wavefront per non-empty brick: the triangles of its cubes, vertices by
@@ -384,14 +418,16 @@ __device__ __forceinline__ float aabb_bound(float4 A0, float4 A1, float px, floa
 // the others).  One node per lane; a wavefront writes two words.
 __global__ __launch_bounds__(256) void k_sign_bits(const double *__restrict__ chi, const double *iso, size_t n,
                                                     uint32_t *__restrict__ sign) {
-    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t base = o - threadIdx.x % 64;
-    if (base >= n) return;   // whole wavefront
     const double c = iso[0];
-    const uint64_t bits = __ballot(o < n && chi[o] >= c);
-    if (threadIdx.x % 64 == 0) {
-        sign[base >> 5] = (uint32_t)bits;
-        if (base + 32 < n) sign[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    // grid-stride in whole wavefronts (stride is a multiple of 64)
+    for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o - threadIdx.x % 64 < n; o += stride) {
+        const size_t base = o - threadIdx.x % 64;
+        const uint64_t bits = __ballot(o < n && chi[o] >= c);
+        if (threadIdx.x % 64 == 0) {
+            sign[base >> 5] = (uint32_t)bits;
+            if (base + 32 < n) sign[(base >> 5) + 1] = (uint32_t)(bits >> 32);
+        }
     }
 }
 
@@ -600,37 +636,39 @@ __global__ __launch_bounds__(256) void k_sdf_T(const float *__restrict__ gphi, c
                                                 const float4 *__restrict__ tri, const int2 *__restrict__ info,
                                                 float *__restrict__ g_chi, double *g_c) {
     const size_t n = d.count();
-    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     double gc = 0.0;
-    const float g = o < n ? gphi[o] : 0.f;
-    const int t = o < n ? argmin[o] : -1;
-    if (g != 0.f && t >= 0) {
-        const double c = iso[0];
-        const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / ((size_t)d.nx * d.ny);
-        const float4 *tr = tri + kTri * (size_t)t;
-        const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
-        float v, w;
-        tri_d2((float)i, (float)j, (float)k, A, B, C, R, v, w);
-        // p - (a + v ab + w ac)
-        float u[3] = {(float)i - A.x - v * B.x - w * C.x, (float)j - A.y - v * B.y - w * C.y,
-                      (float)k - A.z - v * B.z - w * C.z};
-        float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        if (dist > 0.f) {
-            const float sgn = chi[o] >= c ? 1.f : -1.f;
-            const float gd = sgn * (float)h * g;       // dL / d(distance in grid units)
-            const float beta[3] = {1.f - v - w, v, w};
-            const int2 inf = info[t];
-            const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
-            for (int vq = 0; vq < 3; ++vq) {
-                int e = (inf.y >> (4 * vq)) & 15, b0, b1, ax;
-                edge_ends(e, b0, b1, ax);
-                const float geta = -beta[vq] * (u[ax] / dist) * gd;
-                const size_t c1 = (size_t)inf.x + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2);
-                const size_t c2 = (size_t)inf.x + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2);
-                const double x1 = chi[c1], x2 = chi[c2], D = x2 - x1;
-                unsafeAtomicAdd(g_chi + c1, (float)((double)geta * (c - x2) / (D * D)));
-                unsafeAtomicAdd(g_chi + c2, (float)(-(double)geta * (c - x1) / (D * D)));
-                gc += (double)geta / D;
+    // grid-stride over nodes; the wavefront sums g_c once at the end
+    for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (size_t)gridDim.x * blockDim.x) {
+        const float g = gphi[o];
+        const int t = argmin[o];
+        if (g != 0.f && t >= 0) {
+            const double c = iso[0];
+            const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / ((size_t)d.nx * d.ny);
+            const float4 *tr = tri + kTri * (size_t)t;
+            const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
+            float v, w;
+            tri_d2((float)i, (float)j, (float)k, A, B, C, R, v, w);
+            // p - (a + v ab + w ac)
+            float u[3] = {(float)i - A.x - v * B.x - w * C.x, (float)j - A.y - v * B.y - w * C.y,
+                          (float)k - A.z - v * B.z - w * C.z};
+            float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (dist > 0.f) {
+                const float sgn = chi[o] >= c ? 1.f : -1.f;
+                const float gd = sgn * (float)h * g;       // dL / d(distance in grid units)
+                const float beta[3] = {1.f - v - w, v, w};
+                const int2 inf = info[t];
+                const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
+                for (int vq = 0; vq < 3; ++vq) {
+                    int e = (inf.y >> (4 * vq)) & 15, b0, b1, ax;
+                    edge_ends(e, b0, b1, ax);
+                    const float geta = -beta[vq] * (u[ax] / dist) * gd;
+                    const size_t c1 = (size_t)inf.x + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2);
+                    const size_t c2 = (size_t)inf.x + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2);
+                    const double x1 = chi[c1], x2 = chi[c2], D = x2 - x1;
+                    unsafeAtomicAdd(g_chi + c1, (float)((double)geta * (c - x2) / (D * D)));
+                    unsafeAtomicAdd(g_chi + c2, (float)(-(double)geta * (c - x1) / (D * D)));
+                    gc += (double)geta / D;
+                }
             }
         }
     }
@@ -872,7 +910,10 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     NB nb{{nb_[0], nb_[1], nb_[2]}};
     const uint32_t nbr = (uint32_t)nbricks_pad_;
     prof::Scope ps(WG_PROF_MC, st_, 8.0 * (double)d_.count());
-    k_mc_count<<<cdiv(nbr, 4), 256, 0, st_>>>(chi, c, d_, nb, nbr, cnt_b_);
+    // node sides first: the brick counts read them, and so does the distance walk
+    const size_t nodes = d_.count();
+    k_sign_bits<<<std::min(cdiv(nodes, 256), 8192u), 256, 0, st_>>>(chi, c, nodes, sign_);
+    k_mc_count<<<std::min(cdiv(nbr, 4), 16384u), 256, 0, st_>>>(sign_, d_, nb, nbr, cnt_b_);
     WG_LAUNCH_CHECK();
     const uint32_t nblk = cdiv(nbr, scan::kScanBlock);
     scan::k_scan_partial<<<nblk, 256, 0, st_>>>(cnt_b_, nbr, blk_);
@@ -925,12 +966,6 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
     WG_LAUNCH_CHECK();
 }
 
-void Surface::signs(const double *chi, const double *c) {
-    const size_t n = d_.count();
-    k_sign_bits<<<cdiv(n, 256), 256, 0, st_>>>(chi, c, n, sign_);
-    WG_LAUNCH_CHECK();
-}
-
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
@@ -945,7 +980,8 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                     float *g_chi, double *g_c) {
     if (cnt_.n_tris == 0) return;
-    k_sdf_T<<<cdiv(d_.count(), 256), 256, 0, st_>>>(gphi, chi, c, d_, h, argmin, tri_, info_, g_chi, g_c);
+    k_sdf_T<<<std::min(cdiv(d_.count(), 256), 8192u), 256, 0, st_>>>(gphi, chi, c, d_, h, argmin, tri_, info_, g_chi,
+                                                                     g_c);
     WG_LAUNCH_CHECK();
 }
 
