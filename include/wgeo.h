@@ -22,10 +22,13 @@
  *   - Points, normals and queries are float32 [count][3] (x, y, z).
  *   - Every d_* pointer is DEVICE memory owned by the caller.  The library
  *     never frees it and never allocates user-visible outputs.
- *   - Calls enqueue work on the handle's HIP stream.  The only host waits are
- *     inside the Poisson solve (convergence read-backs) and after surface
- *     extraction (triangle count); outputs are ready once the stream reaches
- *     them (synchronise the stream before reading them on the host).
+ *   - Calls enqueue work on the handle's HIP stream.  The host waits only for
+ *     small results: the splat's error flags, the solver's convergence
+ *     scalars, the triangle count after surface extraction, and at the end
+ *     of wg_recon_forward / wg_recon_step / wg_recon_backward for the call's
+ *     statistics (a forward's distance walk included; a pipelined step's walk
+ *     not).  Outputs are ready once the stream reaches them (synchronise the
+ *     stream before reading them on the host).
  *   - Return codes: WG_OK (0), WG_PENDING (> 0, wg_poll only) or a negative
  *     WG_E* value; wg_last_error() gives this thread's last message.  No C++
  *     exception crosses the ABI.
