@@ -65,6 +65,7 @@ class Surface {
     uint32_t *next_tile_ = nullptr;   // per-slab work counters of the distance walk
     uint32_t *tile_cost_ = nullptr;   // work per tile recorded by the last walk
     uint32_t *walk_order_ = nullptr;  // tiles of each slab, costliest first
+    int32_t *seed_ = nullptr;         // nearest triangle of each seed-lattice node
     bool have_order_ = false;
     unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
     SurfaceCounts cnt_{};

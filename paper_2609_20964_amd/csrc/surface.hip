@@ -41,6 +41,27 @@ inline uint32_t walk_tiles(const Dims &d) {
 // order of these costs.
 constexpr uint32_t kCostPop = 1, kCostInner = 50, kCostLeaf = 75;
 constexpr int kCostBuckets = 64;   // two per octave of cost
+// Seeds of the walk: the exact nearest triangle of every node of a lattice of
+// stride kSeedStride (nodes 0, 16, 32, ... per axis, 4096 at 256^3).  Each
+// node's bound starts at its distance to the seed of the lattice node nearest
+// to it, which prunes from the first box on.
+constexpr int kSeedStride = 16;
+constexpr int kSeedStack = 64;
+// A seed search stops after this many nodes with the nearest triangle found so
+// far (any triangle bounds the distance; the walk stays exact).  The search is
+// latency-bound, one lane per lattice node, so its length is the pass's time:
+// 160 measured best among 32 to 400 (it overlaps the next step's solve when
+// steps are pipelined).
+constexpr int kSeedPops = 160;
+// The seed pass costs about a millisecond whatever the grid; it pays only where
+// the walk takes several (256^3: 6.9 -> 6.1 ms), so smaller grids walk unseeded.
+constexpr size_t kSeedMinNodes = (size_t)1 << 23;
+struct SeedDims {
+    int x, y, z;
+};
+inline SeedDims seed_dims(const Dims &d) {
+    return {(int)cdiv(d.nx, kSeedStride), (int)cdiv(d.ny, kSeedStride), (int)cdiv(d.nz, kSeedStride)};
+}
 
 
 __device__ __forceinline__ uint32_t compact3(uint32_t m) {
@@ -413,6 +434,94 @@ __device__ __forceinline__ float aabb_bound(float4 A0, float4 A1, float px, floa
     return d0;
 }
 
+// Squared distance from p to an axis-aligned box (lo, hi in .xyz).
+__device__ __forceinline__ float box_d2(float4 lo, float4 hi, float px, float py, float pz) {
+    const float dx = fmaxf(fmaxf(lo.x - px, px - hi.x), 0.f);
+    const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.f);
+    const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.f);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Squared distance from p to an oriented leaf box (centre and half extents in
+// N0, axes in N1..N3, the half extents of v and n in N1.w, N2.w).
+__device__ __forceinline__ float obb_d2(float4 N0, float4 N1, float4 N2, float4 N3, float px, float py, float pz) {
+    const float rx = px - N0.x, ry = py - N0.y, rz = pz - N0.z;
+    const float du = fmaxf(fabsf(N1.x * rx + N1.y * ry + N1.z * rz) - N0.w, 0.f);
+    const float dv = fmaxf(fabsf(N2.x * rx + N2.y * ry + N2.z * rz) - N1.w, 0.f);
+    const float dn = fmaxf(fabsf(N3.x * rx + N3.y * ry + N3.z * rz) - N2.w, 0.f);
+    return du * du + dv * dv + dn * dn;
+}
+
+// Nearest triangle of each seed-lattice node: one node per lane, each lane
+// with its own nearest-first traversal and stack (few nodes, so divergence
+// costs little), for at most kSeedPops nodes.  A stack that would overflow
+// drops the children.  Either way the seed is still a triangle, only perhaps
+// not the nearest: seeds only bound.
+__global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, const float4 *__restrict__ nodes,
+                                                  const float4 *__restrict__ leaf_aabb, uint32_t root,
+                                                  const float4 *__restrict__ tri, int32_t *__restrict__ seed) {
+    __shared__ uint32_t stk[kSeedStack][64];
+    const int lane = threadIdx.x;
+    const int id = blockIdx.x * 64 + lane;
+    if (id >= nc.x * nc.y * nc.z) return;
+    const float px = (float)min((id % nc.x) * kSeedStride, d.nx - 1);
+    const float py = (float)min(((id / nc.x) % nc.y) * kSeedStride, d.ny - 1);
+    const float pz = (float)min((id / (nc.x * nc.y)) * kSeedStride, d.nz - 1);
+    float best = INFINITY;
+    int arg = -1;
+    int sp = 0;
+    stk[sp++][lane] = root;
+    for (int pops = 0; sp > 0 && pops < kSeedPops; ++pops) {
+        const uint32_t ent = stk[--sp][lane];
+        const float4 *nd = nodes + (size_t)kNode * (ent & ~kLeafEntry);
+        if (ent & kLeafEntry) {
+            const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
+            if (obb_d2(N0, N1, N2, N3, px, py, pz) >= best) continue;
+            const uint32_t word = __float_as_uint(N3.w);
+            const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
+            for (uint32_t t = first; t < first + cnt; ++t) {
+                const float4 *tr = tri + kTri * (size_t)t;
+                float v_, w_;
+                const float dd = tri_d2(px, py, pz, tr[0], tr[1], tr[2], tr[3], v_, w_);
+                if (dd < best) {
+                    best = dd;
+                    arg = (int)t;
+                }
+            }
+            continue;
+        }
+        const float4 A0 = nd[0], A1 = nd[1];
+        if (box_d2(A0, A1, px, py, pz) >= best) continue;
+        const uint32_t word = __float_as_uint(A0.w);
+        const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
+        const bool kids_leaves = (word & kKidsLeaves) != 0;
+        // key: bit 31 = to be visited, then the child's bound (a non-negative
+        // float, ordered like its bits) with the child's index in the low 3 bits
+        uint32_t key[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            key[q] = 0u;
+            if ((uint32_t)q < cnt) {
+                const float4 *cb = kids_leaves ? leaf_aabb + 2 * (size_t)(first + q) : nodes + (size_t)kNode * (first + q);
+                const float b = box_d2(cb[0], cb[1], px, py, pz);
+                if (b < best) key[q] = 0x80000000u | (__float_as_uint(b) & 0x7ffffff8u) | (uint32_t)q;
+            }
+        }
+        if (sp + 8 > kSeedStack) continue;
+        cx_desc(key[0], key[2]); cx_desc(key[1], key[3]); cx_desc(key[4], key[6]); cx_desc(key[5], key[7]);
+        cx_desc(key[0], key[4]); cx_desc(key[1], key[5]); cx_desc(key[2], key[6]); cx_desc(key[3], key[7]);
+        cx_desc(key[0], key[1]); cx_desc(key[2], key[3]); cx_desc(key[4], key[5]); cx_desc(key[6], key[7]);
+        cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
+        cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
+        cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
+        const uint32_t flag = kids_leaves ? kLeafEntry : 0u;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (key[r] != 0u) stk[sp++][lane] = (first + (key[r] & 7u)) | flag;
+    }
+    seed[id] = arg;
+}
+
 // Side of every node: bit (o & 31) of word o >> 5 is set where chi >= c
 // (outside, Eq. 31: the mesh separates exactly the nodes with chi >= c from
 // the others).  One node per lane; a wavefront writes two words.
@@ -440,7 +549,8 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                                               const float4 *__restrict__ tri, uint32_t n_tris,
                                               float *__restrict__ phi, int32_t *__restrict__ argmin, int *err,
                                               uint32_t *next_tile, const uint32_t *__restrict__ order,
-                                              uint32_t *__restrict__ tile_cost) {
+                                              uint32_t *__restrict__ tile_cost, const int32_t *__restrict__ seed,
+                                              SeedDims snc) {
     static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
@@ -478,6 +588,22 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
             pz[k] = (float)min(gk0 + LZ * k, d.nz - 1);
             best[k] = INFINITY;
             arg[k] = -1;
+        }
+        if (seed) {
+            // start from the distance to the seed of the nearest lattice node
+            const int sa = min((i + kSeedStride / 2) / kSeedStride, snc.x - 1);
+            const int sb = min((j + kSeedStride / 2) / kSeedStride, snc.y - 1);
+#pragma unroll
+            for (int k = 0; k < kTZ; ++k) {
+                const int sc = min((min(gk0 + LZ * k, d.nz - 1) + kSeedStride / 2) / kSeedStride, snc.z - 1);
+                const int t = seed[sa + snc.x * (sb + snc.y * sc)];
+                if (t >= 0) {
+                    const float4 *tr = tri + kTri * (size_t)t;
+                    float v_, w_;
+                    best[k] = tri_d2(px, py, pz[k], tr[0], tr[1], tr[2], tr[3], v_, w_);
+                    arg[k] = t;
+                }
+            }
         }
         if (n_tris > 0) {
             int sp = 1;
@@ -834,6 +960,8 @@ void Surface::plan(Arena &a, const Dims &d) {
     a.reserve(kWalkParts * sizeof(uint32_t));             // tile counters of the walk
     a.reserve((size_t)walk_tiles(d) * sizeof(uint32_t));   // tile costs of the walk
     a.reserve((size_t)walk_tiles(d) * sizeof(uint32_t));   // tile order of the walk
+    const SeedDims sd = seed_dims(d);
+    a.reserve((size_t)sd.x * sd.y * sd.z * sizeof(int32_t));   // seeds of the walk
 }
 
 void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
@@ -850,6 +978,10 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     next_tile_ = a.take<uint32_t>(kWalkParts);
     tile_cost_ = a.take<uint32_t>(walk_tiles(d));
     walk_order_ = a.take<uint32_t>(walk_tiles(d));
+    {
+        const SeedDims sd = seed_dims(d);
+        seed_ = a.take<int32_t>((size_t)sd.x * sd.y * sd.z);
+    }
     have_order_ = false;
     // the persistent walk stays one workgroup per compute unit below full
     // residency: its workgroups only retire when the tile queue is empty, and
@@ -954,12 +1086,24 @@ template <int LX, int LY, int LZ, int KZ>
 static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
                        const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
                        int32_t *argmin, int *err, uint32_t *next_tile, uint32_t *order, uint32_t *tile_cost,
-                       bool have_order, unsigned blocks, hipStream_t s) {
+                       bool have_order, int32_t *seed, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
-    k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
-                                                 next_tile, have_order ? order : nullptr, tile_cost);
+    const SeedDims snc = seed_dims(d);
+    const bool seeded = n_tris > 0 && d.count() >= kSeedMinNodes;
+    if (seeded) {
+        const unsigned ns = (unsigned)(snc.x * snc.y * snc.z);
+        k_sdf_seed<<<cdiv(ns, 64), 64, 0, s>>>(d, snc, nodes, leaf_aabb, root, tri, seed);
+        WG_LAUNCH_CHECK();
+    }
+    {
+        prof::Scope ps(WG_PROF_SDF, s, (double)d.count());   // the walk alone
+        k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin,
+                                                     err, next_tile, have_order ? order : nullptr, tile_cost,
+                                                     seeded ? seed : nullptr, snc);
+        WG_LAUNCH_CHECK();
+    }
     // the next walk's order, from this walk's costs (off the critical path of
     // a pipelined step: it runs beside the next step's solve)
     k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost, tiles, order);
@@ -969,11 +1113,10 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
-    prof::Scope ps(WG_PROF_SDF, s, (double)d_.count());
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
-                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, sdf_blocks_,
-                                                  s);
+                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, seed_,
+                                                  sdf_blocks_, s);
     have_order_ = true;   // ordered by the costs of the walk just launched
 }
 
