@@ -452,15 +452,28 @@ __device__ __forceinline__ float obb_d2(float4 N0, float4 N1, float4 N2, float4 
     return du * du + dv * dv + dn * dn;
 }
 
+// Levels of the hierarchy as the seed search indexes them: node `local` of
+// level l (0 = leaves) is nodes[off[l] + local]; its children are the nodes
+// 8 local .. 8 local + 7 of level l - 1 (fewer at the end of a level), and
+// leaf L holds triangles kLeaf L .. kLeaf L + kLeaf - 1.
+struct SeedLevels {
+    uint32_t off[kMaxLevels], cnt[kMaxLevels];
+    int levels;
+};
+
 // Nearest triangle of each seed-lattice node: one node per lane, each lane
-// with its own nearest-first traversal and stack (few nodes, so divergence
-// costs little), for at most kSeedPops nodes.  A stack that would overflow
-// drops the children.  Either way the seed is still a triangle, only perhaps
-// not the nearest: seeds only bound.
-__global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, const float4 *__restrict__ nodes,
-                                                  const float4 *__restrict__ leaf_aabb, uint32_t root,
-                                                  const float4 *__restrict__ tri, int32_t *__restrict__ seed) {
+// with its own nearest-first traversal (few nodes, so divergence costs
+// little), for at most kSeedPops stack entries.  A stack entry carries the
+// level, the index and the box bound it was pushed with, so a pop that the
+// bound rules out touches no memory and every other pop takes one round trip
+// (a leaf's triangles, or a node's child boxes).  A stack that would overflow
+// drops the children.  Either way the seed is a triangle, only perhaps not
+// the nearest: seeds only bound.
+__global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, SeedLevels lv, const float4 *__restrict__ nodes,
+                                                  const float4 *__restrict__ leaf_aabb, const float4 *__restrict__ tri,
+                                                  uint32_t n_tris, int32_t *__restrict__ seed) {
     __shared__ uint32_t stk[kSeedStack][64];
+    __shared__ float stb[kSeedStack][64];
     const int lane = threadIdx.x;
     const int id = blockIdx.x * 64 + lane;
     if (id >= nc.x * nc.y * nc.z) return;
@@ -470,16 +483,18 @@ __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, const floa
     float best = INFINITY;
     int arg = -1;
     int sp = 0;
-    stk[sp++][lane] = root;
+    stk[0][lane] = (uint32_t)(lv.levels - 1) << 27;   // the root, local index 0
+    stb[0][lane] = 0.f;
+    sp = 1;
     for (int pops = 0; sp > 0 && pops < kSeedPops; ++pops) {
-        const uint32_t ent = stk[--sp][lane];
-        const float4 *nd = nodes + (size_t)kNode * (ent & ~kLeafEntry);
-        if (ent & kLeafEntry) {
-            const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
-            if (obb_d2(N0, N1, N2, N3, px, py, pz) >= best) continue;
-            const uint32_t word = __float_as_uint(N3.w);
-            const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
-            for (uint32_t t = first; t < first + cnt; ++t) {
+        --sp;
+        const uint32_t ent = stk[sp][lane];
+        if (stb[sp][lane] >= best) continue;
+        const int l = (int)(ent >> 27);
+        const uint32_t loc = ent & 0x07ffffffu;
+        if (l == 0) {
+            const uint32_t t1 = min(loc * kLeaf + kLeaf, n_tris);
+            for (uint32_t t = loc * kLeaf; t < t1; ++t) {
                 const float4 *tr = tri + kTri * (size_t)t;
                 float v_, w_;
                 const float dd = tri_d2(px, py, pz, tr[0], tr[1], tr[2], tr[3], v_, w_);
@@ -490,19 +505,17 @@ __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, const floa
             }
             continue;
         }
-        const float4 A0 = nd[0], A1 = nd[1];
-        if (box_d2(A0, A1, px, py, pz) >= best) continue;
-        const uint32_t word = __float_as_uint(A0.w);
-        const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
-        const bool kids_leaves = (word & kKidsLeaves) != 0;
+        const uint32_t c0 = 8 * loc, cc = min(8u, lv.cnt[l - 1] - c0);
         // key: bit 31 = to be visited, then the child's bound (a non-negative
-        // float, ordered like its bits) with the child's index in the low 3 bits
+        // float, ordered like its bits; clearing its low 3 bits keeps it a
+        // lower bound) with the child's index in the low 3 bits
         uint32_t key[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             key[q] = 0u;
-            if ((uint32_t)q < cnt) {
-                const float4 *cb = kids_leaves ? leaf_aabb + 2 * (size_t)(first + q) : nodes + (size_t)kNode * (first + q);
+            if ((uint32_t)q < cc) {
+                const float4 *cb = l == 1 ? leaf_aabb + 2 * (size_t)(c0 + q)
+                                          : nodes + (size_t)kNode * (lv.off[l - 1] + c0 + q);
                 const float b = box_d2(cb[0], cb[1], px, py, pz);
                 if (b < best) key[q] = 0x80000000u | (__float_as_uint(b) & 0x7ffffff8u) | (uint32_t)q;
             }
@@ -514,10 +527,14 @@ __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, const floa
         cx_desc(key[2], key[4]); cx_desc(key[3], key[5]);
         cx_desc(key[1], key[4]); cx_desc(key[3], key[6]);
         cx_desc(key[1], key[2]); cx_desc(key[3], key[4]); cx_desc(key[5], key[6]);
-        const uint32_t flag = kids_leaves ? kLeafEntry : 0u;
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-            if (key[r] != 0u) stk[sp++][lane] = (first + (key[r] & 7u)) | flag;
+        for (int r = 0; r < 8; ++r) {
+            if (key[r] != 0u) {
+                stk[sp][lane] = ((uint32_t)(l - 1) << 27) | (c0 + (key[r] & 7u));
+                stb[sp][lane] = __uint_as_float(key[r] & 0x7ffffff8u);
+                ++sp;
+            }
+        }
     }
     seed[id] = arg;
 }
@@ -1086,7 +1103,7 @@ template <int LX, int LY, int LZ, int KZ>
 static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
                        const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
                        int32_t *argmin, int *err, uint32_t *next_tile, uint32_t *order, uint32_t *tile_cost,
-                       bool have_order, int32_t *seed, unsigned blocks, hipStream_t s) {
+                       bool have_order, int32_t *seed, const SeedLevels &lv, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
@@ -1094,7 +1111,7 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
     const bool seeded = n_tris > 0 && d.count() >= kSeedMinNodes;
     if (seeded) {
         const unsigned ns = (unsigned)(snc.x * snc.y * snc.z);
-        k_sdf_seed<<<cdiv(ns, 64), 64, 0, s>>>(d, snc, nodes, leaf_aabb, root, tri, seed);
+        k_sdf_seed<<<cdiv(ns, 64), 64, 0, s>>>(d, snc, lv, nodes, leaf_aabb, tri, n_tris, seed);
         WG_LAUNCH_CHECK();
     }
     {
@@ -1113,9 +1130,15 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
+    SeedLevels lv{};
+    lv.levels = levels_;
+    for (int l = 0; l < levels_; ++l) {
+        lv.off[l] = level_off_[l];
+        lv.cnt[l] = level_cnt_[l];
+    }
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
-                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, seed_,
+                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, seed_, lv,
                                                   sdf_blocks_, s);
     have_order_ = true;   // ordered by the costs of the walk just launched
 }
