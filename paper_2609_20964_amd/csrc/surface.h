@@ -67,6 +67,8 @@ class Surface {
     uint32_t *walk_order_ = nullptr;  // tiles of each slab, costliest first
     int32_t *seed_ = nullptr;         // nearest triangle of each seed-lattice node
     bool have_order_ = false;
+    hipStream_t seed_st_ = nullptr;   // the seed search, beside the walk
+    hipEvent_t ev_pre_ = nullptr, ev_seed_ = nullptr;
     unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
     SurfaceCounts cnt_{};
     // growable

@@ -536,7 +536,7 @@ __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, SeedLevels
             }
         }
     }
-    seed[id] = arg;
+    __hip_atomic_store(seed + id, arg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Side of every node: bit (o & 31) of word o >> 5 is set where chi >= c
@@ -608,13 +608,15 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
         }
         if (seed) {
             // start from the distance to the seed of the nearest lattice node
+            // (being searched beside this walk: any triangle index bounds)
             const int sa = min((i + kSeedStride / 2) / kSeedStride, snc.x - 1);
             const int sb = min((j + kSeedStride / 2) / kSeedStride, snc.y - 1);
 #pragma unroll
             for (int k = 0; k < kTZ; ++k) {
                 const int sc = min((min(gk0 + LZ * k, d.nz - 1) + kSeedStride / 2) / kSeedStride, snc.z - 1);
-                const int t = seed[sa + snc.x * (sb + snc.y * sc)];
-                if (t >= 0) {
+                const int t = __hip_atomic_load(seed + sa + snc.x * (sb + snc.y * sc), __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                if (t >= 0 && (uint32_t)t < n_tris) {
                     const float4 *tr = tri + kTri * (size_t)t;
                     float v_, w_;
                     best[k] = tri_d2(px, py, pz[k], tr[0], tr[1], tr[2], tr[3], v_, w_);
@@ -1022,6 +1024,10 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
 void Surface::set_persistent(bool on) { sdf_blocks_ = on ? sdf_blocks_full_ : ~0u; }
 
 Surface::~Surface() {
+    if (seed_st_) (void)hipStreamSynchronize(seed_st_);
+    if (ev_pre_) (void)hipEventDestroy(ev_pre_);
+    if (ev_seed_) (void)hipEventDestroy(ev_seed_);
+    if (seed_st_) (void)hipStreamDestroy(seed_st_);
     if (tri_) (void)hipFree(tri_);
     if (info_) (void)hipFree(info_);
     if (box_) (void)hipFree(box_);
@@ -1102,44 +1108,57 @@ uint32_t Surface::extract(const double *chi, const double *c) {
 template <int LX, int LY, int LZ, int KZ>
 static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const float4 *nodes,
                        const float4 *leaf_aabb, uint32_t root, const float4 *tri, uint32_t n_tris, float *phi,
-                       int32_t *argmin, int *err, uint32_t *next_tile, uint32_t *order, uint32_t *tile_cost,
-                       bool have_order, int32_t *seed, const SeedLevels &lv, unsigned blocks, hipStream_t s) {
+                       int32_t *argmin, int *err, uint32_t *next_tile, const uint32_t *order, uint32_t *tile_cost,
+                       const int32_t *seed, unsigned blocks, hipStream_t s) {
     const uint32_t tiles = cdiv(d.nx, LX) * cdiv(d.ny, LY) * cdiv(d.nz, LZ * KZ);
     if (blocks > cdiv(tiles, 4)) blocks = cdiv(tiles, 4);
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
-    const SeedDims snc = seed_dims(d);
-    const bool seeded = n_tris > 0 && d.count() >= kSeedMinNodes;
-    if (seeded) {
-        const unsigned ns = (unsigned)(snc.x * snc.y * snc.z);
-        k_sdf_seed<<<cdiv(ns, 64), 64, 0, s>>>(d, snc, lv, nodes, leaf_aabb, tri, n_tris, seed);
-        WG_LAUNCH_CHECK();
-    }
-    {
-        prof::Scope ps(WG_PROF_SDF, s, (double)d.count());   // the walk alone
-        k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin,
-                                                     err, next_tile, have_order ? order : nullptr, tile_cost,
-                                                     seeded ? seed : nullptr, snc);
-        WG_LAUNCH_CHECK();
-    }
-    // the next walk's order, from this walk's costs (off the critical path of
-    // a pipelined step: it runs beside the next step's solve)
-    k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost, tiles, order);
+    prof::Scope ps(WG_PROF_SDF, s, (double)d.count());   // the walk alone
+    k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
+                                                 next_tile, order, tile_cost, seed, seed_dims(d));
     WG_LAUNCH_CHECK();
 }
 
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
-    SeedLevels lv{};
-    lv.levels = levels_;
-    for (int l = 0; l < levels_; ++l) {
-        lv.off[l] = level_off_[l];
-        lv.cnt[l] = level_cnt_[l];
+    // Seeds: searched on a stream of their own, beside the walk rather than
+    // before it.  The walk reads each seed when it starts the tile that needs
+    // it, so early tiles see a previous walk's seed (or, on a new handle,
+    // whatever the buffer holds); the walk takes an index below n_tris as a
+    // triangle, which bounds whichever triangle it is, and ignores others.
+    const bool seeded = cnt_.n_tris > 0 && d_.count() >= kSeedMinNodes;
+    if (seeded) {
+        if (!seed_st_) {
+            WG_HIP(hipStreamCreateWithFlags(&seed_st_, hipStreamNonBlocking));
+            WG_HIP(hipEventCreateWithFlags(&ev_pre_, hipEventDisableTiming));
+            WG_HIP(hipEventCreateWithFlags(&ev_seed_, hipEventDisableTiming));
+        }
+        SeedLevels lv{};
+        lv.levels = levels_;
+        for (int l = 0; l < levels_; ++l) {
+            lv.off[l] = level_off_[l];
+            lv.cnt[l] = level_cnt_[l];
+        }
+        const SeedDims snc = seed_dims(d_);
+        const unsigned ns = (unsigned)(snc.x * snc.y * snc.z);
+        WG_HIP(hipEventRecord(ev_pre_, s));
+        WG_HIP(hipStreamWaitEvent(seed_st_, ev_pre_, 0));
+        k_sdf_seed<<<cdiv(ns, 64), 64, 0, seed_st_>>>(d_, snc, lv, box_, aabb_, tri_, cnt_.n_tris, seed_);
+        WG_LAUNCH_CHECK();
+        WG_HIP(hipEventRecord(ev_seed_, seed_st_));
     }
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
-                                                  err, next_tile_, walk_order_, tile_cost_, have_order_, seed_, lv,
-                                                  sdf_blocks_, s);
+                                                  err, next_tile_, have_order_ ? walk_order_ : nullptr, tile_cost_,
+                                                  seeded ? seed_ : nullptr, sdf_blocks_, s);
+    // the seed search reads the hierarchy the next extraction rewrites: order
+    // the walk's stream (which the next extraction waits for) after it
+    if (seeded) WG_HIP(hipStreamWaitEvent(s, ev_seed_, 0));
+    // the next walk's order, from this walk's costs (off the critical path of
+    // a pipelined step: it runs beside the next step's solve)
+    k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost_, walk_tiles(d_), walk_order_);
+    WG_LAUNCH_CHECK();
     have_order_ = true;   // ordered by the costs of the walk just launched
 }
 
