@@ -47,14 +47,13 @@ constexpr int kCostBuckets = 64;   // two per octave of cost
 // to it, which prunes from the first box on.
 constexpr int kSeedStride = 16;
 constexpr int kSeedStack = 64;
-// A seed search stops after this many nodes with the nearest triangle found so
-// far (any triangle bounds the distance; the walk stays exact).  The search is
-// latency-bound, one lane per lattice node, so its length is the pass's time:
-// 160 measured best among 32 to 400 (it overlaps the next step's solve when
-// steps are pipelined).
+// A seed search stops after this many stack entries with the nearest triangle
+// found so far (any triangle bounds the distance; the walk stays exact).  The
+// search is latency-bound, one lane per lattice node, so its length is the
+// pass's time: 160 measured best among 64 to 640.
 constexpr int kSeedPops = 160;
-// The seed pass costs about a millisecond whatever the grid; it pays only where
-// the walk takes several (256^3: 6.9 -> 6.1 ms), so smaller grids walk unseeded.
+// Seeds arrive about 0.75 ms into a walk whatever the grid; they pay only where
+// the walk takes several (256^3: 6.8 -> 6.3 ms), so smaller grids walk unseeded.
 constexpr size_t kSeedMinNodes = (size_t)1 << 23;
 struct SeedDims {
     int x, y, z;
