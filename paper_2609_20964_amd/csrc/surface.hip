@@ -50,9 +50,10 @@ constexpr int kSeedStack = 64;
 // A seed search stops after this many stack entries with the nearest triangle
 // found so far (any triangle bounds the distance; the walk stays exact).  The
 // search is latency-bound, one lane per lattice node, so its length is the
-// pass's time: 160 measured best among 64 to 640.
-constexpr int kSeedPops = 160;
-// Seeds arrive about 0.75 ms into a walk whatever the grid; they pay only where
+// pass's time.  Beside the walk, 160, 320 and 1000 measured alike (320 best
+// for plain steps, whose next step waits for the search).
+constexpr int kSeedPops = 320;
+// Seeds arrive 1-1.5 ms into a walk whatever the grid; they pay only where
 // the walk takes several (256^3: 6.8 -> 6.3 ms), so smaller grids walk unseeded.
 constexpr size_t kSeedMinNodes = (size_t)1 << 23;
 struct SeedDims {
