@@ -64,18 +64,25 @@ def gpu_run(args):
     q = torch.from_numpy(synth.uniform_queries(nq, 4001)).cuda()
     r = Recon(n, npts)
     kinds = list(_lib.PROF_KINDS)
-    # warm-up; the last warm-up steps are profiled for every kernel kind to find the dominant one
-    _lib.profile_reset()
+    # warm-up, then the last three warm-up clouds again as plain steps (no
+    # overlap, so each kind's event-timed duration is its own) with every
+    # kernel kind profiled, to find the dominant one
     for t in range(args.warmup):
-        if t == max(args.warmup - 3, 0):
-            _lib.profile_enable(kinds)
         st, _, _ = r.step(*clouds[t], q, rel_tol=args.tol, warm_start=t > 0)
         log(f"warmup {t}: iters {st['iters']} rel_res {st['rel_res']:.2e} ms {[round(v, 2) for v in st['ms'][:5]]}")
     r.wait()
     torch.cuda.synchronize()
+    _lib.profile_reset()
+    _lib.profile_enable(kinds)
+    prof_steps = list(range(max(args.warmup - 3, 0), args.warmup)) or [0]
+    n_prof = len(prof_steps)
+    for t in prof_steps:
+        r.forward(*clouds[t], rel_tol=args.tol, warm_start=args.warmup > 0)
+        r.sample(q)
+    torch.cuda.synchronize()
     per_kind = {k: _lib.profile_read(k) for k in kinds}
     dominant = max(per_kind, key=lambda k: per_kind[k]["ms"])
-    log("warm-up kernel time by kind (ms):", {k: round(v["ms"], 3) for k, v in per_kind.items()})
+    log("plain-step kernel time by kind (ms):", {k: round(v["ms"], 3) for k, v in per_kind.items()})
     _lib.profile_enable([])
     _lib.profile_reset()
     _lib.profile_enable([dominant])
@@ -141,7 +148,7 @@ def gpu_run(args):
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
-            "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats}
+            "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -649,7 +656,7 @@ def main():
         # phases of the steps run one after another (in pipelined steps they overlap)
         "phase_ms_plain": {k: float(np.mean([s["ms"][i] for s in res["plain_stats"]]))
                            for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
-        "kernel_ms_per_step_warmup": {k: v["ms"] / 3 for k, v in res["per_kind"].items()},
+        "kernel_ms_per_step_plain": {k: v["ms"] / res["n_prof"] for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
     }
     if not args.no_cpu_baseline:
