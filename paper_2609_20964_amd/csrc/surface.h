@@ -32,8 +32,9 @@ class Surface {
     // distance walk reads the node sides, not chi.
     uint32_t extract(const double *chi, const double *c);
     // phi and the nearest-triangle index on every node, on stream s (after
-    // extract has completed there).
-    void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s);
+    // extract has completed there).  beside: the next step's solve will run
+    // meanwhile (a persistent walk then leaves it room).
+    void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside);
     // reverse of sdf through the vertices: g_chi, g_c (+=)
     void sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                float *g_chi, double *g_c);
@@ -42,7 +43,8 @@ class Surface {
     // first n triangles as float[9] (vertices in grid units)
     void export_tris(float *out, uint32_t n);
     // persistent = true (default): the distance walk runs as many workgroups
-    // as fit on the device at once, each taking tiles from a queue (no tail).
+    // as fit on the device at once, less a few free slots for the other
+    // streams' work, each taking tiles from a queue (no tail).
     // false: one workgroup per 4 tiles, so the walks of concurrent handles
     // interleave workgroup by workgroup.
     void set_persistent(bool on);
@@ -69,7 +71,8 @@ class Surface {
     bool have_order_ = false;
     hipStream_t seed_st_ = nullptr;   // the seed search, beside the walk
     hipEvent_t ev_pre_ = nullptr, ev_seed_ = nullptr;
-    unsigned sdf_blocks_ = 0, sdf_blocks_full_ = 0;
+    bool persistent_ = true;
+    unsigned sdf_blocks_full_ = 0, sdf_blocks_beside_ = 0;   // persistent workgroups: alone, beside a solve
     SurfaceCounts cnt_{};
     // growable
     float4 *tri_ = nullptr;        // [cap][4] records (a,|ab|^2) (ab,ab.ac) (ac,|ac|^2) (reciprocals)

@@ -1002,17 +1002,23 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
         seed_ = a.take<int32_t>((size_t)sd.x * sd.y * sd.z);
     }
     have_order_ = false;
-    // the persistent walk stays one workgroup per compute unit below full
-    // residency: its workgroups only retire when the tile queue is empty, and
-    // work on the handle's other stream (the next step's splat and solve, host
-    // copies) needs free slots meanwhile
+    // The persistent walk stays below full residency: its workgroups only
+    // retire when the tile queues are empty, and work on the other streams
+    // needs free slots meanwhile.  Alone it leaves one workgroup slot per
+    // compute unit (the splat, reductions, host read-backs and the seed
+    // search fit there).  Beside the next step's solve (pipelined steps) it
+    // leaves four, so that one fused V-cycle workgroup (two wavefronts per SIMD
+    // of up to 128 VGPRs) fits too: the walk is slower, but the solve no
+    // longer waits for it (256^3: 8.2 ms per step against 8.55 with one; two or
+    // three free slots are slower than one, five or six much slower; the post
+    // pass squeezed to 96 VGPRs to fit beside a five-slot walk spills).
     int dev = 0, cus = 0, per_cu = 0;
     WG_HIP(hipGetDevice(&dev));
     WG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     WG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sdf<4, 4, 4, 4>, 256, 0));
-    per_cu = per_cu > 1 ? per_cu - 1 : 1;
-    sdf_blocks_full_ = (unsigned)(cus > 0 ? cus : 256) * (unsigned)per_cu;
-    sdf_blocks_ = sdf_blocks_full_;
+    const unsigned ncu = (unsigned)(cus > 0 ? cus : 256);
+    sdf_blocks_full_ = ncu * (unsigned)(per_cu > 1 ? per_cu - 1 : 1);
+    sdf_blocks_beside_ = ncu * (unsigned)(per_cu > 4 ? per_cu - 4 : 1);
     hcnt_.alloc();
     // a first guess at the triangle capacity: ~4 per cube over a few slices
     size_t face = (size_t)d.nx * d.ny;
@@ -1021,7 +1027,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     ensure_capacity((uint32_t)(4 * face), (uint32_t)(face / 4 + 16));
 }
 
-void Surface::set_persistent(bool on) { sdf_blocks_ = on ? sdf_blocks_full_ : ~0u; }
+void Surface::set_persistent(bool on) { persistent_ = on; }
 
 Surface::~Surface() {
     if (seed_st_) (void)hipStreamSynchronize(seed_st_);
@@ -1119,7 +1125,8 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
     WG_LAUNCH_CHECK();
 }
 
-void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s) {
+void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside) {
+    const unsigned blocks = !persistent_ ? ~0u : beside ? sdf_blocks_beside_ : sdf_blocks_full_;
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
     // Seeds: searched on a stream of their own, beside the walk rather than
@@ -1151,7 +1158,7 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,
                                                   err, next_tile_, have_order_ ? walk_order_ : nullptr, tile_cost_,
-                                                  seeded ? seed_ : nullptr, sdf_blocks_, s);
+                                                  seeded ? seed_ : nullptr, blocks, s);
     // the seed search reads the hierarchy the next extraction rewrites: order
     // the walk's stream (which the next extraction waits for) after it
     if (seeded) WG_HIP(hipStreamWaitEvent(s, ev_seed_, 0));
