@@ -212,6 +212,13 @@ def roofline(res):
             out["valu_issue_frac"] = pmc["valu_issue_frac"]
     out.update({"kernel": KIND_KERNEL[kind], "launches": p["launches"], "avg_launch_us": avg_s * 1e6,
                 "units_per_launch": per_launch})
+    # the same kernel in the plain (not overlapped) profiled steps: in the timed
+    # pipelined steps it shares the device with the next step's solve
+    a = res["per_kind"].get(kind)
+    if a and a["launches"] > 0 and a["ms"] > 0:
+        avg_a = a["ms"] / a["launches"] / 1e3
+        frac_a = (out["frac"] * avg_s / avg_a) if out.get("frac") else None
+        out["alone"] = {"launches": a["launches"], "avg_launch_us": avg_a * 1e6, "frac": frac_a}
     return out
 
 
