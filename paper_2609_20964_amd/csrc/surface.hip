@@ -42,10 +42,10 @@ inline uint32_t walk_tiles(const Dims &d) {
 constexpr uint32_t kCostPop = 1, kCostInner = 50, kCostLeaf = 75;
 constexpr int kCostBuckets = 64;   // two per octave of cost
 // Seeds of the walk: the exact nearest triangle of every node of a lattice of
-// stride kSeedStride (nodes 0, 16, 32, ... per axis, 4096 at 256^3).  Each
+// stride kSeedStride (nodes 0, 8, 16, ... per axis, 32768 at 256^3).  Each
 // node's bound starts at its distance to the seed of the lattice node nearest
 // to it, which prunes from the first box on.
-constexpr int kSeedStride = 16;
+constexpr int kSeedStride = 8;   // 16 measured 0.8% slower per pipelined step
 constexpr int kSeedStack = 64;
 // A seed search stops after this many stack entries with the nearest triangle
 // found so far (any triangle bounds the distance; the walk stays exact).  The
