@@ -1,0 +1,45 @@
+"""Host-side logic of bench.py (no GPU): the single-GPU guard and the roofline
+arithmetic of the JSON line, on synthetic profiling records."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+def test_alu_roofline_of_the_walk():
+    # 10 launches of 16.7M nodes in 70 ms (timed) and 3 in 18 ms alone
+    nodes = 16_777_216
+    res = {"dominant": "sdf", "prof": {"launches": 10, "ms": 70.0, "units": 10.0 * nodes},
+           "per_kind": {"sdf": {"launches": 3, "ms": 18.0, "units": 3.0 * nodes}}}
+    r = bench.roofline(res)
+    fpn = bench.load_pmc("sdf")["fp32_flops_per_unit"]
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.FP32_VALU_TFLOPS
+    assert r["avg_launch_us"] == pytest.approx(7000.0)
+    assert r["achieved"] == pytest.approx(fpn * nodes / 7e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert r["alone"]["avg_launch_us"] == pytest.approx(6000.0)
+    assert r["alone"]["frac"] == pytest.approx(r["frac"] * 7.0 / 6.0)
+
+
+def test_solver_roofline_against_peak_and_copy():
+    kinds = {k: {"units": 1e9, "ms": 0.25, "launches": 4} for k in bench.SOLVER_KINDS}
+    res = {"solver_kinds": kinds, "solve_ms": [2.0, 2.0]}
+    s = bench.solver_hbm(res, copy_gbs=5000.0)
+    n = len(bench.SOLVER_KINDS)
+    assert s["kernels_GB_s"] == pytest.approx(n * 1e9 / (n * 0.25 * 1e6))
+    assert s["phase_GB_s"] == pytest.approx(n * 1e9 / (4.0 * 1e6))
+    assert s["kernels_frac"] == pytest.approx(s["kernels_GB_s"] / 8000.0)
+    assert s["kernels_frac_of_copy"] == pytest.approx(s["kernels_GB_s"] / 5000.0)
+    assert s["phase_ms"] == pytest.approx(2.0)
