@@ -999,7 +999,9 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     walk_order_ = a.take<uint32_t>(walk_tiles(d));
     {
         const SeedDims sd = seed_dims(d);
-        seed_ = a.take<int32_t>((size_t)sd.x * sd.y * sd.z);
+        const size_t ns = (size_t)sd.x * sd.y * sd.z;
+        seed_ = a.take<int32_t>(ns);
+        WG_HIP(hipMemsetAsync(seed_, 0xff, ns * sizeof(int32_t), s));   // -1: no seed before the first search
     }
     have_order_ = false;
     // The persistent walk stays below full residency: its workgroups only
@@ -1131,9 +1133,9 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
     // Seeds: searched on a stream of their own, beside the walk rather than
     // before it.  The walk reads each seed when it starts the tile that needs
-    // it, so early tiles see a previous walk's seed (or, on a new handle,
-    // whatever the buffer holds); the walk takes an index below n_tris as a
-    // triangle, which bounds whichever triangle it is, and ignores others.
+    // it, so early tiles see a previous walk's seed (-1 on a new handle); the
+    // walk takes an index below n_tris as a triangle, which bounds whichever
+    // triangle it is, and ignores others.
     const bool seeded = cnt_.n_tris > 0 && d_.count() >= kSeedMinNodes;
     if (seeded) {
         if (!seed_st_) {
