@@ -612,7 +612,7 @@ def main():
     ap.add_argument("--queries", type=int, default=65_536)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--adjoint-steps", type=int, default=3)
-    ap.add_argument("--serving", type=int, default=40, help="requests in the serving replay (0: skip)")
+    ap.add_argument("--serving", type=int, default=160, help="requests in the serving replay (0: skip)")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")

@@ -214,7 +214,10 @@ typedef struct {
 } wg_result;
 
 /* Start a server on `device` with at most max_inflight concurrent requests,
- * each on its own stream, and a device-memory budget for resident handles. */
+ * each on its own stream, and a device-memory budget for resident handles.
+ * Requests start in arrival order, except that requests whose grid has 2^23
+ * cells or more (256^3, say: each keeps the whole device busy) run one at a
+ * time: while one runs, a free slot takes the first smaller request queued. */
 int wg_server_create(wg_server **out, size_t hbm_budget_bytes, int max_inflight, int device);
 
 /* Queue a request (inputs are copied before return); *ticket identifies it.

@@ -12,7 +12,13 @@
 // worker waits when everything resident is busy.  Every handle owns its own
 // HIP stream, so the kernels of concurrent requests overlap on the device; a
 // request that starts alone runs its distance walk persistent, one that starts
-// beside others runs it as independent workgroups.
+// beside others runs it as independent workgroups (see run()).
+//
+// A request whose grid alone keeps every compute unit busy (kFillCells cells
+// or more) gains nothing from overlapping another such request: both would
+// just take twice as long.  At most one of them runs at a time; while one
+// runs, a free worker takes the first queued request that is smaller, so the
+// large ones keep their arrival order and the small ones fill the gaps.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -39,6 +45,12 @@ struct Key {
     }
 };
 
+// 2^23 cells: a distance walk of 32768 256-node tiles (128 per compute unit)
+// and sweeps of 2^15 or more workgroups
+constexpr size_t kFillCells = size_t(1) << 23;
+
+bool fills_device(const wg_grid &g) { return (size_t)g.n[0] * g.n[1] * g.n[2] >= kFillCells; }
+
 int capacity_class(int npts) {
     int c = 1 << 14;
     while (c < npts) c <<= 1;
@@ -53,10 +65,16 @@ struct Handle {
     uint64_t last_use = 0;
 };
 
+struct Buf {
+    float *p = nullptr;
+    size_t cap = 0;   // floats
+};
+
 struct Job {
     uint64_t ticket = 0;
     wg_request req{};
-    float *xyz = nullptr, *nrm = nullptr, *q = nullptr, *gphi = nullptr;   // server-owned copies
+    Buf in[4];   // server-owned copies: points, normals, queries, dL/dphi
+    float *xyz = nullptr, *nrm = nullptr, *q = nullptr, *gphi = nullptr;   // in[k].p
     int state = 0;   // 0 queued, 1 running, 2 done
     wg_result res{};
 };
@@ -83,6 +101,7 @@ class Server {
         (void)hipSetDevice(device_);
         for (auto &h : idle_) destroy(h);
         for (auto &kv : jobs_) free_inputs(*kv.second);
+        for (auto &kv : pool_) (void)hipFree(kv.second);
         (void)hipStreamDestroy(ingest_);
     }
 
@@ -102,18 +121,23 @@ class Server {
         auto job = std::make_unique<Job>();
         job->req = rq;
         job->res.t_submit = now();
-        auto copy = [&](const float *src, size_t n) -> float * {
+        auto copy = [&](int k, const float *src, size_t n) -> float * {
             if (!src || n == 0) return nullptr;
-            float *dst = nullptr;
-            WG_HIP(hipMalloc(&dst, n * sizeof(float)));
-            WG_HIP(hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, ingest_));
-            return dst;
+            job->in[k] = take_buf(n);
+            WG_HIP(hipMemcpyAsync(job->in[k].p, src, n * sizeof(float), hipMemcpyDeviceToDevice, ingest_));
+            return job->in[k].p;
         };
-        job->xyz = copy(rq.d_xyz, 3 * (size_t)rq.n_points);
-        job->nrm = copy(rq.d_nrm, 3 * (size_t)rq.n_points);
-        job->q = copy(rq.d_q, 3 * (size_t)rq.n_q);
-        job->gphi = copy(rq.d_gphi, (size_t)rq.n_q);
-        WG_HIP(hipStreamSynchronize(ingest_));
+        try {
+            job->xyz = copy(0, rq.d_xyz, 3 * (size_t)rq.n_points);
+            job->nrm = copy(1, rq.d_nrm, 3 * (size_t)rq.n_points);
+            job->q = copy(2, rq.d_q, 3 * (size_t)rq.n_q);
+            job->gphi = copy(3, rq.d_gphi, (size_t)rq.n_q);
+            WG_HIP(hipStreamSynchronize(ingest_));
+        } catch (...) {
+            (void)hipStreamSynchronize(ingest_);
+            free_inputs(*job);
+            throw;
+        }
         std::unique_lock<std::mutex> lk(mu_);
         job->ticket = ++next_ticket_;
         *ticket = job->ticket;
@@ -141,9 +165,33 @@ class Server {
     }
 
   private:
+    // Input copies live in buffers that are reused, never freed while the
+    // server runs: hipFree waits for the whole device, so freeing at poll
+    // would hold the caller until every running request's kernels finish.
+    // Capacities are powers of two; the pool's size is bounded by the most
+    // requests ever outstanding at once.
+    Buf take_buf(size_t n) {
+        {
+            std::lock_guard<std::mutex> lk(pool_mu_);
+            auto it = pool_.lower_bound(n);
+            if (it != pool_.end()) {
+                Buf b{it->second, it->first};
+                pool_.erase(it);
+                return b;
+            }
+        }
+        Buf b;
+        b.cap = 1024;
+        while (b.cap < n) b.cap <<= 1;
+        WG_HIP(hipMalloc(&b.p, b.cap * sizeof(float)));
+        return b;
+    }
+
     void free_inputs(Job &j) {
-        for (float *p : {j.xyz, j.nrm, j.q, j.gphi})
-            if (p) (void)hipFree(p);
+        std::lock_guard<std::mutex> lk(pool_mu_);
+        for (Buf &b : j.in)
+            if (b.p) pool_.emplace(b.cap, b.p);
+        for (Buf &b : j.in) b = Buf{};
         j.xyz = j.nrm = j.q = j.gphi = nullptr;
     }
 
@@ -203,10 +251,12 @@ class Server {
     // alone: no other request was running when this one started.  A lone
     // request's distance walk runs persistent (fastest alone); with others
     // running, walks go one workgroup per tile group so concurrent requests
-    // interleave instead of queueing behind a walk that holds every slot.
+    // interleave instead of queueing behind a walk that holds every slot.  A
+    // device-filling request runs it persistent in any case: only smaller
+    // requests run beside it, and they fit in the slots the walk leaves free.
     void run(Job &j, Handle &h, bool alone) {
         const wg_request &rq = j.req;
-        h.r->set_persistent(alone);
+        h.r->set_persistent(alone || fills_device(rq.grid));
         wg_solve_opts o = rq.opts;
         o.warm_start = 0;   // a request's result must not depend on what ran before it
         int st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats);
@@ -227,10 +277,13 @@ class Server {
         (void)hipSetDevice(device_);
         std::unique_lock<std::mutex> lk(mu_);
         for (;;) {
-            cv_.wait(lk, [this] { return stop_ || !queue_.empty(); });
+            std::deque<Job *>::iterator pick;
+            cv_.wait(lk, [&] { return (stop_ && queue_.empty()) || (pick = next_job()) != queue_.end(); });
             if (stop_ && queue_.empty()) return;
-            Job *j = queue_.front();
-            queue_.pop_front();
+            Job *j = *pick;
+            queue_.erase(pick);
+            const bool fills = fills_device(j->req.grid);
+            fill_running_ += fills;
             ++running_;
             j->state = 1;
             Key k{};
@@ -266,9 +319,20 @@ class Server {
             }
             j->state = 2;
             --running_;
+            fill_running_ -= fills;
             release_cv_.notify_all();
             drain_cv_.notify_all();
+            if (fills) cv_.notify_all();   // a held device-filling request may start
         }
+    }
+
+    // First queued request that may start now: any request while no
+    // device-filling one runs, else the first smaller one.
+    std::deque<Job *>::iterator next_job() {
+        auto it = queue_.begin();
+        if (fill_running_ > 0)
+            while (it != queue_.end() && fills_device((*it)->req.grid)) ++it;
+        return it;
     }
 
     size_t budget_;
@@ -280,10 +344,12 @@ class Server {
     std::deque<Job *> queue_;
     std::map<uint64_t, std::unique_ptr<Job>> jobs_;
     std::list<Handle> idle_;
+    std::mutex pool_mu_;
+    std::multimap<size_t, float *> pool_;   // idle input buffers by capacity (floats)
     std::vector<std::thread> workers_;
     size_t resident_ = 0;
     uint64_t next_ticket_ = 0, clock_ = 0;
-    int running_ = 0;
+    int running_ = 0, fill_running_ = 0;
     bool stop_ = false;
 };
 

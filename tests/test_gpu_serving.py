@@ -96,3 +96,20 @@ def test_admission_by_footprint_and_rejection():
         srv.submit(256, _cuda(x), _cuda(nn), _cuda(synth.uniform_queries(16, 1)))
     assert e.value.code == WG_ENOMEM
     srv.close()
+
+
+def test_device_filling_requests_take_turns():
+    """Two 256^3 requests (each fills the device alone) never overlap each
+    other, smaller ones may run beside them, and the two give the same field."""
+    from paper_2609_20964_amd.serving import Server
+    srv = Server(hbm_budget_bytes=16 << 30, max_inflight=3)
+    x, nn = synth.sphere(20000, seed=603)
+    q = synth.uniform_queries(1024, 604)
+    reqs = [(256, x, nn), (256, x, nn), (32, *synth.sphere(4000, seed=605)), (64, *synth.sphere(8000, seed=606))]
+    tickets = [srv.submit(n, _cuda(a), _cuda(b), _cuda(q), rel_tol=1e-6) for n, a, b in reqs]
+    results = _wait(srv, tickets)
+    assert all(st == 0 for st, _, _ in results), [r[2] for r in results]
+    (_, o0, i0), (_, o1, i1) = results[0], results[1]
+    assert i1["t_start"] >= i0["t_done"] or i0["t_start"] >= i1["t_done"], (i0, i1)
+    assert np.abs(o0["phi"].cpu().numpy() - o1["phi"].cpu().numpy()).max() <= 1e-4 / 256
+    srv.close()
