@@ -251,11 +251,11 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         }
         WG_HIP(hipEventRecord(ev_mc_, st_));
         WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
-        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_, true);
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_, true, o.warm_start != 0);
         WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
         sdf_pending_ = true;
     } else {
-        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_, false);
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_, false, o.warm_start != 0);
     }
     tm.mark(5);
     if (!pipelined) check_err("sdf");

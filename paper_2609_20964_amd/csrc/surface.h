@@ -33,8 +33,11 @@ class Surface {
     uint32_t extract(const double *chi, const double *c);
     // phi and the nearest-triangle index on every node, on stream s (after
     // extract has completed there).  beside: the next step's solve will run
-    // meanwhile (a persistent walk then leaves it room).
-    void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside);
+    // meanwhile (a persistent walk then leaves it room).  related: the surface
+    // is close to the last one walked (a warm-started step), so that walk's
+    // tile costs order this one; otherwise, on large grids, the depth of each
+    // tile inside the surface does.  No result depends on the order.
+    void sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside, bool related);
     // reverse of sdf through the vertices: g_chi, g_c (+=)
     void sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                float *g_chi, double *g_c);

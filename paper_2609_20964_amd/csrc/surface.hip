@@ -56,6 +56,17 @@ constexpr int kSeedPops = 320;
 // Seeds arrive 1-1.5 ms into a walk whatever the grid; they pay only where
 // the walk takes several (256^3: 6.8 -> 6.3 ms), so smaller grids walk unseeded.
 constexpr size_t kSeedMinNodes = (size_t)1 << 23;
+// A walk with no related walk before it (a new handle, or a cloud unrelated to
+// the last) orders its tiles by an estimate taken from the node sides: the
+// costliest tiles lie deep inside a body, where many triangles are at nearly
+// the same distance.  A tile with no outside node gets its depth in tile steps
+// (4 cells across x and y, 16 along z) to the nearest tile that has one, by
+// kDepthPasses relaxation passes over the tile grid; deeper tiles tie.  Every
+// other tile ranks below them by its count of inside nodes.
+constexpr int kDepthPasses = 12;
+static_assert(kDepthPasses % 2 == 0, "the last pass writes the first buffer");
+constexpr uint32_t kTileFull = 0x80000000u;   // flag: no outside node; low 16 bits: depth
+constexpr uint32_t kDepthCap = 13;
 struct SeedDims {
     int x, y, z;
 };
@@ -773,6 +784,63 @@ __global__ __launch_bounds__(256) void k_walk_order(const uint32_t *__restrict__
     for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) order[atomicAdd(&pos[cost_bucket(cost[t])], 1u)] = t;
 }
 
+// One wavefront per tile, lanes as in the walk: kTileFull with an unknown
+// depth if no node of the tile is outside, else its count of inside nodes.
+__global__ __launch_bounds__(256) void k_tile_sides(const uint32_t *__restrict__ side, Dims d,
+                                                     uint32_t *__restrict__ out) {
+    constexpr int LX = kWalkLX, LY = kWalkLY, LZ = kWalkLZ, KZ = kWalkKZ, TZ = LZ * KZ;
+    const int lane = threadIdx.x % 64;
+    const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
+    const uint32_t tile = blockIdx.x * 4 + threadIdx.x / 64;
+    if (tile >= (uint32_t)(tx * ty * tz)) return;   // uniform per wavefront
+    const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
+    const int gi = bx * LX + lane % LX, gj = by * LY + (lane / LX) % LY, gk0 = bz * TZ + lane / (LX * LY);
+    uint32_t inside = 0, outside = 0;
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) {
+        const int gk = gk0 + LZ * k;
+        bool in = false, out_ = false;
+        if (gi < d.nx && gj < d.ny && gk < d.nz) {
+            const size_t o = (size_t)gi + (size_t)d.nx * (gj + (size_t)d.ny * gk);
+            out_ = ((side[o >> 5] >> (o & 31)) & 1u) != 0u;
+            in = !out_;
+        }
+        inside += (uint32_t)__popcll(__ballot(in));
+        outside += (uint32_t)__popcll(__ballot(out_));
+    }
+    if (lane == 0) out[tile] = outside == 0 ? (kTileFull | 0xffffu) : inside;
+}
+
+// One relaxation pass of the depths (one thread per tile); tiles beyond the
+// grid count as outside.  last: write the sort keys instead, 512 << depth for
+// tiles with no outside node (above any inside count), the count otherwise.
+__global__ __launch_bounds__(256) void k_tile_depth(const uint32_t *__restrict__ in, Dims d, uint32_t *__restrict__ out,
+                                                     bool last) {
+    const int tx = (d.nx + kWalkLX - 1) / kWalkLX, ty = (d.ny + kWalkLY - 1) / kWalkLY,
+              tz = (d.nz + kWalkLZ * kWalkKZ - 1) / (kWalkLZ * kWalkKZ);
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint32_t)(tx * ty * tz)) return;
+    uint32_t v = in[t];
+    if (v & kTileFull) {
+        const int bx = t % tx, by = (t / tx) % ty, bz = t / (tx * ty);
+        auto dep = [&](int x, int y, int z) -> uint32_t {
+            if (x < 0 || y < 0 || z < 0 || x >= tx || y >= ty || z >= tz) return 0u;
+            const uint32_t u = in[(size_t)x + (size_t)tx * (y + (size_t)ty * z)];
+            return (u & kTileFull) ? (u & 0xffffu) : 0u;
+        };
+        uint32_t m = v & 0xffffu;
+        m = min(m, dep(bx - 1, by, bz) + 1u);
+        m = min(m, dep(bx + 1, by, bz) + 1u);
+        m = min(m, dep(bx, by - 1, bz) + 1u);
+        m = min(m, dep(bx, by + 1, bz) + 1u);
+        m = min(m, dep(bx, by, bz - 1) + 4u);
+        m = min(m, dep(bx, by, bz + 1) + 4u);
+        v = kTileFull | m;
+    }
+    if (last) v = (v & kTileFull) ? (512u << min(v & 0xffffu, kDepthCap)) : v;
+    out[t] = v;
+}
+
 // Reverse of phi through the distance (envelope theorem on Eq. 33) and the
 // Marching Cubes vertices (Eq. 28): g_chi at the two ends of each vertex's
 // edge, g_c in FP64.
@@ -1127,15 +1195,33 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
     WG_LAUNCH_CHECK();
 }
 
-void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside) {
+void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside, bool related) {
     const unsigned blocks = !persistent_ ? ~0u : beside ? sdf_blocks_beside_ : sdf_blocks_full_;
+    // Tile order: the last walk's costs when that walk was of a related
+    // surface; on large grids otherwise the estimate from the node sides (the
+    // walk_order_ buffer holds the alternate relaxation passes).
+    const bool cold = d_.count() >= kSeedMinNodes && (!related || !have_order_);
+    if (cold) {
+        const uint32_t nt = walk_tiles(d_);
+        k_tile_sides<<<cdiv(nt, 4), 256, 0, s>>>(sign_, d_, tile_cost_);
+        for (int p = 0; p < kDepthPasses; ++p) {
+            const bool even = p % 2 == 0;
+            k_tile_depth<<<cdiv(nt, 256), 256, 0, s>>>(even ? tile_cost_ : walk_order_, d_,
+                                                        even ? walk_order_ : tile_cost_, p == kDepthPasses - 1);
+        }
+        k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost_, nt, walk_order_);
+        WG_LAUNCH_CHECK();
+        have_order_ = true;
+    }
     // a one-level hierarchy is a single leaf
     const uint32_t root = levels_ > 1 ? level_off_[levels_ - 1] : kLeafEntry;
-    // Seeds: searched on a stream of their own, beside the walk rather than
-    // before it.  The walk reads each seed when it starts the tile that needs
-    // it, so early tiles see a previous walk's seed (-1 on a new handle); the
-    // walk takes an index below n_tris as a triangle, which bounds whichever
-    // triangle it is, and ignores others.
+    // Seeds: after a related walk, searched on a stream of their own beside
+    // the walk; the walk reads each seed when it starts the tile that needs
+    // it, so early tiles see the previous walk's seed.  After an unrelated
+    // surface (cold) those would bound nothing useful, so the search runs
+    // first, on the walk's stream.  The walk takes an index below n_tris as a
+    // triangle, which bounds whichever triangle it is, and ignores others (-1
+    // on a new handle).
     const bool seeded = cnt_.n_tris > 0 && d_.count() >= kSeedMinNodes;
     if (seeded) {
         if (!seed_st_) {
@@ -1151,11 +1237,14 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
         }
         const SeedDims snc = seed_dims(d_);
         const unsigned ns = (unsigned)(snc.x * snc.y * snc.z);
-        WG_HIP(hipEventRecord(ev_pre_, s));
-        WG_HIP(hipStreamWaitEvent(seed_st_, ev_pre_, 0));
-        k_sdf_seed<<<cdiv(ns, 64), 64, 0, seed_st_>>>(d_, snc, lv, box_, aabb_, tri_, cnt_.n_tris, seed_);
+        hipStream_t ss = cold ? s : seed_st_;
+        if (!cold) {
+            WG_HIP(hipEventRecord(ev_pre_, s));
+            WG_HIP(hipStreamWaitEvent(seed_st_, ev_pre_, 0));
+        }
+        k_sdf_seed<<<cdiv(ns, 64), 64, 0, ss>>>(d_, snc, lv, box_, aabb_, tri_, cnt_.n_tris, seed_);
         WG_LAUNCH_CHECK();
-        WG_HIP(hipEventRecord(ev_seed_, seed_st_));
+        WG_HIP(hipEventRecord(ev_seed_, ss));
     }
     // a wavefront takes 4x4x4 columns of 4 nodes along z (a 4x4x16 tile)
     launch_sdf<kWalkLX, kWalkLY, kWalkLZ, kWalkKZ>(d_, sign_, h, box_, aabb_, root, tri_, cnt_.n_tris, phi, argmin,

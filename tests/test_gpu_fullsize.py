@@ -5,7 +5,9 @@ by one.
 * torus, 200,000 noisy points, 128^3, 1,000,000 queries sampled on the GPU;
 * flapping ellipsoid, 300,000 points, 256^3, warm-started pipelined steps at
   relative residual 1e-6 (the benchmark's loop), then one more step solved to
-  1e-10 so the field can be held to the 1e-5 tolerance.
+  1e-10 so the field can be held to the 1e-5 tolerance;
+* a thick-bodied superellipsoid of the serving stream at 256^3, walked cold
+  (tiles ordered by depth inside the surface) and warm after another surface.
 
 Compared: the field (relative 1e-5), the iso-value, the triangle count, the
 signed distance on random and near-surface nodes (1e-4 h) and the sampled
@@ -99,3 +101,38 @@ def test_flapping_256_benchmark_loop():
     ref = P.Recon(grid, x, nrm)
     _check(grid, ref, r, st, phi, q, phi_q.cpu().numpy(), n_q.cpu().numpy(), 4002, 300, 200)
     r.close()
+
+
+def test_thick_body_256_cold_walk_order():
+    """A 256^3 request of the serving stream (a superellipsoid with a thick
+    interior, ~155k triangles): a cold forward orders its distance walk by the
+    depth of each tile inside the surface, a warm one on another handle by a
+    sphere's walk costs.  Both must write every node: the field and the SDF at
+    sampled nodes against the oracle, and the two walks against each other."""
+    from paper_2609_20964_amd.recon import Recon
+    grid = D.Grid.unit(256)
+    rq = [rq for rq in synth.request_stream(160) if rq.n == 256][0]
+    x, nrm = rq.cloud()
+    print(f"superellipsoid 256^3, {len(x)} points, cold and warm walks", flush=True)
+    cap = max(len(x), 20000)
+    a, b = Recon(256, cap), Recon(256, cap)
+    sa = a.forward(_cuda(x), _cuda(nrm), rel_tol=1e-10, max_iters=5000)
+    xs, ns = synth.sphere(20000, radius=0.3, seed=4011)
+    b.forward(_cuda(xs), _cuda(ns), rel_tol=1e-6)
+    sb = b.forward(_cuda(x), _cuda(nrm), rel_tol=1e-10, max_iters=5000, warm_start=True)
+    assert sa["status"] == 0 and sb["status"] == 0
+    torch.cuda.synchronize()
+    pa, pb = a.fields()["phi"].cpu().numpy(), b.fields()["phi"].cpu().numpy()
+    assert np.abs(pa - pb).max() <= 1e-4 * grid.h
+    ref = P.Recon(grid, x, nrm)
+    assert _rel(a.fields()["chi"].cpu().numpy(), ref.chi) <= 1e-5
+    assert abs(sa["n_tris"] - len(ref.mesh)) <= max(2, 1e-3 * len(ref.mesh))
+    rng = np.random.default_rng(4012)
+    flat = pa.reshape(-1)
+    inside = np.flatnonzero(flat < -20 * grid.h)   # the deep tiles the order puts first
+    nodes = np.concatenate([rng.choice(flat.size, 1500, replace=False), rng.choice(inside, 500, replace=False)])
+    err = np.abs(flat[nodes].astype(np.float64) - ref.phi_nodes(nodes))
+    print(f"phi nodes: max err / h = {err.max() / grid.h:.3e}", flush=True)
+    assert err.max() <= 1e-4 * grid.h
+    a.close()
+    b.close()
