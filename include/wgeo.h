@@ -66,7 +66,13 @@ typedef struct {
 typedef struct {
     double rel_tol;     /* stop at ||P b - A chi||_2 <= rel_tol ||P b||_2 (FP64)  */
     int max_iters;      /* cap on inner preconditioned-CG iterations, all refinements */
-    int warm_start;     /* 1: start from the handle's last solution               */
+    int warm_start;     /* 1: start from the handle's last solution; also marks the
+                           cloud as close to the last one, so the distance walk
+                           reuses the last walk's tile costs and seeds.  0: an
+                           unrelated cloud; on grids of 2^23 nodes or more the
+                           walk orders its tiles by their depth inside the new
+                           surface and searches its seeds first.  No result
+                           depends on this beyond the solver's start.          */
     int reserved0;      /* must be 0                                               */
     int reserved1;      /* must be 0                                               */
 } wg_solve_opts;
