@@ -6,10 +6,11 @@
 // order, so the triangle list is Morton ordered.  Groups of 4 consecutive
 // triangles are the leaves of an 8-ary hierarchy built bottom-up over that
 // order: oriented boxes (thin along the patch normal) at the leaves,
-// axis-aligned boxes above.  The signed distance (Eq. 29-34) of every grid node is the exact
-// minimum over all triangles: one wavefront per 4x4x16 node tile walks the
-// hierarchy together, pruning a box only when it is farther than every lane's
-// current best, so the result equals the brute-force minimum.
+// axis-aligned boxes above.  The signed distance (Eq. 29-34) of every grid
+// node is the exact minimum over all triangles: one wavefront per 4x4x16 node
+// tile (4x4x4 on grids below 2^23 nodes) walks the hierarchy together, pruning
+// a box only when it is farther than every lane's current best, so the result
+// equals the brute-force minimum.
 #pragma once
 
 #include "kernels.h"
