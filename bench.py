@@ -489,6 +489,17 @@ def serving_oracle_error(cmp):
             "requests_compared": [c["n"] for c in cmp], "queries_per_request": 200}
 
 
+def latency_by_grid(grids, lat_s):
+    """p50 / p99 latency (ms) and count of the requests of each grid size."""
+    grids, lat = np.asarray(grids), np.asarray(lat_s, np.float64) * 1e3
+    out = {}
+    for n in sorted(set(grids.tolist())):
+        v = lat[grids == n]
+        out[str(n)] = {"requests": int(v.size), "p50_ms": float(np.percentile(v, 50)),
+                       "p99_ms": float(np.percentile(v, 99))}
+    return out
+
+
 def replay(srv, reqs, time_scale, keep=False):
     import threading
 
@@ -524,6 +535,7 @@ def replay(srv, reqs, time_scale, keep=False):
     cells = sum(rq.n ** 3 for rq, *_ in reqs)
     stats = {"req_per_s": len(reqs) / span, "cells_per_s": cells / span,
              "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+             "by_grid": latency_by_grid([rq.n for rq, *_ in reqs], lat),
              "ok": ok, "requests": len(reqs),
              "max_rel_res": max(d[0][2]["stats"]["rel_res"] for d in done.values())}
     return stats, (done if keep else None)

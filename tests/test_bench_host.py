@@ -1,5 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the single-GPU guard and the roofline
-arithmetic of the JSON line, on synthetic profiling records."""
+"""Host-side logic of bench.py (no GPU): the single-GPU guard, the roofline
+arithmetic of the JSON line on synthetic profiling records, and the serving
+latencies by grid size."""
 import os
 import subprocess
 import sys
@@ -43,3 +44,14 @@ def test_solver_roofline_against_peak_and_copy():
     assert s["kernels_frac"] == pytest.approx(s["kernels_GB_s"] / 8000.0)
     assert s["kernels_frac_of_copy"] == pytest.approx(s["kernels_GB_s"] / 5000.0)
     assert s["phase_ms"] == pytest.approx(2.0)
+
+
+def test_latency_by_grid():
+    grids = [64, 256, 64, 128, 64, 256]
+    lat = [0.001, 0.030, 0.003, 0.010, 0.002, 0.040]
+    out = bench.latency_by_grid(grids, lat)
+    assert list(out) == ["64", "128", "256"]
+    assert out["64"]["requests"] == 3 and out["64"]["p50_ms"] == pytest.approx(2.0)
+    assert out["128"]["p50_ms"] == pytest.approx(10.0) and out["128"]["p99_ms"] == pytest.approx(10.0)
+    assert out["256"]["p50_ms"] == pytest.approx(35.0)
+    assert out["256"]["p99_ms"] == pytest.approx(30.0 + 0.99 * 10.0)
