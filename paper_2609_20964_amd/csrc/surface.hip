@@ -56,6 +56,10 @@ constexpr int kSeedStack = 64;
 // pass's time.  Beside the walk, 160, 320 and 1000 measured alike (320 best
 // for plain steps, whose next step waits for the search).
 constexpr int kSeedPops = 320;
+// Run before the walk (a cold walk, which waits for it), a shorter search
+// pays: ten cold 256^3 serving shapes walked in 110.5-110.9 ms in total at
+// 160 entries, 113.4-113.6 at 320, 113.0 at 80.
+constexpr int kSeedPopsFirst = 160;
 // Seeds arrive 1-1.5 ms into a walk whatever the grid; they pay only where
 // the walk takes several (256^3: 6.8 -> 6.3 ms), so smaller grids walk unseeded.
 constexpr size_t kSeedMinNodes = (size_t)1 << 23;
@@ -481,7 +485,7 @@ struct SeedLevels {
 
 // Nearest triangle of each seed-lattice node: one node per lane, each lane
 // with its own nearest-first traversal (few nodes, so divergence costs
-// little), for at most kSeedPops stack entries.  A stack entry carries the
+// little), for at most max_pops stack entries.  A stack entry carries the
 // level, the index and the box bound it was pushed with, so a pop that the
 // bound rules out touches no memory and every other pop takes one round trip
 // (a leaf's triangles, or a node's child boxes).  A stack that would overflow
@@ -489,7 +493,7 @@ struct SeedLevels {
 // the nearest: seeds only bound.
 __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, SeedLevels lv, const float4 *__restrict__ nodes,
                                                   const float4 *__restrict__ leaf_aabb, const float4 *__restrict__ tri,
-                                                  uint32_t n_tris, int32_t *__restrict__ seed) {
+                                                  uint32_t n_tris, int32_t *__restrict__ seed, int max_pops) {
     __shared__ uint32_t stk[kSeedStack][64];
     __shared__ float stb[kSeedStack][64];
     const int lane = threadIdx.x;
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(64) void k_sdf_seed(Dims d, SeedDims nc, SeedLevels
     stk[0][lane] = (uint32_t)(lv.levels - 1) << 27;   // the root, local index 0
     stb[0][lane] = 0.f;
     sp = 1;
-    for (int pops = 0; sp > 0 && pops < kSeedPops; ++pops) {
+    for (int pops = 0; sp > 0 && pops < max_pops; ++pops) {
         --sp;
         const uint32_t ent = stk[sp][lane];
         if (stb[sp][lane] >= best) continue;
@@ -1249,7 +1253,8 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
             WG_HIP(hipEventRecord(ev_pre_, s));
             WG_HIP(hipStreamWaitEvent(seed_st_, ev_pre_, 0));
         }
-        k_sdf_seed<<<cdiv(ns, 64), 64, 0, ss>>>(d_, snc, lv, box_, aabb_, tri_, cnt_.n_tris, seed_);
+        k_sdf_seed<<<cdiv(ns, 64), 64, 0, ss>>>(d_, snc, lv, box_, aabb_, tri_, cnt_.n_tris, seed_,
+                                                cold ? kSeedPopsFirst : kSeedPops);
         WG_LAUNCH_CHECK();
         WG_HIP(hipEventRecord(ev_seed_, ss));
     }
