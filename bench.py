@@ -43,6 +43,17 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_TFLOPS = 157.3       # MI355X FP32 vector peak
 
 
+def angle_between(a, b):
+    """Angle between rows of two normal fields: normalised in float64 and taken
+    as atan2(|a x b|, a . b) (arccos of a float32 unit vector's dot product
+    reads ~4e-4 rad for a norm off by 1e-7)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    a = a / np.maximum(np.linalg.norm(a, axis=1, keepdims=True), 1e-300)
+    b = b / np.maximum(np.linalg.norm(b, axis=1, keepdims=True), 1e-300)
+    return np.arctan2(np.linalg.norm(np.cross(a, b), axis=1), np.sum(a * b, axis=1))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -391,7 +402,7 @@ def secondary_oracle_error(cmp):
     ref = P.Recon(g32, s["x"], s["nrm"])
     vq, nq = ref.sample(s["q"])
     ok = np.linalg.norm(nq, axis=1) > 0
-    ang = np.arccos(np.clip(np.sum(s["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+    ang = angle_between(s["n_q"][ok], nq[ok])
     sphere = {"phi_grid_max_abs_over_h": float(np.abs(s["phi"].astype(np.float64) - ref.phi_grid()).max() * 32),
               "phi_queries_max_abs_over_h": float(np.abs(s["phi_q"] - vq).max() * 32),
               "normal_angle_max_rad": float(ang.max()), "nodes_compared": 32 ** 3, "queries_compared": len(s["q"])}
@@ -400,7 +411,7 @@ def secondary_oracle_error(cmp):
     ref = P.Recon(grid, t["x"], t["nrm"])
     vq, nq = ref.sample(t["q"])
     ok = np.linalg.norm(nq, axis=1) > 0
-    ang = np.arccos(np.clip(np.sum(t["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+    ang = angle_between(t["n_q"][ok], nq[ok])
     torus = {"chi_rel_l2": float(np.linalg.norm(t["chi"] - ref.chi) / np.linalg.norm(ref.chi)),
              "phi_nodes_max_abs_over_h": float(np.abs(t["phi_nodes"] - ref.phi_nodes(t["nodes"])).max() * 128),
              "phi_queries_max_abs_over_h": float(np.abs(t["phi_q"] - vq).max() * 128),
@@ -483,7 +494,7 @@ def serving_oracle_error(cmp):
         vq, nq = ref.sample(c["q"])
         worst_phi = max(worst_phi, float(np.abs(c["phi_q"] - vq).max() * c["n"]))
         ok = np.linalg.norm(nq, axis=1) > 0
-        ang = np.arccos(np.clip(np.sum(c["n_q"][ok].astype(np.float64) * nq[ok], 1), -1, 1))
+        ang = angle_between(c["n_q"][ok], nq[ok])
         worst_ang = max(worst_ang, float(ang.max()) if ang.size else 0.0)
     return {"phi_queries_max_abs_over_h": worst_phi, "normal_angle_max_rad": worst_ang,
             "requests_compared": [c["n"] for c in cmp], "queries_per_request": 200}

@@ -139,8 +139,9 @@ int wg_recon_step(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_poi
                   const wg_solve_opts *opts, wg_stats *stats);
 
 /* Orders the handle's stream after all work r has left running on its second
- * stream (the last wg_recon_step's walk and sampling).  Does not block the
- * host. */
+ * stream (the last wg_recon_step's walk and sampling), then blocks the host
+ * until that work is complete.  Returns WG_EDEVICE if the last walk failed
+ * (its d_phi / d_nrm_out are then not valid). */
 int wg_recon_wait(wg_recon *r);
 
 /* Reverse pass (Sec. 2.5, Eq. 35-39) of the last forward + sampling at d_q:
@@ -173,6 +174,17 @@ int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc,
  * shares the solver's work buffers with forward/backward/poisson calls on r,
  * which the stream orders. */
 int wg_mg_apply(wg_recon *r, const float *d_r, float *d_z, int bc);
+
+/* Signed-distance reinitialisation of a given implicit field (Sec. 2.4,
+ * Eq. 27-34): the Marching Cubes surface {chi = c} on the dual lattice of r's
+ * grid, then the exact signed distance to it at every grid node (positive
+ * where chi >= c), as wg_recon_forward computes them after its solve.  d_chi:
+ * float64 [N] on the device (copied into the handle); c: the iso-value.
+ * Afterwards wg_sample_sdf_normals, wg_get_fields (chi as given) and
+ * wg_get_mesh see this surface; wg_recon_backward returns WG_ESTATE (there is
+ * no point cloud to differentiate).  stats: iso_c = c, n_tris, ms[3] (surface)
+ * and ms[4] (distance).  Host-synchronising like wg_recon_forward. */
+int wg_sdf_from_field(wg_recon *r, const double *d_chi, double c, wg_stats *stats);
 
 /* Copies of resident fields from the last forward: d_b float32 [N] (the
  * right-hand side), d_chi float64 [N] (zero mean), d_phi float32 [N],
@@ -209,6 +221,8 @@ typedef struct {
     float *d_nrm_out;       /* [n_q][3] or NULL                                  */
     float *d_gxyz;          /* [n_points][3], used iff d_gphi != NULL            */
     float *d_gnrm_pts;      /* [n_points][3], used iff d_gphi != NULL            */
+    const float *d_gnrm;    /* [n_q][3] dL/dn(q) (copied), or NULL; needs d_gphi  */
+    float *d_gq;            /* [n_q][3] dL/dq output, or NULL; needs d_gphi       */
 } wg_request;
 
 typedef struct {

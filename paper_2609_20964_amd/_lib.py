@@ -42,7 +42,7 @@ class WgRequest(C.Structure):
     _fields_ = [("grid", WgGrid), ("d_xyz", C.c_void_p), ("d_nrm", C.c_void_p), ("n_points", C.c_int),
                 ("d_q", C.c_void_p), ("n_q", C.c_int), ("d_gphi", C.c_void_p), ("opts", WgSolveOpts),
                 ("d_phi", C.c_void_p), ("d_nrm_out", C.c_void_p), ("d_gxyz", C.c_void_p),
-                ("d_gnrm_pts", C.c_void_p)]
+                ("d_gnrm_pts", C.c_void_p), ("d_gnrm", C.c_void_p), ("d_gq", C.c_void_p)]
 
 
 class WgResult(C.Structure):
@@ -74,6 +74,7 @@ SIGNATURES = {
     "wg_poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
                                    C.POINTER(WgStats)]),
     "wg_mg_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "wg_sdf_from_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(WgStats)]),
     "wg_get_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "wg_get_mesh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "wg_recon_destroy": (None, [C.c_void_p]),
@@ -109,6 +110,13 @@ def lib():
     """Load libwgeo.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime: load it first, so that libwgeo.so binds
+        # to the runtime torch's tensors and streams belong to (loading the
+        # library first brings in a second runtime that then sees no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_20964_amd.build`")
         L = C.CDLL(LIB_PATH)

@@ -34,6 +34,10 @@ inline void require(bool ok, int code, const std::string &msg) {
     if (!ok) throw Error(code, msg);
 }
 
+// Thread-local message of the last failing ABI call (wg_last_error).
+void set_error(const std::string &m);
+const char *last_error();
+
 // Wait until a kernel on stream s has stored `want` into the host-mapped word
 // *seq (after the data it publishes).  Polling returns as soon as the store
 // lands, without a stream synchronisation's completion round trip; the stream
@@ -74,6 +78,14 @@ class Arena {
         if (plan_ && !base_) WG_HIP(hipMalloc(&base_, plan_));
         used_ = 0;
     }
+    // Carve from caller-owned device memory (256-byte aligned, `bytes` long)
+    // instead of allocating; release() then frees nothing.
+    void adopt(void *base, size_t bytes) {
+        base_ = base;
+        plan_ = bytes;
+        used_ = 0;
+        owned_ = false;
+    }
     template <class T> T *take(size_t count) {
         size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
         require(used_ + bytes <= plan_, WG_EDEVICE, "arena overflow");
@@ -82,15 +94,17 @@ class Arena {
         return p;
     }
     void release() {
-        if (base_) (void)hipFree(base_);
+        if (base_ && owned_) (void)hipFree(base_);
         base_ = nullptr;
         plan_ = used_ = 0;
+        owned_ = true;
     }
     ~Arena() { release(); }
 
   private:
     void *base_ = nullptr;
     size_t plan_ = 0, used_ = 0;
+    bool owned_ = true;
 };
 
 // ---------------------------------------------------------------------------

@@ -23,11 +23,18 @@ class Recon {
     int sample(const float *q, int nq, float *phi, float *nrm, bool pipelined = false);
     // Order the handle stream after everything enqueued on the second stream.
     void join();
+    // join(), then wait on the host for the last walk and check its flags.
+    void finish();
     // distance walk as a persistent kernel (default) or one workgroup per 4 tiles
     void set_persistent(bool on) { surf_.set_persistent(on); }
+    // Called with the extra device bytes before the surface buffers grow past
+    // the handle's footprint (a larger mesh than any before); may throw.
+    void set_grow_hook(std::function<void(size_t)> f) { surf_.set_grow_hook(std::move(f)); }
     int backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
                  float *gq, const wg_solve_opts &o, wg_stats *st);
     int poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st);
+    // Surface and signed distance of a given FP64 field at iso-value c.
+    int sdf_from_field(const double *chi, double c, wg_stats *st);
     int mg_apply(const float *r, float *z, int bc);
     int get_fields(float *b, double *chi, float *phi, int32_t *keys);
     int get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tris);
@@ -40,6 +47,8 @@ class Recon {
   private:
     static void plan(Arena &a, const wg_grid &g, int max_points);
     void check_err(const char *what);
+    void extract_surface();
+    void walk(bool pipelined, bool related);
     void wait_sdf();
 
     wg_grid grid_;
@@ -68,6 +77,7 @@ class Recon {
     HostMapped<Mirror> hm_;
     int n_points_ = 0;
     bool have_forward_ = false;
+    bool field_only_ = false;   // the last surface came from wg_sdf_from_field (no cloud)
     // second stream: the distance walk (and pipelined sampling)
     hipStream_t sdf_st_ = nullptr;
     hipEvent_t ev_mc_ = nullptr, ev_sdf_ = nullptr, ev_tail_ = nullptr;
@@ -76,7 +86,5 @@ class Recon {
     double chi_mean_ = 0.0, iso_c_ = 0.0;
 };
 
-void set_error(const std::string &m);
-const char *last_error();
 
 }  // namespace wg

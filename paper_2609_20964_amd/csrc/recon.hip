@@ -29,6 +29,7 @@ __global__ void k_copy_shift(const double *x, double by, double *out, size_t n) 
 }
 
 __global__ void k_shift_scalar(const double *in, double by, double *out) { out[0] = in[0] - by; }
+__global__ void k_set_scalar(double *out, double v) { out[0] = v; }
 
 struct Timer {
     hipEvent_t ev[9];
@@ -53,12 +54,7 @@ struct Timer {
 size_t Recon::footprint(const wg_grid &g, int max_points) {
     Arena a;
     plan(a, g, max_points);
-    // initial triangle / box buffers of the surface
-    size_t face = (size_t)g.n[0] * g.n[1];
-    if ((size_t)g.n[1] * g.n[2] > face) face = (size_t)g.n[1] * g.n[2];
-    if ((size_t)g.n[0] * g.n[2] > face) face = (size_t)g.n[0] * g.n[2];
-    size_t tris = 4 * face;
-    return a.planned() + (tris + tris / 4 + 64) * (4 * 16 + 8) + (tris / 3) * 6 * 16;
+    return a.planned() + Surface::initial_bytes(Dims{g.n[0], g.n[1], g.n[2], -1});
 }
 
 void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
@@ -163,6 +159,17 @@ void Recon::join() {
     }
 }
 
+void Recon::finish() {
+    join();
+    hm_.fetch(scal_, st_);
+    const Mirror &m = hm_.wait();
+    if (m.err[1] & 2) {
+        // reported here; the next forward must not report it again
+        WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
+        throw Error(WG_EDEVICE, "distance traversal stack overflow (last step)");
+    }
+}
+
 size_t Recon::bytes_resident() const { return arena_.planned() + surf_.bytes(); }
 
 // err_[0]: splat flags (bit 0: a point outside the grid); err_[1]: distance
@@ -227,40 +234,14 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     }
     WG_LAUNCH_CHECK();
     tm.mark(3);
-    // the previous distance walk (and pipelined sampling) reads the triangle
-    // records, the hierarchy, the node sides and phi that follow: wait for it
-    join();
-    hm_.fetch(scal_, st_);        // c and the previous walk's flags
-    surf_.extract(chi_, scal_);   // waits for the triangle count
-    {
-        const Mirror &m = hm_.wait();
-        if (m.err[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
-        iso_c_ = m.scal[0];
-    }
-    WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
+    extract_surface();
     tm.mark(4);
-    if (pipelined) {
-        // distance walk on the second stream (created on first use): it reads
-        // neither chi nor anything the next splat and solve write, so it may
-        // overlap them
-        if (!sdf_st_) {
-            WG_HIP(hipStreamCreateWithFlags(&sdf_st_, hipStreamNonBlocking));
-            WG_HIP(hipEventCreateWithFlags(&ev_mc_, hipEventDisableTiming));
-            WG_HIP(hipEventCreateWithFlags(&ev_sdf_, hipEventDisableTiming));
-            WG_HIP(hipEventCreateWithFlags(&ev_tail_, hipEventDisableTiming));
-        }
-        WG_HIP(hipEventRecord(ev_mc_, st_));
-        WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
-        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_, true, o.warm_start != 0);
-        WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
-        sdf_pending_ = true;
-    } else {
-        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_, false, o.warm_start != 0);
-    }
+    walk(pipelined, o.warm_start != 0);
     tm.mark(5);
     if (!pipelined) check_err("sdf");
     WG_HIP(hipEventSynchronize(tm.ev[5]));   // the timing events (a pipelined walk runs on the second stream)
     have_forward_ = true;
+    field_only_ = false;
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->iters = sr.iters;
@@ -275,6 +256,77 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         st->bytes_resident = bytes_resident();
     }
     return sr.status;
+}
+
+// Marching Cubes of {chi_ = scal_[0]} (F6) once the previous walk is done.
+void Recon::extract_surface() {
+    // the previous distance walk (and pipelined sampling) reads the triangle
+    // records, the hierarchy, the node sides and phi that follow: wait for it
+    join();
+    hm_.fetch(scal_, st_);        // c and the previous walk's flags
+    surf_.extract(chi_, scal_);   // waits for the triangle count
+    {
+        const Mirror &m = hm_.wait();
+        if (m.err[1] & 2) throw Error(WG_EDEVICE, "distance traversal stack overflow (previous forward)");
+        iso_c_ = m.scal[0];
+    }
+    WG_HIP(hipMemsetAsync(err_ + 1, 0, sizeof(int), st_));
+}
+
+// The distance walk (F7) to the extracted surface, on the second stream when
+// pipelined.
+void Recon::walk(bool pipelined, bool related) {
+    if (pipelined) {
+        // distance walk on the second stream (created on first use): it reads
+        // neither chi nor anything the next splat and solve write, so it may
+        // overlap them
+        if (!sdf_st_) {
+            WG_HIP(hipStreamCreateWithFlags(&sdf_st_, hipStreamNonBlocking));
+            WG_HIP(hipEventCreateWithFlags(&ev_mc_, hipEventDisableTiming));
+            WG_HIP(hipEventCreateWithFlags(&ev_sdf_, hipEventDisableTiming));
+            WG_HIP(hipEventCreateWithFlags(&ev_tail_, hipEventDisableTiming));
+        }
+        WG_HIP(hipEventRecord(ev_mc_, st_));
+        WG_HIP(hipStreamWaitEvent(sdf_st_, ev_mc_, 0));
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, sdf_st_, true, related);
+        WG_HIP(hipEventRecord(ev_sdf_, sdf_st_));
+        sdf_pending_ = true;
+    } else {
+        surf_.sdf(grid_.h, phi_, argmin_, err_ + 1, st_, false, related);
+    }
+}
+
+int Recon::sdf_from_field(const double *chi, double c, wg_stats *st) {
+    require(chi != nullptr, WG_EINVAL, "null field");
+    require(std::isfinite(c), WG_EINVAL, "iso-value must be finite");
+    have_forward_ = false;
+    join();
+    const size_t N = d_.count();
+    Timer tm(st_);
+    tm.mark(0);
+    WG_HIP(hipMemcpyAsync(chi_, chi, N * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    k_set_scalar<<<1, 1, 0, st_>>>(scal_, c);
+    WG_LAUNCH_CHECK();
+    chi_mean_ = 0.0;
+    n_points_ = 0;
+    tm.mark(1);
+    extract_surface();
+    tm.mark(2);
+    walk(false, false);
+    tm.mark(3);
+    check_err("sdf");
+    WG_HIP(hipEventSynchronize(tm.ev[3]));
+    have_forward_ = true;
+    field_only_ = true;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iso_c = c;
+        st->n_tris = surf_.n_tris();
+        st->ms[3] = tm.between(1, 2);
+        st->ms[4] = tm.between(2, 3);
+        st->bytes_resident = bytes_resident();
+    }
+    return WG_OK;
 }
 
 int Recon::sample(const float *q, int nq, float *phi, float *nrm, bool pipelined) {
@@ -296,6 +348,7 @@ int Recon::sample(const float *q, int nq, float *phi, float *nrm, bool pipelined
 int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gnrm_q, float *gxyz, float *gnrm_pts,
                     float *gq, const wg_solve_opts &o, wg_stats *st) {
     require(have_forward_, WG_ESTATE, "backward before a successful forward");
+    require(!field_only_, WG_ESTATE, "backward after wg_sdf_from_field (no point cloud to differentiate)");
     require(nq >= 0 && (nq == 0 || (q && gphi_q)), WG_EINVAL, "bad query arguments");
     require(n_points_ == 0 || (gxyz && gnrm_pts), WG_EINVAL, "null point-gradient outputs");
     require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
@@ -503,7 +556,7 @@ int wg_recon_step(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_poi
 int wg_recon_wait(wg_recon *r) {
     return guarded([&] {
         wg::require(r, WG_EINVAL, "null handle");
-        r->impl->join();
+        r->impl->finish();
         return WG_OK;
     });
 }
@@ -530,6 +583,13 @@ int wg_mg_apply(wg_recon *r, const float *d_r, float *d_z, int bc) {
         wg::require(r, WG_EINVAL, "null handle");
         wg::require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
         return r->impl->mg_apply(d_r, d_z, bc);
+    });
+}
+
+int wg_sdf_from_field(wg_recon *r, const double *d_chi, double c, wg_stats *stats) {
+    return guarded([&] {
+        wg::require(r, WG_EINVAL, "null handle");
+        return r->impl->sdf_from_field(d_chi, c, stats);
     });
 }
 

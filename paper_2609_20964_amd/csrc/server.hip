@@ -73,8 +73,8 @@ struct Buf {
 struct Job {
     uint64_t ticket = 0;
     wg_request req{};
-    Buf in[4];   // server-owned copies: points, normals, queries, dL/dphi
-    float *xyz = nullptr, *nrm = nullptr, *q = nullptr, *gphi = nullptr;   // in[k].p
+    Buf in[5];   // server-owned copies: points, normals, queries, dL/dphi, dL/dn(q)
+    float *xyz = nullptr, *nrm = nullptr, *q = nullptr, *gphi = nullptr, *gnrm = nullptr;   // in[k].p
     int state = 0;   // 0 queued, 1 running, 2 done
     wg_result res{};
 };
@@ -115,6 +115,7 @@ class Server {
         require(rq.n_points == 0 || (rq.d_xyz && rq.d_nrm), WG_EINVAL, "null point inputs");
         require(rq.n_q == 0 || (rq.d_q && rq.d_phi), WG_EINVAL, "null query arguments");
         require(!rq.d_gphi || rq.n_points == 0 || (rq.d_gxyz && rq.d_gnrm_pts), WG_EINVAL, "null gradient outputs");
+        require(rq.d_gphi || (!rq.d_gnrm && !rq.d_gq), WG_EINVAL, "query-side gradients need d_gphi");
         const size_t fp = Recon::footprint(rq.grid, capacity_class(rq.n_points));
         require(fp <= budget_, WG_ENOMEM, "request footprint exceeds the server budget");
         WG_HIP(hipSetDevice(device_));
@@ -132,6 +133,7 @@ class Server {
             job->nrm = copy(1, rq.d_nrm, 3 * (size_t)rq.n_points);
             job->q = copy(2, rq.d_q, 3 * (size_t)rq.n_q);
             job->gphi = copy(3, rq.d_gphi, (size_t)rq.n_q);
+            job->gnrm = copy(4, rq.d_gnrm, 3 * (size_t)rq.n_q);
             WG_HIP(hipStreamSynchronize(ingest_));
         } catch (...) {
             (void)hipStreamSynchronize(ingest_);
@@ -192,7 +194,7 @@ class Server {
         for (Buf &b : j.in)
             if (b.p) pool_.emplace(b.cap, b.p);
         for (Buf &b : j.in) b = Buf{};
-        j.xyz = j.nrm = j.q = j.gphi = nullptr;
+        j.xyz = j.nrm = j.q = j.gphi = j.gnrm = nullptr;
     }
 
     void destroy(Handle &h) {
@@ -201,6 +203,33 @@ class Server {
         if (h.s) (void)hipStreamDestroy(h.s);
         h.r = nullptr;
         h.s = nullptr;
+    }
+
+    // Evict least-recently-used idle handles until `need` more bytes fit in
+    // the budget (or nothing idle is left).  Called with lk held.
+    void evict_for(size_t need, std::unique_lock<std::mutex> &lk) {
+        while (resident_ + need > budget_ && !idle_.empty()) {
+            auto victim = idle_.begin();
+            for (auto it = idle_.begin(); it != idle_.end(); ++it)
+                if (it->last_use < victim->last_use) victim = it;
+            Handle h = *victim;
+            idle_.erase(victim);
+            resident_ -= h.bytes;
+            lk.unlock();
+            destroy(h);
+            lk.lock();
+        }
+    }
+
+    // A running handle's surface buffers are about to grow by `extra` bytes
+    // (a mesh larger than its footprint allowed for): charge them to the
+    // budget first, evicting idle handles if needed, or refuse.
+    void reserve_growth(Handle &h, size_t extra) {
+        std::unique_lock<std::mutex> lk(mu_);
+        evict_for(extra, lk);
+        require(resident_ + extra <= budget_, WG_ENOMEM, "surface growth exceeds the server budget");
+        resident_ += extra;
+        h.bytes += extra;
     }
 
     // Take an idle handle of this class or create one within the budget.
@@ -213,18 +242,7 @@ class Server {
                     idle_.erase(it);
                     return h;
                 }
-            // evict least-recently-used idle handles until the new one fits
-            while (resident_ + fp > budget_ && !idle_.empty()) {
-                auto victim = idle_.begin();
-                for (auto it = idle_.begin(); it != idle_.end(); ++it)
-                    if (it->last_use < victim->last_use) victim = it;
-                Handle h = *victim;
-                idle_.erase(victim);
-                resident_ -= h.bytes;
-                lk.unlock();
-                destroy(h);
-                lk.lock();
-            }
+            evict_for(fp, lk);
             if (resident_ + fp <= budget_) {
                 resident_ += fp;   // reserve before allocating outside the lock
                 lk.unlock();
@@ -257,13 +275,14 @@ class Server {
     void run(Job &j, Handle &h, bool alone) {
         const wg_request &rq = j.req;
         h.r->set_persistent(alone || fills_device(rq.grid));
+        h.r->set_grow_hook([this, &h](size_t extra) { reserve_growth(h, extra); });
         wg_solve_opts o = rq.opts;
         o.warm_start = 0;   // a request's result must not depend on what ran before it
         int st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats);
         if (rq.n_q > 0) h.r->sample(j.q, rq.n_q, rq.d_phi, rq.d_nrm_out);
         if (j.gphi) {
             wg_stats bs{};
-            int st2 = h.r->backward(j.q, rq.n_q, j.gphi, nullptr, rq.d_gxyz, rq.d_gnrm_pts, nullptr, o, &bs);
+            int st2 = h.r->backward(j.q, rq.n_q, j.gphi, j.gnrm, rq.d_gxyz, rq.d_gnrm_pts, rq.d_gq, o, &bs);
             j.res.stats.ms[6] = bs.ms[6];
             j.res.stats.ms[7] = bs.ms[7];
             j.res.stats.iters += bs.iters;

@@ -11,8 +11,6 @@
 // products accumulate in FP64, and adds e to x in FP64.
 #pragma once
 
-#include <vector>
-
 #include "common.h"
 
 namespace wg {
@@ -42,8 +40,14 @@ struct SolveResult {
 class Solver {
   public:
     static void plan(Arena &a, int nx, int ny, int nz);
-    void bind(Arena &a, int nx, int ny, int nz, hipStream_t s);
+    // Carve the solver's buffers from a (planned by plan()).  mapped: publish
+    // the scalars the host reads through host-mapped pinned memory (allocated
+    // here); otherwise through a device record inside the arena that the host
+    // copies back, so that binding allocates nothing.
+    void bind(Arena &a, int nx, int ny, int nz, hipStream_t s, bool mapped = true);
     ~Solver();
+    // Timing brackets (wg_profile_*) around the solver's launches; on by default.
+    void set_instrumented(bool on) { instrument_ = on; }
 
     // Solve A x = b (x: FP64, initial guess if opts.warm_start).  The mean of
     // the Neumann solution is reported in x_mean, not removed from x.
@@ -56,11 +60,15 @@ class Solver {
     // (r, z: FP32 on the device, on the solver's stream).
     void mg_apply(const float *r, float *z, int bc);
 
+    // most levels a hierarchy can have (each halves every extent)
+    static constexpr int kMaxLevels = 24;
+
   private:
     struct Level {
         Dims d;
         float *rhs, *x, *x2;
     };
+    int pk(int kind) const { return instrument_ ? kind : -1; }
     void vcycle(int l);
     void precond();
     unsigned rz_blocks() const;
@@ -69,12 +77,15 @@ class Solver {
     void read_scalars();
 
     hipStream_t st_ = nullptr;
-    std::vector<Level> lv_;
+    Level lv_[kMaxLevels] = {};
+    int nlv_ = 0;
     float *e_ = nullptr, *p_[2] = {nullptr, nullptr}, *q_ = nullptr;
     double *partials_ = nullptr;
     SolveScalars *dsc_ = nullptr;
     PublishedScalars *pub_ = nullptr, *pub_dev_ = nullptr;   // host-mapped copy (host / device address)
-    const SolveScalars *hsc_ = nullptr;                       // &pub_->s
+    PublishedScalars host_pub_{};   // without mapped memory: the host's copy of *pub_dev_
+    bool mapped_ = true, instrument_ = true;
+    const SolveScalars *hsc_ = nullptr;                       // &pub_->s or &host_pub_.s
     unsigned seq_ = 0;                                        // sequence number of the last finalize
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;

@@ -386,6 +386,13 @@ __global__ void k_shift64(double *x, double by, size_t n) {
         x[i] -= by;
 }
 
+// zero n 32-bit words (a kernel rather than a memset node, so the clear is an
+// ordinary kernel wherever the launch ends up)
+__global__ void k_zero_words(uint32_t *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void k_fill64(double *x, double v, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         x[i] = v;
@@ -1031,43 +1038,53 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
     __hip_atomic_store(&mirror->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Orthonormal 1-D eigenbasis of the 7-point operator along one axis.
-void basis_1d(int n, int bc, std::vector<double> &phi, std::vector<double> &lam) {
-    phi.assign((size_t)n * n, 0.0);
-    lam.assign(n, 0.0);
-    for (int m = 0; m < n; ++m) {
-        int k = bc == WG_BC_NEUMANN ? m : m + 1;
-        double nrm = bc == WG_BC_NEUMANN ? std::sqrt((k == 0 ? 1.0 : 2.0) / n)
-                                         : std::sqrt((k == n ? 1.0 : 2.0) / n);
-        lam[m] = 4.0 * std::pow(std::sin(M_PI * k / (2.0 * n)), 2);
-        for (int i = 0; i < n; ++i) {
-            double a = M_PI * k * (i + 0.5) / n;
-            phi[(size_t)m * n + i] = nrm * (bc == WG_BC_NEUMANN ? std::cos(a) : std::sin(a));
+// Orthonormal 1-D eigenbases and eigenvalues of the 7-point operator on the
+// coarsest level, laid out for the eigen-solve kernels: phi_x [nx][nx],
+// phi_y [ny][ny], phi_z [nz][nz] (mode-major), then lambda_x, lambda_y,
+// lambda_z.  Mode m of an axis of n cells: Neumann k = m, cos(pi k (i + 1/2) / n)
+// scaled by sqrt((k == 0 ? 1 : 2) / n); Dirichlet k = m + 1, sin(...) scaled by
+// sqrt((k == n ? 1 : 2) / n); lambda = 4 sin^2(pi k / (2 n)).  Formed in FP64
+// on the device, one entry per thread, so binding a solver copies nothing from
+// the host.
+__global__ void k_coarse_basis(float *__restrict__ E, int nx, int ny, int nz, int bc) {
+    const int n[3] = {nx, ny, nz};
+    const int nphi = nx * nx + ny * ny + nz * nz, total = nphi + nx + ny + nz;
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < total; o += gridDim.x * blockDim.x) {
+        int r = o, a = 0;
+        if (o < nphi) {
+            while (r >= n[a] * n[a]) r -= n[a] * n[a], ++a;
+            const int m = r / n[a], i = r % n[a];
+            const int k = bc == WG_BC_NEUMANN ? m : m + 1;
+            const double nrm = bc == WG_BC_NEUMANN ? sqrt((k == 0 ? 1.0 : 2.0) / n[a])
+                                                   : sqrt((k == n[a] ? 1.0 : 2.0) / n[a]);
+            const double t = M_PI * k * (i + 0.5) / n[a];
+            E[o] = (float)(nrm * (bc == WG_BC_NEUMANN ? cos(t) : sin(t)));
+        } else {
+            r -= nphi;
+            while (r >= n[a]) r -= n[a], ++a;
+            const int k = bc == WG_BC_NEUMANN ? r : r + 1;
+            const double sn = sin(M_PI * k / (2.0 * n[a]));
+            E[o] = (float)(4.0 * sn * sn);
         }
     }
 }
 
-// 1-D eigenbases and eigenvalues of the coarsest level, laid out for the eigen-solve kernels.
-std::vector<float> coarse_basis(const Dims &d, int bc) {
-    std::vector<float> out;
-    std::vector<double> phi[3], lam[3];
-    const int n[3] = {d.nx, d.ny, d.nz};
-    for (int a = 0; a < 3; ++a) basis_1d(n[a], bc, phi[a], lam[a]);
-    for (int a = 0; a < 3; ++a) out.insert(out.end(), phi[a].begin(), phi[a].end());
-    for (int a = 0; a < 3; ++a) out.insert(out.end(), lam[a].begin(), lam[a].end());
-    return out;
+size_t basis_floats(const Dims &c) {
+    return (size_t)c.nx * c.nx + (size_t)c.ny * c.ny + (size_t)c.nz * c.nz + c.nx + c.ny + c.nz;
 }
 
-std::vector<Dims> level_dims(int nx, int ny, int nz) {
-    std::vector<Dims> out;
+// The multigrid hierarchy: halve every extent while all are even and >= 4 and
+// one exceeds kCoarseTarget.  Returns the level count.
+int level_dims(int nx, int ny, int nz, Dims (&out)[Solver::kMaxLevels]) {
     Dims d{nx, ny, nz, -1};
-    out.push_back(d);
+    int n = 0;
+    out[n++] = d;
     while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 4 && d.ny >= 4 && d.nz >= 4 &&
-           (d.nx > kCoarseTarget || d.ny > kCoarseTarget || d.nz > kCoarseTarget)) {
+           (d.nx > kCoarseTarget || d.ny > kCoarseTarget || d.nz > kCoarseTarget) && n < Solver::kMaxLevels) {
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, -1};
-        out.push_back(d);
+        out[n++] = d;
     }
-    return out;
+    return n;
 }
 
 // blocks of the sweep kernel that runs on grid d (its reductions write one partial per block)
@@ -1076,11 +1093,11 @@ unsigned sweep_blocks(const Dims &d) {
 }
 
 // blocks of the finest post-smoothing pass (0 for a single-level hierarchy)
-unsigned post_blocks(const std::vector<Dims> &dims) { return dims.size() > 1 ? vtile_of(dims[0]).count() : 0u; }
+unsigned post_blocks(const Dims *dims, int nl) { return nl > 1 ? vtile_of(dims[0]).count() : 0u; }
 
-size_t partial_slots(const std::vector<Dims> &dims) {
+size_t partial_slots(const Dims *dims, int nl) {
     size_t nb = sweep_blocks(dims[0]);
-    const size_t pb = post_blocks(dims);
+    const size_t pb = post_blocks(dims, nl);
     if (pb > nb) nb = pb;
     return (nb > (size_t)kRedBlocks ? nb : (size_t)kRedBlocks) * kMaxRed;
 }
@@ -1093,25 +1110,26 @@ unsigned red_blocks(size_t n) {
 }  // namespace
 
 void Solver::plan(Arena &a, int nx, int ny, int nz) {
-    auto dims = level_dims(nx, ny, nz);
+    Dims dims[kMaxLevels];
+    const int nl = level_dims(nx, ny, nz, dims);
     size_t N = dims[0].count();
     // fine level: r, z, z2, e, p0, p1, q
     for (int k = 0; k < 7; ++k) a.reserve(N * sizeof(float));
-    for (size_t l = 1; l < dims.size(); ++l)
+    for (int l = 1; l < nl; ++l)
         for (int k = 0; k < 3; ++k) a.reserve(dims[l].count() * sizeof(float));
-    a.reserve(partial_slots(dims) * sizeof(double));
+    a.reserve(partial_slots(dims, nl) * sizeof(double));
     a.reserve(sizeof(SolveScalars));
-    const Dims &c = dims.back();
+    a.reserve(sizeof(PublishedScalars));
+    const Dims &c = dims[nl - 1];
     if (c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis)
-        for (int bc = 0; bc < 2; ++bc)
-            a.reserve((size_t)(c.nx * c.nx + c.ny * c.ny + c.nz * c.nz + c.nx + c.ny + c.nz) * sizeof(float));
+        for (int bc = 0; bc < 2; ++bc) a.reserve(basis_floats(c) * sizeof(float));
 }
 
-void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
+void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s, bool mapped) {
     st_ = s;
-    auto dims = level_dims(nx, ny, nz);
+    Dims dims[kMaxLevels];
+    nlv_ = level_dims(nx, ny, nz, dims);
     size_t N = dims[0].count();
-    lv_.resize(dims.size());
     Level &f = lv_[0];
     f.d = dims[0];
     f.rhs = a.take<float>(N);   // the CG residual r
@@ -1121,7 +1139,7 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
     p_[0] = a.take<float>(N);
     p_[1] = a.take<float>(N);
     q_ = a.take<float>(N);
-    for (size_t l = 1; l < dims.size(); ++l) {
+    for (int l = 1; l < nlv_; ++l) {
         Level &L = lv_[l];
         L.d = dims[l];
         size_t n = dims[l].count();
@@ -1129,20 +1147,28 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s) {
         L.x = a.take<float>(n);
         L.x2 = a.take<float>(n);
     }
-    partials_ = a.take<double>(partial_slots(dims));
-    post_blocks_ = post_blocks(dims);
+    partials_ = a.take<double>(partial_slots(dims, nlv_));
+    post_blocks_ = post_blocks(dims, nlv_);
     dsc_ = a.take<SolveScalars>(1);
-    WG_HIP(hipHostMalloc((void **)&pub_, sizeof(PublishedScalars), hipHostMallocMapped | hipHostMallocCoherent));
-    WG_HIP(hipHostGetDevicePointer((void **)&pub_dev_, pub_, 0));
-    pub_->seq = seq_;
-    hsc_ = &pub_->s;
-    const Dims &c = dims.back();
+    PublishedScalars *dev_rec = a.take<PublishedScalars>(1);
+    mapped_ = mapped;
+    if (mapped) {
+        WG_HIP(hipHostMalloc((void **)&pub_, sizeof(PublishedScalars), hipHostMallocMapped | hipHostMallocCoherent));
+        WG_HIP(hipHostGetDevicePointer((void **)&pub_dev_, pub_, 0));
+        pub_->seq = seq_;
+        hsc_ = &pub_->s;
+    } else {
+        pub_dev_ = dev_rec;
+        hsc_ = &host_pub_.s;
+    }
+    const Dims &c = dims[nlv_ - 1];
     coarse_direct_ = c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis;
     if (coarse_direct_) {
+        const size_t nf = basis_floats(c);
         for (int bc = 0; bc < 2; ++bc) {
-            auto E = coarse_basis(c, bc);
-            coarseM_[bc] = a.take<float>(E.size());
-            WG_HIP(hipMemcpy(coarseM_[bc], E.data(), E.size() * sizeof(float), hipMemcpyHostToDevice));
+            coarseM_[bc] = a.take<float>(nf);
+            k_coarse_basis<<<cdiv(nf, 256), 256, 0, st_>>>(coarseM_[bc], c.nx, c.ny, c.nz, bc);
+            WG_LAUNCH_CHECK();
         }
     }
 }
@@ -1157,7 +1183,14 @@ void Solver::finalize(int mode, unsigned nb, int flag) {
 }
 
 // Wait until the last finalize has published its scalars.
-void Solver::read_scalars() { wait_published(&pub_->seq, seq_, st_); }
+void Solver::read_scalars() {
+    if (mapped_) {
+        wait_published(&pub_->seq, seq_, st_);
+    } else {
+        WG_HIP(hipMemcpyAsync(&host_pub_, pub_dev_, sizeof(PublishedScalars), hipMemcpyDeviceToHost, st_));
+        WG_HIP(hipStreamSynchronize(st_));
+    }
+}
 
 // kind / bytes_per_cell: optional timing bracket (WG_PROF_*) and the sweep's
 // algorithmic bytes per cell.
@@ -1178,7 +1211,7 @@ static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStr
 void Solver::vcycle(int l) {
     Level &L = lv_[l];
     L.d.bc_sign = bc_sign_;
-    const int last = (int)lv_.size() - 1;
+    const int last = nlv_ - 1;
     if (l == last) {
         if (coarse_direct_) {
             const float *E = coarseM_[bc_sign_ > 0 ? 1 : 0];
@@ -1199,7 +1232,7 @@ void Solver::vcycle(int l) {
     }
     Level &C = lv_[l + 1];
     C.d.bc_sign = bc_sign_;
-    const int ks = l == 0 ? WG_PROF_SMOOTH : -1, kt = l == 0 ? WG_PROF_TRANSFER : -1;
+    const int ks = l == 0 ? pk(WG_PROF_SMOOTH) : -1, kt = l == 0 ? pk(WG_PROF_TRANSFER) : -1;
     const VTile vt = vtile_of(L.d);
     {
         // rhs read, x written; 1/8 of a cell's bytes for the coarse rhs
@@ -1225,7 +1258,7 @@ void Solver::vcycle(int l) {
 // z = M r with r.z summed into partials_ (rz_blocks() of them).
 void Solver::precond() {
     vcycle(0);
-    if (lv_.size() == 1) {
+    if (nlv_ == 1) {
         // the coarsest solve alone forms no sum: one more pass
         Level &F = lv_[0];
         const size_t N = F.d.count();
@@ -1234,12 +1267,12 @@ void Solver::precond() {
     }
 }
 
-unsigned Solver::rz_blocks() const { return lv_.size() > 1 ? post_blocks_ : red_blocks(lv_[0].d.count()); }
+unsigned Solver::rz_blocks() const { return nlv_ > 1 ? post_blocks_ : red_blocks(lv_[0].d.count()); }
 
 void Solver::mg_apply(const float *r, float *z, int bc) {
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
     bc_sign_ = bc == WG_BC_NEUMANN ? -1 : +1;
-    for (auto &L : lv_) L.d.bc_sign = bc_sign_;
+    for (int l = 0; l < nlv_; ++l) lv_[l].d.bc_sign = bc_sign_;
     Level &F = lv_[0];
     const size_t N = F.d.count();
     WG_HIP(hipMemcpyAsync(F.rhs, r, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
@@ -1261,13 +1294,13 @@ int Solver::pcg(double tol, int max_it, double rr0) {
     for (; it < max_it; ++it) {
         if (it == 0)
             launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, F.d, partials_, st_,
-                           WG_PROF_SWEEP, 12.0);
+                           pk(WG_PROF_SWEEP), 12.0);
         else   // beta = rz / rz_old, formed by the last finalize, read on the device
             launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, F.d, partials_, st_,
-                           WG_PROF_SWEEP, 16.0);
+                           pk(WG_PROF_SWEEP), 16.0);
         finalize(FIN_PQ, tb, 0);
         {
-            prof::Scope ps(WG_PROF_CGUPDATE, st_, (it == 0 ? 20.0 : 24.0) * (double)N);
+            prof::Scope ps(pk(WG_PROF_CGUPDATE), st_, (it == 0 ? 20.0 : 24.0) * (double)N);
             if (it == 0)
                 k_cg_update<true><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
             else
@@ -1292,13 +1325,15 @@ int Solver::pcg(double tol, int max_it, double rr0) {
 SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts &o) {
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
     bc_sign_ = bc == WG_BC_NEUMANN ? -1 : +1;
-    for (auto &L : lv_) L.d.bc_sign = bc_sign_;
+    for (int l = 0; l < nlv_; ++l) lv_[l].d.bc_sign = bc_sign_;
     Level &F = lv_[0];
     const size_t N = F.d.count();
     const unsigned tb = sweep_blocks(F.d);
     const unsigned gb = red_blocks(N);
     SolveResult res;
-    WG_HIP(hipMemsetAsync(dsc_, 0, sizeof(SolveScalars), st_));
+    static_assert(sizeof(SolveScalars) % 4 == 0, "scalars are whole words");
+    k_zero_words<<<1, 64, 0, st_>>>(reinterpret_cast<uint32_t *>(dsc_), sizeof(SolveScalars) / 4);
+    WG_LAUNCH_CHECK();
     if (!o.warm_start) {
         k_fill64<<<gb, kBlock, 0, st_>>>(x, 0.0, N);
         WG_LAUNCH_CHECK();
@@ -1315,7 +1350,7 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, WG_PROF_RESID64, 16.0);
+        launch_stencil(OpResid64{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, pk(WG_PROF_RESID64), 16.0);
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;

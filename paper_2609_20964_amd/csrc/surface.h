@@ -13,6 +13,8 @@
 // equals the brute-force minimum.
 #pragma once
 
+#include <functional>
+
 #include "kernels.h"
 
 namespace wg {
@@ -25,8 +27,16 @@ struct SurfaceCounts {
 class Surface {
   public:
     static void plan(Arena &a, const Dims &d);
+    // Bytes of the triangle and hierarchy buffers a handle starts with (a
+    // part of its footprint): room for about 4 triangles per cell of the
+    // grid's largest face.
+    static size_t initial_bytes(const Dims &d);
+    static uint32_t initial_tris(const Dims &d);
     void bind(Arena &a, const Dims &d, hipStream_t s);
     ~Surface();
+    // Called with the extra bytes before the triangle or hierarchy buffers
+    // grow past what they hold; it may throw (WG_ENOMEM) to refuse.
+    void set_grow_hook(std::function<void(size_t)> f) { grow_hook_ = std::move(f); }
 
     // Side of every node (chi >= c: outside) and the mesh of {chi = *c} (c on
     // the device).  Host-synchronising: returns the triangle count.  The
@@ -54,10 +64,13 @@ class Surface {
     void set_persistent(bool on);
     const float4 *tris() const { return tri_; }
     const int2 *tri_info() const { return info_; }
-    size_t bytes() const { return cap_ * (4 * sizeof(float4) + sizeof(int2)) + box_cap_ * 6 * sizeof(float4); }
+    size_t bytes() const { return buf_bytes(cap_, box_cap_) + retired_bytes_; }
 
   private:
-    void ensure_capacity(uint32_t tris, uint32_t active);
+    static size_t buf_bytes(size_t tri_cap, size_t box_cap) {
+        return tri_cap * (4 * sizeof(float4) + sizeof(int2)) + box_cap * 6 * sizeof(float4);
+    }
+    void ensure_capacity(uint32_t tris);
 
     hipStream_t st_ = nullptr;
     Dims d_{};
@@ -84,6 +97,12 @@ class Surface {
     float4 *box_ = nullptr;        // [box_cap][4] oriented-box nodes of every hierarchy level
     float4 *aabb_ = nullptr;       // [box_cap][2] axis-aligned box of every node (the walk reads the leaves')
     size_t cap_ = 0, box_cap_ = 0;
+    // Buffers outgrown by a larger surface.  They are freed with the handle,
+    // not when outgrown: hipFree waits for the whole device, which would stall
+    // every other stream's work (other requests of a server) mid-forward.
+    std::vector<void *> retired_;
+    size_t retired_bytes_ = 0;
+    std::function<void(size_t)> grow_hook_;
     std::vector<uint32_t> level_off_, level_cnt_;
     int levels_ = 0;
 };

@@ -15,7 +15,12 @@ namespace {
 
 constexpr int kBrick = 4;                   // cubes per brick edge (64 = one wavefront)
 constexpr int kMaxLevels = 12;
-constexpr int kStack = 64;
+// Traversal stack of the distance walk (per wavefront).  A pop of an internal
+// node at depth l (root 0) finds at most 7 unvisited siblings of it and of each
+// ancestor below the root on the stack (7 l entries) and pushes at most 8
+// children; internal nodes sit at depths up to kMaxLevels - 2, which extract()
+// enforces.  So the stack never holds more than 7 (kMaxLevels - 2) + 8 entries.
+constexpr int kStack = 7 * (kMaxLevels - 2) + 8;
 constexpr uint32_t kLeaf = 4;               // triangles per hierarchy leaf
 constexpr int kNode = 4;                    // float4 per hierarchy node
 constexpr int kTri = 4;                     // float4 per triangle record
@@ -249,8 +254,9 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
         tri[o] = make_float4(a[0], a[1], a[2], (float)aa);
         tri[o + 1] = make_float4(ab[0], ab[1], ab[2], (float)bc);
         tri[o + 2] = make_float4(ac[0], ac[1], ac[2], (float)cc);
-        tri[o + 3] = make_float4(aa > 0 ? (float)(1.0 / aa) : 0.f, cc > 0 ? (float)(1.0 / cc) : 0.f,
-                                 ee > 0 ? (float)(1.0 / ee) : 0.f, det > 0 ? (float)(1.0 / det) : 0.f);
+        // a reciprocal that does not fit a finite float marks the length (or area) as zero
+        auto rcp = [](double x) { return x > 0 && 1.0 / x < 3.0e38 ? (float)(1.0 / x) : 0.f; };
+        tri[o + 3] = make_float4(rcp(aa), rcp(cc), rcp(ee), rcp(det));
         info[base + t] = make_int2((int)cell, packed);
     }
 }
@@ -382,10 +388,12 @@ __global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ 
 // R, so a region costs one or two multiplications.  The regions are tested in
 // the method's order (vertices, edges, face interior); neighbouring nodes of a
 // wavefront mostly share a region, so the branches rarely diverge.  A
-// zero-area triangle falls back to vertex a in the interior case, never closer
-// than its true nearest point (its edges are shared with neighbours, which
-// supply the exact distance).  Returns the squared distance; (v, w) are the
-// barycentric weights of b and c at the closest point.
+// zero-area triangle (R.w = 0: a vertex of Marching Cubes landed exactly on a
+// cube corner) is a segment or a point: its nearest point is the nearest one
+// on its three edges (the Voronoi tests assume a proper triangle there).  The
+// walk takes one triangle for the whole wavefront, so that branch is uniform.
+// Returns the squared distance; (v, w) are the barycentric weights of b and c
+// at the closest point.
 __device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, float4 B, float4 C, float4 R,
                                         float &v, float &w) {
     const float apx = px - A.x, apy = py - A.y, apz = pz - A.z;
@@ -393,6 +401,23 @@ __device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, 
     const float d2 = C.x * apx + C.y * apy + C.z * apz;
     const float d3 = d1 - A.w, d4 = d2 - B.w;   // against p - b
     const float d5 = d1 - B.w, d6 = d2 - C.w;   // against p - c
+    if (R.w == 0.f) {
+        // nearest of the edges ab (parameter d1 / |ab|^2), ac (d2 / |ac|^2) and
+        // bc ((d4 - d3) / |bc|^2), each clamped to the segment
+        v = fminf(fmaxf(d1 * R.x, 0.f), 1.f);
+        w = 0.f;
+        float qx = apx - v * B.x, qy = apy - v * B.y, qz = apz - v * B.z;
+        float best = qx * qx + qy * qy + qz * qz;
+        float t = fminf(fmaxf(d2 * R.y, 0.f), 1.f);
+        qx = apx - t * C.x; qy = apy - t * C.y; qz = apz - t * C.z;
+        float dd = qx * qx + qy * qy + qz * qz;
+        if (dd < best) { best = dd; v = 0.f; w = t; }
+        t = fminf(fmaxf((d4 - d3) * R.z, 0.f), 1.f);
+        qx = apx - (1.f - t) * B.x - t * C.x; qy = apy - (1.f - t) * B.y - t * C.y; qz = apz - (1.f - t) * B.z - t * C.z;
+        dd = qx * qx + qy * qy + qz * qz;
+        if (dd < best) { best = dd; v = 1.f - t; w = t; }
+        return best;
+    }
     const float vc = d1 * d4 - d3 * d2;
     const float vb = d5 * d2 - d1 * d6;
     const float va = d3 * d6 - d5 * d4;
@@ -729,7 +754,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                                                                              : 0u;
                     }
                 }
-                if (sp + 8 > kStack) {
+                if (sp + 8 > kStack) {   // cannot happen (see kStack); kept as a guard
                     atomicOr(err, 2);
                     continue;
                 }
@@ -852,48 +877,127 @@ __global__ __launch_bounds__(256) void k_tile_depth(const uint32_t *__restrict__
     out[t] = v;
 }
 
-// Reverse of phi through the distance (envelope theorem on Eq. 33) and the
-// Marching Cubes vertices (Eq. 28): g_chi at the two ends of each vertex's
-// edge, g_c in FP64.
+// Closest point to the origin on the triangle (a, b, c) in FP64, by the same
+// Voronoi-region method as tri_d2 (Ericson 2005, Sec. 5.1.5) with its
+// divisions; a zero-area triangle takes the nearest point of its three edges.
+// Returns the barycentric weights (v, w) of b and c.
+__device__ void closest_on_tri64(const double (&a)[3], const double (&b)[3], const double (&c)[3], double &v,
+                                 double &w) {
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ac[k] = c[k] - a[k];
+        ap[k] = -a[k];
+        bp[k] = -b[k];
+        cp[k] = -c[k];
+    }
+    auto dot = [](const double *x, const double *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    const double cr[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
+    if (dot(cr, cr) == 0.0) {
+        // segment or point: nearest of the edges ab, ac, bc
+        double best = INFINITY;
+        const double *P[3] = {a, a, b}, *Q[3] = {b, c, c};
+        for (int e = 0; e < 3; ++e) {
+            double pq[3], pp[3];
+            for (int k = 0; k < 3; ++k) {
+                pq[k] = Q[e][k] - P[e][k];
+                pp[k] = -P[e][k];
+            }
+            const double l2 = dot(pq, pq);
+            const double t = l2 > 0 ? fmin(fmax(dot(pp, pq) / l2, 0.0), 1.0) : 0.0;
+            double dd = 0;
+            for (int k = 0; k < 3; ++k) dd += (pp[k] - t * pq[k]) * (pp[k] - t * pq[k]);
+            if (dd < best) {
+                best = dd;
+                v = e == 0 ? t : e == 1 ? 0.0 : 1.0 - t;
+                w = e == 0 ? 0.0 : t;
+            }
+        }
+        return;
+    }
+    const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+    if (d1 <= 0 && d2 <= 0) { v = 0; w = 0; return; }
+    const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3 >= 0 && d4 <= d3) { v = 1; w = 0; return; }
+    const double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0 && d1 >= 0 && d3 <= 0) { v = d1 / (d1 - d3); w = 0; return; }
+    const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+    if (d6 >= 0 && d5 <= d6) { v = 0; w = 1; return; }
+    const double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0 && d2 >= 0 && d6 <= 0) { v = 0; w = d2 / (d2 - d6); return; }
+    const double va = d3 * d6 - d5 * d4;
+    if (va <= 0 && (d4 - d3) >= 0 && (d5 - d6) >= 0) {
+        w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        v = 1 - w;
+        return;
+    }
+    const double den = 1.0 / (va + vb + vc);
+    v = vb * den;
+    w = vc * den;
+}
+
+// B2: reverse of the distance through the Marching Cubes vertices.  With p*
+// the closest point of the node's nearest triangle (recorded by the walk) and
+// beta its barycentric weights, d dist / d v_k = -beta_k (p - p*) / dist; a
+// vertex on the edge chi1 -> chi2 along axis a sits at eta = (c - chi1) /
+// (chi2 - chi1), so d eta / d chi1 = (c - chi2) / D^2, d eta / d chi2 =
+// -(c - chi1) / D^2 and d eta / d c = 1 / D (D = chi2 - chi1).  The vertices
+// are rebuilt here in FP64 from chi and the triangle's edge ids, relative to
+// the node, as Marching Cubes formed them: the FP32 records the walk reads
+// carry absolute grid coordinates (a rounding of up to ~1e-5 cells at 256
+// cells per axis), too coarse for the direction (p - p*) / dist at nodes a
+// small fraction of a cell from the surface.
 __global__ __launch_bounds__(256) void k_sdf_T(const float *__restrict__ gphi, const double *__restrict__ chi,
                                                 const double *iso, Dims d, double h, const int32_t *__restrict__ argmin,
-                                                const float4 *__restrict__ tri, const int2 *__restrict__ info,
-                                                float *__restrict__ g_chi, double *g_c) {
+                                                const int2 *__restrict__ info, float *__restrict__ g_chi,
+                                                double *g_c) {
     const size_t n = d.count();
+    const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
     double gc = 0.0;
     // grid-stride over nodes; the wavefront sums g_c once at the end
     for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (size_t)gridDim.x * blockDim.x) {
         const float g = gphi[o];
         const int t = argmin[o];
-        if (g != 0.f && t >= 0) {
-            const double c = iso[0];
-            const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / ((size_t)d.nx * d.ny);
-            const float4 *tr = tri + kTri * (size_t)t;
-            const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
-            float v, w;
-            tri_d2((float)i, (float)j, (float)k, A, B, C, R, v, w);
-            // p - (a + v ab + w ac)
-            float u[3] = {(float)i - A.x - v * B.x - w * C.x, (float)j - A.y - v * B.y - w * C.y,
-                          (float)k - A.z - v * B.z - w * C.z};
-            float dist = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            if (dist > 0.f) {
-                const float sgn = chi[o] >= c ? 1.f : -1.f;
-                const float gd = sgn * (float)h * g;       // dL / d(distance in grid units)
-                const float beta[3] = {1.f - v - w, v, w};
-                const int2 inf = info[t];
-                const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
-                for (int vq = 0; vq < 3; ++vq) {
-                    int e = (inf.y >> (4 * vq)) & 15, b0, b1, ax;
-                    edge_ends(e, b0, b1, ax);
-                    const float geta = -beta[vq] * (u[ax] / dist) * gd;
-                    const size_t c1 = (size_t)inf.x + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2);
-                    const size_t c2 = (size_t)inf.x + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2);
-                    const double x1 = chi[c1], x2 = chi[c2], D = x2 - x1;
-                    unsafeAtomicAdd(g_chi + c1, (float)((double)geta * (c - x2) / (D * D)));
-                    unsafeAtomicAdd(g_chi + c2, (float)(-(double)geta * (c - x1) / (D * D)));
-                    gc += (double)geta / D;
-                }
-            }
+        if (g == 0.f || t < 0) continue;
+        const double c = iso[0];
+        const int i = o % d.nx, j = (o / d.nx) % d.ny, k = o / sz;
+        const int2 inf = info[t];
+        const int ci = inf.x % d.nx, cj = (inf.x / d.nx) % d.ny, ck = inf.x / (int)sz;
+        double V[3][3], Dq[3];
+        size_t C1[3], C2[3];
+        int AX[3];
+        for (int vq = 0; vq < 3; ++vq) {
+            int b0, b1, ax;
+            edge_ends((inf.y >> (4 * vq)) & 15, b0, b1, ax);
+            C1[vq] = (size_t)inf.x + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2);
+            C2[vq] = (size_t)inf.x + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2);
+            const double x1 = chi[C1[vq]], x2 = chi[C2[vq]];
+            Dq[vq] = x2 - x1;
+            AX[vq] = ax;
+            V[vq][0] = (double)(ci + (b0 & 1) - i);
+            V[vq][1] = (double)(cj + ((b0 >> 1) & 1) - j);
+            V[vq][2] = (double)(ck + (b0 >> 2) - k);
+            V[vq][ax] += (c - x1) / Dq[vq];
+        }
+        double v, w;
+        closest_on_tri64(V[0], V[1], V[2], v, w);
+        const double beta[3] = {1.0 - v - w, v, w};
+        // p - p* (p at the origin)
+        double u[3], dist = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            u[a] = -(beta[0] * V[0][a] + beta[1] * V[1][a] + beta[2] * V[2][a]);
+            dist += u[a] * u[a];
+        }
+        dist = sqrt(dist);
+        if (!(dist > 0.0)) continue;
+        const double sgn = chi[o] >= c ? 1.0 : -1.0;
+        const double gd = sgn * h * (double)g;   // dL / d(distance in grid units)
+        for (int vq = 0; vq < 3; ++vq) {
+            const double geta = -beta[vq] * (u[AX[vq]] / dist) * gd;
+            const double x1 = chi[C1[vq]], x2 = chi[C2[vq]], D = Dq[vq];
+            unsafeAtomicAdd(g_chi + C1[vq], (float)(geta * (c - x2) / (D * D)));
+            unsafeAtomicAdd(g_chi + C2[vq], (float)(-geta * (c - x1) / (D * D)));
+            gc += geta / D;
         }
     }
     gc = wave_sum(gc);
@@ -1101,11 +1205,7 @@ void Surface::bind(Arena &a, const Dims &d, hipStream_t s) {
     sdf_blocks_full_ = ncu * (unsigned)(per_cu > 1 ? per_cu - 1 : 1);
     sdf_blocks_beside_ = ncu * (unsigned)(per_cu > 4 ? per_cu - 4 : 1);
     hcnt_.alloc();
-    // a first guess at the triangle capacity: ~4 per cube over a few slices
-    size_t face = (size_t)d.nx * d.ny;
-    if ((size_t)d.ny * d.nz > face) face = (size_t)d.ny * d.nz;
-    if ((size_t)d.nx * d.nz > face) face = (size_t)d.nx * d.nz;
-    ensure_capacity((uint32_t)(4 * face), (uint32_t)(face / 4 + 16));
+    ensure_capacity(initial_tris(d));
 }
 
 void Surface::set_persistent(bool on) { persistent_ = on; }
@@ -1119,32 +1219,61 @@ Surface::~Surface() {
     if (info_) (void)hipFree(info_);
     if (box_) (void)hipFree(box_);
     if (aabb_) (void)hipFree(aabb_);
+    for (void *p : retired_) (void)hipFree(p);
 }
 
-void Surface::ensure_capacity(uint32_t tris, uint32_t active) {
-    if (tris > cap_) {
-        if (tri_) WG_HIP(hipFree(tri_));
-        if (info_) WG_HIP(hipFree(info_));
-        tri_ = nullptr;
-        info_ = nullptr;
-        size_t c = (size_t)tris + tris / 4 + 64;
-        WG_HIP(hipMalloc(&tri_, c * kTri * sizeof(float4)));
-        WG_HIP(hipMalloc(&info_, c * sizeof(int2)));
-        cap_ = c;
+namespace {
+// triangle capacity for t triangles (with slack) and hierarchy nodes over them
+size_t tri_cap_for(size_t t) { return t + t / 4 + 64; }
+size_t box_cap_for(size_t t) {
+    const size_t leaves = (t + kLeaf - 1) / kLeaf;
+    const size_t need = leaves + leaves / 7 + kMaxLevels + 1;
+    return need + need / 4 + 64;
+}
+}  // namespace
+
+uint32_t Surface::initial_tris(const Dims &d) {
+    size_t face = (size_t)d.nx * d.ny;
+    if ((size_t)d.ny * d.nz > face) face = (size_t)d.ny * d.nz;
+    if ((size_t)d.nx * d.nz > face) face = (size_t)d.nx * d.nz;
+    return (uint32_t)(4 * face);
+}
+
+size_t Surface::initial_bytes(const Dims &d) {
+    const size_t t = initial_tris(d);
+    return buf_bytes(tri_cap_for(t), box_cap_for(t));
+}
+
+void Surface::ensure_capacity(uint32_t tris) {
+    const bool grow_tris = tris > cap_;
+    const size_t tcap = grow_tris ? tri_cap_for(tris) : cap_;
+    const size_t leaves = ((size_t)tris + kLeaf - 1) / kLeaf;
+    const bool grow_boxes = leaves + leaves / 7 + kMaxLevels + 1 > box_cap_;
+    const size_t bcap = grow_boxes ? box_cap_for(tris) : box_cap_;
+    if (!grow_tris && !grow_boxes) return;
+    // a handle's first buffers are part of its footprint; growth is extra
+    const size_t extra = buf_bytes(grow_tris ? tcap : 0, grow_boxes ? bcap : 0);
+    if (grow_hook_ && (cap_ > 0 || box_cap_ > 0)) grow_hook_(extra);
+    auto retire = [&](void *&p, size_t bytes) {
+        if (p) {
+            retired_.push_back(p);
+            retired_bytes_ += bytes;
+        }
+        p = nullptr;
+    };
+    if (grow_tris) {
+        retire(reinterpret_cast<void *&>(tri_), cap_ * kTri * sizeof(float4));
+        retire(reinterpret_cast<void *&>(info_), cap_ * sizeof(int2));
+        WG_HIP(hipMalloc(&tri_, tcap * kTri * sizeof(float4)));
+        WG_HIP(hipMalloc(&info_, tcap * sizeof(int2)));
+        cap_ = tcap;
     }
-    // boxes of every level: leaves = ceil(tris / kLeaf), then 8-ary levels
-    (void)active;
-    size_t leaves = ((size_t)tris + kLeaf - 1) / kLeaf;
-    size_t need = leaves + leaves / 7 + kMaxLevels + 1;
-    if (need > box_cap_) {
-        if (box_) WG_HIP(hipFree(box_));
-        box_ = nullptr;
-        size_t c = need + need / 4 + 64;
-        WG_HIP(hipMalloc(&box_, c * kNode * sizeof(float4)));
-        if (aabb_) WG_HIP(hipFree(aabb_));
-        aabb_ = nullptr;
-        WG_HIP(hipMalloc(&aabb_, c * 2 * sizeof(float4)));
-        box_cap_ = c;
+    if (grow_boxes) {
+        retire(reinterpret_cast<void *&>(box_), box_cap_ * kNode * sizeof(float4));
+        retire(reinterpret_cast<void *&>(aabb_), box_cap_ * 2 * sizeof(float4));
+        WG_HIP(hipMalloc(&box_, bcap * kNode * sizeof(float4)));
+        WG_HIP(hipMalloc(&aabb_, bcap * 2 * sizeof(float4)));
+        box_cap_ = bcap;
     }
 }
 
@@ -1168,7 +1297,7 @@ uint32_t Surface::extract(const double *chi, const double *c) {
     level_off_.clear();
     level_cnt_.clear();
     if (cnt_.n_tris == 0) return 0;
-    ensure_capacity(cnt_.n_tris, cnt_.n_active);
+    ensure_capacity(cnt_.n_tris);
     k_mc_emit<<<cdiv(cnt_.n_active, 4), 256, 0, st_>>>(chi, c, d_, nb, active_, cnt_.n_active, off_b_, tri_, info_);
     WG_LAUNCH_CHECK();
     uint32_t n = cdiv(cnt_.n_tris, kLeaf), off = 0;
@@ -1282,8 +1411,7 @@ void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s
 void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const int32_t *argmin, double h,
                     float *g_chi, double *g_c) {
     if (cnt_.n_tris == 0) return;
-    k_sdf_T<<<std::min(cdiv(d_.count(), 256), 8192u), 256, 0, st_>>>(gphi, chi, c, d_, h, argmin, tri_, info_, g_chi,
-                                                                     g_c);
+    k_sdf_T<<<std::min(cdiv(d_.count(), 256), 8192u), 256, 0, st_>>>(gphi, chi, c, d_, h, argmin, info_, g_chi, g_c);
     WG_LAUNCH_CHECK();
 }
 

@@ -98,6 +98,20 @@ class Recon:
         self.last_stats = st.as_dict()
         return self.last_stats
 
+    def sdf_from_field(self, chi, c):
+        """Surface {chi = c} and the signed distance to it on every node (F6-F7)
+        for a given float64 field chi [N] (wg_sdf_from_field).  Returns stats."""
+        if chi.numel() != self.cells:
+            raise ValueError(f"chi must hold {self.cells} cells")
+        st = L.WgStats()
+        chi = chi.contiguous()
+        L.check(L.lib().wg_sdf_from_field(self._alive(), _dev(chi, torch.float64, None, "chi"), float(c),
+                                          C.byref(st)))
+        self.generation += 1
+        self.n_points = 0
+        self.last_stats = st.as_dict()
+        return self.last_stats
+
     def sample(self, q, normals=True):
         """SDF and unit normals at query points q [Q,3] (F8)."""
         nq = int(q.shape[0])

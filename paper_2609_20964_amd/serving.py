@@ -32,8 +32,13 @@ class Server:
     def now(self):
         return L.lib().wg_server_now(self._h)
 
-    def submit(self, n, xyz, nrm, q, gphi=None, rel_tol=1e-6, max_iters=500, normals=True, lo=(0, 0, 0), h=None):
-        """Queue one reconstruction; returns a Ticket.  Inputs are copied before return."""
+    def submit(self, n, xyz, nrm, q, gphi=None, rel_tol=1e-6, max_iters=500, normals=True, lo=(0, 0, 0), h=None,
+               gnrm=None, want_gq=False):
+        """Queue one reconstruction; returns a Ticket.  Inputs are copied before return.
+
+        gphi (dL/dphi(q), [Q]) asks for the reverse pass: the outputs then hold
+        g_xyz and g_nrm for the points, and g_q [Q,3] if want_gq; gnrm [Q,3]
+        adds dL/dn(q)."""
         req = L.WgRequest()
         req.grid = L.make_grid(n, lo, h)
         npts, nq = int(xyz.shape[0]), int(q.shape[0])
@@ -41,22 +46,32 @@ class Server:
             assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
         phi = torch.empty(nq, dtype=torch.float32, device=q.device)
         nout = torch.empty((nq, 3), dtype=torch.float32, device=q.device) if normals else None
-        gx = gn = None
+        gx = gn = gq = None
+        if gphi is None and (gnrm is not None or want_gq):
+            raise ValueError("gnrm / want_gq need gphi")
         if gphi is not None:
+            gphi = gphi.contiguous()     # held in a local until wg_submit has copied it
             gx = torch.empty((npts, 3), dtype=torch.float32, device=q.device)
             gn = torch.empty((npts, 3), dtype=torch.float32, device=q.device)
+            if want_gq:
+                gq = torch.empty((nq, 3), dtype=torch.float32, device=q.device)
+        if gnrm is not None:
+            assert gnrm.is_cuda and gnrm.dtype == torch.float32 and gnrm.shape == (nq, 3)
+            gnrm = gnrm.contiguous()
         req.d_xyz, req.d_nrm, req.n_points = xyz.data_ptr(), nrm.data_ptr(), npts
         req.d_q, req.n_q = q.data_ptr(), nq
-        req.d_gphi = gphi.contiguous().data_ptr() if gphi is not None else None
+        req.d_gphi = gphi.data_ptr() if gphi is not None else None
         req.opts = L.make_opts(rel_tol, max_iters, False)
         req.d_phi = phi.data_ptr()
         req.d_nrm_out = nout.data_ptr() if nout is not None else None
         req.d_gxyz = gx.data_ptr() if gx is not None else None
         req.d_gnrm_pts = gn.data_ptr() if gn is not None else None
+        req.d_gnrm = gnrm.data_ptr() if gnrm is not None else None
+        req.d_gq = gq.data_ptr() if gq is not None else None
         torch.cuda.current_stream().synchronize()      # inputs must be complete before the copy
         tid = C.c_uint64()
         L.check(L.lib().wg_submit(self._h, C.byref(req), C.byref(tid)))
-        return Ticket(tid.value, {"phi": phi, "nrm": nout, "g_xyz": gx, "g_nrm": gn}, npts)
+        return Ticket(tid.value, {"phi": phi, "nrm": nout, "g_xyz": gx, "g_nrm": gn, "g_q": gq}, npts)
 
     def poll(self, ticket):
         """None while pending; else (status, outputs dict, result dict)."""

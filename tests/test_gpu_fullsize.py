@@ -17,6 +17,7 @@ at the 99th percentile).
 import numpy as np
 import pytest
 
+from angles import angle
 from oracle import discretize as D
 from oracle import pipeline as P
 from paper_2609_20964_amd import synth
@@ -57,7 +58,7 @@ def _check(grid, ref, r, st, phi, q_all, phi_q_all, n_q_all, seed, nq_rand, nq_n
     print(f"phi queries: max err / h = {errq.max() / grid.h:.3e}", flush=True)
     assert errq.max() <= 1e-4 * grid.h
     ok = np.linalg.norm(n_ref, axis=1) > 0
-    ang = np.arccos(np.clip(np.sum(n_q_all[pick][ok].astype(np.float64) * n_ref[ok], 1), -1, 1))
+    ang = angle(n_q_all[pick][ok], n_ref[ok])
     assert np.percentile(ang, 99) <= 1e-3 and ang.max() <= 2e-2
     assert np.isfinite(phi_q_all).all() and np.isfinite(n_q_all).all()
 
