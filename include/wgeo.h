@@ -164,6 +164,21 @@ int wg_recon_backward(wg_recon *r, const float *d_q, int n_q, const float *d_gph
 int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc,
                      const wg_solve_opts *opts, wg_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of wg_poisson_solve on `grid`, with no handle and no allocation.  Every work
+ * buffer comes from a fixed 10 MiB device array inside the library (one copy
+ * per GPU, held until the process ends), which holds the solver state of any
+ * grid of up to 64^3 cells; a grid needing more gives WG_EINVAL before any
+ * device work.  d_b, d_x, bc, opts and the result are as for wg_poisson_solve
+ * (same kernels, same launch configuration).  Work runs on hip_stream (a
+ * hipStream_t, NULL = default stream); the call returns once the solve is
+ * complete (it blocks the host).  Calls on one GPU share its array and are
+ * serialised by the library; the array keeps the last call's contents.
+ * stats->ms[1] is the call's wall time; bytes_resident is 0. */
+int wg_poisson_solve_noalloc(const wg_grid *grid, const float *d_b, double *d_x, int bc,
+                             const wg_solve_opts *opts, wg_stats *stats, void *hip_stream);
+
 /* One application z = M r of the multigrid preconditioner that the Poisson
  * solves (Eq. 20-21 operator, Sec. 2.5's iterative solve) use on r's grid:
  * a V-cycle with cell-centred trilinear prolongation P, restriction P^T / 2,

@@ -73,6 +73,8 @@ SIGNATURES = {
                                     C.c_void_p, C.c_void_p, C.POINTER(WgSolveOpts), C.POINTER(WgStats)]),
     "wg_poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
                                    C.POINTER(WgStats)]),
+    "wg_poisson_solve_noalloc": (C.c_int, [C.POINTER(WgGrid), C.c_void_p, C.c_void_p, C.c_int,
+                                           C.POINTER(WgSolveOpts), C.POINTER(WgStats), C.c_void_p]),
     "wg_mg_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "wg_sdf_from_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(WgStats)]),
     "wg_get_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
