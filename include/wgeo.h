@@ -57,6 +57,17 @@ enum {
 
 enum { WG_BC_NEUMANN = 0, WG_BC_DIRICHLET = 1 };
 
+/* wg_solve_opts.precision */
+enum {
+    WG_FP32_FP64REDUCE = 0, /* splat weights and sums in FP32 (FP32 atomics); stencil
+                               sweeps FP32 with FP64 inner products; the solution
+                               refined in FP64                                    */
+    WG_FP64 = 1             /* the right-hand side b in FP64: splat weights and the
+                               divergence in FP64, summed exactly in 64-bit fixed
+                               point (so also deterministic); FP64 residuals and
+                               solution as above                                  */
+};
+
 typedef struct {
     int n[3];           /* cells per axis (x, y, z), each >= 4                    */
     double lo[3];       /* world position of the grid's lower corner              */
@@ -73,8 +84,16 @@ typedef struct {
                            walk orders its tiles by their depth inside the new
                            surface and searches its seeds first.  No result
                            depends on this beyond the solver's start.          */
-    int reserved0;      /* must be 0                                               */
-    int reserved1;      /* must be 0                                               */
+    int precision;      /* WG_FP32_FP64REDUCE (0) or WG_FP64 (1)                   */
+    int deterministic;  /* 1: the splat sums each cell's contributions in 64-bit
+                           fixed point (integer adds, in any order), so b -- and
+                           with it chi, the surface and phi -- is the same bit for
+                           bit however points, threads and concurrent requests
+                           interleave.  The fixed-point unit is 2^-e with e the
+                           largest exponent for which npts * 3.75 h^-2 max|n_k|
+                           fits below 2^61 (a bound on any cell's sum).  Forward
+                           pass only: the reverse pass still scatters with FP32
+                           atomics.  0: FP32 atomics (WG_FP64 implies 1).      */
 } wg_solve_opts;
 
 typedef struct {

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libwgeo.so")
 WG_OK, WG_PENDING = 0, 1
 WG_EINVAL, WG_ENOMEM, WG_ENOTCONV, WG_ENUMERIC, WG_EDEVICE, WG_ESTATE = -1, -2, -3, -4, -5, -6
 WG_BC_NEUMANN, WG_BC_DIRICHLET = 0, 1
+WG_FP32_FP64REDUCE, WG_FP64 = 0, 1
 CODE_NAMES = {WG_EINVAL: "WG_EINVAL", WG_ENOMEM: "WG_ENOMEM", WG_ENOTCONV: "WG_ENOTCONV",
               WG_ENUMERIC: "WG_ENUMERIC", WG_EDEVICE: "WG_EDEVICE", WG_ESTATE: "WG_ESTATE"}
 
@@ -24,7 +25,7 @@ class WgGrid(C.Structure):
 
 class WgSolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_iters", C.c_int), ("warm_start", C.c_int),
-                ("reserved0", C.c_int), ("reserved1", C.c_int)]
+                ("precision", C.c_int), ("deterministic", C.c_int)]
 
 
 class WgStats(C.Structure):
@@ -152,11 +153,13 @@ def make_grid(n, lo=(0.0, 0.0, 0.0), h=None):
     return g
 
 
-def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False):
+def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False, precision=WG_FP32_FP64REDUCE, deterministic=False):
     o = WgSolveOpts()
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
     o.warm_start = int(bool(warm_start))
+    o.precision = int(precision)
+    o.deterministic = int(bool(deterministic))
     return o
 
 

@@ -69,16 +69,27 @@ template <class T> class HostMapped {
 };
 
 // ---- splat.hip -------------------------------------------------------------
+// Fixed-point unit of the deterministic splat: value = sum * inv, scale = 1 / inv.
+struct FixedScale {
+    double scale, inv;
+};
+enum { kSplatF32 = 0, kSplatFixed = 1, kSplatFixed64 = 2 };
+
 __global__ void k_bin_points(const float *xyz, const float *nrm, int npts, GridF g, TileDims td, int32_t *keys,
                              float *xyz_c, float *nrm_c, int32_t *tile_of, uint32_t *rank, uint32_t *tile_cnt,
-                             int *err);
+                             int *err, uint32_t *nmax_bits);
 __global__ void k_tile_scatter(const int32_t *tile_of, const uint32_t *rank, const uint32_t *tile_off, int npts,
                                uint32_t *perm);
 __global__ void k_chunk_counts(const uint32_t *tile_cnt, uint32_t ntiles, uint32_t *ch_cnt);
 __global__ void k_chunk_tiles(const uint32_t *ch_cnt, const uint32_t *ch_off, uint32_t ntiles, uint32_t *chunk_tile);
+template <int Mode>
 __global__ void k_splat_chunks(const uint32_t *perm, const uint32_t *tile_off, const uint32_t *tile_cnt,
                                const uint32_t *ch_off, const uint32_t *chunk_tile, const uint32_t *n_chunks,
-                               const float *xyz_c, const float *nrm_c, GridF g, TileDims td, float *b);
+                               const float *xyz_c, const float *nrm_c, GridF g, TileDims td, float *b,
+                               unsigned long long *acc, const FixedScale *fix);
+__global__ void k_fixed_scale(const uint32_t *nmax_bits, int npts, double h, FixedScale *fix, int *err);
+template <class T>
+__global__ void k_fixed_to_b(const long long *acc, const FixedScale *fix, size_t n, T *b);
 __global__ void k_iso_partial(const float *xyz, int npts, GridF g, const double *chi, double *partials);
 __global__ void k_iso_finalize(const double *partials, int nb, int npts, double *out);
 __global__ void k_iso_T(const float *xyz, int npts, GridF g, const double *g_c, float *g_chi);

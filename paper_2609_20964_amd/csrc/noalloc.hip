@@ -59,7 +59,8 @@ static int poisson_noalloc(const wg_grid *grid, const float *d_b, double *d_x, i
     require(g.n[0] >= 4 && g.n[1] >= 4 && g.n[2] >= 4, WG_EINVAL, "each grid extent must be >= 4");
     require((double)g.n[0] * g.n[1] * g.n[2] < 2.0e9, WG_EINVAL, "grid too large for 32-bit cell indices");
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
-    require(opts->reserved0 == 0 && opts->reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    require(opts->precision == WG_FP32_FP64REDUCE || opts->precision == WG_FP64, WG_EINVAL, "unknown precision");
+    require(opts->deterministic == 0 || opts->deterministic == 1, WG_EINVAL, "deterministic must be 0 or 1");
     const size_t need = scratch_need(g);
     require(need <= kScratchBytes, WG_EINVAL,
             "grid " + std::to_string(g.n[0]) + "x" + std::to_string(g.n[1]) + "x" + std::to_string(g.n[2]) +

@@ -8,6 +8,9 @@
 
 namespace wg {
 
+// Validates precision / deterministic (WG_EINVAL otherwise).
+void check_opts(const wg_solve_opts &o);
+
 class Recon {
   public:
     Recon(const wg_grid &g, int max_points, hipStream_t s);
@@ -70,6 +73,8 @@ class Recon {
     // scal_[0..7] (c, c shifted, g_c) and err_[0..3] are one device block,
     // mirrored whole into hm_
     int *err_ = nullptr;
+    FixedScale *fix_ = nullptr;   // fixed-point unit of the deterministic splat
+    uint32_t *nmax_ = nullptr;    // largest |normal component| (float bits)
     struct Mirror {
         double scal[8];
         int err[4];

@@ -82,6 +82,8 @@ void Recon::plan(Arena &a, const wg_grid &g, int max_points) {
     a.reserve((nt + (size_t)max_points / kChunk + 1) * sizeof(uint32_t));   // tile of each chunk
     a.reserve(kIsoBlocks * sizeof(double));
     a.reserve(8 * sizeof(double) + 4 * sizeof(int));   // scalars (c, c_shifted, g_c), then error flags
+    a.reserve(sizeof(FixedScale));                       // fixed-point unit of the deterministic splat
+    a.reserve(sizeof(uint32_t));                         // largest |normal component| (float bits)
     Solver::plan(a, d.nx, d.ny, d.nz);
     Surface::plan(a, d);
 }
@@ -127,6 +129,8 @@ Recon::Recon(const wg_grid &g, int max_points, hipStream_t s) : grid_(g), max_po
     iso_part_ = arena_.take<double>(kIsoBlocks);
     scal_ = arena_.take<double>(10);
     err_ = reinterpret_cast<int *>(scal_ + 8);
+    fix_ = arena_.take<FixedScale>(1);
+    nmax_ = arena_.take<uint32_t>(1);
     solver_.bind(arena_, d_.nx, d_.ny, d_.nz, st_);
     surf_.bind(arena_, d_, st_);
     hm_.alloc();
@@ -141,6 +145,11 @@ Recon::~Recon() {
     if (ev_sdf_) (void)hipEventDestroy(ev_sdf_);
     if (ev_tail_) (void)hipEventDestroy(ev_tail_);
     if (sdf_st_) (void)hipStreamDestroy(sdf_st_);
+}
+
+void check_opts(const wg_solve_opts &o) {
+    require(o.precision == WG_FP32_FP64REDUCE || o.precision == WG_FP64, WG_EINVAL, "unknown precision");
+    require(o.deterministic == 0 || o.deterministic == 1, WG_EINVAL, "deterministic must be 0 or 1");
 }
 
 // The handle stream waits (on the device) for the last distance walk.
@@ -179,6 +188,7 @@ void Recon::check_err(const char *what) {
     hm_.fetch(scal_, st_);
     const Mirror &m = hm_.wait();
     if (m.err[0] & 1) throw Error(WG_EINVAL, std::string(what) + ": a point lies outside the grid");
+    if (m.err[0] & 4) throw Error(WG_ENUMERIC, std::string(what) + ": a normal is NaN or infinite");
     if (!sdf_pending_ && (m.err[1] & 2)) throw Error(WG_EDEVICE, "distance traversal stack overflow");
 }
 
@@ -186,12 +196,21 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
                    bool pipelined) {
     require(npts >= 0 && npts <= max_points_, WG_EINVAL, "n_points outside [0, max_points]");
     require(npts == 0 || (xyz && nrm), WG_EINVAL, "null point or normal pointer");
-    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    check_opts(o);
     have_forward_ = false;
     const size_t N = d_.count();
+    // WG_FP64 and deterministic splats sum in 64-bit fixed point, in the
+    // lambda buffer (the reverse pass's; free during a forward)
+    const bool fp64 = o.precision == WG_FP64, fixed = fp64 || o.deterministic;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lam_);
     Timer tm(st_);
     tm.mark(0);
-    WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
+    if (fixed) {
+        WG_HIP(hipMemsetAsync(acc, 0, N * sizeof(unsigned long long), st_));
+        WG_HIP(hipMemsetAsync(nmax_, 0, sizeof(uint32_t), st_));
+    } else {
+        WG_HIP(hipMemsetAsync(b_, 0, N * sizeof(float), st_));
+    }
     WG_HIP(hipMemsetAsync(err_, 0, sizeof(int), st_));
     if (npts > 0) {
         // per point: 24 B read, 24 B copied, 4 B key, tile bookkeeping, 81 contributions to b
@@ -199,7 +218,7 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         const uint32_t nt = (uint32_t)td_.count();
         WG_HIP(hipMemsetAsync(tile_cnt_, 0, nt * sizeof(uint32_t), st_));
         k_bin_points<<<cdiv(npts, 256), 256, 0, st_>>>(xyz, nrm, npts, gf_, td_, keys_, xyz_, nrm_, tile_of_, rank_,
-                                                      tile_cnt_, err_);
+                                                      tile_cnt_, err_, fixed ? nmax_ : nullptr);
         const uint32_t nblk = cdiv(nt, scan::kScanBlock);
         scan::k_scan_partial<<<nblk, 256, 0, st_>>>(tile_cnt_, nt, tile_blk_);
         scan::k_scan_top<<<1, 256, 0, st_>>>(tile_blk_, nblk, tile_tot_);
@@ -211,14 +230,37 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         scan::k_scan_final<<<nblk, 256, 0, st_>>>(ch_cnt_, nt, ch_blk_, ch_off_, ch_act_);
         k_chunk_tiles<<<cdiv(nt, 256), 256, 0, st_>>>(ch_cnt_, ch_off_, nt, chunk_tile_);
         const unsigned grid = std::min<unsigned>(2048u, nt + cdiv(npts, kChunk));
-        k_splat_chunks<<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_, chunk_tile_, ch_tot_, xyz_, nrm_,
-                                              gf_, td_, b_);
+        if (!fixed) {
+            k_splat_chunks<kSplatF32><<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_, chunk_tile_,
+                                                             ch_tot_, xyz_, nrm_, gf_, td_, b_, nullptr, nullptr);
+        } else {
+            k_fixed_scale<<<1, 1, 0, st_>>>(nmax_, npts, grid_.h, fix_, err_);
+            if (fp64)
+                k_splat_chunks<kSplatFixed64><<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_,
+                                                                     chunk_tile_, ch_tot_, xyz_, nrm_, gf_, td_,
+                                                                     nullptr, acc, fix_);
+            else
+                k_splat_chunks<kSplatFixed><<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_,
+                                                                   chunk_tile_, ch_tot_, xyz_, nrm_, gf_, td_, nullptr,
+                                                                   acc, fix_);
+        }
+        WG_LAUNCH_CHECK();
+    } else if (fixed) {
+        k_fixed_scale<<<1, 1, 0, st_>>>(nmax_, 0, grid_.h, fix_, err_);
+        WG_LAUNCH_CHECK();
+    }
+    if (fixed) {
+        // b = sums * unit: FP32 always (the exported right-hand side), FP64 in place for WG_FP64
+        const unsigned gb = std::min<unsigned>(cdiv(N, 256), 4096u);
+        const long long *sums = reinterpret_cast<const long long *>(acc);
+        k_fixed_to_b<float><<<gb, 256, 0, st_>>>(sums, fix_, N, b_);
+        if (fp64) k_fixed_to_b<double><<<gb, 256, 0, st_>>>(sums, fix_, N, lam_);
         WG_LAUNCH_CHECK();
     }
     check_err("splat");
     tm.mark(1);
     n_points_ = npts;
-    SolveResult sr = solver_.solve(b_, chi_, WG_BC_NEUMANN, o);
+    SolveResult sr = fp64 ? solver_.solve(lam_, chi_, WG_BC_NEUMANN, o) : solver_.solve(b_, chi_, WG_BC_NEUMANN, o);
     if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the Poisson solve");
     chi_mean_ = sr.x_mean;
     tm.mark(2);
@@ -351,7 +393,7 @@ int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gn
     require(!field_only_, WG_ESTATE, "backward after wg_sdf_from_field (no point cloud to differentiate)");
     require(nq >= 0 && (nq == 0 || (q && gphi_q)), WG_EINVAL, "bad query arguments");
     require(n_points_ == 0 || (gxyz && gnrm_pts), WG_EINVAL, "null point-gradient outputs");
-    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    check_opts(o);
     const size_t N = d_.count();
     join();
     Timer tm(st_);
@@ -400,7 +442,7 @@ int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gn
 
 int Recon::poisson(const float *b, double *x, int bc, const wg_solve_opts &o, wg_stats *st) {
     require(b && x, WG_EINVAL, "null pointer");
-    require(o.reserved0 == 0 && o.reserved1 == 0, WG_EINVAL, "reserved solve options must be 0");
+    check_opts(o);
     Timer tm(st_);
     tm.mark(0);
     SolveResult sr = solver_.solve(b, x, bc, o);
@@ -447,7 +489,7 @@ int Recon::get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tri
     const int64_t T = surf_.n_tris();
     if (n_tris) *n_tris = T;
     const int64_t m = T < max_tris ? T : max_tris;
-    if (m > 0 && tris) surf_.export_tris(tris, (uint32_t)m);
+    if (m > 0 && tris) surf_.export_tris(chi_, scal_, tris, (uint32_t)m);
     if (m > 0 && info)
         WG_HIP(hipMemcpyAsync(info, surf_.tri_info(), (size_t)m * sizeof(int2), hipMemcpyDeviceToDevice, st_));
     return WG_OK;

@@ -52,6 +52,8 @@ class Solver {
     // Solve A x = b (x: FP64, initial guess if opts.warm_start).  The mean of
     // the Neumann solution is reported in x_mean, not removed from x.
     SolveResult solve(const float *b, double *x, int bc, const wg_solve_opts &o);
+    // the same with an FP64 right-hand side (WG_FP64)
+    SolveResult solve(const double *b, double *x, int bc, const wg_solve_opts &o);
 
     // x -= mean (FP64), used where a zero-mean field is promised.
     void shift(double *x, double by);
@@ -69,6 +71,7 @@ class Solver {
         float *rhs, *x, *x2;
     };
     int pk(int kind) const { return instrument_ ? kind : -1; }
+    template <class TB> SolveResult solve_impl(const TB *b, double *x, int bc, const wg_solve_opts &o);
     void vcycle(int l);
     void precond();
     unsigned rz_blocks() const;

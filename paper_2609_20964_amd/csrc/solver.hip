@@ -210,11 +210,12 @@ __global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, doub
 // r = (b - mb) - A x in FP64 (r stored FP32); sums of r, r^2, x, b - mb,
 // (b - mb)^2.  mb is the mean of b for zero-flux boundaries (the compatibility
 // projection of the right-hand side), 0 otherwise.
+template <class TB>
 struct OpResid64 {
     using T = double;
     static constexpr int NRED = 5;
     const double *x;
-    const float *b;
+    const TB *b;   // the right-hand side, FP32 or FP64
     float *r;
     const SolveScalars *sc;   // mean of b formed on the device (Neumann), or null (no shift)
     double mb;
@@ -233,7 +234,7 @@ struct OpResid64 {
     }
     __device__ void apply4(size_t i, const V4<double> &c, const V4<double> &s, const V4<double> &dg,
                            double *acc) const {
-        const V4<float> bb = ld4(b + i);
+        const V4<TB> bb = ld4(b + i);
         V4<float> out;
         for (int q = 0; q < 4; ++q) {
             const double bv = (double)bb.v[q] - mb;
@@ -346,7 +347,8 @@ struct OpPMatvec {
 };
 
 __device__ __forceinline__ void fetch_scalars(OpPMatvec<false> &op) { op.beta = (float)op.sc->beta; }
-__device__ __forceinline__ void fetch_scalars(OpResid64 &op) { op.mb = op.sc ? op.sc->mean_b : 0.0; }
+template <class TB>
+__device__ __forceinline__ void fetch_scalars(OpResid64<TB> &op) { op.mb = op.sc ? op.sc->mean_b : 0.0; }
 
 template <bool FIRST>
 __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float *__restrict__ r,
@@ -367,7 +369,8 @@ __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum(const float *__restrict__ x, size_t n, double *partials) {
+template <class TB>
+__global__ __launch_bounds__(256) void k_sum(const TB *__restrict__ x, size_t n, double *partials) {
     double acc[1] = {0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         acc[0] += (double)x[i];
@@ -1322,7 +1325,11 @@ int Solver::pcg(double tol, int max_it, double rr0) {
     return it;
 }
 
-SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts &o) {
+SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts &o) { return solve_impl(b, x, bc, o); }
+SolveResult Solver::solve(const double *b, double *x, int bc, const wg_solve_opts &o) { return solve_impl(b, x, bc, o); }
+
+template <class TB>
+SolveResult Solver::solve_impl(const TB *b, double *x, int bc, const wg_solve_opts &o) {
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
     bc_sign_ = bc == WG_BC_NEUMANN ? -1 : +1;
     for (int l = 0; l < nlv_; ++l) lv_[l].d.bc_sign = bc_sign_;
@@ -1341,7 +1348,7 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
     // Neumann: the residual kernel subtracts the mean of b, formed on the device
     const SolveScalars *mean_src = nullptr;
     if (bc == WG_BC_NEUMANN) {
-        k_sum<<<gb, kBlock, 0, st_>>>(b, N, partials_);
+        k_sum<TB><<<gb, kBlock, 0, st_>>>(b, N, partials_);
         WG_LAUNCH_CHECK();
         finalize(FIN_BSUM, gb, 0);
         mean_src = dsc_;
@@ -1350,7 +1357,8 @@ SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, pk(WG_PROF_RESID64), 16.0);
+        launch_stencil(OpResid64<TB>{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, pk(WG_PROF_RESID64),
+                       12.0 + sizeof(TB));
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;

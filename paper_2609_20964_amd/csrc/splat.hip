@@ -9,6 +9,7 @@
 // one along each axis.  Points are binned into 8^3-cell tiles; a workgroup
 // accumulates one tile's points in LDS and adds the window to b once.
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -18,34 +19,37 @@ namespace {
 
 // Per-axis data of one point: central cell k, fractional offset f in [0,1),
 // factors 1/2 (1 - |D|/2) of Eq. 25 for the offsets -1, 0, +1 (0 outside the
-// grid) and their x-derivatives -sign(D)/(4h).
+// grid) and their x-derivatives -sign(D)/(4h); in FP32 or (WG_FP64) FP64.
+template <class T>
 struct AxisW {
     int k;
-    float f;
-    float a[3];
-    float da[3];
+    T f;
+    T a[3];
+    T da[3];
 };
 
-__device__ __forceinline__ bool bin_axis(float x, double lo, double h, int n, AxisW &w, float inv4h) {
+template <class T>
+__device__ __forceinline__ bool bin_axis(float x, double lo, double h, int n, AxisW<T> &w, T inv4h) {
     double t = ((double)x - lo) / h;
     if (!(t >= 0.0 && t < (double)n)) return false;    // also rejects NaN
     int k = (int)floor(t);
     if (k >= n) return false;
     w.k = k;
-    w.f = (float)(t - (double)k);
+    w.f = (T)(t - (double)k);
     for (int d = -1; d <= 1; ++d) {
-        float D = w.f - 0.5f - (float)d;
+        T D = w.f - T(0.5) - (T)d;
         bool in = (k + d >= 0) && (k + d < n);
-        w.a[d + 1] = in ? 0.5f * (1.f - fabsf(D) * 0.5f) : 0.f;
-        float sg = D > 0.f ? 1.f : (D < 0.f ? -1.f : 0.f);
-        w.da[d + 1] = in ? -sg * inv4h : 0.f;
+        w.a[d + 1] = in ? T(0.5) * (T(1) - fabs(D) * T(0.5)) : T(0);
+        T sg = D > T(0) ? T(1) : (D < T(0) ? T(-1) : T(0));
+        w.da[d + 1] = in ? -sg * inv4h : T(0);
     }
     return true;
 }
 
-__device__ __forceinline__ float raw_w(const AxisW &X, const AxisW &Y, const AxisW &Z, int dx, int dy, int dz) {
-    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return 0.f;
-    if (dx == 0 && dy == 0 && dz == 0) return 0.5f;
+template <class T>
+__device__ __forceinline__ T raw_w(const AxisW<T> &X, const AxisW<T> &Y, const AxisW<T> &Z, int dx, int dy, int dz) {
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return T(0);
+    if (dx == 0 && dy == 0 && dz == 0) return T(0.5);
     return X.a[dx + 1] * Y.a[dy + 1] * Z.a[dz + 1];
 }
 
@@ -56,12 +60,14 @@ __device__ __forceinline__ bool in_range(int k, int o, int n) { return k + o >= 
 // Contributions of one point to b: calls emit(cx, cy, cz, value) for every
 // cell k + (cx, cy, cz) of the 81-cell support (|c| <= 2, at most one |c| = 2)
 // inside the grid.  value = -(h/2) h^-3 / S * sum_xi n_xi (face terms).
-template <class Emit>
-__device__ __forceinline__ void point_divergence(const AxisW &X, const AxisW &Y, const AxisW &Z, float n0, float n1,
-                                                 float n2, const GridF &g, Emit &&emit) {
-    const float Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
-    const float S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + 0.5f;     // Eq. 24 normaliser
-    const float coef = -0.5f * (float)g.h * (float)(1.0 / (g.h * g.h * g.h)) / S;
+// |value| <= 3.75 h^-2 max_k |n_k|: |h^-2 / (2 S)| <= h^-2 (S >= 1/2), and each
+// face term pairs two raw weights summing to at most 0.625.
+template <class T, class Emit>
+__device__ __forceinline__ void point_divergence(const AxisW<T> &X, const AxisW<T> &Y, const AxisW<T> &Z, T n0, T n1,
+                                                 T n2, const GridF &g, Emit &&emit) {
+    const T Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
+    const T S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + T(0.5);     // Eq. 24 normaliser
+    const T coef = T(-0.5) * (T)g.h * (T)(1.0 / (g.h * g.h * g.h)) / S;
 #pragma unroll
     for (int cz = -2; cz <= 2; ++cz)
 #pragma unroll
@@ -71,15 +77,15 @@ __device__ __forceinline__ void point_divergence(const AxisW &X, const AxisW &Y,
                 if ((cx == -2 || cx == 2) + (cy == -2 || cy == 2) + (cz == -2 || cz == 2) > 1) continue;
                 if (!in_range(X.k, cx, g.d.nx) || !in_range(Y.k, cy, g.d.ny) || !in_range(Z.k, cz, g.d.nz))
                     continue;
-                const float r0 = raw_w(X, Y, Z, cx, cy, cz);
-                float acc = 0.f;
+                const T r0 = raw_w(X, Y, Z, cx, cy, cz);
+                T acc = T(0);
                 if (in_range(X.k, cx + 1, g.d.nx)) acc += n0 * (r0 + raw_w(X, Y, Z, cx + 1, cy, cz));
                 if (in_range(X.k, cx - 1, g.d.nx)) acc -= n0 * (raw_w(X, Y, Z, cx - 1, cy, cz) + r0);
                 if (in_range(Y.k, cy + 1, g.d.ny)) acc += n1 * (r0 + raw_w(X, Y, Z, cx, cy + 1, cz));
                 if (in_range(Y.k, cy - 1, g.d.ny)) acc -= n1 * (raw_w(X, Y, Z, cx, cy - 1, cz) + r0);
                 if (in_range(Z.k, cz + 1, g.d.nz)) acc += n2 * (r0 + raw_w(X, Y, Z, cx, cy, cz + 1));
                 if (in_range(Z.k, cz - 1, g.d.nz)) acc -= n2 * (raw_w(X, Y, Z, cx, cy, cz - 1) + r0);
-                if (acc != 0.f) emit(cx, cy, cz, coef * acc);
+                if (acc != T(0)) emit(cx, cy, cz, coef * acc);
             }
 }
 
@@ -91,13 +97,20 @@ __global__ __launch_bounds__(256) void k_bin_points(const float *__restrict__ xy
                                                      int npts, GridF g, TileDims td, int32_t *__restrict__ keys,
                                                      float *__restrict__ xyz_c, float *__restrict__ nrm_c,
                                                      int32_t *__restrict__ tile_of, uint32_t *__restrict__ rank,
-                                                     uint32_t *__restrict__ tile_cnt, int *err) {
+                                                     uint32_t *__restrict__ tile_cnt, int *err,
+                                                     uint32_t *nmax_bits) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     const float x0 = xyz[3 * i], x1 = xyz[3 * i + 1], x2 = xyz[3 * i + 2];
     xyz_c[3 * i] = x0; xyz_c[3 * i + 1] = x1; xyz_c[3 * i + 2] = x2;
     nrm_c[3 * i] = nrm[3 * i]; nrm_c[3 * i + 1] = nrm[3 * i + 1]; nrm_c[3 * i + 2] = nrm[3 * i + 2];
-    AxisW X, Y, Z;
+    if (nmax_bits) {
+        // largest |normal component| as float bits (NaN and Inf order above every finite value)
+        uint32_t m = max(max(__float_as_uint(fabsf(nrm[3 * i])), __float_as_uint(fabsf(nrm[3 * i + 1]))),
+                         __float_as_uint(fabsf(nrm[3 * i + 2])));
+        atomicMax(nmax_bits, m);
+    }
+    AxisW<float> X, Y, Z;
     if (!bin_axis(x0, g.lo[0], g.h, g.d.nx, X, 0.f) || !bin_axis(x1, g.lo[1], g.h, g.d.ny, Y, 0.f) ||
         !bin_axis(x2, g.lo[2], g.h, g.d.nz, Z, 0.f)) {
         keys[i] = -1;
@@ -141,8 +154,15 @@ __global__ __launch_bounds__(256) void k_chunk_tiles(const uint32_t *__restrict_
 // F2 + F3: a workgroup takes chunks (at most kChunk points of one tile); the
 // points add their divergence contributions into a (kTile + 4)^3 window in
 // LDS (the support reaches two cells out), then each touched cell of the
-// window gets one atomic add into b.  b must be zero on entry.  The grid
-// strides over the chunks; their count is read on the device.
+// window gets one atomic add into the global sums.  The grid strides over the
+// chunks; their count is read on the device.  Modes:
+//   kSplatF32:   FP32 contributions, FP32 atomics into b (b zero on entry);
+//   kSplatFixed: FP32 contributions rounded to 64-bit fixed point (unit
+//                fix->inv), integer atomics into acc (zero on entry);
+//   kSplatFixed64: the same with FP64 weights and contributions.
+// Integer sums do not depend on the order the adds arrive in, so the fixed
+// point modes give the same acc however threads and workgroups interleave.
+template <int Mode>
 __global__ __launch_bounds__(256) void k_splat_chunks(const uint32_t *__restrict__ perm,
                                                        const uint32_t *__restrict__ tile_off,
                                                        const uint32_t *__restrict__ tile_cnt,
@@ -150,42 +170,91 @@ __global__ __launch_bounds__(256) void k_splat_chunks(const uint32_t *__restrict
                                                        const uint32_t *__restrict__ chunk_tile,
                                                        const uint32_t *__restrict__ n_chunks,
                                                        const float *__restrict__ xyz_c, const float *__restrict__ nrm_c,
-                                                       GridF g, TileDims td, float *__restrict__ b) {
-    constexpr int W = kTile + 4;
-    __shared__ float win[W * W * W];
+                                                       GridF g, TileDims td, float *__restrict__ b,
+                                                       unsigned long long *__restrict__ acc, const FixedScale *fix) {
+    using T = typename std::conditional<Mode == kSplatFixed64, double, float>::type;
+    using W = typename std::conditional<Mode == kSplatF32, float, unsigned long long>::type;
+    constexpr int WN = kTile + 4;
+    __shared__ W win[WN * WN * WN];
     const uint32_t total = n_chunks[0];
+    const double scale = Mode == kSplatF32 ? 0.0 : fix->scale;
     for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
         const uint32_t tile = chunk_tile[ch];
         const uint32_t c = ch - ch_off[tile];
         const uint32_t p0 = c * kChunk, p1 = min(p0 + kChunk, tile_cnt[tile]);
-        for (int l = threadIdx.x; l < W * W * W; l += blockDim.x) win[l] = 0.f;
+        for (int l = threadIdx.x; l < WN * WN * WN; l += blockDim.x) win[l] = W(0);
         __syncthreads();
         const int T0x = (int)(tile % td.tx) * kTile, T0y = (int)((tile / td.tx) % td.ty) * kTile,
                   T0z = (int)(tile / (td.tx * td.ty)) * kTile;
         const uint32_t off = tile_off[tile];
         for (uint32_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
             const uint32_t i = perm[off + p];
-            AxisW X, Y, Z;
-            bin_axis(xyz_c[3 * i], g.lo[0], g.h, g.d.nx, X, 0.f);
-            bin_axis(xyz_c[3 * i + 1], g.lo[1], g.h, g.d.ny, Y, 0.f);
-            bin_axis(xyz_c[3 * i + 2], g.lo[2], g.h, g.d.nz, Z, 0.f);
+            AxisW<T> X, Y, Z;
+            bin_axis(xyz_c[3 * i], g.lo[0], g.h, g.d.nx, X, T(0));
+            bin_axis(xyz_c[3 * i + 1], g.lo[1], g.h, g.d.ny, Y, T(0));
+            bin_axis(xyz_c[3 * i + 2], g.lo[2], g.h, g.d.nz, Z, T(0));
             const int lx = X.k - T0x + 2, ly = Y.k - T0y + 2, lz = Z.k - T0z + 2;
-            point_divergence(X, Y, Z, nrm_c[3 * i], nrm_c[3 * i + 1], nrm_c[3 * i + 2], g,
-                             [&](int cx, int cy, int cz, float v) {
-                                 atomicAdd(win + (lx + cx) + W * ((ly + cy) + W * (lz + cz)), v);
+            point_divergence(X, Y, Z, (T)nrm_c[3 * i], (T)nrm_c[3 * i + 1], (T)nrm_c[3 * i + 2], g,
+                             [&](int cx, int cy, int cz, T v) {
+                                 W *dst = win + (lx + cx) + WN * ((ly + cy) + WN * (lz + cz));
+                                 if constexpr (Mode == kSplatF32) atomicAdd(dst, v);
+                                 else atomicAdd(dst, (unsigned long long)__double2ll_rn((double)v * scale));
                              });
         }
         __syncthreads();
-        for (int l = threadIdx.x; l < W * W * W; l += blockDim.x) {
-            const float v = win[l];
-            if (v == 0.f) continue;
-            const int gx = T0x - 2 + l % W, gy = T0y - 2 + (l / W) % W, gz = T0z - 2 + l / (W * W);
+        for (int l = threadIdx.x; l < WN * WN * WN; l += blockDim.x) {
+            const W v = win[l];
+            if (v == W(0)) continue;
+            const int gx = T0x - 2 + l % WN, gy = T0y - 2 + (l / WN) % WN, gz = T0z - 2 + l / (WN * WN);
             // contributions only ever target cells inside the grid
-            unsafeAtomicAdd(b + (size_t)gx + (size_t)g.d.nx * (gy + (size_t)g.d.ny * gz), v);
+            const size_t o = (size_t)gx + (size_t)g.d.nx * (gy + (size_t)g.d.ny * gz);
+            if constexpr (Mode == kSplatF32) unsafeAtomicAdd(b + o, v);
+            else atomicAdd(acc + o, v);
         }
         __syncthreads();
     }
 }
+
+template __global__ void k_splat_chunks<kSplatF32>(const uint32_t *, const uint32_t *, const uint32_t *,
+                                                   const uint32_t *, const uint32_t *, const uint32_t *, const float *,
+                                                   const float *, GridF, TileDims, float *, unsigned long long *,
+                                                   const FixedScale *);
+template __global__ void k_splat_chunks<kSplatFixed>(const uint32_t *, const uint32_t *, const uint32_t *,
+                                                     const uint32_t *, const uint32_t *, const uint32_t *,
+                                                     const float *, const float *, GridF, TileDims, float *,
+                                                     unsigned long long *, const FixedScale *);
+template __global__ void k_splat_chunks<kSplatFixed64>(const uint32_t *, const uint32_t *, const uint32_t *,
+                                                       const uint32_t *, const uint32_t *, const uint32_t *,
+                                                       const float *, const float *, GridF, TileDims, float *,
+                                                       unsigned long long *, const FixedScale *);
+
+// The fixed-point unit of the deterministic splat: 2^-e with e the largest
+// exponent for which npts * 3.75 h^-2 max|n_k| (a bound on any cell's sum, see
+// point_divergence) stays below 2^61 in units.  A non-finite normal sets bit 2
+// of *err and leaves the scale 0.
+__global__ void k_fixed_scale(const uint32_t *nmax_bits, int npts, double h, FixedScale *fix, int *err) {
+    const uint32_t bits = *nmax_bits;
+    if (bits >= 0x7f800000u) {
+        atomicOr(err, 4);
+        fix->scale = fix->inv = 0.0;
+        return;
+    }
+    const double bound = (double)npts * 3.75 * (double)__uint_as_float(bits) / (h * h);
+    int e = 0;
+    if (bound > 0.0) e = 61 - (int)ceil(log2(bound));
+    fix->scale = ldexp(1.0, e);
+    fix->inv = ldexp(1.0, -e);
+}
+
+// b = acc * unit, as float or (in place over acc) as double.
+template <class T>
+__global__ __launch_bounds__(256) void k_fixed_to_b(const long long *acc, const FixedScale *fix, size_t n, T *b) {
+    const double inv = fix->inv;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (T)((double)acc[i] * inv);
+}
+template __global__ void k_fixed_to_b<float>(const long long *, const FixedScale *, size_t, float *);
+template __global__ void k_fixed_to_b<double>(const long long *, const FixedScale *, size_t, double *);
 
 namespace {
 
@@ -282,7 +351,7 @@ __global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, 
     const int kk[3] = {key % g.d.nx, (key / g.d.nx) % g.d.ny, key / (g.d.nx * g.d.ny)};
     const int nn[3] = {g.d.nx, g.d.ny, g.d.nz};
     const float inv4h = (float)(0.25 / g.h);
-    AxisW W[3];
+    AxisW<float> W[3];
     for (int a = 0; a < 3; ++a) {
         double t = ((double)xv[a] - g.lo[a]) / g.h;
         W[a].k = kk[a];
@@ -295,7 +364,7 @@ __global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, 
             W[a].da[d + 1] = in ? -sg * inv4h : 0.f;
         }
     }
-    const AxisW &X = W[0], &Y = W[1], &Z = W[2];
+    const AxisW<float> &X = W[0], &Y = W[1], &Z = W[2];
     const float Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
     const float S = Sx * Sy * Sz - X.a[1] * Y.a[1] * Z.a[1] + 0.5f;
     const float dSx = (X.da[0] + X.da[1] + X.da[2]) * Sy * Sz - X.da[1] * Y.a[1] * Z.a[1];

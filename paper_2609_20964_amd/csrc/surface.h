@@ -54,8 +54,9 @@ class Surface {
                float *g_chi, double *g_c);
 
     uint32_t n_tris() const { return cnt_.n_tris; }
-    // first n triangles as float[9] (vertices in grid units)
-    void export_tris(float *out, uint32_t n);
+    // first n triangles as float[9] (vertices in grid units), rebuilt from the
+    // field chi and iso-value *c the mesh was extracted from
+    void export_tris(const double *chi, const double *c, float *out, uint32_t n);
     // persistent = true (default): the distance walk runs as many workgroups
     // as fit on the device at once, less a few free slots for the other
     // streams' work, each taking tiles from a queue (no tail).

@@ -238,6 +238,34 @@ __global__ __launch_bounds__(256) void k_mc_emit(const double *__restrict__ chi,
             ab[k] = (float)(V[1][k] - V[0][k]);
             ac[k] = (float)(V[2][k] - V[0][k]);
         }
+        {
+            // A zero-area triangle (a vertex on a cube corner: chi = c there) is
+            // a segment or a point.  Store it as (P, Q, P), P and Q its two
+            // vertices farthest apart: with ac = 0 the walk's Voronoi tests
+            // give the exact nearest point of PQ (see tri_d2).  The mesh export
+            // and the reverse pass rebuild the vertices from chi and the edge
+            // ids, so they still see the three Marching Cubes vertices.
+            const double cx = (double)ab[1] * ac[2] - (double)ab[2] * ac[1];
+            const double cy = (double)ab[2] * ac[0] - (double)ab[0] * ac[2];
+            const double cz = (double)ab[0] * ac[1] - (double)ab[1] * ac[0];
+            if (cx * cx + cy * cy + cz * cz == 0.0) {
+                double l2[3] = {0, 0, 0};   // |ab|^2, |ac|^2, |bc|^2
+                for (int k = 0; k < 3; ++k) {
+                    l2[0] += (double)ab[k] * ab[k];
+                    l2[1] += (double)ac[k] * ac[k];
+                    l2[2] += ((double)ac[k] - ab[k]) * ((double)ac[k] - ab[k]);
+                }
+                for (int k = 0; k < 3; ++k) {
+                    if (l2[2] > l2[0] && l2[2] > l2[1]) {   // b -> c
+                        a[k] = (float)V[1][k];
+                        ab[k] = (float)(V[2][k] - V[1][k]);
+                    } else if (l2[1] > l2[0]) {               // a -> c
+                        ab[k] = ac[k];
+                    }
+                    ac[k] = 0.f;
+                }
+            }
+        }
         double aa = 0, bc = 0, cc = 0, ee = 0;
         for (int k = 0; k < 3; ++k) {
             aa += (double)ab[k] * ab[k];
@@ -368,15 +396,28 @@ __global__ __launch_bounds__(256) void k_parent_nodes(float4 *__restrict__ nodes
     nd[1] = make_float4(hi.x, hi.y, hi.z, 0.f);
 }
 
-// Mesh export: vertices a, a + ab, a + ac as float[9] per triangle.
-__global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ tri, uint32_t n, float *__restrict__ out) {
+// Mesh export: the three Marching Cubes vertices of each triangle (Eq. 28),
+// rebuilt in FP64 from chi and the triangle's cube and edge ids as k_mc_emit
+// formed them, as float[9] (the walk's records can hold a zero-area triangle
+// as a segment).
+__global__ __launch_bounds__(256) void k_export_tris(const double *__restrict__ chi, const double *iso, Dims d,
+                                                      const int2 *__restrict__ info, uint32_t n, float *__restrict__ out) {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    float4 A = tri[kTri * (size_t)t], B = tri[kTri * (size_t)t + 1], C = tri[kTri * (size_t)t + 2];
+    const double c = iso[0];
+    const size_t sy = d.nx, sz = (size_t)d.nx * d.ny;
+    const int2 inf = info[t];
+    const int ci = inf.x % d.nx, cj = (inf.x / d.nx) % d.ny, ck = inf.x / (int)sz;
     float *o = out + 9 * (size_t)t;
-    o[0] = A.x; o[1] = A.y; o[2] = A.z;
-    o[3] = A.x + B.x; o[4] = A.y + B.y; o[5] = A.z + B.z;
-    o[6] = A.x + C.x; o[7] = A.y + C.y; o[8] = A.z + C.z;
+    for (int q = 0; q < 3; ++q) {
+        int b0, b1, ax;
+        edge_ends((inf.y >> (4 * q)) & 15, b0, b1, ax);
+        const double x1 = chi[(size_t)inf.x + (b0 & 1) + sy * ((b0 >> 1) & 1) + sz * (b0 >> 2)];
+        const double x2 = chi[(size_t)inf.x + (b1 & 1) + sy * ((b1 >> 1) & 1) + sz * (b1 >> 2)];
+        double v[3] = {(double)(ci + (b0 & 1)), (double)(cj + ((b0 >> 1) & 1)), (double)(ck + (b0 >> 2))};
+        v[ax] += (c - x1) / (x2 - x1);
+        for (int k = 0; k < 3; ++k) o[3 * q + k] = (float)v[k];
+    }
 }
 
 // Closest point of a triangle to p by Voronoi-region classification (Ericson,
@@ -388,10 +429,9 @@ __global__ __launch_bounds__(256) void k_export_tris(const float4 *__restrict__ 
 // R, so a region costs one or two multiplications.  The regions are tested in
 // the method's order (vertices, edges, face interior); neighbouring nodes of a
 // wavefront mostly share a region, so the branches rarely diverge.  A
-// zero-area triangle (R.w = 0: a vertex of Marching Cubes landed exactly on a
-// cube corner) is a segment or a point: its nearest point is the nearest one
-// on its three edges (the Voronoi tests assume a proper triangle there).  The
-// walk takes one triangle for the whole wavefront, so that branch is uniform.
+// zero-area triangle is stored as the segment (P, Q, P) (see k_mc_emit): with
+// ac = 0, d2 = d4 = d6 = 0 and vc = 0 exactly, so the vertex tests and the ab
+// edge test alone decide it, and they give the exact nearest point of PQ.
 // Returns the squared distance; (v, w) are the barycentric weights of b and c
 // at the closest point.
 __device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, float4 B, float4 C, float4 R,
@@ -401,23 +441,6 @@ __device__ __forceinline__ float tri_d2(float px, float py, float pz, float4 A, 
     const float d2 = C.x * apx + C.y * apy + C.z * apz;
     const float d3 = d1 - A.w, d4 = d2 - B.w;   // against p - b
     const float d5 = d1 - B.w, d6 = d2 - C.w;   // against p - c
-    if (R.w == 0.f) {
-        // nearest of the edges ab (parameter d1 / |ab|^2), ac (d2 / |ac|^2) and
-        // bc ((d4 - d3) / |bc|^2), each clamped to the segment
-        v = fminf(fmaxf(d1 * R.x, 0.f), 1.f);
-        w = 0.f;
-        float qx = apx - v * B.x, qy = apy - v * B.y, qz = apz - v * B.z;
-        float best = qx * qx + qy * qy + qz * qz;
-        float t = fminf(fmaxf(d2 * R.y, 0.f), 1.f);
-        qx = apx - t * C.x; qy = apy - t * C.y; qz = apz - t * C.z;
-        float dd = qx * qx + qy * qy + qz * qz;
-        if (dd < best) { best = dd; v = 0.f; w = t; }
-        t = fminf(fmaxf((d4 - d3) * R.z, 0.f), 1.f);
-        qx = apx - (1.f - t) * B.x - t * C.x; qy = apy - (1.f - t) * B.y - t * C.y; qz = apz - (1.f - t) * B.z - t * C.z;
-        dd = qx * qx + qy * qy + qz * qz;
-        if (dd < best) { best = dd; v = 1.f - t; w = t; }
-        return best;
-    }
     const float vc = d1 * d4 - d3 * d2;
     const float vb = d5 * d2 - d1 * d6;
     const float va = d3 * d6 - d5 * d4;
@@ -487,16 +510,6 @@ __device__ __forceinline__ float box_d2(float4 lo, float4 hi, float px, float py
     const float dy = fmaxf(fmaxf(lo.y - py, py - hi.y), 0.f);
     const float dz = fmaxf(fmaxf(lo.z - pz, pz - hi.z), 0.f);
     return dx * dx + dy * dy + dz * dz;
-}
-
-// Squared distance from p to an oriented leaf box (centre and half extents in
-// N0, axes in N1..N3, the half extents of v and n in N1.w, N2.w).
-__device__ __forceinline__ float obb_d2(float4 N0, float4 N1, float4 N2, float4 N3, float px, float py, float pz) {
-    const float rx = px - N0.x, ry = py - N0.y, rz = pz - N0.z;
-    const float du = fmaxf(fabsf(N1.x * rx + N1.y * ry + N1.z * rz) - N0.w, 0.f);
-    const float dv = fmaxf(fabsf(N2.x * rx + N2.y * ry + N2.z * rz) - N1.w, 0.f);
-    const float dn = fmaxf(fabsf(N3.x * rx + N3.y * ry + N3.z * rz) - N2.w, 0.f);
-    return du * du + dv * dv + dn * dn;
 }
 
 // Levels of the hierarchy as the seed search indexes them: node `local` of
@@ -1415,9 +1428,9 @@ void Surface::sdf_T(const float *gphi, const double *chi, const double *c, const
     WG_LAUNCH_CHECK();
 }
 
-void Surface::export_tris(float *out, uint32_t n) {
+void Surface::export_tris(const double *chi, const double *c, float *out, uint32_t n) {
     if (n == 0) return;
-    k_export_tris<<<cdiv(n, 256), 256, 0, st_>>>(tri_, n, out);
+    k_export_tris<<<cdiv(n, 256), 256, 0, st_>>>(chi, c, d_, info_, n, out);
     WG_LAUNCH_CHECK();
 }
 

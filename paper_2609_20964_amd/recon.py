@@ -28,6 +28,13 @@ def _dev(t, dtype, shape_last=None, name="tensor"):
     return C.c_void_p(t.data_ptr())
 
 
+def _precision(p):
+    codes = {"fp32": L.WG_FP32_FP64REDUCE, "fp64": L.WG_FP64}
+    if p not in codes:
+        raise ValueError(f"precision must be one of {sorted(codes)}")
+    return codes[p]
+
+
 class Recon:
     """One reconstruction grid resident on the current CUDA device.
 
@@ -80,15 +87,21 @@ class Recon:
         return self._h
 
     # -- forward ---------------------------------------------------------------
-    def forward(self, xyz, nrm, rel_tol=1e-6, max_iters=500, warm_start=False):
-        """Splat, solve, extract, distance (F1-F7).  Returns the stats dict."""
+    def forward(self, xyz, nrm, rel_tol=1e-6, max_iters=500, warm_start=False, precision="fp32",
+                deterministic=False):
+        """Splat, solve, extract, distance (F1-F7).  Returns the stats dict.
+
+        precision "fp32" (FP32 splat, FP32 sweeps, FP64 reductions and
+        refinement) or "fp64" (the right-hand side in FP64, summed exactly);
+        deterministic: the splat sums in 64-bit fixed point, so b, chi and phi
+        do not depend on the order points and threads are taken in."""
         npts = int(xyz.shape[0])
         px = _dev(xyz, torch.float32, 3, "xyz")
         pn = _dev(nrm, torch.float32, 3, "nrm")
         if nrm.shape[0] != npts:
             raise ValueError("xyz and nrm differ in length")
         st = L.WgStats()
-        o = L.make_opts(rel_tol, max_iters, warm_start)
+        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic)
         rc = L.check(L.lib().wg_recon_forward(self._alive(), px, pn, npts, C.byref(o), C.byref(st)),
                      allow=(L.WG_OK, L.WG_ENOTCONV))
         if rc == L.WG_ENOTCONV:
@@ -122,7 +135,8 @@ class Recon:
                                               C.c_void_p(nrm.data_ptr()) if nrm is not None else None))
         return phi, nrm
 
-    def step(self, xyz, nrm, q, rel_tol=1e-6, max_iters=500, warm_start=True, normals=True):
+    def step(self, xyz, nrm, q, rel_tol=1e-6, max_iters=500, warm_start=True, normals=True, precision="fp32",
+             deterministic=False):
         """Pipelined forward + sampling for moving-boundary loops (wg_recon_step):
         returns (stats, phi [Q], nrm [Q,3] or None) once the surface is extracted;
         the distance walk and the sampling finish on the handle's second stream
@@ -136,7 +150,7 @@ class Recon:
         phi = torch.empty(nq, dtype=torch.float32, device=q.device)
         nout = torch.empty((nq, 3), dtype=torch.float32, device=q.device) if normals else None
         st = L.WgStats()
-        o = L.make_opts(rel_tol, max_iters, warm_start)
+        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic)
         rc = L.check(L.lib().wg_recon_step(self._alive(), px, pn, npts, pq, nq, C.c_void_p(phi.data_ptr()),
                                            C.c_void_p(nout.data_ptr()) if nout is not None else None,
                                            C.byref(o), C.byref(st)), allow=(L.WG_OK, L.WG_ENOTCONV))
@@ -231,8 +245,9 @@ class Recon:
 
 class _ReconFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xyz, nrm, q, recon, rel_tol, max_iters, warm_start):
-        recon.forward(xyz.detach().contiguous(), nrm.detach().contiguous(), rel_tol, max_iters, warm_start)
+    def forward(ctx, xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic):
+        recon.forward(xyz.detach().contiguous(), nrm.detach().contiguous(), rel_tol, max_iters, warm_start, precision,
+                      deterministic)
         phi, n = recon.sample(q.detach().contiguous())
         ctx.recon = recon
         ctx.generation = recon.generation
@@ -251,11 +266,12 @@ class _ReconFn(torch.autograd.Function):
         gx, gnp, gq = r.backward(q.detach().contiguous(), gphi.contiguous(),
                                  gn.contiguous() if gn is not None else None,
                                  want_gq=ctx.needs_input_grad[2], rel_tol=ctx.rel_tol, max_iters=ctx.max_iters)
-        return gx, gnp, gq, None, None, None, None
+        return gx, gnp, gq, None, None, None, None, None, None
 
 
-def reconstruct(xyz, nrm, q, recon: Recon, rel_tol=1e-6, max_iters=500, warm_start=False):
+def reconstruct(xyz, nrm, q, recon: Recon, rel_tol=1e-6, max_iters=500, warm_start=False, precision="fp32",
+                deterministic=False):
     """Differentiable SDF and normals at q from the oriented cloud (xyz, nrm).
 
     Gradients flow to xyz, nrm and q through the library's adjoint."""
-    return _ReconFn.apply(xyz, nrm, q, recon, rel_tol, max_iters, warm_start)
+    return _ReconFn.apply(xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic)

@@ -33,11 +33,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=None):
+def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=None, tol_field=1e-5, **mode):
     from paper_2609_20964_amd.recon import Recon
     ref = P.Recon(grid, x, n)
     r = Recon(grid.n, len(x), lo=grid.lo, h=grid.h)
-    st = r.forward(_cuda(x), _cuda(n), rel_tol=tol_res, max_iters=5000)
+    st = r.forward(_cuda(x), _cuda(n), rel_tol=tol_res, max_iters=5000, **mode)
     print("stats", {k: st[k] for k in ("iters", "refinements", "rel_res", "n_tris", "iso_c")}, flush=True)
     assert st["status"] == 0 and st["rel_res"] <= tol_res
     f = r.fields()
@@ -49,7 +49,8 @@ def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=Non
     # F4: field, both zero mean
     chi = f["chi"].cpu().numpy()
     assert abs(chi.mean()) <= 1e-12 * np.abs(chi).max()
-    assert _rel(chi, ref.chi) <= 1e-5
+    print(f"field rel err {_rel(chi, ref.chi):.2e}", flush=True)
+    assert _rel(chi, ref.chi) <= tol_field
     # F5: iso-value
     assert abs(st["iso_c"] - ref.c) <= 1e-5 * np.abs(ref.chi).max()
     # F6: same triangles (matched by cube and local edges), vertices within 1e-5 cells
@@ -250,6 +251,53 @@ def test_exact_ties_give_zero_area_triangles():
     r.close()
 
 
+def test_precision_fp64_field_within_1e8():
+    """WG_FP64: splat weights and the divergence in FP64, summed in 64-bit fixed
+    point; solved to rel. res 1e-12 the field matches the oracle within 1e-8
+    (kappa ~ 1.2e3 at 32^3, 5e3 at 64^3), and every other output to the usual
+    tolerances."""
+    g = D.Grid.unit(32)
+    x, n = synth.sphere()
+    q = synth.uniform_queries(4096, 102)
+    _forward_parity(g, x, n, q, tol_res=1e-12, tol_field=1e-8, precision="fp64")
+    g = D.Grid.unit(64)
+    x, n = synth.torus(n_points=30000)
+    q = synth.uniform_queries(3000, 205)
+    rng = np.random.default_rng(206)
+    _forward_parity(g, x, n, q, tol_res=1e-12, tol_field=1e-8, precision="fp64", full_phi=False,
+                    node_sample=rng.choice(64 ** 3, 3000, replace=False))
+
+
+def test_deterministic_splat_is_order_independent():
+    """deterministic=1: the same cloud in two different point orders gives the
+    same b, chi, iso-value, mesh and phi bit for bit (64-bit fixed-point sums do
+    not depend on the order of the adds), and matches the oracle like the FP32
+    path.  Also in WG_FP64."""
+    from paper_2609_20964_amd.recon import Recon
+    g = D.Grid.unit(48)
+    x, n = synth.torus(n_points=60000)
+    perm = np.random.default_rng(31).permutation(len(x))
+    q = synth.uniform_queries(3000, 32)
+    _forward_parity(g, x, n, q, full_phi=False, node_sample=np.random.default_rng(33).choice(48 ** 3, 2000,
+                                                                                                replace=False),
+                    deterministic=True)
+    for prec in ("fp32", "fp64"):
+        outs = []
+        for order in (np.arange(len(x)), perm):
+            r = Recon(48, len(x))
+            st = r.forward(_cuda(x[order]), _cuda(n[order]), rel_tol=1e-10, max_iters=5000, precision=prec,
+                           deterministic=True)
+            f = {k: v.cpu().numpy() for k, v in r.fields().items()}
+            f["iso_c"], f["n_tris"] = st["iso_c"], st["n_tris"]
+            f["keys"] = f["keys"][np.argsort(order)]
+            outs.append(f)
+            r.close()
+        a, b = outs
+        for k in ("b", "chi", "phi", "keys"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+        assert a["iso_c"] == b["iso_c"] and a["n_tris"] == b["n_tris"]
+
+
 def test_iteration_cap_reports_not_converged():
     from paper_2609_20964_amd.recon import Recon
     g = D.Grid.unit(32)
@@ -261,23 +309,31 @@ def test_iteration_cap_reports_not_converged():
     r.close()
 
 
-def test_warm_start_reaches_same_field():
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_warm_start_reaches_same_field(deterministic):
     from paper_2609_20964_amd.recon import Recon
     fl = synth.Flapping(n_points=20000)
     r = Recon(32, 20000)
     x0, n0 = fl.step(0)
-    r.forward(_cuda(x0), _cuda(n0), rel_tol=1e-10)
+    r.forward(_cuda(x0), _cuda(n0), rel_tol=1e-10, deterministic=deterministic)
     x1, n1 = fl.step(1)
-    st_w = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=True)
-    chi_w = r.fields()["chi"].cpu().numpy()
-    st_c = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=False)
-    chi_c = r.fields()["chi"].cpu().numpy()
+    st_w = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=True, deterministic=deterministic)
+    f_w = r.fields()
+    chi_w, b_w = f_w["chi"].cpu().numpy(), f_w["b"].cpu().numpy()
+    st_c = r.forward(_cuda(x1), _cuda(n1), rel_tol=1e-10, warm_start=False, deterministic=deterministic)
+    f_c = r.fields()
+    chi_c, b_c = f_c["chi"].cpu().numpy(), f_c["b"].cpu().numpy()
     # both solves stop at rel. residual 1e-10, so each field is within
     # kappa(A) * 1e-10 of the exact one (kappa ~ 12 n^2 / pi^2 on the zero-mean
-    # subspace); the two passes also re-splat b with FP32 atomics in a
-    # different order, which moves b (and chi) by ~1e-7 relative
+    # subspace).  With FP32 atomics the two passes also re-splat b in a
+    # different order, which moves b (and chi) by ~1e-7 relative; the
+    # deterministic splat gives the same b bit for bit, so no slack is added.
     kappa = 12 * 32 ** 2 / math.pi ** 2
-    assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10 + 1e-6
+    if deterministic:
+        assert np.array_equal(b_w, b_c)
+        assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10
+    else:
+        assert _rel(chi_w, chi_c) <= 2 * kappa * 1e-10 + 1e-6
     assert st_w["iters"] <= st_c["iters"]
     r.close()
 

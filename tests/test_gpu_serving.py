@@ -81,6 +81,40 @@ def test_alone_equals_in_the_mix():
     srv.close()
 
 
+def test_deterministic_requests_alone_equal_mix_bit_for_bit():
+    """deterministic=1: each request served in the mix (four slots, persistent
+    and non-persistent walks) gives the SDF and normals of the same request run
+    alone, bit for bit; the reverse pass (FP32 atomics) within 1e-3."""
+    from paper_2609_20964_amd.recon import Recon
+    from paper_2609_20964_amd.serving import Server
+    reqs = _requests()
+    alone = []
+    for n, x, nn, q, grad in reqs:
+        r = Recon(n, len(x))
+        r.forward(_cuda(x), _cuda(nn), rel_tol=1e-10, max_iters=5000, deterministic=True)
+        phi, nq = r.sample(_cuda(q))
+        res = {"phi": phi.cpu().numpy(), "nrm": nq.cpu().numpy()}
+        if grad:
+            gphi = 2.0 * phi / len(q)
+            gx, gn, _ = r.backward(_cuda(q), gphi.contiguous(), rel_tol=1e-10, max_iters=5000)
+            res["gphi"], res["g_xyz"], res["g_nrm"] = gphi, gx.cpu().numpy(), gn.cpu().numpy()
+        alone.append(res)
+        r.close()
+    srv = Server(hbm_budget_bytes=8 << 30, max_inflight=4)
+    tickets = [srv.submit(n, _cuda(x), _cuda(nn), _cuda(q), gphi=a.get("gphi"), rel_tol=1e-10, max_iters=5000,
+                          deterministic=True) for (n, x, nn, q, grad), a in zip(reqs, alone)]
+    results = _wait(srv, tickets)
+    srv.close()
+    for (n, x, nn, q, grad), a, (st, outs, info) in zip(reqs, alone, results):
+        assert st == 0, info
+        assert np.array_equal(outs["phi"].cpu().numpy(), a["phi"])
+        assert np.array_equal(outs["nrm"].cpu().numpy(), a["nrm"])
+        if grad:
+            for k in ("g_xyz", "g_nrm"):
+                got, want = outs[k].cpu().numpy(), a[k]
+                assert np.linalg.norm(got - want) <= 1e-3 * np.linalg.norm(want)
+
+
 def test_admission_by_footprint_and_rejection():
     from paper_2609_20964_amd._lib import WG_ENOMEM, WgError
     from paper_2609_20964_amd.recon import Recon
