@@ -116,10 +116,14 @@ typedef struct wg_server wg_server;
  * Reconstruction handle
  * ------------------------------------------------------------------------- */
 
-/* Allocate the resident state for one grid and up to max_points points
- * (splat buffers, FP64 solution, solver and multigrid vectors, SDF grid,
- * surface buffers).  hip_stream: a hipStream_t (NULL = default stream).
- * Returns WG_EINVAL for n[d] < 4 or h <= 0, WG_ENOMEM if allocation fails. */
+/* Allocate the resident state for one uniform grid of n[0] x n[1] x n[2]
+ * cubic cells of edge h from lo (Sec. 2.3: the domain discretised by l x m x n
+ * cells of size h, one unknown per cell, Eq. 16-17) and up to max_points
+ * points (splat buffers, FP64 solution, solver and multigrid vectors, SDF
+ * grid, surface buffers).  hip_stream: a hipStream_t (NULL = default stream),
+ * on which every call on the handle enqueues its work.  The caller owns *out
+ * and frees it with wg_recon_destroy.  Returns WG_EINVAL for n[d] < 4, h <= 0
+ * or more than 2^31 cells, WG_ENOMEM if allocation fails. */
 int wg_recon_create(wg_recon **out, const wg_grid *grid, int max_points, void *hip_stream);
 
 /* Footprint (bytes) that wg_recon_create would allocate. */
@@ -135,11 +139,16 @@ size_t wg_recon_footprint(const wg_grid *grid, int max_points);
 int wg_recon_forward(wg_recon *r, const float *d_xyz, const float *d_nrm, int n_points,
                      const wg_solve_opts *opts, wg_stats *stats);
 
-/* Sample the last forward's SDF at n_q query points (trilinear in the node
- * values) and the unit normal grad(phi)/|grad(phi)| (grid central differences,
- * one-sided on boundary cells, interpolated trilinearly; 0 where the gradient
- * vanishes).  d_q: [n_q][3]; d_phi: [n_q]; d_nrm_out: [n_q][3] or NULL.
- * Queries outside the grid's cell-centre box are clamped to it. */
+/* Sample the last forward's SDF at n_q query points and the surface normal
+ * there (Sec. 2.4: phi is a grid field, Eq. 34, whose normal is
+ * grad(phi)/|grad(phi)| as after Eq. 32): phi(q) trilinear in the node values,
+ * the normal from grid central differences (one-sided on boundary cells)
+ * interpolated trilinearly and normalised (0 where the gradient vanishes).
+ * d_q: [n_q][3] float32 (read); d_phi: [n_q] and d_nrm_out: [n_q][3] or NULL
+ * (written); all caller-owned device memory.  Queries outside the grid's
+ * cell-centre box are clamped to it.  WG_ESTATE before a forward,
+ * WG_EINVAL for n_q < 0 or a null pointer with n_q > 0.  Enqueued on the
+ * handle's stream (after the last pipelined walk); does not block. */
 int wg_sample_sdf_normals(wg_recon *r, const float *d_q, int n_q, float *d_phi, float *d_nrm_out);
 
 /* Forward reconstruction followed by sampling at d_q, pipelined with the next
@@ -220,10 +229,13 @@ int wg_mg_apply(wg_recon *r, const float *d_r, float *d_z, int bc);
  * and ms[4] (distance).  Host-synchronising like wg_recon_forward. */
 int wg_sdf_from_field(wg_recon *r, const double *d_chi, double c, wg_stats *stats);
 
-/* Copies of resident fields from the last forward: d_b float32 [N] (the
- * right-hand side), d_chi float64 [N] (zero mean), d_phi float32 [N],
- * d_keys int32 [n_points] (linear central-cell index i + n0 (j + n1 k)).
- * Any pointer may be NULL. */
+/* Copies of resident fields from the last forward into caller-owned device
+ * buffers: d_b float32 [N] (the right-hand side b of Eq. 20, as Eq. 26 forms
+ * it), d_chi float64 [N] (the coefficients a of Eq. 16, zero mean), d_phi
+ * float32 [N] (the signed distance of Eq. 34 at the cell centres), d_keys
+ * int32 [n_points] (each point's central cell of the 27-cell stencil of
+ * Eq. 24-25, linear index i + n0 (j + n1 k)).  Any pointer may be NULL.
+ * WG_ESTATE before a forward.  Enqueued on the handle's stream. */
 int wg_get_fields(wg_recon *r, float *d_b, double *d_chi, float *d_phi, int32_t *d_keys);
 
 /* Copy of the last forward's triangles: d_tris float32 [n_tris][9] (three
