@@ -40,7 +40,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VALU_TFLOPS = 157.3       # MI355X FP32 vector peak
+FP32_VALU_TFLOPS = 157.3       # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+FP32_UNPACKED_TFLOPS = 78.6    # the same without packed FP32 (the library is built with packed FP32 off)
+
+# FP32 operations of one test of the distance walk, counted from its formulas
+# (every FP32 VALU operation, min / max / abs included, as they issue at the
+# same rate; comparisons, selects and the stack bookkeeping not counted).  A
+# lane's kTZ nodes share x and y, so part of each test is done once per lane
+# and part once per node: (shared, per node).  Node-triangle test (tri_d2):
+# shared p - a in x and y and the x, y parts of ab.ap and ac.ap (2 + 3 + 3);
+# per node the z parts (1 + 2 + 2), the offsets d3..d6 (4), the three region
+# determinants (3 x 3), the barycentric weights (2), the closest-point offset
+# ap - v ab - w ac (12) and its squared length (5).  Axis-aligned box: shared
+# the clamped x and y distances and their squares (11), per node the z
+# distance and the sum (7).  Oriented box: shared the offsets and the three
+# in-plane projections (17), per node three clamped distances and the sum (18).
+WALK_OPS = {"tri": (8.0, 37.0), "aabb": (11.0, 7.0), "obb": (17.0, 18.0)}
+
+
+def walk_flops(counts, ktz):
+    """Algorithmic FP32 operations of the walk from its counted tests."""
+    per_node = {k: sh / ktz + pn for k, (sh, pn) in WALK_OPS.items()}
+    return (counts["tri_tests"] * per_node["tri"] + counts["aabb_tests"] * per_node["aabb"]
+            + counts["obb_tests"] * per_node["obb"])
 
 
 def angle_between(a, b):
@@ -92,6 +114,7 @@ def gpu_run(args):
         r.sample(q)
     torch.cuda.synchronize()
     per_kind = {k: _lib.profile_read(k) for k in kinds}
+    walk_plain = _lib.profile_walk_counts()
     dominant = max(per_kind, key=lambda k: per_kind[k]["ms"])
     log("plain-step kernel time by kind (ms):", {k: round(v["ms"], 3) for k, v in per_kind.items()})
     _lib.profile_enable([])
@@ -112,6 +135,7 @@ def gpu_run(args):
     t1 = time.perf_counter()
     _lib.profile_enable([])
     prof = _lib.profile_read(dominant)
+    walk_timed = _lib.profile_walk_counts()
     elapsed = t1 - t0
 
     # the same loop without pipelining (forward, then sample), for reference
@@ -159,7 +183,8 @@ def gpu_run(args):
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
-            "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof}
+            "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof,
+            "walk_timed": walk_timed, "walk_plain": walk_plain, "walk_ktz": 4 if n ** 3 >= 1 << 23 else 1}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -212,15 +237,19 @@ def roofline(res):
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     else:
-        # distance walk: FP32 operations per node (counted once with rocprofv3
-        # for this workload) x nodes per launch / event-timed launch duration
-        fpn = pmc.get("fp32_flops_per_unit")
-        achieved = fpn * per_launch / avg_s / 1e12 if fpn else None
+        # distance walk: FP32 operations of the tests it counted on the device
+        # during these launches, over the event-timed launch duration
+        counts, ktz = res["walk_timed"], res["walk_ktz"]
+        flops = walk_flops(counts, ktz) / p["launches"]
+        achieved = flops / avg_s / 1e12
+        nodes = max(counts["nodes"], 1)
         out = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-               "frac": achieved / FP32_VALU_TFLOPS if achieved else None, "traffic": traffic,
-               "nodes_per_s": per_launch / avg_s}
-        if pmc.get("valu_issue_frac") is not None:
-            out["valu_issue_frac"] = pmc["valu_issue_frac"]
+               "frac": achieved / FP32_VALU_TFLOPS, "traffic": traffic,
+               "peak_unpacked": FP32_UNPACKED_TFLOPS, "frac_unpacked": achieved / FP32_UNPACKED_TFLOPS,
+               "flops_per_launch": flops, "flops_per_node": flops / per_launch, "nodes_per_s": per_launch / avg_s,
+               "tests_per_node": {"triangle": counts["tri_tests"] / nodes, "aabb": counts["aabb_tests"] / nodes,
+                                  "obb": counts["obb_tests"] / nodes},
+               "valu_lane_util": pmc.get("valu_lane_util")}
     out.update({"kernel": KIND_KERNEL[kind], "launches": p["launches"], "avg_launch_us": avg_s * 1e6,
                 "units_per_launch": per_launch})
     # the same kernel in the plain (not overlapped) profiled steps: in the timed
@@ -228,22 +257,45 @@ def roofline(res):
     a = res["per_kind"].get(kind)
     if a and a["launches"] > 0 and a["ms"] > 0:
         avg_a = a["ms"] / a["launches"] / 1e3
-        frac_a = (out["frac"] * avg_s / avg_a) if out.get("frac") else None
-        out["alone"] = {"launches": a["launches"], "avg_launch_us": avg_a * 1e6, "frac": frac_a}
+        alone = {"launches": a["launches"], "avg_launch_us": avg_a * 1e6}
+        if out["bound"] == "alu":
+            fl = walk_flops(res["walk_plain"], res["walk_ktz"]) / a["launches"]
+            alone.update({"achieved": fl / avg_a / 1e12, "frac": fl / avg_a / 1e12 / FP32_VALU_TFLOPS,
+                          "frac_unpacked": fl / avg_a / 1e12 / FP32_UNPACKED_TFLOPS,
+                          "traffic": pmc.get("traffic_bytes_per_launch_alone")})
+        else:
+            alone["frac"] = out["frac"] * avg_s / avg_a
+        out["alone"] = alone
     return out
+
+
+def source_sha(rel):
+    """First 16 hex digits of the SHA-256 of a source file of the library."""
+    import hashlib
+    return hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()[:16]
+
+
+# the file each profiled kernel kind is compiled from
+KIND_SOURCE = {"sdf": "paper_2609_20964_amd/csrc/surface.hip", "mc": "paper_2609_20964_amd/csrc/surface.hip",
+               "sample": "paper_2609_20964_amd/csrc/surface.hip", "splat": "paper_2609_20964_amd/csrc/splat.hip"}
 
 
 def load_pmc(kind):
     """Per-launch figures from the committed rocprofv3 counter summary for this
-    kernel and workload (`key value` lines), if one exists."""
+    kernel and workload (`key value` lines), if one exists and was taken on the
+    current source of the kernel (its `source_sha` line); counters of an older
+    build are not reported."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kind}_flapping256.txt")
     vals = {}
     if os.path.exists(path):
         for line in open(path):
             parts = line.split()
-            if len(parts) == 2 and parts[0] in ("traffic_bytes_per_launch", "fp32_flops_per_unit",
-                                                 "valu_issue_frac"):
-                vals[parts[0]] = float(parts[1])
+            if len(parts) == 2 and parts[0] in ("traffic_bytes_per_launch", "traffic_bytes_per_launch_alone",
+                                                 "valu_lane_util", "source_sha"):
+                vals[parts[0]] = parts[1] if parts[0] == "source_sha" else float(parts[1])
+    src = KIND_SOURCE.get(kind, "paper_2609_20964_amd/csrc/solver.hip")
+    if vals.get("source_sha") != source_sha(src):
+        return {}
     return vals
 
 
@@ -553,18 +605,23 @@ def replay(srv, reqs, time_scale, keep=False):
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
-    """Device-to-device copy rate (GB/s, read + write bytes) timed with events:
-    the bandwidth a streaming kernel reaches on this device."""
+    """Device-to-device copy rate (GB/s, read + write bytes) of the library's
+    streaming copy kernel (wg_stream_copy), timed with events on the stream it
+    runs on: the bandwidth a streaming kernel reaches on this device."""
     import torch
+
+    from paper_2609_20964_amd import _lib
 
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    s = torch.cuda.current_stream()
+    run = lambda: _lib.check(_lib.lib().wg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream))
+    run()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(s)
     for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
+        run()
+    e1.record(s)
     e1.synchronize()
     gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
@@ -573,13 +630,18 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
 
 
 def copy_probe():
+    """Five 1 GiB streaming copies (wg_stream_copy): the calibration run of
+    the rocprofv3 byte counters."""
     import torch
+
+    from paper_2609_20964_amd import _lib
 
     nbytes = 1 << 30
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
-        dst.copy_(src)
+        _lib.check(_lib.lib().wg_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes,
+                                             torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
 
@@ -600,29 +662,45 @@ def short_kernel_name(name):
     return name
 
 
-def pmc_summary(path):
+def pmc_summary(path, periods=()):
     """Mean counter value per dispatch, by kernel name (namespaces and
-    argument lists dropped) and grid size (a kernel that runs on every
-    multigrid level gets one line per level)."""
+    argument lists dropped) and grid size.  A kernel that runs on several
+    multigrid levels with the same grid size is split by its dispatch order
+    (`periods`: NAME=P gives level i mod P of that kernel's dispatches of one
+    grid size).  Dispatches below 5% of their group's median are launches that
+    returned at once (an inner iteration enqueued after the one that stopped
+    the solve): they are counted apart and left out of the means."""
     import csv
     from collections import defaultdict
 
-    acc = defaultdict(lambda: defaultdict(float))
-    disp = defaultdict(set)
+    period = dict(p.split("=") for p in periods)
+    rows_by = defaultdict(list)
     with open(path) as f:
         rows = csv.DictReader(f)
         if "Kernel_Name" not in (rows.fieldnames or []) or "Counter_Name" not in rows.fieldnames:
             raise SystemExit(f"unexpected columns in {path}: {rows.fieldnames}")
         for row in rows:
             name = short_kernel_name(row["Kernel_Name"])
-            if row.get("Grid_Size"):
-                name += f" [grid {row['Grid_Size']}]"
-            acc[name][row["Counter_Name"]] += float(row["Counter_Value"])
-            disp[name].add(row["Dispatch_Id"])
-    for name in sorted(acc, key=lambda k: -len(disp[k])):
-        n = len(disp[name])
-        vals = " ".join(f"{c}={v / n:.6g}" for c, v in sorted(acc[name].items()))
-        print(f"{name} | dispatches={n} | {vals}")
+            rows_by[(name, row.get("Grid_Size", ""))].append(row)
+    for (name, grid), rs in sorted(rows_by.items(), key=lambda kv: -len(kv[1])):
+        disp = sorted({int(r["Dispatch_Id"]) for r in rs})
+        per = int(period.get(name, 1))
+        for lvl in range(per):
+            ids = set(disp[lvl::per])
+            vals = defaultdict(dict)
+            for r in rs:
+                d = int(r["Dispatch_Id"])
+                if d in ids:
+                    vals[d][r["Counter_Name"]] = vals[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            first = sorted({c for v in vals.values() for c in v})
+            key = first[0] if first else None
+            med = sorted(v.get(key, 0.0) for v in vals.values())[len(vals) // 2] if vals else 0.0
+            live = [v for v in vals.values() if v.get(key, 0.0) >= 0.05 * med]
+            if not live:
+                continue
+            means = " ".join(f"{c}={sum(v.get(c, 0.0) for v in live) / len(live):.6g}" for c in first)
+            tag = f" [grid {grid}]" + (f" [level {lvl} of {per}]" if per > 1 else "")
+            print(f"{name}{tag} | dispatches={len(live)} (+{len(vals) - len(live)} returned at once) | {means}")
 
 
 def main():
@@ -641,11 +719,13 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--pmc-period", metavar="NAME=P", action="append", default=[],
+                    help="with --pmc-summary: split NAME's dispatches of one grid size into P levels by order")
     ap.add_argument("--pmc-summary", metavar="CSV",
                     help="only summarise a rocprofv3 counter_collection.csv: mean per dispatch by kernel")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(args.pmc_summary)
+        pmc_summary(args.pmc_summary, args.pmc_period)
         return
     if args.copy_probe:
         copy_probe()

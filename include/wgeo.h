@@ -337,6 +337,21 @@ int wg_profile_read(int kind, double *total_ms, int64_t *launches, double *units
 
 void wg_profile_reset(void);
 
+/* Work of the distance walk (Eq. 33's minimum over triangles, taken by a
+ * hierarchy walk), counted on the device while WG_PROF_SDF is enabled, summed
+ * over launches since the last wg_profile_reset: out[0] node-triangle distance
+ * tests, out[1] node-box bound tests against axis-aligned boxes, out[2]
+ * against oriented boxes, out[3] node slots walked (tiles x nodes per tile).
+ * A wavefront tests every visited triangle and box for each of its nodes.
+ * Synchronises the device. */
+int wg_profile_walk_counts(uint64_t out[4]);
+
+/* Streaming device copy of `bytes` (a multiple of 16, both pointers 16-byte
+ * aligned) from d_src to d_dst on hip_stream: the bandwidth reference that
+ * the library's HBM fractions are compared with (instrumentation).  Enqueues
+ * and returns; WG_EINVAL for misaligned or null arguments. */
+int wg_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *wg_last_error(void);
 

@@ -90,6 +90,8 @@ SIGNATURES = {
     "wg_profile_enable": (None, [C.c_uint]),
     "wg_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "wg_profile_reset": (None, []),
+    "wg_profile_walk_counts": (C.c_int, [C.POINTER(C.c_uint64 * 4)]),
+    "wg_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
 }
 
 PROF_KINDS = {"splat": 0, "sweep": 1, "smooth": 2, "resid64": 3, "transfer": 4, "cgupdate": 5, "mc": 6,
@@ -107,6 +109,13 @@ def profile_read(kind):
     ms, n, u = C.c_double(), C.c_int64(), C.c_double()
     check(lib().wg_profile_read(PROF_KINDS[kind], C.byref(ms), C.byref(n), C.byref(u)))
     return {"ms": ms.value, "launches": n.value, "units": u.value}
+
+
+def profile_walk_counts():
+    """Distance-walk test counts since the last reset (wg_profile_walk_counts)."""
+    out = (C.c_uint64 * 4)()
+    check(lib().wg_profile_walk_counts(C.byref(out)))
+    return {"tri_tests": out[0], "aabb_tests": out[1], "obb_tests": out[2], "nodes": out[3]}
 
 
 def lib():

@@ -20,16 +20,25 @@ struct SolveScalars {
     double res_sum, res_sq, x_sum, b_sum, b_sq;
     double mean_r, res_norm2, b_norm2;
     double mean_b;   // mean of the right-hand side (Neumann)
-    int bad;
-    int pad;
+    // inner PCG, decided on the device after each iteration's r.r
+    double stop_rr;  // stop at r.r <= stop_rr (tol^2 times the starting r.r)
+    double best;     // smallest r.r of the stall test so far
+    int stall;       // iterations since r.r last halved
+    int iters;       // iterations taken by this inner solve
+    int done;        // the inner solve has stopped: its kernels return at once
+    int bad;         // bit 0: a non-finite sum; bit 1: p.Ap <= 0
 };
 
-// Host-mapped copy of the scalars: the finalize that writes it stores seq
-// last, and the host waits for the value it expects.
+// Host-mapped copies of the scalars.  A finalize of the refinement stores the
+// whole record, then seq, and the host waits for the value it expects.  Each
+// inner iteration's r.r finalize stores one 64-bit status word instead (read
+// whole, so never torn while a later iteration's finalize writes it):
+// (its own sequence number << 32) | iters << 2 | (non-finite) << 1 | done.
 struct PublishedScalars {
     SolveScalars s;
     unsigned seq;
     unsigned pad;
+    unsigned long long status;
 };
 
 struct SolveResult {
@@ -75,9 +84,11 @@ class Solver {
     void vcycle(int l);
     void precond();
     unsigned rz_blocks() const;
-    int pcg(double tol, int max_it, double rr0);
+    int pcg(double tol, int max_it, bool &non_finite);
+    void pcg_iteration(int it, int &cur);
     void finalize(int mode, unsigned nb, int flag);
     void read_scalars();
+    unsigned long long wait_status(unsigned want);
 
     hipStream_t st_ = nullptr;
     Level lv_[kMaxLevels] = {};
@@ -90,6 +101,8 @@ class Solver {
     bool mapped_ = true, instrument_ = true;
     const SolveScalars *hsc_ = nullptr;                       // &pub_->s or &host_pub_.s
     unsigned seq_ = 0;                                        // sequence number of the last finalize
+    unsigned sseq_ = 0;                                       // ... of the last status word
+    const int *skip_ = nullptr;   // &dsc_->done while an inner PCG runs, else null
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
     unsigned post_blocks_ = 0;   // workgroups of the finest post-smoothing pass (partials of r.z)

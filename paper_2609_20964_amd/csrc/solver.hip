@@ -9,6 +9,7 @@
 // contiguous slab.
 // Every reduction is two-stage and deterministic: one FP64 partial per block
 // (fixed block order), summed by a single-block finalize kernel.
+#include <atomic>
 #include <cmath>
 
 #include "prof.h"
@@ -25,6 +26,11 @@ constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi factor of the sweeps 
 constexpr int kCoarseTarget = 32;       // coarsen until every extent is <= this (or odd)
 constexpr int kCoarseAxis = 32;         // exact coarsest solve when every extent is <= this
 
+// An inner PCG enqueues its next iteration before the host has seen whether
+// the current one stopped it; once a finalize has set the flag, the kernels of
+// that iteration return at once (skip: null outside an inner solve).
+__device__ __forceinline__ bool skipped(const int *skip) { return skip != nullptr && *skip != 0; }
+
 struct Tiles {
     unsigned gx, gy, gz;
     __host__ __device__ unsigned count() const { return gx * gy * gz; }
@@ -37,8 +43,9 @@ Tiles tiles_of(const Dims &d) { return {cdiv(d.nx, TX), cdiv(d.ny, TY), cdiv(d.n
 template <class Op> __device__ __forceinline__ void fetch_scalars(Op &) {}
 
 template <class Op>
-__global__ __launch_bounds__(256) void k_stencil(Op op, Dims d, Tiles t, double *partials) {
+__global__ __launch_bounds__(256) void k_stencil(Op op, Dims d, Tiles t, double *partials, const int *skip) {
     using T = typename Op::T;
+    if (skipped(skip)) return;
     fetch_scalars(op);
     const unsigned nb = t.count();
     const unsigned lb = xcd_logical_block(blockIdx.x, nb);
@@ -136,8 +143,9 @@ inline Waves4 waves4_of(const Dims &d, bool even = false) {
 }
 
 template <class Op>
-__global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, double *partials) {
+__global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, double *partials, const int *skip) {
     using T = typename Op::T;
+    if (skipped(skip)) return;
     fetch_scalars(op);
     const unsigned nb = gridDim.x;
     const unsigned lb = xcd_logical_block(blockIdx.x, nb);
@@ -354,6 +362,7 @@ template <bool FIRST>
 __global__ __launch_bounds__(256) void k_cg_update(float *__restrict__ x, float *__restrict__ r,
                                                     const float *__restrict__ p, const float *__restrict__ q,
                                                     const SolveScalars *sc, size_t n, double *partials) {
+    if (sc->done) return;
     const float a = (float)sc->alpha;
     double acc[1] = {0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -552,8 +561,9 @@ __device__ __forceinline__ void zero_pads(float *s, int W, int Ht) {
 // pre: xo = x2 of the pre-smoothing from a zero guess, crhs = 1/2 P^T (rhs - A xo).
 __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, float *__restrict__ xo,
                                                  float *__restrict__ crhs, Dims df, Dims dc, VTile vt, float wa,
-                                                 float wb) {
+                                                 float wb, const int *skip) {
     constexpr int H = kPreH, CPT = kPreCPT;
+    if (skipped(skip)) return;
     __shared__ float sR[2][kPreLds];
     __shared__ float sX[2][kPreLds];
     __shared__ float sr[2][kPreLds];
@@ -697,8 +707,10 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
 template <bool DOT>
 __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x, const float *__restrict__ rhs,
                                                      const float *__restrict__ e, float *__restrict__ xo, Dims df,
-                                                     Dims dc, VTile vt, float wb, float wa, double *partials) {
+                                                     Dims dc, VTile vt, float wb, float wa, double *partials,
+                                                     const int *skip) {
     constexpr int H = kPostH, CPT = kPostCPT;
+    if (skipped(skip)) return;
     __shared__ float sU[2][kPostLds];
     __shared__ float sV[2][kPostLds];
     __shared__ float sQ[3][kPostLds];   // x/y-interpolated coarse planes, by coarse index mod 3
@@ -859,7 +871,8 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
 
 // out = rhs . x summed per block (the r.z of a single-level hierarchy).
 __global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const float *__restrict__ b, size_t n,
-                                              double *partials) {
+                                              double *partials, const int *skip) {
+    if (skipped(skip)) return;
     double acc[1] = {0.0};
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         acc[0] += (double)a[i] * (double)b[i];
@@ -887,7 +900,8 @@ static_assert(256 % kEigN == 0, "a row of the slice is a whole number of lanes")
 // inverse: f[k][j][i] = sum_my sum_mx phi_y[my][j] phi_x[mx][i] c[k][my][mx].
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_eig_plane(const float *__restrict__ src, float *__restrict__ dst,
-                                                   const float *__restrict__ E, int cx, int cy) {
+                                                   const float *__restrict__ E, int cx, int cy, const int *skip) {
+    if (skipped(skip)) return;
     __shared__ float T[kEigN][kEigN + 1];
     __shared__ float U[kEigN][kEigN + 1];
     __shared__ float Px[kEigN][kEigN + 1];   // Px[i][m] = phi_x[m][i]
@@ -941,7 +955,8 @@ __global__ __launch_bounds__(256) void k_eig_plane(const float *__restrict__ src
 // In place on the coefficients of y mode my = blockIdx.x: transform along z,
 // divide by the eigenvalue (0 for the constant mode), transform back.
 __global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const float *__restrict__ E, int cx, int cy,
-                                               int cz) {
+                                               int cz, const int *skip) {
+    if (skipped(skip)) return;
     __shared__ float V[kEigN][kEigN + 1];
     __shared__ float Wz[kEigN][kEigN + 1];
     __shared__ float Pz[kEigN][kEigN + 1];   // Pz[k][n] = phi_z[n][k]
@@ -979,11 +994,16 @@ __global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const fl
 enum { FIN_RESID = 0, FIN_RZ = 1, FIN_PQ = 2, FIN_RR = 3, FIN_BSUM = 4 };
 
 // Final stage of a two-stage reduction: sums the per-block partials in a
-// fixed order, updates the solver scalars and copies them to `mirror`, a
-// host-mapped buffer the host reads after synchronising the stream.
+// fixed order and updates the solver scalars.  The refinement's finalizes
+// (FIN_RESID, FIN_BSUM) copy the scalars to the host-mapped record and store
+// seq after them.  An inner iteration's FIN_RR decides on the device whether
+// the inner solve stops (r.r at the target, r.r not halved in four iterations,
+// or a breakdown) and stores the status word (see PublishedScalars); FIN_PQ,
+// FIN_RZ and FIN_RR return at once once it has stopped.
 __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsigned nb, int mode, int flag,
                                                    SolveScalars *sc, double ncells, PublishedScalars *mirror,
                                                    unsigned seq) {
+    if ((mode == FIN_PQ || mode == FIN_RR || (mode == FIN_RZ && !flag)) && sc->done) return;
     const int nred = mode == FIN_RESID ? 5 : 1;
     double v[5] = {0, 0, 0, 0, 0};
     for (int k = 0; k < nred; ++k) {
@@ -996,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
     if (threadIdx.x != 0) return;
     bool bad = false;
     for (int k = 0; k < nred; ++k) bad |= !isfinite(v[k]);
-    if (bad) sc->bad = 1;
+    if (bad) sc->bad |= 1;
     switch (mode) {
         case FIN_RESID: {
             sc->res_sum = v[0];
@@ -1021,15 +1041,28 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
             sc->rz = v[0];
             sc->beta = flag ? 0.0 : (sc->rz_old != 0.0 ? v[0] / sc->rz_old : 0.0);
             sc->rz_old = v[0];
-            break;
+            return;
         case FIN_PQ:
             sc->pq = v[0];
             sc->alpha = (v[0] > 0.0 && isfinite(v[0])) ? sc->rz / v[0] : 0.0;
             if (!(v[0] > 0.0)) sc->bad |= 2;
-            break;
-        case FIN_RR:
-            sc->rr = v[0];
-            break;
+            return;
+        case FIN_RR: {
+            const double rr = v[0];
+            sc->rr = rr;
+            sc->iters += 1;
+            int done = 0;
+            if (sc->bad || !isfinite(rr)) done = 1;
+            else if (rr <= sc->stop_rr) done = 1;
+            else if (rr < 0.5 * sc->best) { sc->best = rr; sc->stall = 0; }
+            else if (++sc->stall >= 4) done = 1;
+            sc->done = done;
+            const unsigned long long st = ((unsigned long long)seq << 32) | ((unsigned long long)sc->iters << 2) |
+                                          ((unsigned long long)(sc->bad & 1) << 1) | (unsigned long long)done;
+            __threadfence_system();
+            __hip_atomic_store(&mirror->status, st, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            return;
+        }
         case FIN_BSUM:
             sc->b_sum = v[0];
             sc->mean_b = v[0] / ncells;
@@ -1039,6 +1072,17 @@ __global__ __launch_bounds__(256) void k_finalize(const double *partials, unsign
     // the host reads the scalars once it sees seq: make them visible first
     __threadfence_system();
     __hip_atomic_store(&mirror->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Start of an inner PCG: clears the stop flag and sets the target r.r from
+// the refinement residual's r.r (rr0 = res_norm2).
+__global__ void k_pcg_begin(SolveScalars *sc, double tol2) {
+    sc->done = 0;
+    sc->iters = 0;
+    sc->stall = 0;
+    sc->bad &= ~2;
+    sc->best = sc->res_norm2;
+    sc->stop_rr = tol2 * sc->res_norm2;
 }
 
 // Orthonormal 1-D eigenbases and eigenvalues of the 7-point operator on the
@@ -1159,6 +1203,7 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s, bool mapped) 
         WG_HIP(hipHostMalloc((void **)&pub_, sizeof(PublishedScalars), hipHostMallocMapped | hipHostMallocCoherent));
         WG_HIP(hipHostGetDevicePointer((void **)&pub_dev_, pub_, 0));
         pub_->seq = seq_;
+        pub_->status = 0;
         hsc_ = &pub_->s;
     } else {
         pub_dev_ = dev_rec;
@@ -1181,11 +1226,13 @@ Solver::~Solver() {
 }
 
 void Solver::finalize(int mode, unsigned nb, int flag) {
-    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count(), pub_dev_, ++seq_);
+    // FIN_RR publishes a status word with a sequence number of its own
+    const unsigned seq = mode == FIN_RR ? ++sseq_ : (mode == FIN_RESID || mode == FIN_BSUM ? ++seq_ : 0u);
+    k_finalize<<<1, 256, 0, st_>>>(partials_, nb, mode, flag, dsc_, (double)lv_[0].d.count(), pub_dev_, seq);
     WG_LAUNCH_CHECK();
 }
 
-// Wait until the last finalize has published its scalars.
+// Wait until the last refinement finalize has published its scalars.
 void Solver::read_scalars() {
     if (mapped_) {
         wait_published(&pub_->seq, seq_, st_);
@@ -1195,18 +1242,42 @@ void Solver::read_scalars() {
     }
 }
 
+// Wait until the status word carries sequence number `want` or a later one
+// (a later iteration's word also tells whether the solve has stopped) and
+// return it.
+unsigned long long Solver::wait_status(unsigned want) {
+    if (!mapped_) {
+        WG_HIP(hipMemcpyAsync(&host_pub_, pub_dev_, sizeof(PublishedScalars), hipMemcpyDeviceToHost, st_));
+        WG_HIP(hipStreamSynchronize(st_));
+        return host_pub_.status;
+    }
+    for (unsigned k = 1;; ++k) {
+        const unsigned long long st = __atomic_load_n(&pub_->status, __ATOMIC_ACQUIRE);
+        if ((int)((unsigned)(st >> 32) - want) >= 0) return st;
+        if ((k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(st_);
+            if (e == hipSuccess) {
+                const unsigned long long s2 = __atomic_load_n(&pub_->status, __ATOMIC_ACQUIRE);
+                if ((int)((unsigned)(s2 >> 32) - want) >= 0) return s2;
+                throw Error(WG_EDEVICE, "the solver's status never arrived");
+            }
+            if (e != hipErrorNotReady) hip_check(e, "hipStreamQuery", __FILE__, __LINE__);
+        }
+    }
+}
+
 // kind / bytes_per_cell: optional timing bracket (WG_PROF_*) and the sweep's
-// algorithmic bytes per cell.
+// algorithmic bytes per cell; skip: see skipped().
 template <class Op>
 static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStream_t s, int kind = -1,
-                           double bytes_per_cell = 0.0) {
+                           double bytes_per_cell = 0.0, const int *skip = nullptr) {
     prof::Scope ps(kind, s, bytes_per_cell * (double)d.count());
     if (d.nx % 4 == 0) {
         const Waves4 wv = waves4_of(d);
-        k_stencil4<Op><<<cdiv(wv.tasks(), 4), 256, 0, s>>>(op, d, wv, partials);
+        k_stencil4<Op><<<cdiv(wv.tasks(), 4), 256, 0, s>>>(op, d, wv, partials, skip);
     } else {
         const Tiles t = tiles_of(d);
-        k_stencil<Op><<<t.count(), TX * TY, 0, s>>>(op, d, t, partials);
+        k_stencil<Op><<<t.count(), TX * TY, 0, s>>>(op, d, t, partials, skip);
     }
     WG_LAUNCH_CHECK();
 }
@@ -1218,18 +1289,18 @@ void Solver::vcycle(int l) {
     if (l == last) {
         if (coarse_direct_) {
             const float *E = coarseM_[bc_sign_ > 0 ? 1 : 0];
-            k_eig_plane<true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny);
-            k_eig_z<<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz);
-            k_eig_plane<false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny);
+            k_eig_plane<true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny, skip_);
+            k_eig_z<<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz, skip_);
+            k_eig_plane<false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny, skip_);
             WG_LAUNCH_CHECK();
         } else {
             // no direct solve possible (odd extents): a fixed, even number of sweeps
-            launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
+            launch_stencil(OpSmoothFirst{L.rhs, L.x2, kOmega}, L.d, nullptr, st_, -1, 0.0, skip_);
             for (int k = 0; k < 15; ++k) {
-                launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
-                launch_stencil(OpSmooth{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_);
+                launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_, -1, 0.0, skip_);
+                launch_stencil(OpSmooth{L.x, L.rhs, L.x2, kOmega}, L.d, nullptr, st_, -1, 0.0, skip_);
             }
-            launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_);
+            launch_stencil(OpSmooth{L.x2, L.rhs, L.x, kOmega}, L.d, nullptr, st_, -1, 0.0, skip_);
         }
         return;
     }
@@ -1240,7 +1311,7 @@ void Solver::vcycle(int l) {
     {
         // rhs read, x written; 1/8 of a cell's bytes for the coarse rhs
         prof::Scope ps(ks, st_, 8.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
-        k_vc_pre<<<vt.count(), kVB, 0, st_>>>(L.rhs, L.x, C.rhs, L.d, C.d, vt, kChebWa, kChebWb);
+        k_vc_pre<<<vt.count(), kVB, 0, st_>>>(L.rhs, L.x, C.rhs, L.d, C.d, vt, kChebWa, kChebWb, skip_);
         WG_LAUNCH_CHECK();
     }
     vcycle(l + 1);
@@ -1249,10 +1320,10 @@ void Solver::vcycle(int l) {
         prof::Scope ps(kt, st_, 12.0 * (double)L.d.count() + 4.0 * (double)C.d.count());
         if (l == 0)   // + r.z
             k_vc_post<true><<<vt.count(), kVB, 0, st_>>>(L.x, L.rhs, C.x, L.x2, L.d, C.d, vt, kChebWb, kChebWa,
-                                                           partials_);
+                                                           partials_, skip_);
         else
             k_vc_post<false><<<vt.count(), kVB, 0, st_>>>(L.x, L.rhs, C.x, L.x2, L.d, C.d, vt, kChebWb, kChebWa,
-                                                            nullptr);
+                                                            nullptr, skip_);
         WG_LAUNCH_CHECK();
         std::swap(L.x, L.x2);
     }
@@ -1265,7 +1336,7 @@ void Solver::precond() {
         // the coarsest solve alone forms no sum: one more pass
         Level &F = lv_[0];
         const size_t N = F.d.count();
-        k_dot<<<red_blocks(N), kBlock, 0, st_>>>(F.rhs, F.x, N, partials_);
+        k_dot<<<red_blocks(N), kBlock, 0, st_>>>(F.rhs, F.x, N, partials_, skip_);
         WG_LAUNCH_CHECK();
     }
 }
@@ -1283,46 +1354,79 @@ void Solver::mg_apply(const float *r, float *z, int bc) {
     WG_HIP(hipMemcpyAsync(z, F.x, N * sizeof(float), hipMemcpyDeviceToDevice, st_));
 }
 
-int Solver::pcg(double tol, int max_it, double rr0) {
+// Iteration `it` of the inner PCG: for it > 0 first z = M r and beta (the
+// step after the last r.r test), then the direction with q = A p and alpha,
+// the update of the correction and of r, and the r.r finalize that decides
+// on the device whether to stop.  Every kernel returns at once once stopped.
+void Solver::pcg_iteration(int it, int &cur) {
     Level &F = lv_[0];
     const size_t N = F.d.count();
-    const unsigned tb = sweep_blocks(F.d);
-    const unsigned rb = red_blocks(N);
-    // z = M r, rz = r.z ; the first finalize must not form beta
-    precond();
-    finalize(FIN_RZ, rz_blocks(), 1);
-    int cur = 0, it = 0;
-    double best = rr0;
-    int stall = 0;
-    for (; it < max_it; ++it) {
-        if (it == 0)
-            launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, F.d, partials_, st_,
-                           pk(WG_PROF_SWEEP), 12.0);
-        else   // beta = rz / rz_old, formed by the last finalize, read on the device
-            launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, F.d, partials_, st_,
-                           pk(WG_PROF_SWEEP), 16.0);
-        finalize(FIN_PQ, tb, 0);
-        {
-            prof::Scope ps(pk(WG_PROF_CGUPDATE), st_, (it == 0 ? 20.0 : 24.0) * (double)N);
-            if (it == 0)
-                k_cg_update<true><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
-            else
-                k_cg_update<false><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
-            WG_LAUNCH_CHECK();
-        }
-        finalize(FIN_RR, rb, 0);
-        // test r.r before the preconditioner: the last iteration forms no z
-        read_scalars();
-        const double rr = hsc_->rr;
-        if (hsc_->bad || !std::isfinite(rr)) { ++it; break; }
-        if (rr <= tol * tol * rr0) { ++it; break; }
-        if (rr < 0.5 * best) { best = rr; stall = 0; }
-        else if (++stall >= 4) { ++it; break; }
+    if (it > 0) {
         precond();   // z for the next direction
         finalize(FIN_RZ, rz_blocks(), 0);   // beta = rz / rz_old
         cur ^= 1;
     }
-    return it;
+    if (it == 0)
+        launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, F.d, partials_, st_,
+                       pk(WG_PROF_SWEEP), 12.0, skip_);
+    else   // beta = rz / rz_old, formed by the last finalize, read on the device
+        launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, F.d, partials_, st_,
+                       pk(WG_PROF_SWEEP), 16.0, skip_);
+    finalize(FIN_PQ, sweep_blocks(F.d), 0);
+    const unsigned rb = red_blocks(N);
+    {
+        prof::Scope ps(pk(WG_PROF_CGUPDATE), st_, (it == 0 ? 20.0 : 24.0) * (double)N);
+        if (it == 0)
+            k_cg_update<true><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
+        else
+            k_cg_update<false><<<rb, kBlock, 0, st_>>>(e_, F.rhs, p_[cur], q_, dsc_, N, partials_);
+        WG_LAUNCH_CHECK();
+    }
+    finalize(FIN_RR, rb, 0);
+}
+
+// Inner PCG on A e = r (r in the finest level's rhs) from e = 0, to r.r <=
+// tol^2 r0.r0 or max_it iterations.  The host keeps one iteration enqueued
+// beyond the one whose status it waits for, so the device does not idle
+// through a host round trip; the iteration after the stopping one returns
+// at once in every kernel.  Returns the iterations taken.
+int Solver::pcg(double tol, int max_it, bool &non_finite) {
+    non_finite = false;
+    k_pcg_begin<<<1, 1, 0, st_>>>(dsc_, tol * tol);
+    WG_LAUNCH_CHECK();
+    skip_ = &dsc_->done;
+    // z = M r, rz = r.z ; the first finalize must not form beta
+    precond();
+    finalize(FIN_RZ, rz_blocks(), 1);
+    int cur = 0, enq = 0, checked = 0, iters = 0;
+    unsigned seq_of[2] = {0, 0};
+    // timing records of each iteration are grouped, so that those of an
+    // iteration that returned at once can be dropped
+    static std::atomic<unsigned long long> next_group{1};
+    unsigned long long group_of[2] = {0, 0};
+    auto push = [&] {
+        group_of[enq % 2] = instrument_ ? next_group.fetch_add(1) : 0ull;
+        prof::set_group(group_of[enq % 2]);
+        pcg_iteration(enq, cur);
+        prof::set_group(0);
+        seq_of[enq % 2] = sseq_;
+        ++enq;
+    };
+    push();
+    for (;;) {
+        if (enq < max_it) push();
+        const unsigned long long st = wait_status(seq_of[checked % 2]);
+        ++checked;
+        iters = (int)((st >> 2) & 0x3fffffffu);
+        if (st & 3u) {
+            non_finite = (st & 2u) != 0;
+            break;
+        }
+        if (checked == enq) break;   // the budget is spent
+    }
+    if (enq > iters) prof::drop_group(group_of[(enq - 1) % 2]);   // enqueued after the stop: did nothing
+    skip_ = nullptr;
+    return iters;
 }
 
 SolveResult Solver::solve(const float *b, double *x, int bc, const wg_solve_opts &o) { return solve_impl(b, x, bc, o); }
@@ -1391,8 +1495,9 @@ SolveResult Solver::solve_impl(const TB *b, double *x, int bc, const wg_solve_op
         if (inner > 0.5) inner = 0.5;
         int budget = max_iters - res.iters;
         if (budget > 60) budget = 60;
-        res.iters += pcg(inner, budget, hsc_->res_norm2);
-        if (hsc_->bad & 1) {
+        bool non_finite = false;
+        res.iters += pcg(inner, budget, non_finite);
+        if (non_finite) {
             res.status = WG_ENUMERIC;
             res.rel_res = NAN;
             return res;

@@ -627,21 +627,24 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                                               float *__restrict__ phi, int32_t *__restrict__ argmin, int *err,
                                               uint32_t *next_tile, const uint32_t *__restrict__ order,
                                               uint32_t *__restrict__ tile_cost, const int32_t *__restrict__ seed,
-                                              SeedDims snc) {
+                                              SeedDims snc, unsigned long long *__restrict__ counts) {
     static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
+    // test counts of this wavefront (wave-uniform; each applies to its 64 kTZ
+    // nodes), added to counts[] at exit when profiling
+    uint32_t n_tri = 0, n_aabb = 0, n_obb = 0, n_tiles = 0, n_seed = 0;
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     constexpr int TZ = LZ * kTZ;
     const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
-    const uint32_t n_tiles = (uint32_t)(tx * ty * tz);
+    const uint32_t n_tiles_all = (uint32_t)(tx * ty * tz);
     // persistent: each wavefront takes the next tile of its slab's queue, then
     // of the following slabs', until every queue is empty (each queue is left
     // once it runs dry, so every wavefront exits after at most kWalkParts
     // failed takes)
     int part = (int)(blockIdx.x % kWalkParts), visited = 0;
     for (;;) {
-        const uint32_t t0 = (uint32_t)((uint64_t)n_tiles * part / kWalkParts);
-        const uint32_t t1 = (uint32_t)((uint64_t)n_tiles * (part + 1) / kWalkParts);
+        const uint32_t t0 = (uint32_t)((uint64_t)n_tiles_all * part / kWalkParts);
+        const uint32_t t1 = (uint32_t)((uint64_t)n_tiles_all * (part + 1) / kWalkParts);
         uint32_t slot = 0;
         if (lane == 0) slot = t0 + atomicAdd(next_tile + part, 1u);
         slot = __builtin_amdgcn_readfirstlane(slot);
@@ -682,6 +685,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                     best[k] = tri_d2(px, py, pz[k], tr[0], tr[1], tr[2], tr[3], v_, w_);
                     arg[k] = t;
                 }
+                if (counts) n_seed += (uint32_t)__popcll(__ballot(t >= 0 && (uint32_t)t < n_tris));
             }
         }
         if (n_tris > 0) {
@@ -697,10 +701,12 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                     const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
                     bool need = false;
                     obb_bound<kTZ>(N0, N1, N2, N3, px, py, pz, best, need);
+                    ++n_obb;
                     if (__ballot(need) == 0) continue;
                     work += kCostLeaf;
                     const uint32_t word = __float_as_uint(N3.w);
                     const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
+                    n_tri += cnt;
                     for (uint32_t t = first; t < first + cnt; ++t) {
                         const float4 *tr = tri + kTri * (size_t)t;
                         const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
@@ -721,9 +727,11 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                 {
                     bool need = false;
                     aabb_bound<kTZ>(A0, A1, px, py, pz, best, need);
+                    ++n_aabb;
                     if (__ballot(need) == 0) continue;
                 }
                 work += kCostInner;
+                n_aabb += 8;   // the eight child boxes (clamped to the last child)
                 const uint32_t word = __float_as_uint(A0.w);
                 const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
                 const bool kids_leaves = (word & kKidsLeaves) != 0;
@@ -743,6 +751,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                         aabb_bound<kTZ>(ab[0], ab[1], px, py, pz, best, vis);
                         if ((uint32_t)q < cnt && __ballot(vis) != 0) pass |= 1u << q;
                     }
+                    n_obb += (uint32_t)__popc(pass);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         key[q] = 0u;
@@ -788,7 +797,8 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                 }
             }
         }
-        if (lane == 0 && tile < n_tiles) tile_cost[tile] = work;
+        if (lane == 0 && tile < n_tiles_all) tile_cost[tile] = work;
+        ++n_tiles;
         if (gi < d.nx && gj < d.ny) {
 #pragma unroll
             for (int k = 0; k < kTZ; ++k) {
@@ -799,6 +809,13 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                 argmin[o] = arg[k];
             }
         }
+    }
+    if (counts && lane == 0) {
+        constexpr unsigned long long kNodes = 64ull * kTZ;
+        atomicAdd(counts + 0, kNodes * n_tri + n_seed);
+        atomicAdd(counts + 1, kNodes * n_aabb);
+        atomicAdd(counts + 2, kNodes * n_obb);
+        atomicAdd(counts + 3, kNodes * n_tiles);
     }
 }
 
@@ -1344,7 +1361,8 @@ static void launch_sdf(const Dims &d, const uint32_t *sign, double h, const floa
     WG_HIP(hipMemsetAsync(next_tile, 0, kWalkParts * sizeof(uint32_t), s));
     prof::Scope ps(WG_PROF_SDF, s, (double)d.count());   // the walk alone
     k_sdf<LX, LY, LZ, KZ><<<blocks, 256, 0, s>>>(sign, d, h, nodes, leaf_aabb, root, tri, n_tris, phi, argmin, err,
-                                                 next_tile, order, tile_cost, seed, seed_dims(d));
+                                                 next_tile, order, tile_cost, seed, seed_dims(d),
+                                                 prof::walk_counters());
     WG_LAUNCH_CHECK();
 }
 

@@ -20,18 +20,38 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_alu_roofline_of_the_walk():
-    # 10 launches of 16.7M nodes in 70 ms (timed) and 3 in 18 ms alone
+    # 10 launches of 16.7M nodes in 70 ms (timed) and 3 in 18 ms alone, with
+    # test counts taken on the device during each set of launches
     nodes = 16_777_216
+    walk = lambda k: {"tri_tests": 300.0 * k * nodes, "aabb_tests": 800.0 * k * nodes,
+                      "obb_tests": 100.0 * k * nodes, "nodes": k * nodes}
     res = {"dominant": "sdf", "prof": {"launches": 10, "ms": 70.0, "units": 10.0 * nodes},
-           "per_kind": {"sdf": {"launches": 3, "ms": 18.0, "units": 3.0 * nodes}}}
+           "per_kind": {"sdf": {"launches": 3, "ms": 18.0, "units": 3.0 * nodes}},
+           "walk_timed": walk(10), "walk_plain": walk(3), "walk_ktz": 4}
     r = bench.roofline(res)
-    fpn = bench.load_pmc("sdf")["fp32_flops_per_unit"]
+    per_node = 300 * (8.0 / 4 + 37.0) + 800 * (11.0 / 4 + 7.0) + 100 * (17.0 / 4 + 18.0)
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == bench.FP32_VALU_TFLOPS
     assert r["avg_launch_us"] == pytest.approx(7000.0)
-    assert r["achieved"] == pytest.approx(fpn * nodes / 7e-3 / 1e12)
-    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert r["flops_per_node"] == pytest.approx(per_node)
+    assert r["achieved"] == pytest.approx(per_node * nodes / 7e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    assert r["frac_unpacked"] == pytest.approx(r["achieved"] / 78.6)
+    assert r["tests_per_node"]["triangle"] == pytest.approx(300.0)
     assert r["alone"]["avg_launch_us"] == pytest.approx(6000.0)
     assert r["alone"]["frac"] == pytest.approx(r["frac"] * 7.0 / 6.0)
+
+
+def test_stale_counter_profiles_are_not_reported(tmp_path, monkeypatch):
+    # a counter summary taken on another build of the kernel's source is ignored
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "pmc_sdf_flapping256.txt").write_text("source_sha 0123456789abcdef\ntraffic_bytes_per_launch 5e8\n")
+    real = bench.source_sha("paper_2609_20964_amd/csrc/surface.hip")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_sha", lambda rel: real)
+    assert bench.load_pmc("sdf") == {}
+    (prof / "pmc_sdf_flapping256.txt").write_text(f"source_sha {real}\ntraffic_bytes_per_launch 5e8\n")
+    assert bench.load_pmc("sdf")["traffic_bytes_per_launch"] == 5e8
 
 
 def test_solver_roofline_against_peak_and_copy():
