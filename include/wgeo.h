@@ -126,6 +126,27 @@ typedef struct wg_server wg_server;
  * or more than 2^31 cells, WG_ENOMEM if allocation fails. */
 int wg_recon_create(wg_recon **out, const wg_grid *grid, int max_points, void *hip_stream);
 
+/* A grid over a bounding box (Sec. 2.3: the domain is the point cloud's
+ * bounding box, discretised uniformly; Table 1's grid density d sets the
+ * cells per axis, read here as d cells per unit length, h = 1/d).  lo, hi:
+ * the box corners (hi >= lo per axis).  The box is widened by pad_cells cells
+ * on each side (the 27-cell splat reaches two cells past a point's cell, so
+ * use pad_cells >= 3 for a cloud in the box) and each extent rounded up to a
+ * multiple of 2^L, L the fewest halvings that bring the largest extent to 32
+ * or less, and to at least 2^(L+1) cells, so that the solver's multigrid
+ * hierarchy reaches an exactly solved coarsest level; the box sits at the
+ * centre.  Host arithmetic only; WG_EINVAL for density <= 0, a bad box or a
+ * grid above 2^31 cells. */
+int wg_grid_from_bbox(const double lo[3], const double hi[3], double density, int pad_cells, wg_grid *out);
+
+/* wg_grid_from_bbox over the bounding box of n_points device points d_xyz
+ * ([n_points][3] float32), taken on the device (exact minima and maxima) on
+ * hip_stream.  Synchronises the stream (and allocates a small record); for
+ * set-up, not per step.  WG_EINVAL for an empty cloud or a non-finite
+ * coordinate. */
+int wg_grid_from_cloud(const float *d_xyz, int n_points, double density, int pad_cells, wg_grid *out,
+                       void *hip_stream);
+
 /* Footprint (bytes) that wg_recon_create would allocate. */
 size_t wg_recon_footprint(const wg_grid *grid, int max_points);
 

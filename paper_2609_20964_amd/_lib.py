@@ -63,6 +63,9 @@ _lib = None
 SIGNATURES = {
     "wg_last_error": (C.c_char_p, []),
     "wg_recon_footprint": (C.c_size_t, [C.POINTER(WgGrid), C.c_int]),
+    "wg_grid_from_bbox": (C.c_int, [C.POINTER(C.c_double * 3), C.POINTER(C.c_double * 3), C.c_double, C.c_int,
+                                    C.POINTER(WgGrid)]),
+    "wg_grid_from_cloud": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.POINTER(WgGrid), C.c_void_p]),
     "wg_recon_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(WgGrid), C.c_int, C.c_void_p]),
     "wg_recon_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(WgSolveOpts),
                                    C.POINTER(WgStats)]),
@@ -160,6 +163,14 @@ def make_grid(n, lo=(0.0, 0.0, 0.0), h=None):
     g.lo[:] = [float(v) for v in lo]
     g.h = float(1.0 / max(n) if h is None else h)
     return g
+
+
+def grid_from_bbox(lo, hi, density, pad=3):
+    """(n, lo, h) of wg_grid_from_bbox (host arithmetic)."""
+    g = WgGrid()
+    check(lib().wg_grid_from_bbox(C.byref((C.c_double * 3)(*map(float, lo))), C.byref((C.c_double * 3)(*map(float, hi))),
+                                  float(density), int(pad), C.byref(g)))
+    return tuple(g.n), tuple(g.lo), g.h
 
 
 def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False, precision=WG_FP32_FP64REDUCE, deterministic=False):

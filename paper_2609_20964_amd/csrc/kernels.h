@@ -87,6 +87,7 @@ __global__ void k_splat_chunks(const uint32_t *perm, const uint32_t *tile_off, c
                                const uint32_t *ch_off, const uint32_t *chunk_tile, const uint32_t *n_chunks,
                                const float *xyz_c, const float *nrm_c, GridF g, TileDims td, float *b,
                                unsigned long long *acc, const FixedScale *fix);
+__global__ void k_bbox(const float *xyz, int npts, uint32_t *box, int *err);
 __global__ void k_fixed_scale(const uint32_t *nmax_bits, int npts, double h, FixedScale *fix, int *err);
 template <class T>
 __global__ void k_fixed_to_b(const long long *acc, const FixedScale *fix, size_t n, T *b);

@@ -496,6 +496,77 @@ int Recon::get_mesh(float *tris, int32_t *info, int64_t max_tris, int64_t *n_tri
 }
 
 // ---------------------------------------------------------------------------
+// grids over a cloud's bounding box
+// ---------------------------------------------------------------------------
+
+// Sec. 2.3 takes the domain as the cloud's bounding box on a uniform grid
+// whose density d (Table 1) sets the cell count along each axis; read as d
+// cells per unit length (h = 1/d).  The box is widened by `pad` cells on each
+// side (the splat reaches two cells past a point's cell) and each extent is
+// rounded up to a multiple of q = 2^L, L the fewest halvings that bring the
+// largest extent to at most 32, and to at least 2q, so that the solver's
+// multigrid hierarchy coarsens to an exactly solved level; the box is centred.
+void grid_from_bbox(const double lo[3], const double hi[3], double density, int pad, wg_grid &g) {
+    require(std::isfinite(density) && density > 0.0, WG_EINVAL, "grid density must be positive");
+    require(pad >= 0 && pad <= 1024, WG_EINVAL, "pad outside [0, 1024] cells");
+    const double h = 1.0 / density;
+    double need[3];
+    double most = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        require(std::isfinite(lo[a]) && std::isfinite(hi[a]) && hi[a] >= lo[a], WG_EINVAL, "empty or non-finite box");
+        need[a] = std::ceil((hi[a] - lo[a]) / h) + 2.0 * pad;
+        if (need[a] < 1.0) need[a] = 1.0;
+        most = std::max(most, need[a]);
+    }
+    int L = 0;
+    while (most / std::ldexp(1.0, L) > 32.0) ++L;
+    const double q = std::ldexp(1.0, L);
+    double cells = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const double n = std::max(std::ceil(need[a] / q), 2.0) * q;
+        require(n <= 1 << 20, WG_EINVAL, "grid extent above 2^20 cells");
+        g.n[a] = (int)n;
+        cells *= n;
+        g.lo[a] = 0.5 * (lo[a] + hi[a]) - 0.5 * n * h;
+    }
+    require(cells < 2.0e9, WG_EINVAL, "grid too large for 32-bit cell indices");
+    g.h = h;
+}
+
+void grid_from_cloud(const float *xyz, int npts, double density, int pad, wg_grid &g, hipStream_t s) {
+    require(npts > 0 && xyz != nullptr, WG_EINVAL, "an empty cloud has no bounding box");
+    // a small device record and its host copy (set-up, not a hot path)
+    uint32_t *dev = nullptr;
+    WG_HIP(hipMalloc(&dev, 8 * sizeof(uint32_t)));
+    uint32_t host[8] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u, 0u};
+    try {
+        WG_HIP(hipMemcpyAsync(dev, host, sizeof(host), hipMemcpyHostToDevice, s));
+        const unsigned blocks = std::min<unsigned>(cdiv(npts, 256), 1024u);
+        k_bbox<<<blocks, 256, 0, s>>>(xyz, npts, dev, reinterpret_cast<int *>(dev + 6));
+        WG_LAUNCH_CHECK();
+        WG_HIP(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s));
+        WG_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipFree(dev);
+        throw;
+    }
+    WG_HIP(hipFree(dev));
+    require(host[6] == 0, WG_EINVAL, "a point coordinate is NaN or infinite");
+    auto value = [](uint32_t k) {
+        const uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+        float f;
+        std::memcpy(&f, &b, 4);
+        return (double)f;
+    };
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = value(host[a]);
+        hi[a] = value(host[3 + a]);
+    }
+    grid_from_bbox(lo, hi, density, pad, g);
+}
+
+// ---------------------------------------------------------------------------
 // error channel
 // ---------------------------------------------------------------------------
 
@@ -632,6 +703,23 @@ int wg_sdf_from_field(wg_recon *r, const double *d_chi, double c, wg_stats *stat
     return guarded([&] {
         wg::require(r, WG_EINVAL, "null handle");
         return r->impl->sdf_from_field(d_chi, c, stats);
+    });
+}
+
+int wg_grid_from_bbox(const double lo[3], const double hi[3], double density, int pad_cells, wg_grid *out) {
+    return guarded([&] {
+        wg::require(lo && hi && out, WG_EINVAL, "null argument");
+        wg::grid_from_bbox(lo, hi, density, pad_cells, *out);
+        return WG_OK;
+    });
+}
+
+int wg_grid_from_cloud(const float *d_xyz, int n_points, double density, int pad_cells, wg_grid *out,
+                       void *hip_stream) {
+    return guarded([&] {
+        wg::require(out != nullptr, WG_EINVAL, "null argument");
+        wg::grid_from_cloud(d_xyz, n_points, density, pad_cells, *out, (hipStream_t)hip_stream);
+        return WG_OK;
     });
 }
 

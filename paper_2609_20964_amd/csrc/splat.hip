@@ -256,6 +256,39 @@ __global__ __launch_bounds__(256) void k_fixed_to_b(const long long *acc, const 
 template __global__ void k_fixed_to_b<float>(const long long *, const FixedScale *, size_t, float *);
 template __global__ void k_fixed_to_b<double>(const long long *, const FixedScale *, size_t, double *);
 
+// Bounding box of a cloud: per axis the minimum and maximum coordinate, as
+// order-preserving unsigned keys (a float's bits with the sign bit flipped for
+// non-negative values and all bits flipped for negative ones), so that
+// unsigned atomics take exact minima and maxima in any order.  box[0..2] min,
+// box[3..5] max; box is set to (0xffffffff x 3, 0 x 3) before the launch.
+__device__ __forceinline__ uint32_t order_key(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ xyz, int npts, uint32_t *box, int *err) {
+    uint32_t mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
+    bool bad = false;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            const float v = xyz[3 * i + a];
+            bad |= !isfinite(v);
+            const uint32_t k = order_key(v);
+            mn[a] = min(mn[a], k);
+            mx[a] = max(mx[a], k);
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = min(mn[a], (uint32_t)__shfl_xor((int)mn[a], o, 64));
+            mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], o, 64));
+        }
+    if (__ballot(bad) != 0 && threadIdx.x % 64 == 0) atomicOr(err, 1);
+    if (threadIdx.x % 64 == 0)
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(box + a, mn[a]);
+            atomicMax(box + 3 + a, mx[a]);
+        }
+}
+
 namespace {
 
 // Trilinear stencil of a cell-centred field at a world point: base cell and

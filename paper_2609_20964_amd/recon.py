@@ -35,6 +35,15 @@ def _precision(p):
     return codes[p]
 
 
+def grid_from_cloud(xyz, density, pad=3):
+    """(n, lo, h) of a grid over the bounding box of the device points xyz
+    [N,3] with density cells per unit length (wg_grid_from_cloud)."""
+    g = L.WgGrid()
+    L.check(L.lib().wg_grid_from_cloud(_dev(xyz, torch.float32, 3, "xyz"), int(xyz.shape[0]), float(density),
+                                       int(pad), C.byref(g), C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return tuple(g.n), tuple(g.lo), g.h
+
+
 class Recon:
     """One reconstruction grid resident on the current CUDA device.
 

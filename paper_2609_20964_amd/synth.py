@@ -182,6 +182,16 @@ def star(coeffs, n_points, dir_seed, semi_axes=(0.30, 0.12, 0.15), p=3.0, rotati
     return _f32(pts.detach().numpy()), _f32(nrm.detach().numpy())
 
 
+def fish(n_points=200_000, seed=(811, 812), semi_axes=(0.40, 0.14, 0.18), p=2.5):
+    """A fish-like body for bounding-box grids: an elongated star shape
+    (semi-axes 0.40 x 0.14 x 0.18, exponent 2.5, 16 seeded Fourier
+    coefficients) centred at (0.5, 0.5, 0.5): bounding box about 0.8 x 0.28 x
+    0.36, the proportions of the paper's fish grid (338 x 120 x 151 cells).
+    Returns float32 points and unit normals."""
+    c = draw_star_coeffs(seed[0])
+    return star(c, n_points, seed[1], semi_axes=semi_axes, p=p)
+
+
 @dataclass
 class DiffCase:
     """The differentiable workload: 16 coefficients, 100k points, 65,536 targets."""

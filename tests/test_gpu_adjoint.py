@@ -152,3 +152,37 @@ def test_adjoint_against_central_differences_on_the_gpu():
     print(f"positions ({stay.mean():.3f} of points moved): adjoint {ad:.6e} fd {fd:.6e}", flush=True)
     assert abs(ad - fd) <= 2e-2 * abs(fd)
     r.close()
+
+
+def test_shape_optimisation_recovers_the_target_shape():
+    """Sec. 3.3's inverse design on the library's gradients: Adam over the 16
+    coefficients of a star-shaped body, started from the target's coefficients
+    perturbed by up to 0.02 each.  The loss is Eq. (40): the squared mismatch
+    of the reconstructed SDF with the target's SDF (reconstructed from the
+    target shape's cloud by the same pipeline), at 8192 points in a band
+    around the target surface, 64^3 grid; it is 0 at the target's coefficients.
+    Within 60 epochs the loss falls by at least 10x and the largest coefficient
+    error by at least 2x."""
+    import torch
+
+    from paper_2609_20964_amd.optimize import optimise_shape
+    from paper_2609_20964_amd.recon import Recon
+    c_t = synth.draw_star_coeffs(1101)
+    start = c_t + np.random.default_rng(1102).uniform(-0.02, 0.02, c_t.shape)
+    dirs = synth.unit_sphere_dirs(np.random.default_rng(1103), 20000)
+    rng = np.random.default_rng(1104)
+    tdirs = synth.unit_sphere_dirs(rng, 8192)
+    q = (synth.X0 + (synth.StarShape(c_t).rho(tdirs) * rng.uniform(0.85, 1.15, 8192))[:, None] * tdirs)
+    q = q.astype(np.float32)
+    pts, nrm = synth.star_points_torch(synth.StarShape(c_t), dirs, torch.tensor(c_t, dtype=torch.float64))
+    r = Recon(64, len(dirs))
+    r.forward(pts.detach().float().cuda().contiguous(), nrm.detach().float().cuda().contiguous(), rel_tol=1e-6)
+    phi_t, _ = r.sample(_cuda(q), normals=False)
+    phi_t = phi_t.cpu().numpy()
+    r.close()
+    _, hist = optimise_shape(synth.StarShape(start), dirs, start, q, phi_target=phi_t, n=64, epochs=60, lr=2e-3,
+                             target_coeffs=c_t)
+    print("loss", [f"{v:.3e}" for v in hist.loss[::6]], "coeff err", [f"{v:.4f}" for v in hist.coeff_err[::6]],
+          flush=True)
+    assert min(hist.loss[-5:]) <= hist.loss[0] / 10
+    assert hist.coeff_err[-1] <= hist.coeff_err[0] / 2
