@@ -18,12 +18,17 @@ import numpy as np
 
 from . import adjoint as adj
 from . import discretize as D
+from . import galerkin as G
 from . import surface as S
 
 
 class Recon:
-    def __init__(self, grid: D.Grid, x32, n32, keys=None, bc="neumann"):
+    """exact=True: the Galerkin system with exact quadrature (oracle/galerkin.py)
+    instead of vertex quadrature (the 7-point operator)."""
+
+    def __init__(self, grid: D.Grid, x32, n32, keys=None, bc="neumann", exact=False):
         self.grid = grid
+        self.exact = exact
         self.x = np.asarray(x32, np.float64)
         self.n = np.asarray(n32, np.float64)
         k, inside = D.cell_keys(grid, x32)
@@ -32,8 +37,12 @@ class Recon:
         self.keys = k if keys is None else np.asarray(keys, np.int64)
         self.cells, self.alpha = D.splat_weights(grid, x32, self.keys)
         self.V = D.normal_field(grid, self.cells, self.alpha, n32)
-        self.b = D.divergence(grid, self.V)
-        self.chi = D.solve(self.b)
+        if exact:
+            self.b = G.divergence(grid, self.V)
+            self.chi = G.solve(self.b)
+        else:
+            self.b = D.divergence(grid, self.V)
+            self.chi = D.solve(self.b)
         self.c = D.iso_value(grid, self.chi, x32)
         self.mesh = S.extract(self.chi, self.c)
         N = int(np.prod(grid.n))
@@ -131,9 +140,9 @@ class Recon:
         g_chi += adj.scatter(g.shape, pc, pw * (g_c / Np))
         g_x = (g_c / Np) * np.sum(pdw * D.gather(self.chi, pc)[..., None], axis=1)
         # B4: adjoint solve (A symmetric), Eq. 38
-        lam = D.solve(D.project_mean(g_chi))
-        # B5, B6: Eq. 39 through b = -h^2 D_h V(x, n)
-        gV = adj.divergence_T(g, lam)
+        lam = (G.solve if self.exact else D.solve)(D.project_mean(g_chi))
+        # B5, B6: Eq. 39 through b = -h^2 D_h V(x, n) (or its exact-quadrature form)
+        gV = G.divergence_T(g, lam) if self.exact else adj.divergence_T(g, lam)
         dalpha = adj.splat_weight_grad(g, self.x, self.keys)
         gx2, g_n = adj.splat_T(g, self.cells, self.alpha, dalpha, self.n, gV)
         self.lam = lam
