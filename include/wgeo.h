@@ -57,6 +57,19 @@ enum {
 
 enum { WG_BC_NEUMANN = 0, WG_BC_DIRICHLET = 1 };
 
+/* wg_solve_opts.quadrature: how the Galerkin integrals of Eq. 21 and 26 are taken */
+enum {
+    WG_VERTEX_QUADRATURE = 0, /* at the grid vertices: the 7-point operator (diagonal =
+                                 interior neighbours, off-diagonal -1) and b = -h^2 D_h V
+                                 with face-averaged fluxes                          */
+    WG_EXACT_QUADRATURE = 1   /* exactly, for the trilinear tents mirrored across the
+                                 outer faces: the 27-point Q1 stiffness {8/3, 0, -1/6,
+                                 -1/12} (indices clamped at the faces) and b = h sum_xi
+                                 (g along xi, m across) V_xi with the 1-D mass m =
+                                 (1/6, 2/3, 1/6); the solver keeps the 7-point
+                                 multigrid as preconditioner.  FP32 splat only.      */
+};
+
 /* wg_solve_opts.precision */
 enum {
     WG_FP32_FP64REDUCE = 0, /* splat weights and sums in FP32 (FP32 atomics); stencil
@@ -94,6 +107,7 @@ typedef struct {
                            fits below 2^61 (a bound on any cell's sum).  Forward
                            pass only: the reverse pass still scatters with FP32
                            atomics.  0: FP32 atomics (WG_FP64 implies 1).      */
+    int quadrature;     /* WG_VERTEX_QUADRATURE (0) or WG_EXACT_QUADRATURE (1)     */
 } wg_solve_opts;
 
 typedef struct {
@@ -197,7 +211,9 @@ int wg_recon_wait(wg_recon *r);
  * given dL/dphi(q) (d_gphi, [n_q]) and optionally dL/dn(q) (d_gnrm, [n_q][3]
  * or NULL), writes dL/dx (d_gxyz, [n_points][3]) and dL/dn_i (d_gnrm_pts,
  * [n_points][3]) for the points of the last forward, and dL/dq (d_gq,
- * [n_q][3], or NULL).  Runs one adjoint Poisson solve with opts.
+ * [n_q][3], or NULL).  Runs one adjoint Poisson solve with opts; the
+ * quadrature is the last forward's whatever opts->quadrature says (the
+ * reverse pass differentiates the system that forward solved).
  * Gradients hold almost everywhere: the central cell of each point is kept
  * fixed, Marching Cubes cases and nearest triangles are those of the forward.
  * WG_ESTATE if no forward has run on r. */
@@ -208,7 +224,8 @@ int wg_recon_backward(wg_recon *r, const float *d_q, int n_q, const float *d_gph
 /* Standalone Poisson solve on r's grid (Eq. 20-21): A x = b with bc
  * WG_BC_NEUMANN (zero flux; b is projected to zero mean and x returned with
  * zero mean) or WG_BC_DIRICHLET (cell-centred ghost = -x; test mode).
- * d_b: [N] float32; d_x: [N] float64, used as the initial guess when
+ * opts->quadrature picks the operator (exact: WG_BC_NEUMANN only, else
+ * WG_EINVAL).  d_b: [N] float32; d_x: [N] float64, used as the initial guess when
  * opts->warm_start is set, overwritten with the solution. */
 int wg_poisson_solve(wg_recon *r, const float *d_b, double *d_x, int bc,
                      const wg_solve_opts *opts, wg_stats *stats);

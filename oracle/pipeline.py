@@ -110,9 +110,9 @@ class Recon:
             gn = np.asarray(g_n_q, np.float64)
             nodes = cells.reshape(-1, 3)
             gc = S.node_gradient(g, self.phi, nodes).reshape(M, 8, 3)
-            G = np.sum(w[..., None] * gc, axis=1)
-            nG = np.linalg.norm(G, axis=1, keepdims=True)
-            nh = G / np.where(nG > 0, nG, 1.0)
+            Gs = np.sum(w[..., None] * gc, axis=1)
+            nG = np.linalg.norm(Gs, axis=1, keepdims=True)
+            nh = Gs / np.where(nG > 0, nG, 1.0)
             gG = np.where(nG > 0, (gn - nh * np.sum(nh * gn, 1, keepdims=True)) / np.where(nG > 0, nG, 1.0), 0.0)
             g_q += np.einsum("mcx,mcy,my->mx", dw, gc, gG)
             g_gc = (w[..., None] * gG[:, None, :]).reshape(-1, 3)       # dL/d grad_c

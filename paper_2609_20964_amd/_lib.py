@@ -15,6 +15,7 @@ WG_OK, WG_PENDING = 0, 1
 WG_EINVAL, WG_ENOMEM, WG_ENOTCONV, WG_ENUMERIC, WG_EDEVICE, WG_ESTATE = -1, -2, -3, -4, -5, -6
 WG_BC_NEUMANN, WG_BC_DIRICHLET = 0, 1
 WG_FP32_FP64REDUCE, WG_FP64 = 0, 1
+WG_VERTEX_QUADRATURE, WG_EXACT_QUADRATURE = 0, 1
 CODE_NAMES = {WG_EINVAL: "WG_EINVAL", WG_ENOMEM: "WG_ENOMEM", WG_ENOTCONV: "WG_ENOTCONV",
               WG_ENUMERIC: "WG_ENUMERIC", WG_EDEVICE: "WG_EDEVICE", WG_ESTATE: "WG_ESTATE"}
 
@@ -25,7 +26,7 @@ class WgGrid(C.Structure):
 
 class WgSolveOpts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_iters", C.c_int), ("warm_start", C.c_int),
-                ("precision", C.c_int), ("deterministic", C.c_int)]
+                ("precision", C.c_int), ("deterministic", C.c_int), ("quadrature", C.c_int)]
 
 
 class WgStats(C.Structure):
@@ -173,13 +174,15 @@ def grid_from_bbox(lo, hi, density, pad=3):
     return tuple(g.n), tuple(g.lo), g.h
 
 
-def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False, precision=WG_FP32_FP64REDUCE, deterministic=False):
+def make_opts(rel_tol=1e-6, max_iters=500, warm_start=False, precision=WG_FP32_FP64REDUCE, deterministic=False,
+              quadrature=WG_VERTEX_QUADRATURE):
     o = WgSolveOpts()
     o.rel_tol = float(rel_tol)
     o.max_iters = int(max_iters)
     o.warm_start = int(bool(warm_start))
     o.precision = int(precision)
     o.deterministic = int(bool(deterministic))
+    o.quadrature = int(quadrature)
     return o
 
 

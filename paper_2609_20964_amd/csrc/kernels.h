@@ -73,7 +73,7 @@ template <class T> class HostMapped {
 struct FixedScale {
     double scale, inv;
 };
-enum { kSplatF32 = 0, kSplatFixed = 1, kSplatFixed64 = 2 };
+enum { kSplatF32 = 0, kSplatFixed = 1, kSplatFixed64 = 2, kSplatExact = 3 };
 
 __global__ void k_bin_points(const float *xyz, const float *nrm, int npts, GridF g, TileDims td, int32_t *keys,
                              float *xyz_c, float *nrm_c, int32_t *tile_of, uint32_t *rank, uint32_t *tile_cnt,
@@ -94,7 +94,14 @@ __global__ void k_fixed_to_b(const long long *acc, const FixedScale *fix, size_t
 __global__ void k_iso_partial(const float *xyz, int npts, GridF g, const double *chi, double *partials);
 __global__ void k_iso_finalize(const double *partials, int nb, int npts, double *out);
 __global__ void k_iso_T(const float *xyz, int npts, GridF g, const double *g_c, float *g_chi);
+// three cell fields (the exact-quadrature g_V by axis)
+struct Planes3 {
+    float *p[3];
+};
+template <bool EXACT>
 __global__ void k_splat_T(const float *xyz, const float *nrm, const int32_t *keys, int npts, GridF g,
-                          const double *lam, const double *chi, const double *g_c, float *gxyz, float *gnrm);
+                          const double *lam, Planes3 gvp, const double *chi, const double *g_c, float *gxyz,
+                          float *gnrm);
+__global__ void k_grad27_T(const double *lam, Dims d, double h, Planes3 gv);
 
 }  // namespace wg

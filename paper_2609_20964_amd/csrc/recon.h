@@ -83,6 +83,7 @@ class Recon {
     int n_points_ = 0;
     bool have_forward_ = false;
     bool field_only_ = false;   // the last surface came from wg_sdf_from_field (no cloud)
+    int quad_ = WG_VERTEX_QUADRATURE;   // quadrature of the last forward's system
     // second stream: the distance walk (and pipelined sampling)
     hipStream_t sdf_st_ = nullptr;
     hipEvent_t ev_mc_ = nullptr, ev_sdf_ = nullptr, ev_tail_ = nullptr;

@@ -150,6 +150,10 @@ Recon::~Recon() {
 void check_opts(const wg_solve_opts &o) {
     require(o.precision == WG_FP32_FP64REDUCE || o.precision == WG_FP64, WG_EINVAL, "unknown precision");
     require(o.deterministic == 0 || o.deterministic == 1, WG_EINVAL, "deterministic must be 0 or 1");
+    require(o.quadrature == WG_VERTEX_QUADRATURE || o.quadrature == WG_EXACT_QUADRATURE, WG_EINVAL,
+            "unknown quadrature");
+    require(o.quadrature == WG_VERTEX_QUADRATURE || (o.precision == WG_FP32_FP64REDUCE && o.deterministic == 0),
+            WG_EINVAL, "exact quadrature runs with the FP32 splat only (no WG_FP64, not deterministic)");
 }
 
 // The handle stream waits (on the device) for the last distance walk.
@@ -230,7 +234,10 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
         scan::k_scan_final<<<nblk, 256, 0, st_>>>(ch_cnt_, nt, ch_blk_, ch_off_, ch_act_);
         k_chunk_tiles<<<cdiv(nt, 256), 256, 0, st_>>>(ch_cnt_, ch_off_, nt, chunk_tile_);
         const unsigned grid = std::min<unsigned>(2048u, nt + cdiv(npts, kChunk));
-        if (!fixed) {
+        if (o.quadrature == WG_EXACT_QUADRATURE) {
+            k_splat_chunks<kSplatExact><<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_, chunk_tile_,
+                                                               ch_tot_, xyz_, nrm_, gf_, td_, b_, nullptr, nullptr);
+        } else if (!fixed) {
             k_splat_chunks<kSplatF32><<<grid, 256, 0, st_>>>(perm_, tile_off_, tile_cnt_, ch_off_, chunk_tile_,
                                                              ch_tot_, xyz_, nrm_, gf_, td_, b_, nullptr, nullptr);
         } else {
@@ -284,6 +291,7 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     WG_HIP(hipEventSynchronize(tm.ev[5]));   // the timing events (a pipelined walk runs on the second stream)
     have_forward_ = true;
     field_only_ = false;
+    quad_ = o.quadrature;
     if (st) {
         std::memset(st, 0, sizeof(*st));
         st->iters = sr.iters;
@@ -393,7 +401,10 @@ int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gn
     require(!field_only_, WG_ESTATE, "backward after wg_sdf_from_field (no point cloud to differentiate)");
     require(nq >= 0 && (nq == 0 || (q && gphi_q)), WG_EINVAL, "bad query arguments");
     require(n_points_ == 0 || (gxyz && gnrm_pts), WG_EINVAL, "null point-gradient outputs");
-    check_opts(o);
+    wg_solve_opts ao = o;
+    ao.warm_start = 0;
+    ao.quadrature = quad_;
+    check_opts(ao);
     const size_t N = d_.count();
     join();
     Timer tm(st_);
@@ -412,14 +423,19 @@ int Recon::backward(const float *q, int nq, const float *gphi_q, const float *gn
     }
     tm.mark(1);
     // B4: adjoint solve A lambda = P g_chi (A symmetric), from zero
-    wg_solve_opts ao = o;
-    ao.warm_start = 0;
     SolveResult sr = solver_.solve(gchi_, lam_, WG_BC_NEUMANN, ao);
     if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the adjoint solve");
     // B5 + B6: transposed divergence and splat, plus the iso-value point term
-    if (n_points_ > 0) {
-        k_splat_T<<<cdiv(n_points_, 256), 256, 0, st_>>>(xyz_, nrm_, keys_, n_points_, gf_, lam_, chi_, scal_ + 2,
-                                                         gxyz, gnrm_pts);
+    if (n_points_ > 0 && quad_ == WG_EXACT_QUADRATURE) {
+        // g_V by axis on the whole grid, in three solver vectors that are free after the solve
+        const Planes3 gv{{solver_.spare(0), solver_.spare(1), solver_.spare(2)}};
+        k_grad27_T<<<std::min<unsigned>(cdiv(N, 256), 8192u), 256, 0, st_>>>(lam_, d_, grid_.h, gv);
+        k_splat_T<true><<<cdiv(n_points_, 256), 256, 0, st_>>>(xyz_, nrm_, keys_, n_points_, gf_, lam_, gv, chi_,
+                                                               scal_ + 2, gxyz, gnrm_pts);
+        WG_LAUNCH_CHECK();
+    } else if (n_points_ > 0) {
+        k_splat_T<false><<<cdiv(n_points_, 256), 256, 0, st_>>>(xyz_, nrm_, keys_, n_points_, gf_, lam_, Planes3{},
+                                                                chi_, scal_ + 2, gxyz, gnrm_pts);
         WG_LAUNCH_CHECK();
     }
     tm.mark(2);

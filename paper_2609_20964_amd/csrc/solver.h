@@ -4,6 +4,10 @@
 // vertex quadrature, A = -h^2 L_h: (A x)_i = sum over the cell's interior
 // faces of (x_i - x_j); zero-flux (Neumann, Eq. 19) boundaries, or the
 // cell-centred Dirichlet test mode (ghost = -x, diagonal 6 + #boundary faces).
+// With exact quadrature (zero-flux only) the fine-level operator is the
+// 27-point Q1 stiffness of the same equations; the multigrid preconditioner
+// stays the 7-point one, whose spectrum bounds the 27-point one from above
+// and within a factor 9 from below.
 //
 // Precision scheme: the solution lives in FP64; each refinement step forms the
 // FP64 residual r = P(b - A x) (P: mean removal for Neumann), solves A e = r
@@ -67,6 +71,10 @@ class Solver {
     // x -= mean (FP64), used where a zero-mean field is promised.
     void shift(double *x, double by);
 
+    // Three fine-level FP32 vectors (the CG directions and A p) that hold
+    // nothing between solves; callers may use them as scratch there.
+    float *spare(int k) const { return k == 0 ? p_[0] : (k == 1 ? p_[1] : q_); }
+
     // z = M r: one V-cycle of the preconditioner with boundary condition bc
     // (r, z: FP32 on the device, on the solver's stream).
     void mg_apply(const float *r, float *z, int bc);
@@ -87,6 +95,8 @@ class Solver {
     int pcg(double tol, int max_it, bool &non_finite);
     void pcg_iteration(int it, int &cur);
     void finalize(int mode, unsigned nb, int flag);
+    template <class Op> void sweep(const Op &op, int kind, double bytes_per_cell, const int *skip);
+    unsigned sweep_partials() const;
     void read_scalars();
     unsigned long long wait_status(unsigned want);
 
@@ -107,6 +117,7 @@ class Solver {
     int coarse_direct_ = 0;
     unsigned post_blocks_ = 0;   // workgroups of the finest post-smoothing pass (partials of r.z)
     int bc_sign_ = -1;
+    bool exact_ = false;   // fine-level operator: the 27-point exact-quadrature stiffness
 };
 
 }  // namespace wg

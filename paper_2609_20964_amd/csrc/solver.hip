@@ -215,6 +215,72 @@ __global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, doub
     }
 }
 
+// 27-point sweep of the exact-quadrature stiffness (Eq. 21 integrated exactly
+// for trilinear tents mirrored across the outer faces):
+//   A = k (x) m (x) m + m (x) k (x) m + m (x) m (x) k,
+// with m = (1, 4, 1)/6 and k = (-1, 2, -1) along each axis and indices clamped
+// to the grid (Neumann only).  A wavefront holds 64 consecutive x cells of one
+// row (x neighbours by lane shuffles, the row ends load theirs), a workgroup
+// four rows, and each marches ZC planes in z.  Per plane it forms the in-plane
+// filters Q = m_x m_y u and P = (k_x m_y + m_x k_y) u and keeps three planes;
+// plane z's output is sum_dz m(dz) P(z + dz) + k(dz) Q(z + dz), z + dz clamped.
+// Op::applyA(idx, centre, A u, acc) consumes one cell.
+template <class Op>
+__global__ __launch_bounds__(256) void k_stencil27(Op op, Dims d, Tiles t, double *partials, const int *skip) {
+    using T = typename Op::T;
+    if (skipped(skip)) return;
+    fetch_scalars(op);
+    const unsigned nb = t.count();
+    const unsigned lb = xcd_logical_block(blockIdx.x, nb);
+    const unsigned bx = lb % t.gx, by = (lb / t.gx) % t.gy, bz = lb / (t.gx * t.gy);
+    const int lane = threadIdx.x % TX;
+    const int i = bx * TX + lane;
+    const int j = by * TY + threadIdx.x / TX;   // one row per wavefront
+    const int z0 = bz * ZC;
+    double acc[Op::NRED > 0 ? Op::NRED : 1];
+    for (int k = 0; k < (Op::NRED > 0 ? Op::NRED : 1); ++k) acc[k] = 0.0;
+    if (j < d.ny) {   // uniform over the wavefront
+        const size_t plane = (size_t)d.nx * d.ny;
+        const int ic = min(i, d.nx - 1);   // lanes past the row end shadow its last cell
+        const size_t rows[3] = {(size_t)max(j - 1, 0) * d.nx, (size_t)j * d.nx, (size_t)min(j + 1, d.ny - 1) * d.nx};
+        const T sixth = T(1) / T(6);
+        // in-plane filters of plane z: P, Q and the centre value
+        auto filt = [&](int z, T &P, T &Q, T &C) {
+            T mx[3], kx[3];
+            for (int r = 0; r < 3; ++r) {
+                const size_t base = (size_t)z * plane + rows[r];
+                const T c = op.load(base + ic);
+                T l = __shfl_up(c, 1, 64), rr = __shfl_down(c, 1, 64);
+                if (lane == 0) l = op.load(base + max(ic - 1, 0));
+                if (lane == TX - 1 || i + 1 >= d.nx) rr = i + 1 < d.nx ? op.load(base + i + 1) : c;
+                mx[r] = (l + T(4) * c + rr) * sixth;
+                kx[r] = T(2) * c - l - rr;
+                if (r == 1) C = c;
+            }
+            Q = (mx[0] + T(4) * mx[1] + mx[2]) * sixth;
+            P = (kx[0] + T(4) * kx[1] + kx[2]) * sixth + (T(2) * mx[1] - mx[0] - mx[2]);
+        };
+        const int z1 = min(z0 + ZC, d.nz);
+        T Pm, Qm, Cm, Pc, Qc, Cc;
+        filt(max(z0 - 1, 0), Pm, Qm, Cm);
+        filt(z0, Pc, Qc, Cc);
+        for (int k = z0; k < z1; ++k) {
+            T Pp, Qp, Cp;
+            filt(min(k + 1, d.nz - 1), Pp, Qp, Cp);
+            const T au = (Pm + T(4) * Pc + Pp) * sixth + (T(2) * Qc - Qm - Qp);
+            if (i < d.nx) op.applyA(rows[1] + (size_t)i + (size_t)k * plane, Cc, au, acc);
+            Pm = Pc; Qm = Qc; Cm = Cc;
+            Pc = Pp; Qc = Qp; Cc = Cp;
+        }
+    }
+    if constexpr (Op::NRED > 0) {
+        __shared__ double lds[4][Op::NRED];
+        block_sum<Op::NRED>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < Op::NRED; ++k) partials[(size_t)k * nb + lb] = acc[k];
+    }
+}
+
 // r = (b - mb) - A x in FP64 (r stored FP32); sums of r, r^2, x, b - mb,
 // (b - mb)^2.  mb is the mean of b for zero-flux boundaries (the compatibility
 // projection of the right-hand side), 0 otherwise.
@@ -255,6 +321,16 @@ struct OpResid64 {
             acc[4] += bv * bv;
         }
         st4(r + i, out);
+    }
+    __device__ void applyA(size_t i, double c, double au, double *acc) const {
+        const double bv = (double)b[i] - mb;
+        const double rv = bv - au;
+        r[i] = (float)rv;
+        acc[0] += rv;
+        acc[1] += rv * rv;
+        acc[2] += c;
+        acc[3] += bv;
+        acc[4] += bv * bv;
     }
 };
 
@@ -351,6 +427,11 @@ struct OpPMatvec {
         }
         st4(pnew + i, c);
         st4(q + i, qq);
+    }
+    __device__ void applyA(size_t i, float c, float au, double *acc) const {
+        pnew[i] = c;
+        q[i] = au;
+        acc[0] += (double)c * (double)au;
     }
 };
 
@@ -1144,6 +1225,7 @@ unsigned post_blocks(const Dims *dims, int nl) { return nl > 1 ? vtile_of(dims[0
 
 size_t partial_slots(const Dims *dims, int nl) {
     size_t nb = sweep_blocks(dims[0]);
+    if (tiles_of(dims[0]).count() > nb) nb = tiles_of(dims[0]).count();   // the 27-point sweep
     const size_t pb = post_blocks(dims, nl);
     if (pb > nb) nb = pb;
     return (nb > (size_t)kRedBlocks ? nb : (size_t)kRedBlocks) * kMaxRed;
@@ -1282,6 +1364,22 @@ static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStr
     WG_LAUNCH_CHECK();
 }
 
+// The fine-level operator: the 7-point sweep, or (exact quadrature) the 27-point one.
+template <class Op>
+void Solver::sweep(const Op &op, int kind, double bytes_per_cell, const int *skip) {
+    const Dims &d = lv_[0].d;
+    if (!exact_) {
+        launch_stencil(op, d, partials_, st_, kind, bytes_per_cell, skip);
+        return;
+    }
+    prof::Scope ps(kind, st_, bytes_per_cell * (double)d.count());
+    const Tiles t = tiles_of(d);
+    k_stencil27<Op><<<t.count(), TX * TY, 0, st_>>>(op, d, t, partials_, skip);
+    WG_LAUNCH_CHECK();
+}
+
+unsigned Solver::sweep_partials() const { return exact_ ? tiles_of(lv_[0].d).count() : sweep_blocks(lv_[0].d); }
+
 void Solver::vcycle(int l) {
     Level &L = lv_[l];
     L.d.bc_sign = bc_sign_;
@@ -1367,12 +1465,10 @@ void Solver::pcg_iteration(int it, int &cur) {
         cur ^= 1;
     }
     if (it == 0)
-        launch_stencil(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, F.d, partials_, st_,
-                       pk(WG_PROF_SWEEP), 12.0, skip_);
+        sweep(OpPMatvec<true>{F.x, nullptr, p_[cur], q_, nullptr, 0.f}, pk(WG_PROF_SWEEP), 12.0, skip_);
     else   // beta = rz / rz_old, formed by the last finalize, read on the device
-        launch_stencil(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, F.d, partials_, st_,
-                       pk(WG_PROF_SWEEP), 16.0, skip_);
-    finalize(FIN_PQ, sweep_blocks(F.d), 0);
+        sweep(OpPMatvec<false>{F.x, p_[cur ^ 1], p_[cur], q_, dsc_, 0.f}, pk(WG_PROF_SWEEP), 16.0, skip_);
+    finalize(FIN_PQ, sweep_partials(), 0);
     const unsigned rb = red_blocks(N);
     {
         prof::Scope ps(pk(WG_PROF_CGUPDATE), st_, (it == 0 ? 20.0 : 24.0) * (double)N);
@@ -1435,11 +1531,16 @@ SolveResult Solver::solve(const double *b, double *x, int bc, const wg_solve_opt
 template <class TB>
 SolveResult Solver::solve_impl(const TB *b, double *x, int bc, const wg_solve_opts &o) {
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
+    require(o.quadrature == WG_VERTEX_QUADRATURE || o.quadrature == WG_EXACT_QUADRATURE, WG_EINVAL,
+            "unknown quadrature");
+    require(o.quadrature == WG_VERTEX_QUADRATURE || bc == WG_BC_NEUMANN, WG_EINVAL,
+            "exact quadrature is defined for zero-flux boundaries only");
+    exact_ = o.quadrature == WG_EXACT_QUADRATURE;
     bc_sign_ = bc == WG_BC_NEUMANN ? -1 : +1;
     for (int l = 0; l < nlv_; ++l) lv_[l].d.bc_sign = bc_sign_;
     Level &F = lv_[0];
     const size_t N = F.d.count();
-    const unsigned tb = sweep_blocks(F.d);
+    const unsigned tb = sweep_partials();
     const unsigned gb = red_blocks(N);
     SolveResult res;
     static_assert(sizeof(SolveScalars) % 4 == 0, "scalars are whole words");
@@ -1461,8 +1562,7 @@ SolveResult Solver::solve_impl(const TB *b, double *x, int bc, const wg_solve_op
     const int max_iters = o.max_iters > 0 ? o.max_iters : 500;
     double bnorm = -1.0;
     for (;;) {
-        launch_stencil(OpResid64<TB>{x, b, F.rhs, mean_src, 0.0}, F.d, partials_, st_, pk(WG_PROF_RESID64),
-                       12.0 + sizeof(TB));
+        sweep(OpResid64<TB>{x, b, F.rhs, mean_src, 0.0}, pk(WG_PROF_RESID64), 12.0 + sizeof(TB), nullptr);
         finalize(FIN_RESID, tb, bc == WG_BC_NEUMANN);
         read_scalars();
         ++res.refinements;

@@ -62,7 +62,9 @@ __device__ __forceinline__ bool in_range(int k, int o, int n) { return k + o >= 
 // inside the grid.  value = -(h/2) h^-3 / S * sum_xi n_xi (face terms).
 // |value| <= 3.75 h^-2 max_k |n_k|: |h^-2 / (2 S)| <= h^-2 (S >= 1/2), and each
 // face term pairs two raw weights summing to at most 0.625.
-template <class T, class Emit>
+// AXES: the three axis terms separately, emit(cx, cy, cz, vx, vy, vz) (the
+// exact-quadrature right-hand side filters each with the mass across its axis).
+template <bool AXES = false, class T, class Emit>
 __device__ __forceinline__ void point_divergence(const AxisW<T> &X, const AxisW<T> &Y, const AxisW<T> &Z, T n0, T n1,
                                                  T n2, const GridF &g, Emit &&emit) {
     const T Sx = X.a[0] + X.a[1] + X.a[2], Sy = Y.a[0] + Y.a[1] + Y.a[2], Sz = Z.a[0] + Z.a[1] + Z.a[2];
@@ -78,14 +80,21 @@ __device__ __forceinline__ void point_divergence(const AxisW<T> &X, const AxisW<
                 if (!in_range(X.k, cx, g.d.nx) || !in_range(Y.k, cy, g.d.ny) || !in_range(Z.k, cz, g.d.nz))
                     continue;
                 const T r0 = raw_w(X, Y, Z, cx, cy, cz);
-                T acc = T(0);
-                if (in_range(X.k, cx + 1, g.d.nx)) acc += n0 * (r0 + raw_w(X, Y, Z, cx + 1, cy, cz));
-                if (in_range(X.k, cx - 1, g.d.nx)) acc -= n0 * (raw_w(X, Y, Z, cx - 1, cy, cz) + r0);
-                if (in_range(Y.k, cy + 1, g.d.ny)) acc += n1 * (r0 + raw_w(X, Y, Z, cx, cy + 1, cz));
-                if (in_range(Y.k, cy - 1, g.d.ny)) acc -= n1 * (raw_w(X, Y, Z, cx, cy - 1, cz) + r0);
-                if (in_range(Z.k, cz + 1, g.d.nz)) acc += n2 * (r0 + raw_w(X, Y, Z, cx, cy, cz + 1));
-                if (in_range(Z.k, cz - 1, g.d.nz)) acc -= n2 * (raw_w(X, Y, Z, cx, cy, cz - 1) + r0);
-                if (acc != T(0)) emit(cx, cy, cz, coef * acc);
+                // one sum (in this order) or one per axis
+                T acc[3] = {T(0), T(0), T(0)};
+                T &ax = acc[0], &ay = acc[AXES ? 1 : 0], &az = acc[AXES ? 2 : 0];
+                if (in_range(X.k, cx + 1, g.d.nx)) ax += n0 * (r0 + raw_w(X, Y, Z, cx + 1, cy, cz));
+                if (in_range(X.k, cx - 1, g.d.nx)) ax -= n0 * (raw_w(X, Y, Z, cx - 1, cy, cz) + r0);
+                if (in_range(Y.k, cy + 1, g.d.ny)) ay += n1 * (r0 + raw_w(X, Y, Z, cx, cy + 1, cz));
+                if (in_range(Y.k, cy - 1, g.d.ny)) ay -= n1 * (raw_w(X, Y, Z, cx, cy - 1, cz) + r0);
+                if (in_range(Z.k, cz + 1, g.d.nz)) az += n2 * (r0 + raw_w(X, Y, Z, cx, cy, cz + 1));
+                if (in_range(Z.k, cz - 1, g.d.nz)) az -= n2 * (raw_w(X, Y, Z, cx, cy, cz - 1) + r0);
+                if constexpr (AXES) {
+                    if (acc[0] != T(0) || acc[1] != T(0) || acc[2] != T(0))
+                        emit(cx, cy, cz, coef * acc[0], coef * acc[1], coef * acc[2]);
+                } else if (acc[0] != T(0)) {
+                    emit(cx, cy, cz, coef * acc[0]);
+                }
             }
 }
 
@@ -159,7 +168,15 @@ __global__ __launch_bounds__(256) void k_chunk_tiles(const uint32_t *__restrict_
 //   kSplatF32:   FP32 contributions, FP32 atomics into b (b zero on entry);
 //   kSplatFixed: FP32 contributions rounded to 64-bit fixed point (unit
 //                fix->inv), integer atomics into acc (zero on entry);
-//   kSplatFixed64: the same with FP64 weights and contributions.
+//   kSplatFixed64: the same with FP64 weights and contributions;
+//   kSplatExact: the exact-quadrature right-hand side (Eq. 26 integrated
+//                exactly), b = sum_xi M_perp,xi b_xi, where b_xi is the
+//                kSplatF32 sum's xi term and M_perp,xi applies the 1-D mass
+//                m = (1, 4, 1)/6 (indices clamped to the grid) along the two
+//                other axes.  The three terms go to three LDS windows; after
+//                the chunk's points, each cell of the window widened by one
+//                (the mass reaches one cell further) gathers its filtered sum
+//                and adds it to b (FP32 atomics, b zero on entry).
 // Integer sums do not depend on the order the adds arrive in, so the fixed
 // point modes give the same acc however threads and workgroups interleave.
 template <int Mode>
@@ -172,17 +189,19 @@ __global__ __launch_bounds__(256) void k_splat_chunks(const uint32_t *__restrict
                                                        const float *__restrict__ xyz_c, const float *__restrict__ nrm_c,
                                                        GridF g, TileDims td, float *__restrict__ b,
                                                        unsigned long long *__restrict__ acc, const FixedScale *fix) {
+    constexpr bool kFloat = Mode == kSplatF32 || Mode == kSplatExact;
     using T = typename std::conditional<Mode == kSplatFixed64, double, float>::type;
-    using W = typename std::conditional<Mode == kSplatF32, float, unsigned long long>::type;
-    constexpr int WN = kTile + 4;
-    __shared__ W win[WN * WN * WN];
+    using W = typename std::conditional<kFloat, float, unsigned long long>::type;
+    constexpr int WN = kTile + 4, W3 = WN * WN * WN;
+    constexpr int NW = Mode == kSplatExact ? 3 : 1;
+    __shared__ W win[NW * W3];
     const uint32_t total = n_chunks[0];
-    const double scale = Mode == kSplatF32 ? 0.0 : fix->scale;
+    const double scale = kFloat ? 0.0 : fix->scale;
     for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
         const uint32_t tile = chunk_tile[ch];
         const uint32_t c = ch - ch_off[tile];
         const uint32_t p0 = c * kChunk, p1 = min(p0 + kChunk, tile_cnt[tile]);
-        for (int l = threadIdx.x; l < WN * WN * WN; l += blockDim.x) win[l] = W(0);
+        for (int l = threadIdx.x; l < NW * W3; l += blockDim.x) win[l] = W(0);
         __syncthreads();
         const int T0x = (int)(tile % td.tx) * kTile, T0y = (int)((tile / td.tx) % td.ty) * kTile,
                   T0z = (int)(tile / (td.tx * td.ty)) * kTile;
@@ -194,14 +213,56 @@ __global__ __launch_bounds__(256) void k_splat_chunks(const uint32_t *__restrict
             bin_axis(xyz_c[3 * i + 1], g.lo[1], g.h, g.d.ny, Y, T(0));
             bin_axis(xyz_c[3 * i + 2], g.lo[2], g.h, g.d.nz, Z, T(0));
             const int lx = X.k - T0x + 2, ly = Y.k - T0y + 2, lz = Z.k - T0z + 2;
-            point_divergence(X, Y, Z, (T)nrm_c[3 * i], (T)nrm_c[3 * i + 1], (T)nrm_c[3 * i + 2], g,
-                             [&](int cx, int cy, int cz, T v) {
-                                 W *dst = win + (lx + cx) + WN * ((ly + cy) + WN * (lz + cz));
-                                 if constexpr (Mode == kSplatF32) atomicAdd(dst, v);
-                                 else atomicAdd(dst, (unsigned long long)__double2ll_rn((double)v * scale));
-                             });
+            if constexpr (Mode == kSplatExact) {
+                point_divergence<true>(X, Y, Z, nrm_c[3 * i], nrm_c[3 * i + 1], nrm_c[3 * i + 2], g,
+                                       [&](int cx, int cy, int cz, float vx, float vy, float vz) {
+                                           float *dst = win + (lx + cx) + WN * ((ly + cy) + WN * (lz + cz));
+                                           atomicAdd(dst, vx);
+                                           atomicAdd(dst + W3, vy);
+                                           atomicAdd(dst + 2 * W3, vz);
+                                       });
+            } else {
+                point_divergence(X, Y, Z, (T)nrm_c[3 * i], (T)nrm_c[3 * i + 1], (T)nrm_c[3 * i + 2], g,
+                                 [&](int cx, int cy, int cz, T v) {
+                                     W *dst = win + (lx + cx) + WN * ((ly + cy) + WN * (lz + cz));
+                                     if constexpr (Mode == kSplatF32) atomicAdd(dst, v);
+                                     else atomicAdd(dst, (unsigned long long)__double2ll_rn((double)v * scale));
+                                 });
+            }
         }
         __syncthreads();
+        if constexpr (Mode == kSplatExact) {
+            // output cells T0 - 3 .. T0 + kTile + 2 per axis; window coordinate
+            // of a grid cell: g - T0 + 2, valid in [0, WN)
+            constexpr int WO = kTile + 6;
+            const float mw[3] = {1.f / 6.f, 2.f / 3.f, 1.f / 6.f};
+            for (int l = threadIdx.x; l < WO * WO * WO; l += blockDim.x) {
+                const int gx = T0x - 3 + l % WO, gy = T0y - 3 + (l / WO) % WO, gz = T0z - 3 + l / (WO * WO);
+                if (gx < 0 || gx >= g.d.nx || gy < 0 || gy >= g.d.ny || gz < 0 || gz >= g.d.nz) continue;
+                // window coordinates of the clamped neighbours (-1: outside the window)
+                int wx[3], wy[3], wz[3];
+                for (int a = 0; a < 3; ++a) {
+                    const int ux = min(max(gx + a - 1, 0), g.d.nx - 1) - T0x + 2;
+                    const int uy = min(max(gy + a - 1, 0), g.d.ny - 1) - T0y + 2;
+                    const int uz = min(max(gz + a - 1, 0), g.d.nz - 1) - T0z + 2;
+                    wx[a] = (ux >= 0 && ux < WN) ? ux : -1;
+                    wy[a] = (uy >= 0 && uy < WN) ? uy : -1;
+                    wz[a] = (uz >= 0 && uz < WN) ? uz * WN * WN : -1;
+                }
+                float v = 0.f;
+                for (int a = 0; a < 3; ++a)
+                    for (int e = 0; e < 3; ++e) {
+                        const float w = mw[a] * mw[e];
+                        if (wx[1] >= 0 && wy[a] >= 0 && wz[e] >= 0) v += w * win[wx[1] + WN * wy[a] + wz[e]];
+                        if (wy[1] >= 0 && wx[a] >= 0 && wz[e] >= 0) v += w * win[W3 + wx[a] + WN * wy[1] + wz[e]];
+                        if (wz[1] >= 0 && wx[a] >= 0 && wy[e] >= 0)
+                            v += w * win[2 * W3 + wx[a] + WN * wy[e] + wz[1]];
+                    }
+                if (v != 0.f) unsafeAtomicAdd(b + (size_t)gx + (size_t)g.d.nx * (gy + (size_t)g.d.ny * gz), v);
+            }
+            __syncthreads();
+            continue;
+        }
         for (int l = threadIdx.x; l < WN * WN * WN; l += blockDim.x) {
             const W v = win[l];
             if (v == W(0)) continue;
@@ -220,6 +281,10 @@ template __global__ void k_splat_chunks<kSplatF32>(const uint32_t *, const uint3
                                                    const float *, GridF, TileDims, float *, unsigned long long *,
                                                    const FixedScale *);
 template __global__ void k_splat_chunks<kSplatFixed>(const uint32_t *, const uint32_t *, const uint32_t *,
+                                                     const uint32_t *, const uint32_t *, const uint32_t *,
+                                                     const float *, const float *, GridF, TileDims, float *,
+                                                     unsigned long long *, const FixedScale *);
+template __global__ void k_splat_chunks<kSplatExact>(const uint32_t *, const uint32_t *, const uint32_t *,
                                                      const uint32_t *, const uint32_t *, const uint32_t *,
                                                      const float *, const float *, GridF, TileDims, float *,
                                                      unsigned long long *, const FixedScale *);
@@ -365,17 +430,49 @@ __global__ __launch_bounds__(256) void k_iso_T(const float *__restrict__ xyz, in
             }
 }
 
+// Transpose of the exact-quadrature right-hand side at every cell:
+// g_V_xi = h (g^T along xi, m across) lambda, with g the 1-D face-average
+// divergence (g^T u at p: (u[p+1] - u[p-1]) / 2, indices clamped to the grid)
+// and m = (1, 4, 1)/6 with clamped indices; FP64 sums, stored FP32 in the
+// three fields gv.p[xi].
+__global__ __launch_bounds__(256) void k_grad27_T(const double *__restrict__ lam, Dims d, double h, Planes3 gv) {
+    const size_t N = d.count();
+    const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
+    const double mw[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % sy), j = (int)((c / sy) % d.ny), k = (int)(c / sz);
+        size_t ox[3], oy[3], oz[3];
+        for (int a = 0; a < 3; ++a) {
+            ox[a] = (size_t)min(max(i + a - 1, 0), d.nx - 1);
+            oy[a] = (size_t)min(max(j + a - 1, 0), d.ny - 1) * sy;
+            oz[a] = (size_t)min(max(k + a - 1, 0), d.nz - 1) * sz;
+        }
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int e = 0; e < 3; ++e) {
+                const double w = mw[a] * mw[e];
+                gx += w * (lam[ox[2] + oy[a] + oz[e]] - lam[ox[0] + oy[a] + oz[e]]);
+                gy += w * (lam[ox[a] + oy[2] + oz[e]] - lam[ox[a] + oy[0] + oz[e]]);
+                gz += w * (lam[ox[a] + oy[e] + oz[2]] - lam[ox[a] + oy[e] + oz[0]]);
+            }
+        gv.p[0][c] = (float)(0.5 * h * gx);
+        gv.p[1][c] = (float)(0.5 * h * gy);
+        gv.p[2][c] = (float)(0.5 * h * gz);
+    }
+}
+
 // B5 + B6 (+ the point term of the iso-value reverse).  With lambda the
 // adjoint solution, g_V = -h^2 D_h^T lambda is formed on the fly at each of
-// the 27 stencil cells, then
+// the 27 stencil cells (EXACT: read from the fields k_grad27_T wrote), then
 //   g_n_i = h^-3 sum_o alpha_o g_V,o,
 //   g_x_i = h^-3 sum_o (d alpha_o / d x_i) (n_i . g_V,o) + (g_c / N) grad chi_h(x_i).
 // The central cell of each point is the one recorded by the forward pass.
+template <bool EXACT>
 __global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, const float *__restrict__ nrm,
                                                   const int32_t *__restrict__ keys, int npts, GridF g,
-                                                  const double *__restrict__ lam, const double *__restrict__ chi,
-                                                  const double *g_c, float *__restrict__ gxyz,
-                                                  float *__restrict__ gnrm) {
+                                                  const double *__restrict__ lam, Planes3 gvp,
+                                                  const double *__restrict__ chi, const double *g_c,
+                                                  float *__restrict__ gxyz, float *__restrict__ gnrm) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     const float xv[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
@@ -413,15 +510,19 @@ __global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, 
             for (int dx = -1; dx <= 1; ++dx) {
                 if (!in_range(X.k, dx, g.d.nx) || !in_range(Y.k, dy, g.d.ny) || !in_range(Z.k, dz, g.d.nz)) continue;
                 const size_t o = c0 + (ptrdiff_t)dx + (ptrdiff_t)dy * (ptrdiff_t)sy + (ptrdiff_t)dz * (ptrdiff_t)sz;
-                const double lo_ = lam[o];
-                const int off[3] = {dx, dy, dz};
-                const size_t st[3] = {1, sy, sz};
                 float gv[3];
-                for (int a = 0; a < 3; ++a) {
-                    double acc = 0.0;
-                    if (in_range(kk[a], off[a] - 1, nn[a])) acc += lam[o - st[a]] - lo_;
-                    if (in_range(kk[a], off[a] + 1, nn[a])) acc += lo_ - lam[o + st[a]];
-                    gv[a] = (float)(-half_h * acc);
+                if constexpr (EXACT) {
+                    for (int a = 0; a < 3; ++a) gv[a] = gvp.p[a][o];
+                } else {
+                    const double lo_ = lam[o];
+                    const int off[3] = {dx, dy, dz};
+                    const size_t st[3] = {1, sy, sz};
+                    for (int a = 0; a < 3; ++a) {
+                        double acc = 0.0;
+                        if (in_range(kk[a], off[a] - 1, nn[a])) acc += lam[o - st[a]] - lo_;
+                        if (in_range(kk[a], off[a] + 1, nn[a])) acc += lo_ - lam[o + st[a]];
+                        gv[a] = (float)(-half_h * acc);
+                    }
                 }
                 const bool centre = dx == 0 && dy == 0 && dz == 0;
                 const float ax = X.a[dx + 1], ay = Y.a[dy + 1], az = Z.a[dz + 1];
@@ -467,5 +568,10 @@ __global__ __launch_bounds__(256) void k_splat_T(const float *__restrict__ xyz, 
     }
     for (int a = 0; a < 3; ++a) gxyz[3 * i + a] = gx[a];
 }
+
+template __global__ void k_splat_T<false>(const float *, const float *, const int32_t *, int, GridF, const double *,
+                                          Planes3, const double *, const double *, float *, float *);
+template __global__ void k_splat_T<true>(const float *, const float *, const int32_t *, int, GridF, const double *,
+                                         Planes3, const double *, const double *, float *, float *);
 
 }  // namespace wg

@@ -35,6 +35,13 @@ def _precision(p):
     return codes[p]
 
 
+def _quadrature(q):
+    codes = {"vertex": L.WG_VERTEX_QUADRATURE, "exact": L.WG_EXACT_QUADRATURE}
+    if q not in codes:
+        raise ValueError(f"quadrature must be one of {sorted(codes)}")
+    return codes[q]
+
+
 def grid_from_cloud(xyz, density, pad=3):
     """(n, lo, h) of a grid over the bounding box of the device points xyz
     [N,3] with density cells per unit length (wg_grid_from_cloud)."""
@@ -97,20 +104,23 @@ class Recon:
 
     # -- forward ---------------------------------------------------------------
     def forward(self, xyz, nrm, rel_tol=1e-6, max_iters=500, warm_start=False, precision="fp32",
-                deterministic=False):
+                deterministic=False, quadrature="vertex"):
         """Splat, solve, extract, distance (F1-F7).  Returns the stats dict.
 
         precision "fp32" (FP32 splat, FP32 sweeps, FP64 reductions and
         refinement) or "fp64" (the right-hand side in FP64, summed exactly);
         deterministic: the splat sums in 64-bit fixed point, so b, chi and phi
-        do not depend on the order points and threads are taken in."""
+        do not depend on the order points and threads are taken in;
+        quadrature "vertex" (the 7-point system) or "exact" (the Galerkin
+        integrals of Eq. 21 and 26 taken exactly: 27-point stiffness and
+        consistent right-hand side; fp32 and not deterministic)."""
         npts = int(xyz.shape[0])
         px = _dev(xyz, torch.float32, 3, "xyz")
         pn = _dev(nrm, torch.float32, 3, "nrm")
         if nrm.shape[0] != npts:
             raise ValueError("xyz and nrm differ in length")
         st = L.WgStats()
-        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic)
+        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic, _quadrature(quadrature))
         rc = L.check(L.lib().wg_recon_forward(self._alive(), px, pn, npts, C.byref(o), C.byref(st)),
                      allow=(L.WG_OK, L.WG_ENOTCONV))
         if rc == L.WG_ENOTCONV:
@@ -145,7 +155,7 @@ class Recon:
         return phi, nrm
 
     def step(self, xyz, nrm, q, rel_tol=1e-6, max_iters=500, warm_start=True, normals=True, precision="fp32",
-             deterministic=False):
+             deterministic=False, quadrature="vertex"):
         """Pipelined forward + sampling for moving-boundary loops (wg_recon_step):
         returns (stats, phi [Q], nrm [Q,3] or None) once the surface is extracted;
         the distance walk and the sampling finish on the handle's second stream
@@ -159,7 +169,7 @@ class Recon:
         phi = torch.empty(nq, dtype=torch.float32, device=q.device)
         nout = torch.empty((nq, 3), dtype=torch.float32, device=q.device) if normals else None
         st = L.WgStats()
-        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic)
+        o = L.make_opts(rel_tol, max_iters, warm_start, _precision(precision), deterministic, _quadrature(quadrature))
         rc = L.check(L.lib().wg_recon_step(self._alive(), px, pn, npts, pq, nq, C.c_void_p(phi.data_ptr()),
                                            C.c_void_p(nout.data_ptr()) if nout is not None else None,
                                            C.byref(o), C.byref(st)), allow=(L.WG_OK, L.WG_ENOTCONV))
@@ -201,7 +211,7 @@ class Recon:
         return gx, gn, gq
 
     # -- standalone solve and exports ---------------------------------------------
-    def poisson(self, b, x=None, bc="neumann", rel_tol=1e-10, max_iters=1000):
+    def poisson(self, b, x=None, bc="neumann", rel_tol=1e-10, max_iters=1000, quadrature="vertex"):
         """Solve A x = b on this grid (float32 b [N], float64 x [N])."""
         if b.numel() != self.cells or (x is not None and x.numel() != self.cells):
             raise ValueError(f"b and x must hold {self.cells} cells")
@@ -211,7 +221,7 @@ class Recon:
         else:
             warm = True
         st = L.WgStats()
-        o = L.make_opts(rel_tol, max_iters, warm)
+        o = L.make_opts(rel_tol, max_iters, warm, quadrature=_quadrature(quadrature))
         bcode = {"neumann": L.WG_BC_NEUMANN, "dirichlet": L.WG_BC_DIRICHLET}[bc]
         rc = L.check(L.lib().wg_poisson_solve(self._alive(), _dev(b, torch.float32, None, "b"),
                                               _dev(x, torch.float64, None, "x"), bcode, C.byref(o),
@@ -254,9 +264,9 @@ class Recon:
 
 class _ReconFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic):
+    def forward(ctx, xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic, quadrature):
         recon.forward(xyz.detach().contiguous(), nrm.detach().contiguous(), rel_tol, max_iters, warm_start, precision,
-                      deterministic)
+                      deterministic, quadrature)
         phi, n = recon.sample(q.detach().contiguous())
         ctx.recon = recon
         ctx.generation = recon.generation
@@ -275,12 +285,12 @@ class _ReconFn(torch.autograd.Function):
         gx, gnp, gq = r.backward(q.detach().contiguous(), gphi.contiguous(),
                                  gn.contiguous() if gn is not None else None,
                                  want_gq=ctx.needs_input_grad[2], rel_tol=ctx.rel_tol, max_iters=ctx.max_iters)
-        return gx, gnp, gq, None, None, None, None, None, None
+        return gx, gnp, gq, None, None, None, None, None, None, None
 
 
 def reconstruct(xyz, nrm, q, recon: Recon, rel_tol=1e-6, max_iters=500, warm_start=False, precision="fp32",
-                deterministic=False):
+                deterministic=False, quadrature="vertex"):
     """Differentiable SDF and normals at q from the oriented cloud (xyz, nrm).
 
     Gradients flow to xyz, nrm and q through the library's adjoint."""
-    return _ReconFn.apply(xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic)
+    return _ReconFn.apply(xyz, nrm, q, recon, rel_tol, max_iters, warm_start, precision, deterministic, quadrature)

@@ -33,7 +33,7 @@ class Server:
         return L.lib().wg_server_now(self._h)
 
     def submit(self, n, xyz, nrm, q, gphi=None, rel_tol=1e-6, max_iters=500, normals=True, lo=(0, 0, 0), h=None,
-               gnrm=None, want_gq=False, precision="fp32", deterministic=False):
+               gnrm=None, want_gq=False, precision="fp32", deterministic=False, quadrature="vertex"):
         """Queue one reconstruction; returns a Ticket.  Inputs are copied before return.
 
         gphi (dL/dphi(q), [Q]) asks for the reverse pass: the outputs then hold
@@ -62,7 +62,8 @@ class Server:
         req.d_q, req.n_q = q.data_ptr(), nq
         req.d_gphi = gphi.data_ptr() if gphi is not None else None
         req.opts = L.make_opts(rel_tol, max_iters, False, {"fp32": L.WG_FP32_FP64REDUCE, "fp64": L.WG_FP64}[precision],
-                               deterministic)
+                               deterministic,
+                               {"vertex": L.WG_VERTEX_QUADRATURE, "exact": L.WG_EXACT_QUADRATURE}[quadrature])
         req.d_phi = phi.data_ptr()
         req.d_nrm_out = nout.data_ptr() if nout is not None else None
         req.d_gxyz = gx.data_ptr() if gx is not None else None

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     # sizes implied by include/wgeo.h on x86-64
     assert ctypes.sizeof(_lib.WgGrid) == 12 + 4 + 24 + 8
-    assert ctypes.sizeof(_lib.WgSolveOpts) == 8 + 4 * 4
+    assert ctypes.sizeof(_lib.WgSolveOpts) == 8 + 5 * 4 + 4   # + tail padding to 8
     assert ctypes.sizeof(_lib.WgStats) == 4 + 4 + 8 + 8 + 8 + 8 + 4 + 32 + 4 + 8
 
 

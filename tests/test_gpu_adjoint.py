@@ -52,6 +52,34 @@ def test_reverse_pass_small_star_with_normals_and_queries():
     r.close()
 
 
+@pytest.mark.parametrize("n", [(20, 20, 20), (24, 20, 28)])
+def test_reverse_pass_exact_quadrature(n):
+    """The reverse pass of the exact-quadrature system: the adjoint solve on
+    the 27-point stiffness and the transposed consistent right-hand side."""
+    from paper_2609_20964_amd.recon import Recon
+    g = D.Grid(n, (0.0, 0.0, 0.0), 1.0 / 20)
+    c0 = np.array([0.03, -0.02, 0.015, 0.01])
+    x, nr = synth.star(c0, 1500, 12, semi_axes=(0.3, 0.2, 0.22))
+    tdirs = synth.unit_sphere_dirs(np.random.default_rng(13), 300)
+    q = (synth.X0 + synth.StarShape(c0 + 0.01, semi_axes=(0.3, 0.2, 0.22)).rho(tdirs)[:, None] * tdirs)
+    q = q.astype(np.float32)
+    wn = np.random.default_rng(14).standard_normal((300, 3)).astype(np.float32) / 300
+    ref = P.Recon(g, x, nr, exact=True)
+    phi_ref, _ = ref.sample(q)
+    gphi = (2.0 * phi_ref / 300).astype(np.float32)
+    gx_ref, gn_ref, gq_ref = ref.backward(q, gphi.astype(np.float64), wn.astype(np.float64))
+    r = Recon(n, len(x), h=1.0 / 20)
+    r.forward(_cuda(x), _cuda(nr), rel_tol=1e-10, max_iters=5000, quadrature="exact")
+    phi, _ = r.sample(_cuda(q))
+    assert np.abs(phi.cpu().numpy() - phi_ref).max() <= 1e-4 * g.h
+    # the reverse pass follows the forward's quadrature whatever its options say
+    gx, gn, gq = r.backward(_cuda(q), _cuda(gphi), _cuda(wn), want_gq=True, rel_tol=1e-10, max_iters=5000)
+    assert _close(gx.cpu().numpy(), gx_ref)
+    assert _close(gn.cpu().numpy(), gn_ref)
+    assert _close(gq.cpu().numpy(), gq_ref)
+    r.close()
+
+
 def test_autograd_function_matches_oracle_chain():
     from paper_2609_20964_amd.recon import Recon, reconstruct
     g = D.Grid.unit(24)

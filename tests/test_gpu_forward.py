@@ -11,6 +11,7 @@ import pytest
 
 from angles import angle
 from oracle import discretize as D
+from oracle import galerkin as G
 from oracle import pipeline as P
 from paper_2609_20964_amd import synth
 
@@ -35,7 +36,7 @@ def _rel(a, b):
 
 def _forward_parity(grid, x, n, q, tol_res=1e-10, full_phi=True, node_sample=None, tol_field=1e-5, **mode):
     from paper_2609_20964_amd.recon import Recon
-    ref = P.Recon(grid, x, n)
+    ref = P.Recon(grid, x, n, exact=mode.get("quadrature") == "exact")
     r = Recon(grid.n, len(x), lo=grid.lo, h=grid.h)
     st = r.forward(_cuda(x), _cuda(n), rel_tol=tol_res, max_iters=5000, **mode)
     print("stats", {k: st[k] for k in ("iters", "refinements", "rel_res", "n_tris", "iso_c")}, flush=True)
@@ -133,6 +134,85 @@ def test_torus_noisy_64():
     rng = np.random.default_rng(34)
     nodes = rng.choice(64 ** 3, 3000, replace=False)
     _forward_parity(g, x, n, q, full_phi=False, node_sample=nodes)
+
+
+@pytest.mark.parametrize("case", ["sphere32", "ragged20x24x28", "partial96x80x72"])
+def test_exact_quadrature_forward(case):
+    """The Galerkin system with exact quadrature (27-point stiffness,
+    consistent right-hand side) against the oracle's, step by step."""
+    if case == "sphere32":
+        g = D.Grid.unit(32)
+        x, n = synth.sphere()
+        q = synth.uniform_queries(4096, 102)
+        _forward_parity(g, x, n, q, quadrature="exact")
+        return
+    if case == "ragged20x24x28":
+        g = D.Grid((20, 24, 28), (-0.1, 0.05, 0.0), 0.04)
+        x, n = synth.sphere(3000, radius=0.2, seed=31)
+        x = (x.astype(np.float64) - 0.5 + np.array([0.3, 0.5, 0.55])).astype(np.float32)
+    else:
+        g = D.Grid((96, 80, 72), (0.0, 0.0, 0.0), 1.0 / 96)
+        x, n = synth.sphere(20000, radius=0.22, seed=35)
+        x = (x.astype(np.float64) - 0.5 + np.array([0.48, 0.40, 0.36])).astype(np.float32)
+    rng = np.random.default_rng(36)
+    lo = np.array(g.lo)
+    hi = lo + np.array(g.n) * g.h
+    q = rng.uniform(lo, hi, (3000, 3)).astype(np.float32)
+    if case == "ragged20x24x28":
+        _forward_parity(g, x, n, q, quadrature="exact")
+    else:
+        nodes = rng.choice(96 * 80 * 72, 3000, replace=False)
+        _forward_parity(g, x, n, q, full_phi=False, node_sample=nodes, quadrature="exact")
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (20, 24, 28), (96, 80, 72), (16, 12, 16), (13, 17, 19)])
+def test_exact_quadrature_poisson(n):
+    """27-point solve against the oracle's DCT solve on a random zero-mean
+    right-hand side, and on cosine modes with their closed-form eigenvalues
+    (khat mhat mhat + mhat khat mhat + mhat mhat khat)."""
+    from paper_2609_20964_amd.recon import Recon
+    shape = (n[2], n[1], n[0])
+    rng = np.random.default_rng(sum(n))
+    b = rng.standard_normal(shape)
+    b -= b.mean()
+    ks = [(1, 2, 3), (3, 1, 1), (2, 2, 5), (n[0] - 1, n[1] - 1, n[2] - 1)]
+    lam = G.eigenvalues(shape)
+    u = np.zeros(shape)
+    bm = np.zeros(shape)
+    for i, k in enumerate(ks):
+        m = _mode("neumann", shape, k)
+        u += (i + 1) * m
+        bm += (i + 1) * lam[k[2], k[1], k[0]] * m
+    r = Recon(n, 16)
+    for rhs, want in ((b, None), (bm, u)):
+        b32 = rhs.astype(np.float32)
+        x, st = r.poisson(_cuda(b32.reshape(-1)), rel_tol=1e-10, max_iters=5000, quadrature="exact")
+        print("stats", st, flush=True)
+        assert st["status"] == 0 and st["rel_res"] <= 1e-10
+        xg = x.cpu().numpy().reshape(shape)
+        xr = G.solve(b32.astype(np.float64))
+        assert _rel(xg, xr) <= 1e-5
+        assert G.rel_residual(xg, b32.astype(np.float64)) <= 1e-9
+        if want is not None:
+            assert _rel(xg, want) <= 1e-5
+    r.close()
+
+
+def test_exact_quadrature_option_errors():
+    from paper_2609_20964_amd.recon import Recon
+    from paper_2609_20964_amd._lib import WgError
+    x, n = synth.sphere(500, seed=3)
+    r = Recon(16, 500)
+    b = torch.zeros(16 ** 3, dtype=torch.float32, device="cuda")
+    with pytest.raises(WgError):
+        r.poisson(b, bc="dirichlet", quadrature="exact")
+    with pytest.raises(WgError):
+        r.forward(_cuda(x), _cuda(n), precision="fp64", quadrature="exact")
+    with pytest.raises(WgError):
+        r.forward(_cuda(x), _cuda(n), deterministic=True, quadrature="exact")
+    with pytest.raises(ValueError):
+        r.forward(_cuda(x), _cuda(n), quadrature="gauss")
+    r.close()
 
 
 def _mode(bc, shape, k):

@@ -502,14 +502,16 @@ def test_query_gradient_vs_fd():
     assert np.allclose(g_q, fd, rtol=1e-5, atol=1e-5 * np.abs(fd).max())
 
 
-def test_whole_chain_gradient_with_normal_term_vs_frozen_fd():
+@pytest.mark.parametrize("exact", [False, True])
+def test_whole_chain_gradient_with_normal_term_vs_frozen_fd(exact):
+    # exact: the system with exact quadrature (27-point stiffness, consistent right-hand side)
     torch, shape, dirs, targets = _small_diff_problem()
     g = D.Grid.unit(20)
     c0 = shape.coeffs
     wdir = np.random.default_rng(16).standard_normal((len(targets), 3))
 
     def loss(xn, nn, keys=None):
-        r = P.Recon(g, xn, nn, keys=keys)
+        r = P.Recon(g, xn, nn, keys=keys, exact=exact)
         phi, nq = r.sample(targets)
         return float(np.mean(phi ** 2) + np.mean(np.sum(wdir * nq, 1))), r, phi
 
