@@ -5,9 +5,8 @@
 // faces of (x_i - x_j); zero-flux (Neumann, Eq. 19) boundaries, or the
 // cell-centred Dirichlet test mode (ghost = -x, diagonal 6 + #boundary faces).
 // With exact quadrature (zero-flux only) the fine-level operator is the
-// 27-point Q1 stiffness of the same equations; the multigrid preconditioner
-// stays the 7-point one, whose spectrum bounds the 27-point one from above
-// and within a factor 9 from below.
+// 27-point Q1 stiffness of the same equations; the preconditioner is the
+// 7-point V-cycle between two Jacobi steps on the 27-point operator.
 //
 // Precision scheme: the solution lives in FP64; each refinement step forms the
 // FP64 residual r = P(b - A x) (P: mean removal for Neumann), solves A e = r
@@ -96,6 +95,7 @@ class Solver {
     void pcg_iteration(int it, int &cur);
     void finalize(int mode, unsigned nb, int flag);
     template <class Op> void sweep(const Op &op, int kind, double bytes_per_cell, const int *skip);
+    template <class Op> void sweep27(const Op &op, int kind, double bytes_per_cell, const int *skip);
     unsigned sweep_partials() const;
     void read_scalars();
     unsigned long long wait_status(unsigned want);

@@ -435,6 +435,44 @@ struct OpPMatvec {
     }
 };
 
+// Exact quadrature: the 7-point V-cycle M7 is wrapped between two Jacobi
+// steps on the 27-point operator A, z = M r with
+//   z1 = w r,  z2 = z1 + M7 (r - A z1),  z = z2 + w (r - A z2),
+// i.e. I - M A = (I - w A)(I - M7 A)(I - w A): symmetric, and M >= w I, so
+// positive definite.  On the cosine modes A lies in (0, 4) and A / A7 in
+// [1/9, 1]; M7 alone leaves the modes high in all three axes at A / A7 ~ 1/9,
+// which the steps with w = 3/8 (the inverse of A's diagonal 8/3) damp by
+// (1 - w A)^2 <= 1/4.
+constexpr float kJacobi27 = 0.375f;
+
+// first step: out = r - w A r
+struct OpJacobi27a {
+    using T = float;
+    static constexpr int NRED = 0;
+    const float *r;
+    float *out;
+    float w;
+    __device__ float load(size_t i) const { return r[i]; }
+    __device__ void applyA(size_t i, float c, float au, double *) const { out[i] = c - w * au; }
+};
+
+// last step, with u = w r + y (y = M7 applied to the first step's output):
+// z = u + w (r - A u), and the sum r.z
+struct OpJacobi27b {
+    using T = float;
+    static constexpr int NRED = 1;
+    const float *r, *y;
+    float *z;
+    float w;
+    __device__ float load(size_t i) const { return w * r[i] + y[i]; }
+    __device__ void applyA(size_t i, float c, float au, double *acc) const {
+        const float ri = r[i];
+        const float zz = c + w * (ri - au);
+        z[i] = zz;
+        acc[0] += (double)ri * (double)zz;
+    }
+};
+
 __device__ __forceinline__ void fetch_scalars(OpPMatvec<false> &op) { op.beta = (float)op.sc->beta; }
 template <class TB>
 __device__ __forceinline__ void fetch_scalars(OpResid64<TB> &op) { op.mb = op.sc ? op.sc->mean_b : 0.0; }
@@ -1367,11 +1405,13 @@ static void launch_stencil(const Op &op, const Dims &d, double *partials, hipStr
 // The fine-level operator: the 7-point sweep, or (exact quadrature) the 27-point one.
 template <class Op>
 void Solver::sweep(const Op &op, int kind, double bytes_per_cell, const int *skip) {
+    if (exact_) sweep27(op, kind, bytes_per_cell, skip);
+    else launch_stencil(op, lv_[0].d, partials_, st_, kind, bytes_per_cell, skip);
+}
+
+template <class Op>
+void Solver::sweep27(const Op &op, int kind, double bytes_per_cell, const int *skip) {
     const Dims &d = lv_[0].d;
-    if (!exact_) {
-        launch_stencil(op, d, partials_, st_, kind, bytes_per_cell, skip);
-        return;
-    }
     prof::Scope ps(kind, st_, bytes_per_cell * (double)d.count());
     const Tiles t = tiles_of(d);
     k_stencil27<Op><<<t.count(), TX * TY, 0, st_>>>(op, d, t, partials_, skip);
@@ -1429,6 +1469,19 @@ void Solver::vcycle(int l) {
 
 // z = M r with r.z summed into partials_ (rz_blocks() of them).
 void Solver::precond() {
+    if (exact_) {
+        // M7 between two Jacobi steps on the 27-point operator; q_ (free
+        // until the next direction's matvec) takes the first step's output
+        Level &F = lv_[0];
+        float *r = F.rhs;
+        sweep27(OpJacobi27a{r, q_, kJacobi27}, pk(WG_PROF_SMOOTH), 8.0, skip_);
+        F.rhs = q_;
+        vcycle(0);
+        F.rhs = r;
+        sweep27(OpJacobi27b{r, F.x, F.x2, kJacobi27}, pk(WG_PROF_SMOOTH), 12.0, skip_);
+        std::swap(F.x, F.x2);
+        return;
+    }
     vcycle(0);
     if (nlv_ == 1) {
         // the coarsest solve alone forms no sum: one more pass
@@ -1439,7 +1492,10 @@ void Solver::precond() {
     }
 }
 
-unsigned Solver::rz_blocks() const { return nlv_ > 1 ? post_blocks_ : red_blocks(lv_[0].d.count()); }
+unsigned Solver::rz_blocks() const {
+    if (exact_) return tiles_of(lv_[0].d).count();
+    return nlv_ > 1 ? post_blocks_ : red_blocks(lv_[0].d.count());
+}
 
 void Solver::mg_apply(const float *r, float *z, int bc) {
     require(bc == WG_BC_NEUMANN || bc == WG_BC_DIRICHLET, WG_EINVAL, "unknown boundary condition");
