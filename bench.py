@@ -179,12 +179,68 @@ def gpu_run(args):
         torch.cuda.synchronize()
         if k > 0:
             adj_ms.append((time.perf_counter() - a0) * 1e3)
+    exact = exact_run(args, r, clouds, q, kinds) if args.exact_steps else None
     r.close()
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
+            "exact": exact,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
             "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof,
-            "walk_timed": walk_timed, "walk_plain": walk_plain, "walk_ktz": 4 if n ** 3 >= 1 << 23 else 1}
+            "walk_timed": walk_timed, "walk_plain": walk_plain, "walk_ktz": 4 if n ** 3 >= 1 << 23 else 1,
+            "tol": args.tol}
+
+
+def exact_run(args, r, clouds, q, kinds):
+    """The Galerkin system with exact quadrature (27-point stiffness,
+    consistent right-hand side) on the same handle and clouds: plain steps
+    (forward, then sampling), timed, then two more with the solver's kernels
+    profiled.  The first step switches the system and is not timed."""
+    import torch
+
+    from paper_2609_20964_amd import _lib
+
+    ns = args.exact_steps
+    base = max(args.warmup + args.steps - ns - 3, 0)
+    cl = lambda t: clouds[t % len(clouds)]
+    r.forward(*cl(base), rel_tol=args.tol, warm_start=True, quadrature="exact")
+    r.sample(q)
+    torch.cuda.synchronize()
+    st = []
+    t0 = time.perf_counter()
+    for k in range(ns):
+        st.append(r.forward(*cl(base + 1 + k), rel_tol=args.tol, warm_start=True, quadrature="exact"))
+        r.sample(q)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / ns * 1e3
+    _lib.profile_reset()
+    _lib.profile_enable(kinds)
+    solve_ms = []
+    for k in range(2):
+        solve_ms.append(r.forward(*cl(base + 1 + k), rel_tol=args.tol, warm_start=True,
+                                  quadrature="exact")["ms"][1])
+    torch.cuda.synchronize()
+    _lib.profile_enable([])
+    out = {"ms_per_step_plain": ms, "steps": ns, "stats": st, "solve_ms": solve_ms,
+           "solver_kinds": {k: _lib.profile_read(k) for k in SOLVER_KINDS}, "splat": _lib.profile_read("splat")}
+    _lib.profile_reset()
+    return out
+
+
+def exact_summary(res, copy_gbs):
+    e = res["exact"]
+    st = e["stats"]
+    return {"ms_per_step_plain": e["ms_per_step_plain"], "recons_per_s_plain": 1e3 / e["ms_per_step_plain"],
+            "vertex_ms_per_step_plain": res["plain_ms"], "steps": e["steps"],
+            "iters_mean": float(np.mean([s["iters"] for s in st])),
+            "rel_res_max": float(max(s["rel_res"] for s in st)),
+            "phase_ms_plain": {k: float(np.mean([s["ms"][i] for s in st]))
+                               for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
+            "splat_kernel_ms": e["splat"]["ms"] / 2,
+            "solver_roofline": solver_hbm({"solver_kinds": e["solver_kinds"], "solve_ms": e["solve_ms"]}, copy_gbs),
+            "kernels": "k_splat_chunks<kSplatExact>, k_stencil27<OpPMatvec> (sweep), k_stencil27<OpResid64> "
+                       "(resid64), k_stencil27<OpJacobi27a/b> + k_vc_pre (smooth)",
+            "workload": "the headline clouds and grid, exact-quadrature system, plain steps, rel res "
+                        f"{res['tol']:g}"}
 
 
 # algorithmic cost model of each timed kind: units are bytes, except the distance walk (nodes)
@@ -713,6 +769,8 @@ def main():
     ap.add_argument("--queries", type=int, default=65_536)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--adjoint-steps", type=int, default=3)
+    ap.add_argument("--exact-steps", type=int, default=5,
+                    help="plain steps of the exact-quadrature system on the same clouds (0: skip)")
     ap.add_argument("--serving", type=int, default=160, help="requests in the serving replay (0: skip)")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -736,6 +794,7 @@ def main():
         sys.exit(2)
 
     res = gpu_run(args)
+    copy_gbs = copy_bandwidth()
     steps = args.steps
     value = steps / res["elapsed"]
     st = res["stats"]
@@ -756,7 +815,7 @@ def main():
                                f"rel res {args.tol:g}, {args.queries} queries sampled per step",
                    "grid": args.n, "points": args.points, "queries": args.queries, "rel_tol": args.tol},
         "roofline": roofline(res),
-        "solver_roofline": solver_hbm(res, copy_bandwidth()),
+        "solver_roofline": solver_hbm(res, copy_gbs),
         "solver": {"iters_mean": float(np.mean([s["iters"] for s in st])),
                    "refinements_mean": float(np.mean([s["refinements"] for s in st])),
                    "rel_res_max": float(max(s["rel_res"] for s in st)),
@@ -768,6 +827,7 @@ def main():
                            for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
         "kernel_ms_per_step_plain": {k: v["ms"] / res["n_prof"] for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
+        "exact_quadrature": exact_summary(res, copy_gbs) if res["exact"] else None,
     }
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(res, args.n, args.cpu_sample_nodes)

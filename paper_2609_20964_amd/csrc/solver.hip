@@ -281,6 +281,85 @@ __global__ __launch_bounds__(256) void k_stencil27(Op op, Dims d, Tiles t, doubl
     }
 }
 
+// The same 27-point sweep with four consecutive x cells per lane (x extent
+// divisible by 4), in the wavefront layout of k_stencil4: a lane loads one
+// 16-byte vector per row and plane, the x neighbours inside it are its own,
+// those of the two ends come from the next lanes (or a load at a row
+// segment's end).  Op::applyA4(idx, centres, A u, acc) consumes four cells.
+template <class Op>
+__global__ __launch_bounds__(256) void k_stencil27x4(Op op, Dims d, Waves4 wv, double *partials, const int *skip) {
+    using T = typename Op::T;
+    if (skipped(skip)) return;
+    fetch_scalars(op);
+    const unsigned nb = gridDim.x;
+    const unsigned lb = xcd_logical_block(blockIdx.x, nb);
+    const unsigned task = lb * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    double acc[Op::NRED > 0 ? Op::NRED : 1];
+    for (int k = 0; k < (Op::NRED > 0 ? Op::NRED : 1); ++k) acc[k] = 0.0;
+    const unsigned W4 = (unsigned)d.nx / 4;
+    const unsigned seg = task % wv.S, grp = (task / wv.S) % wv.G, zc = task / (wv.S * wv.G);
+    const unsigned sl = lane % wv.L, rr = lane / wv.L;
+    const unsigned x4 = seg * wv.L + sl;
+    const int j = (int)(grp * wv.R + rr);
+    const bool valid = task < wv.tasks() && rr < wv.R && x4 < W4 && j < d.ny;
+    if (task < wv.tasks()) {   // uniform over the wavefront
+        const int i = 4 * (int)(valid ? x4 : 0);
+        const int jj = valid ? j : 0;
+        const size_t plane = (size_t)d.nx * d.ny;
+        const size_t rows[3] = {(size_t)max(jj - 1, 0) * d.nx, (size_t)jj * d.nx,
+                                (size_t)min(jj + 1, d.ny - 1) * d.nx};
+        const bool xl = i > 0, xr = i + 4 < d.nx;                    // neighbours exist
+        const bool shl = sl > 0, shr = sl + 1 < wv.L && x4 + 1 < W4;  // ... and sit in the next lane
+        const T sixth = T(1) / T(6);
+        auto filt = [&](int z, V4<T> &P, V4<T> &Q, V4<T> &C) {
+            V4<T> mx[3], kx[3];
+            for (int r = 0; r < 3; ++r) {
+                const size_t base = (size_t)z * plane + rows[r] + i;
+                V4<T> c;
+                if (valid) c = op.load4(base);
+                else for (int q = 0; q < 4; ++q) c.v[q] = T(0);
+                T left = __shfl_up(c.v[3], 1, 64), right = __shfl_down(c.v[0], 1, 64);
+                if (!shl) left = (valid && xl) ? op.load1(base - 1) : c.v[0];
+                if (!shr) right = (valid && xr) ? op.load1(base + 4) : c.v[3];
+                if (!xl) left = c.v[0];    // clamped: the mirror image of the first cell
+                if (!xr) right = c.v[3];
+                for (int q = 0; q < 4; ++q) {
+                    const T l = q == 0 ? left : c.v[q - 1], rt = q == 3 ? right : c.v[q + 1];
+                    mx[r].v[q] = (l + T(4) * c.v[q] + rt) * sixth;
+                    kx[r].v[q] = T(2) * c.v[q] - l - rt;
+                }
+                if (r == 1) C = c;
+            }
+            for (int q = 0; q < 4; ++q) {
+                Q.v[q] = (mx[0].v[q] + T(4) * mx[1].v[q] + mx[2].v[q]) * sixth;
+                P.v[q] = (kx[0].v[q] + T(4) * kx[1].v[q] + kx[2].v[q]) * sixth +
+                         (T(2) * mx[1].v[q] - mx[0].v[q] - mx[2].v[q]);
+            }
+        };
+        const int z0 = (int)(zc * wv.zlen);
+        const int z1 = min(z0 + (int)wv.zlen, d.nz);
+        V4<T> Pm, Qm, Cm, Pc, Qc, Cc;
+        filt(max(z0 - 1, 0), Pm, Qm, Cm);
+        filt(z0, Pc, Qc, Cc);
+        for (int k = z0; k < z1; ++k) {
+            V4<T> Pp, Qp, Cp, au;
+            filt(min(k + 1, d.nz - 1), Pp, Qp, Cp);
+            for (int q = 0; q < 4; ++q)
+                au.v[q] = (Pm.v[q] + T(4) * Pc.v[q] + Pp.v[q]) * sixth + (T(2) * Qc.v[q] - Qm.v[q] - Qp.v[q]);
+            if (valid) op.applyA4(rows[1] + (size_t)i + (size_t)k * plane, Cc, au, acc);
+            Pm = Pc; Qm = Qc; Cm = Cc;
+            Pc = Pp; Qc = Qp; Cc = Cp;
+        }
+    }
+    if constexpr (Op::NRED > 0) {
+        __shared__ double lds[4][Op::NRED];
+        block_sum<Op::NRED>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < Op::NRED; ++k) partials[(size_t)k * nb + lb] = acc[k];
+    }
+}
+
 // r = (b - mb) - A x in FP64 (r stored FP32); sums of r, r^2, x, b - mb,
 // (b - mb)^2.  mb is the mean of b for zero-flux boundaries (the compatibility
 // projection of the right-hand side), 0 otherwise.
@@ -331,6 +410,21 @@ struct OpResid64 {
         acc[2] += c;
         acc[3] += bv;
         acc[4] += bv * bv;
+    }
+    __device__ void applyA4(size_t i, const V4<double> &c, const V4<double> &au, double *acc) const {
+        const V4<TB> bb = ld4(b + i);
+        V4<float> out;
+        for (int q = 0; q < 4; ++q) {
+            const double bv = (double)bb.v[q] - mb;
+            const double rv = bv - au.v[q];
+            out.v[q] = (float)rv;
+            acc[0] += rv;
+            acc[1] += rv * rv;
+            acc[2] += c.v[q];
+            acc[3] += bv;
+            acc[4] += bv * bv;
+        }
+        st4(r + i, out);
     }
 };
 
@@ -433,6 +527,11 @@ struct OpPMatvec {
         q[i] = au;
         acc[0] += (double)c * (double)au;
     }
+    __device__ void applyA4(size_t i, const V4<float> &c, const V4<float> &au, double *acc) const {
+        for (int k = 0; k < 4; ++k) acc[0] += (double)c.v[k] * (double)au.v[k];
+        st4(pnew + i, c);
+        st4(q + i, au);
+    }
 };
 
 // Exact quadrature: the 7-point V-cycle M7 is wrapped between two Jacobi
@@ -453,7 +552,14 @@ struct OpJacobi27a {
     float *out;
     float w;
     __device__ float load(size_t i) const { return r[i]; }
+    __device__ float load1(size_t i) const { return r[i]; }
+    __device__ V4<float> load4(size_t i) const { return ld4(r + i); }
     __device__ void applyA(size_t i, float c, float au, double *) const { out[i] = c - w * au; }
+    __device__ void applyA4(size_t i, const V4<float> &c, const V4<float> &au, double *) const {
+        V4<float> o;
+        for (int k = 0; k < 4; ++k) o.v[k] = c.v[k] - w * au.v[k];
+        st4(out + i, o);
+    }
 };
 
 // last step, with u = w r + y (y = M7 applied to the first step's output):
@@ -465,11 +571,27 @@ struct OpJacobi27b {
     float *z;
     float w;
     __device__ float load(size_t i) const { return w * r[i] + y[i]; }
+    __device__ float load1(size_t i) const { return load(i); }
+    __device__ V4<float> load4(size_t i) const {
+        const V4<float> a = ld4(r + i), b = ld4(y + i);
+        V4<float> o;
+        for (int k = 0; k < 4; ++k) o.v[k] = w * a.v[k] + b.v[k];
+        return o;
+    }
     __device__ void applyA(size_t i, float c, float au, double *acc) const {
         const float ri = r[i];
         const float zz = c + w * (ri - au);
         z[i] = zz;
         acc[0] += (double)ri * (double)zz;
+    }
+    __device__ void applyA4(size_t i, const V4<float> &c, const V4<float> &au, double *acc) const {
+        const V4<float> rr = ld4(r + i);
+        V4<float> o;
+        for (int k = 0; k < 4; ++k) {
+            o.v[k] = c.v[k] + w * (rr.v[k] - au.v[k]);
+            acc[0] += (double)rr.v[k] * (double)o.v[k];
+        }
+        st4(z + i, o);
     }
 };
 
@@ -1258,12 +1380,17 @@ unsigned sweep_blocks(const Dims &d) {
     return d.nx % 4 == 0 ? cdiv(waves4_of(d).tasks(), 4) : tiles_of(d).count();
 }
 
+// ... and of the 27-point sweep
+unsigned sweep27_blocks(const Dims &d) {
+    return d.nx % 4 == 0 ? cdiv(waves4_of(d).tasks(), 4) : tiles_of(d).count();
+}
+
 // blocks of the finest post-smoothing pass (0 for a single-level hierarchy)
 unsigned post_blocks(const Dims *dims, int nl) { return nl > 1 ? vtile_of(dims[0]).count() : 0u; }
 
 size_t partial_slots(const Dims *dims, int nl) {
     size_t nb = sweep_blocks(dims[0]);
-    if (tiles_of(dims[0]).count() > nb) nb = tiles_of(dims[0]).count();   // the 27-point sweep
+    if (sweep27_blocks(dims[0]) > nb) nb = sweep27_blocks(dims[0]);
     const size_t pb = post_blocks(dims, nl);
     if (pb > nb) nb = pb;
     return (nb > (size_t)kRedBlocks ? nb : (size_t)kRedBlocks) * kMaxRed;
@@ -1413,12 +1540,17 @@ template <class Op>
 void Solver::sweep27(const Op &op, int kind, double bytes_per_cell, const int *skip) {
     const Dims &d = lv_[0].d;
     prof::Scope ps(kind, st_, bytes_per_cell * (double)d.count());
-    const Tiles t = tiles_of(d);
-    k_stencil27<Op><<<t.count(), TX * TY, 0, st_>>>(op, d, t, partials_, skip);
+    if (d.nx % 4 == 0) {
+        const Waves4 wv = waves4_of(d);
+        k_stencil27x4<Op><<<cdiv(wv.tasks(), 4), 256, 0, st_>>>(op, d, wv, partials_, skip);
+    } else {
+        const Tiles t = tiles_of(d);
+        k_stencil27<Op><<<t.count(), TX * TY, 0, st_>>>(op, d, t, partials_, skip);
+    }
     WG_LAUNCH_CHECK();
 }
 
-unsigned Solver::sweep_partials() const { return exact_ ? tiles_of(lv_[0].d).count() : sweep_blocks(lv_[0].d); }
+unsigned Solver::sweep_partials() const { return exact_ ? sweep27_blocks(lv_[0].d) : sweep_blocks(lv_[0].d); }
 
 void Solver::vcycle(int l) {
     Level &L = lv_[l];
@@ -1493,7 +1625,7 @@ void Solver::precond() {
 }
 
 unsigned Solver::rz_blocks() const {
-    if (exact_) return tiles_of(lv_[0].d).count();
+    if (exact_) return sweep27_blocks(lv_[0].d);
     return nlv_ > 1 ? post_blocks_ : red_blocks(lv_[0].d.count());
 }
 

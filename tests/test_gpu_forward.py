@@ -165,7 +165,10 @@ def test_exact_quadrature_forward(case):
         _forward_parity(g, x, n, q, full_phi=False, node_sample=nodes, quadrature="exact")
 
 
-@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (20, 24, 28), (96, 80, 72), (16, 12, 16), (13, 17, 19)])
+# x extents: multiples of 4 (four cells per lane) below, at and above one
+# wavefront's 64 vectors (288: a second row segment of eight lanes), and odd (one cell per lane)
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 64, 64), (20, 24, 28), (96, 80, 72), (16, 12, 16), (13, 17, 19),
+                               (288, 64, 64)])
 def test_exact_quadrature_poisson(n):
     """27-point solve against the oracle's DCT solve on a random zero-mean
     right-hand side, and on cosine modes with their closed-form eigenvalues
