@@ -390,6 +390,53 @@ int wg_profile_walk_counts(uint64_t out[4]);
  * and returns; WG_EINVAL for misaligned or null arguments. */
 int wg_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
 
+/* ---- Unoriented clouds: normals and their orientation (Sec. 2.1-2.2) ----- */
+
+/* Unoriented normals by distance-weighted PCA (Sec. 2.1, Eq. 1-6).  For each
+ * point x_i: the neighbours within `radius` (Eq. 1; x_i itself included;
+ * membership decided on the FP32 squared distance, summed x, y, z, against
+ * radius^2 rounded to FP32), weights 1/(|x_j - x_i| + eps) (Eq. 2), the
+ * weighted centroid (Eq. 3) and covariance about it (Eq. 4) in FP64; the
+ * normal is the unit eigenvector of the smallest eigenvalue (Eq. 5-6).
+ * d_xyz [n_points][3] float32 (device); d_nrm_out [n_points][3] float32
+ * (device; sign arbitrary, undefined where the two smallest eigenvalues
+ * coincide, as for a point without neighbours).  eps <= 0 selects
+ * 1e-6 radius.  Allocates its work buffers on the stream and frees them;
+ * blocks until done.  WG_EINVAL for n_points < 1, radius <= 0 or a
+ * non-finite coordinate. */
+int wg_dpca_normals(const float *d_xyz, int n_points, double radius, double eps, float *d_nrm_out,
+                    void *hip_stream);
+
+typedef struct {
+    double gamma_r; /* detection-radius expansion factor (Eq. 14; Table 1: 2.5), >= 1 */
+    int n_tol;      /* initial-one threshold of the refinement (Table 1: 2) */
+    int refine;     /* 1: the refinement iterations of Sec. 2.2; 0: plain parity (Eq. 12) */
+} wg_orient_opts;
+
+typedef struct {
+    double spacing2;  /* max_i min_{j != i} of the FP32 squared distance */
+    double rd0, rd;   /* Eq. 13 and Eq. 14 */
+    double ds;        /* probe spacing, 0.75 rd */
+    int n_probes;     /* M: probes m = 0..M per ray, ceil((box diagonal + rd) / ds) + 1 */
+    int n_flipped;    /* normals whose sign this call changed */
+} wg_orient_info;
+
+/* Outward orientation by point-cloud ray casting (Sec. 2.2, Eq. 7-14).  Rays
+ * from each point along +n and -n, probes y_m = x + m ds n (FP32), detection
+ * d_m = [some point within rd of y_m] (FP32 squared distances against rd^2
+ * rounded to FP32), N = (1 -> 0 transitions) - 1 and N_one = the leading
+ * detecting probes.  Iteration 0 flips an odd N; with refine, a normal whose
+ * initial block is longer than n_tol probes is flipped (iteration 1) and
+ * flipped back if that direction crosses more often than the other
+ * (iteration 2).  d_nrm [n_points][3] float32, flipped in place (signs only);
+ * d_counts NULL or [n_points][4] int32 (N, N_one along the input +n, then
+ * along -n); info NULL or filled.  Allocates its work buffers on the stream
+ * and frees them; blocks until done.  WG_EINVAL for n_points < 2, gamma_r < 1,
+ * a non-finite coordinate, or a cloud whose points all have coincident twins
+ * (rd = 0) or one whose rays would need more than 1e5 probes. */
+int wg_orient_normals(const float *d_xyz, int n_points, float *d_nrm, const wg_orient_opts *opts,
+                      int32_t *d_counts, wg_orient_info *info, void *hip_stream);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *wg_last_error(void);
 

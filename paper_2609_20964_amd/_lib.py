@@ -52,6 +52,18 @@ class WgResult(C.Structure):
                 ("t_start", C.c_double), ("t_done", C.c_double)]
 
 
+class WgOrientOpts(C.Structure):
+    _fields_ = [("gamma_r", C.c_double), ("n_tol", C.c_int), ("refine", C.c_int)]
+
+
+class WgOrientInfo(C.Structure):
+    _fields_ = [("spacing2", C.c_double), ("rd0", C.c_double), ("rd", C.c_double), ("ds", C.c_double),
+                ("n_probes", C.c_int), ("n_flipped", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class WgError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{CODE_NAMES.get(code, code)}: {msg}")
@@ -96,6 +108,9 @@ SIGNATURES = {
     "wg_profile_reset": (None, []),
     "wg_profile_walk_counts": (C.c_int, [C.POINTER(C.c_uint64 * 4)]),
     "wg_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "wg_dpca_normals": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "wg_orient_normals": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(WgOrientOpts), C.c_void_p,
+                                    C.POINTER(WgOrientInfo), C.c_void_p]),
 }
 
 PROF_KINDS = {"splat": 0, "sweep": 1, "smooth": 2, "resid64": 3, "transfer": 4, "cgupdate": 5, "mc": 6,

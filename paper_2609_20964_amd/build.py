@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwgeo.so")
-SOURCES = ["solver.hip", "splat.hip", "surface.hip", "recon.hip", "server.hip", "prof.hip", "noalloc.hip"]
+SOURCES = ["solver.hip", "splat.hip", "surface.hip", "recon.hip", "server.hip", "prof.hip", "noalloc.hip",
+           "normals.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC]

@@ -1,0 +1,129 @@
+"""GPU normal estimation and orientation (Sec. 2.1-2.2, through the C ABI)
+against the oracle.
+
+Bars: D-PCA normals within 1e-5 rad of the oracle's (up to sign) wherever the
+two smallest eigenvalues of C_i are apart (relative gap > 1e-2; the output is
+FP32, the sums FP64 in both); orientation bit-exact: the ray counts, the
+nearest-spacing maximum, the probe count and every sign, since both sides
+take each detection in the same FP32 arithmetic.
+"""
+import numpy as np
+import pytest
+
+from angles import angle
+from oracle import normals as NO
+from paper_2609_20964_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _random_signs(n, seed):
+    s = np.where(np.random.default_rng(seed).uniform(size=len(n)) < 0.5, -1.0, 1.0)
+    return (n * s[:, None]).astype(np.float32)
+
+
+def _axis_angle(a, b):
+    """Angle between the lines spanned by a and b (sign ignored)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    flip = np.sum(a * b, 1) < 0
+    b = np.where(flip[:, None], -b, b)
+    return angle(a, b)
+
+
+@pytest.mark.parametrize("case", ["star", "star_shifted", "plane"])
+def test_dpca_matches_oracle(case):
+    from paper_2609_20964_amd.normals import dpca_normals
+    if case == "plane":
+        rng = np.random.default_rng(91)
+        ab = rng.uniform(-0.3, 0.3, (3000, 2))
+        x = np.stack([0.5 + ab[:, 0], 0.5 + ab[:, 1], np.full(3000, 0.5)], 1).astype(np.float32)
+        R = 0.05
+    else:
+        c = synth.draw_star_coeffs(92)
+        x, _ = synth.star(c, 4000, 93)
+        R = 0.08
+        if case == "star_shifted":
+            # away from the unit cube, with a non-uniform scale
+            x = (x.astype(np.float64) * np.array([1.5, 1.0, 0.8]) + np.array([3.0, -2.0, 5.0])).astype(np.float32)
+    n_ref, lam = NO.dpca_normals(x, R=R)
+    n_gpu = dpca_normals(_cuda(x), radius=R).cpu().numpy()
+    assert np.allclose(np.linalg.norm(n_gpu, axis=1), 1.0, atol=1e-6)
+    gap = (lam[:, 1] - lam[:, 0]) / np.maximum(lam[:, 2], 1e-300)
+    ok = gap > 1e-2
+    ang = _axis_angle(n_gpu, n_ref)
+    print(f"{case}: {ok.mean():.3f} with gap, max angle {ang[ok].max():.2e} rad", flush=True)
+    assert ok.mean() > 0.95
+    assert ang[ok].max() <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["sphere", "torus", "thin_slab", "star_noisy"])
+def test_orientation_bit_exact(case):
+    from paper_2609_20964_amd.normals import orient_normals
+    from test_normals_oracle import _thin_slab
+    if case == "sphere":
+        x, n = synth.sphere(2500, radius=0.3, seed=76)
+    elif case == "torus":
+        x, n = synth.torus(6000, pos_sigma=0.0, ang_sigma_deg=0.0, seeds=(78, 79, 80))
+    elif case == "thin_slab":
+        x, n = _thin_slab(t=0.02, spacing=0.016, seed=82)
+    else:
+        c = synth.draw_star_coeffs(94)
+        x, n = synth.star(c, 5000, 95)
+        x = (x + np.random.default_rng(96).normal(0, 0.002, x.shape)).astype(np.float32)
+    nn = _random_signs(n, 97)
+    out_ref, s_ref, counts_ref, p = NO.orient(x, nn)
+    out, info, counts = orient_normals(_cuda(x), _cuda(nn), counts=True)
+    counts = counts.cpu().numpy()
+    print(case, info, flush=True)
+    assert info["spacing2"] == float(p["d2max"])
+    assert info["n_probes"] == p["M"]
+    assert abs(info["rd"] - p["rd"]) <= 1e-15 * p["rd"]
+    assert (counts == counts_ref).all()
+    assert (out.cpu().numpy() == out_ref).all()
+    assert info["n_flipped"] == int((s_ref < 0).sum())
+    # plain parity too
+    out0, _, _ = orient_normals(_cuda(x), _cuda(nn), refine=False)
+    assert (out0.cpu().numpy() == (NO.orient_signs(counts_ref, refine=False)[:, None] * nn)).all()
+
+
+def test_estimated_and_oriented_normals_point_outward():
+    """D-PCA then orientation on a noisy star-shaped body: the normals the
+    Poisson path takes, against the shape's analytic outward normals."""
+    from paper_2609_20964_amd.normals import oriented_normals
+    c = synth.draw_star_coeffs(98)
+    x, n_true = synth.star(c, 60000, 99)
+    x = (x + np.random.default_rng(100).normal(0, 0.001, x.shape)).astype(np.float32)
+    n, info = oriented_normals(_cuda(x), radius=0.03)
+    n = n.cpu().numpy().astype(np.float64)
+    cosang = np.sum(n * n_true, 1)
+    print("outward", (cosang > 0).mean(), "median angle", np.median(np.arccos(np.clip(np.abs(cosang), 0, 1))),
+          info, flush=True)
+    assert (cosang > 0).mean() > 0.99
+    assert np.median(np.arccos(np.clip(cosang, -1, 1))) < 0.05
+
+
+def test_normal_option_errors():
+    from paper_2609_20964_amd._lib import WgError
+    from paper_2609_20964_amd.normals import dpca_normals, orient_normals
+    x = _cuda(np.random.default_rng(101).uniform(0, 1, (100, 3)))
+    with pytest.raises(WgError):
+        dpca_normals(x, radius=0.0)
+    with pytest.raises(WgError):
+        orient_normals(x[:1], x[:1])
+    with pytest.raises(WgError):
+        orient_normals(x, x, gamma_r=0.5)
+    bad = x.clone()
+    bad[7, 1] = float("nan")
+    with pytest.raises(WgError):
+        dpca_normals(bad, radius=0.1)
+    with pytest.raises(WgError):
+        orient_normals(bad, x)
+    twins = torch.cat([x, x])
+    with pytest.raises(WgError):
+        orient_normals(twins, twins)
