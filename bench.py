@@ -496,6 +496,79 @@ def secondary_run():
     return out, cmp
 
 
+def normals_run(n_points=200_000, radius=0.1, gamma_r=2.5, n_tol=2, reps=3):
+    """Unoriented clouds (Sec. 2.1-2.2) at the defaults of Table 1: D-PCA
+    normals and their orientation for the fish-like cloud (200,000 points,
+    bounding box 0.8 x 0.28 x 0.36), timed per call (each call blocks and
+    allocates its work buffers on the stream); quality against the body's
+    analytic outward normals.  Keeps a seeded sample for the oracle."""
+    import torch
+
+    from paper_2609_20964_amd import synth
+    from paper_2609_20964_amd.normals import dpca_normals, orient_normals
+
+    x, n_true = synth.fish(n_points)
+    xd = torch.from_numpy(x).cuda()
+    nd = dpca_normals(xd, radius)
+    orient_normals(xd, nd, gamma_r, n_tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nd = dpca_normals(xd, radius)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        no, info, cnt = orient_normals(xd, nd, gamma_r, n_tol, counts=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    un, on = nd.cpu().numpy(), no.cpu().numpy()
+    cosang = np.sum(on.astype(np.float64) * n_true, 1)
+    line_ang = np.arccos(np.clip(np.abs(np.sum(un.astype(np.float64) * n_true, 1)), 0, 1))
+    out = {"dpca_ms": (t1 - t0) / reps * 1e3, "orient_ms": (t2 - t1) / reps * 1e3,
+           "points_per_s": n_points / ((t2 - t0) / reps), "outward_frac": float((cosang > 0).mean()),
+           "dpca_angle_median_rad": float(np.median(line_ang)), "dpca_angle_p99_rad": float(np.percentile(line_ang, 99)),
+           "orient_info": info,
+           "workload": f"fish-like star body, {n_points} points, R = {radius}, gamma_r = {gamma_r}, N_tol = {n_tol} "
+                       "(Table 1 defaults)"}
+    rng = np.random.default_rng(4101)
+    pick = np.sort(rng.choice(n_points, 200, replace=False))
+    cmp = {"x": x, "pick": pick, "dpca": un[pick], "nrm_in": un, "counts": cnt.cpu().numpy()[pick],
+           "oriented": on[pick], "info": info, "radius": radius, "gamma_r": gamma_r, "n_tol": n_tol}
+    return out, cmp
+
+
+def normals_oracle_error(cmp):
+    """Part of the cpu_baseline leg: the oracle's D-PCA normal and ray counts
+    at 200 seeded points of the fish cloud (full neighbourhoods and rays
+    against the whole cloud)."""
+    from scipy.spatial import cKDTree
+
+    from oracle import normals as NO
+
+    x = cmp["x"]
+    t0 = time.perf_counter()
+    tree = cKDTree(x.astype(np.float64))
+    p = NO.ray_params(x, cmp["gamma_r"])
+    worst, counts_equal, signs_equal = 0.0, 0, 0
+    R2 = NO.r2_f32(cmp["radius"])
+    for k, i in enumerate(cmp["pick"]):
+        cand = np.asarray(tree.query_ball_point(x[i].astype(np.float64), cmp["radius"] * 1.00001), np.int64)
+        nb = np.sort(cand[NO._d2_f32(x[i], x[cand]) <= R2])
+        n_ref, _ = NO.dpca_point(x, i, nb, 1e-6 * cmp["radius"])
+        g = cmp["dpca"][k].astype(np.float64)
+        worst = max(worst, float(np.arctan2(np.linalg.norm(np.cross(g, n_ref)), abs(g @ n_ref))))
+        c = []
+        for sg in (np.float32(1), np.float32(-1)):
+            y = NO.probes(x[i], (sg * cmp["nrm_in"][i]).astype(np.float32), p["M"], p["ds_f32"])
+            c.extend(NO.crossings(NO.detect(tree, x, y, p["rd"], p["rd2_f32"])))
+        counts_equal += int((np.asarray(c) == cmp["counts"][k]).all())
+        s = NO.orient_signs(np.asarray([c]), cmp["n_tol"])[0]
+        signs_equal += int((s * cmp["nrm_in"][i] == cmp["oriented"][k]).all())
+    return {"dpca_max_angle_rad": worst, "ray_counts_equal": counts_equal, "signs_equal": signs_equal,
+            "points_compared": len(cmp["pick"]), "spacing2_equal": bool(cmp["info"]["spacing2"] == float(p["d2max"])),
+            "seconds": time.perf_counter() - t0}
+
+
 def secondary_oracle_error(cmp):
     """Part of the cpu_baseline leg: the GPU results of the smaller workloads
     against the FP64 oracle (the sphere's SDF on every node and at every
@@ -775,6 +848,7 @@ def main():
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")
+    ap.add_argument("--no-normals", action="store_true", help="skip the normal estimation and orientation run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--pmc-period", metavar="NAME=P", action="append", default=[],
@@ -837,6 +911,10 @@ def main():
         line["serving"], scmp = serving_run(args.serving, 4, 64.0)
         if not args.no_cpu_baseline:
             line["serving"]["oracle_error"] = serving_oracle_error(scmp)
+    if not args.no_normals:
+        line["normals"], ncmp = normals_run()
+        if not args.no_cpu_baseline:
+            line["normals"]["oracle_error"] = normals_oracle_error(ncmp)
     if not args.no_secondary:
         line["secondary"], cmp = secondary_run()
         if not args.no_cpu_baseline:

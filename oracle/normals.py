@@ -80,7 +80,9 @@ def dpca_point(x32, i, nbr, eps):
     W = w.sum()
     xbar = (w[:, None] * X).sum(0) / W                   # Eq. 3
     A = np.sqrt(w / W)[:, None] * (X - xbar)             # C_i = A^T A, Eq. 4
-    _, s, vt = np.linalg.svd(A, full_matrices=True)
+    if len(A) < 3:                                       # zero rows leave A^T A unchanged
+        A = np.concatenate([A, np.zeros((3 - len(A), 3))])
+    _, s, vt = np.linalg.svd(A, full_matrices=False)     # vt: all three right singular vectors
     sv = np.zeros(3)
     sv[:len(s)] = s
     lam = np.sort(sv ** 2)
