@@ -13,6 +13,8 @@
 // order, with no contraction: the same arithmetic as the host-side statement
 // of the method, so the neighbour sets, detection arrays and flips are the
 // same bit for bit.  Everything after a neighbour set is formed is FP64.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -88,6 +90,21 @@ __global__ __launch_bounds__(256) void k_pg_scatter(const float *__restrict__ xy
 
 __global__ void k_set_word(uint32_t *p, uint32_t v) { *p = v; }
 
+// chunks of at most `per` points of one cell: their count per cell, then the
+// cell of every chunk
+__global__ __launch_bounds__(256) void k_cell_chunks(const uint32_t *__restrict__ cnt, uint32_t cells, uint32_t per,
+                                                      uint32_t *__restrict__ ch_cnt) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < cells) ch_cnt[c] = (cnt[c] + per - 1) / per;
+}
+__global__ __launch_bounds__(256) void k_chunk_cells(const uint32_t *__restrict__ ch_cnt,
+                                                      const uint32_t *__restrict__ ch_off, uint32_t cells,
+                                                      uint32_t *__restrict__ chunk_cell) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    for (uint32_t k = 0; k < ch_cnt[c]; ++k) chunk_cell[ch_off[c] + k] = c;
+}
+
 // ---- D-PCA (Sec. 2.1) ---------------------------------------------------------
 
 // Eigenvector of the smallest eigenvalue of the symmetric 3x3 matrix
@@ -132,37 +149,90 @@ __device__ void min_eigvec3(const double a[6], double v[3]) {
     for (int k = 0; k < 3; ++k) v[k] = V[k][m] / nn;
 }
 
-// One thread per point, in sorted order.  Neighbours: FP32 squared distance
-// <= R^2 (Eq. 1).  Weights 1/(d + eps) with d in FP64 (Eq. 2); the weighted
-// first and second moments of the offsets q - p in FP64 give the centroid
-// (Eq. 3) and the covariance about it (Eq. 4), C = S2/W - m m^T with m = S1/W.
-__global__ __launch_bounds__(256) void k_dpca(PGrid g, int npts, float R2, float reach, double eps,
-                                               float *__restrict__ nrm) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npts) return;
-    const float4 p = g.pts[t];
-    double W = 0.0, s1[3] = {0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
-    for_near(g, p.x, p.y, p.z, reach, [&](const float4 &q) {
-        if (d2f(p.x, p.y, p.z, q.x, q.y, q.z) <= R2) {
-            const double dx = (double)q.x - (double)p.x, dy = (double)q.y - (double)p.y,
-                         dz = (double)q.z - (double)p.z;
-            const double w = 1.0 / (sqrt(dx * dx + dy * dy + dz * dz) + eps);
-            W += w;
-            s1[0] += w * dx;
-            s1[1] += w * dy;
-            s1[2] += w * dz;
-            s2[0] += w * dx * dx;
-            s2[1] += w * dx * dy;
-            s2[2] += w * dx * dz;
-            s2[3] += w * dy * dy;
-            s2[4] += w * dy * dz;
-            s2[5] += w * dz * dz;
+// D-PCA of every point.  Neighbours: FP32 squared distance
+// <= R^2 (Eq. 1).  Weights 1/(d + eps) (Eq. 2) in FP32 from the root of that
+// same squared distance (hardware root and reciprocal, 1 ulp each; relative
+// error ~2e-7, which moves a normal by about
+// 1e-7 over the relative gap of the two smallest eigenvalues); the weighted
+// first and second moments of the offsets q - p accumulate in FP64 and give
+// the centroid (Eq. 3) and the covariance about it (Eq. 4),
+// C = S2/W - m m^T with m = S1/W.
+//
+// A workgroup of four wavefronts takes a chunk of at most 64 points of one
+// cell (so they share one search box; lane l of every wavefront holds point
+// l) and streams the candidates of that box through LDS in tiles of 256: one
+// coalesced load per tile, then wavefront w tests candidates 64w..64w+63 of
+// the tile against its lane's point (a broadcast LDS read per candidate).
+// The four partial sums of each point are added in LDS at the end.
+constexpr int kDpcaChunk = 64;
+constexpr int kDpcaWaves = 4;
+
+__global__ __launch_bounds__(kDpcaChunk * kDpcaWaves) void k_dpca(PGrid g, const uint32_t *__restrict__ chunk_cell,
+                                                                   const uint32_t *__restrict__ ch_off, float R2,
+                                                                   float reach, float eps, float *__restrict__ nrm) {
+    constexpr int NT = kDpcaChunk * kDpcaWaves;
+    __shared__ float4 tile[NT];
+    __shared__ double part[kDpcaWaves - 1][10][kDpcaChunk];
+    const int lane = threadIdx.x % kDpcaChunk, wv = threadIdx.x / kDpcaChunk;
+    const uint32_t ch = blockIdx.x;
+    const uint32_t c = chunk_cell[ch];
+    const uint32_t first = g.start[c] + (ch - ch_off[c]) * kDpcaChunk, last = g.start[c + 1];
+    const uint32_t me = first + lane;
+    const bool live = me < last;
+    const float4 p = g.pts[live ? me : first];
+    // the cell's search box: the cells within reach of any point of the cell
+    const int cx = (int)(c % (uint32_t)g.n[0]), cy = (int)((c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]),
+              cz = (int)(c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
+    const float cs = 1.0f / g.inv_cs;
+    const float lx = g.lo[0] + cx * cs, ly = g.lo[1] + cy * cs, lz = g.lo[2] + cz * cs;
+    const int x0 = min(cell_of(g, 0, lx - reach), cx), x1 = max(cell_of(g, 0, lx + cs + reach), cx);
+    const int y0 = min(cell_of(g, 1, ly - reach), cy), y1 = max(cell_of(g, 1, ly + cs + reach), cy);
+    const int z0 = min(cell_of(g, 2, lz - reach), cz), z1 = max(cell_of(g, 2, lz + cs + reach), cz);
+    const double px = p.x, py = p.y, pz = p.z;
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // W, S1 (3), S2 (6)
+    for (int bz = z0; bz <= z1; ++bz)
+        for (int by = y0; by <= y1; ++by) {
+            const size_t row = (size_t)g.n[0] * (by + (size_t)g.n[1] * bz);
+            const uint32_t b = g.start[row + x0], e = g.start[row + x1 + 1];
+            for (uint32_t j0 = b; j0 < e; j0 += NT) {
+                const uint32_t cnt = min((uint32_t)NT, e - j0);
+                __syncthreads();
+                if (threadIdx.x < cnt) tile[threadIdx.x] = g.pts[j0 + threadIdx.x];
+                __syncthreads();
+                const uint32_t k0 = (uint32_t)wv * kDpcaChunk, k1 = min(k0 + kDpcaChunk, cnt);
+#pragma unroll 4
+                for (uint32_t k = k0; k < k1; ++k) {
+                    const float4 q = tile[k];
+                    const float d2 = d2f(p.x, p.y, p.z, q.x, q.y, q.z);
+                    if (d2 <= R2) {
+                        // hardware root and reciprocal (1 ulp): the weight's error stays ~1e-7 relative
+                        const double w = (double)__builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(d2) + eps);
+                        const double dx = (double)q.x - px, dy = (double)q.y - py, dz = (double)q.z - pz;
+                        const double wx = w * dx, wy = w * dy, wz = w * dz;
+                        acc[0] += w;
+                        acc[1] += wx;
+                        acc[2] += wy;
+                        acc[3] += wz;
+                        acc[4] += wx * dx;
+                        acc[5] += wx * dy;
+                        acc[6] += wx * dz;
+                        acc[7] += wy * dy;
+                        acc[8] += wy * dz;
+                        acc[9] += wz * dz;
+                    }
+                }
+            }
         }
-        return false;
-    });
-    const double m[3] = {s1[0] / W, s1[1] / W, s1[2] / W};
-    const double C[6] = {s2[0] / W - m[0] * m[0], s2[1] / W - m[0] * m[1], s2[2] / W - m[0] * m[2],
-                         s2[3] / W - m[1] * m[1], s2[4] / W - m[1] * m[2], s2[5] / W - m[2] * m[2]};
+    if (wv > 0)
+        for (int k = 0; k < 10; ++k) part[wv - 1][k][lane] = acc[k];
+    __syncthreads();
+    if (wv > 0 || !live) return;
+    for (int w = 0; w < kDpcaWaves - 1; ++w)
+        for (int k = 0; k < 10; ++k) acc[k] += part[w][k][lane];
+    const double W = acc[0];
+    const double m[3] = {acc[1] / W, acc[2] / W, acc[3] / W};
+    const double C[6] = {acc[4] / W - m[0] * m[0], acc[5] / W - m[0] * m[1], acc[6] / W - m[0] * m[2],
+                         acc[7] / W - m[1] * m[1], acc[8] / W - m[1] * m[2], acc[9] / W - m[2] * m[2]};
     double v[3];
     min_eigvec3(C, v);
     const int i = __float_as_int(p.w);
@@ -178,7 +248,7 @@ __global__ __launch_bounds__(256) void k_dpca(PGrid g, int npts, float R2, float
 // unsigned integers).  Rings of cells around the point's cell, until the
 // nearest point found is nearer than any point outside the searched cube can
 // be (every point outside is at least ring x cell size away).
-__global__ __launch_bounds__(256) void k_nn_spacing(PGrid g, float cs, int npts, uint32_t *d2max_bits) {
+__global__ __launch_bounds__(256) void k_nn_spacing(PGrid g, float cs, float slack, int npts, uint32_t *d2max_bits) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts) return;
     const float4 p = g.pts[t];
@@ -208,8 +278,8 @@ __global__ __launch_bounds__(256) void k_nn_spacing(PGrid g, float cs, int npts,
                     }
                 }
             }
-        const float reach = (float)r * cs;
-        if (best < reach * reach * 0.9999f || r >= maxn) break;
+        const float reach = (float)r * cs - slack;   // every point outside the cube is farther than this
+        if ((reach > 0.0f && best < reach * reach) || r >= maxn) break;
     }
     if (best < INFINITY) atomicMax(d2max_bits, __float_as_uint(best));
 }
@@ -217,7 +287,28 @@ __global__ __launch_bounds__(256) void k_nn_spacing(PGrid g, float cs, int npts,
 struct RayParams {
     float rd2, ds, reach;
     int M, n_tol, refine;
+    float box_lo[3], box_hi[3];   // the cloud's box widened by reach: no detection outside
+    const uint32_t *near;         // bit per cell: some point within reach of the cell's range
 };
+
+// Bit c of `near`: cell c lies in [cell(q - reach), cell(q + reach)] on every
+// axis for some point q.  A probe within reach of q lies in that range too
+// (cell_of is monotone), so a probe whose cell has no bit detects nothing.
+__global__ __launch_bounds__(256) void k_mark_near(const float *__restrict__ xyz, int npts, PGrid g, float reach,
+                                                    uint32_t *near) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    const int x0 = cell_of(g, 0, x - reach), x1 = cell_of(g, 0, x + reach);
+    const int y0 = cell_of(g, 1, y - reach), y1 = cell_of(g, 1, y + reach);
+    const int z0 = cell_of(g, 2, z - reach), z1 = cell_of(g, 2, z + reach);
+    for (int cz = z0; cz <= z1; ++cz)
+        for (int cy = y0; cy <= y1; ++cy)
+            for (int cx = x0; cx <= x1; ++cx) {
+                const uint32_t c = (uint32_t)cx + (uint32_t)g.n[0] * ((uint32_t)cy + (uint32_t)g.n[1] * (uint32_t)cz);
+                atomicOr(near + (c >> 5), 1u << (c & 31));
+            }
+}
 
 // Detection array of one ray (Eq. 8-9) reduced on the fly to (N_i, N_one)
 // (Eq. 10-11 and the initial-one count).  Probe y_m = x + (m ds) s, FP32,
@@ -230,9 +321,16 @@ __device__ __forceinline__ void cast_ray(const PGrid &g, const RayParams &rp, fl
     for (int m = 0; m <= rp.M; ++m) {
         const float t = (float)m * rp.ds;
         const float px = x + t * sx, py = y + t * sy, pz = z + t * sz;
-        const int d = for_near(g, px, py, pz, rp.reach, [&](const float4 &q) {
-            return d2f(px, py, pz, q.x, q.y, q.z) <= rp.rd2;
-        }) ? 1 : 0;
+        int d = 0;
+        if (px >= rp.box_lo[0] && px <= rp.box_hi[0] && py >= rp.box_lo[1] && py <= rp.box_hi[1] &&
+            pz >= rp.box_lo[2] && pz <= rp.box_hi[2]) {
+            const uint32_t c = (uint32_t)cell_of(g, 0, px) +
+                               (uint32_t)g.n[0] * ((uint32_t)cell_of(g, 1, py) + (uint32_t)g.n[1] * (uint32_t)cell_of(g, 2, pz));
+            if ((rp.near[c >> 5] >> (c & 31)) & 1u)
+                d = for_near(g, px, py, pz, rp.reach, [&](const float4 &q) {
+                    return d2f(px, py, pz, q.x, q.y, q.z) <= rp.rd2;
+                }) ? 1 : 0;
+        }
         if (m > 0 && d == 0 && prev == 1) ++n_all;
         if (first) {
             if (d) ++ones;
@@ -244,25 +342,31 @@ __device__ __forceinline__ void cast_ray(const PGrid &g, const RayParams &rp, fl
     n_one = ones;
 }
 
-// One thread per point: rays along +n and -n, then the flips of Sec. 2.2:
-// iteration 0 flips an odd N_i; a normal whose ray (along the normal after
-// iteration 0) starts with more than n_tol detecting probes is flipped
-// (iteration 1) and flipped back if the flipped direction shows more
-// crossings than the other (iteration 2).
+// Two lanes per point (adjacent, so one shuffle pairs them): the even lane
+// casts the ray along +n, the odd one along -n; then the even lane takes the
+// flips of Sec. 2.2: iteration 0 flips an odd N_i; a normal whose ray (along
+// the normal after iteration 0) starts with more than n_tol detecting probes
+// is flipped (iteration 1) and flipped back if the flipped direction shows
+// more crossings than the other (iteration 2).
 __global__ __launch_bounds__(256) void k_orient(PGrid g, RayParams rp, const float *__restrict__ xyz, int npts,
                                                  float *__restrict__ nrm, int32_t *__restrict__ counts,
                                                  uint32_t *n_flipped) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
-    const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-    const float nx = nrm[3 * i], ny = nrm[3 * i + 1], nz = nrm[3 * i + 2];
-    int Np, N1p, Nm, N1m;
-    cast_ray(g, rp, x, y, z, nx, ny, nz, Np, N1p);
-    cast_ray(g, rp, x, y, z, -nx, -ny, -nz, Nm, N1m);
-    int s = (Np % 2 != 0) ? -1 : 1;   // iteration 0 (N_i >= -1; -1 is even)
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = tid >> 1, dir = tid & 1;
+    const bool live = i < npts;
+    const int ii = live ? i : npts - 1;   // lanes past the end pair up on the last point
+    const float x = xyz[3 * ii], y = xyz[3 * ii + 1], z = xyz[3 * ii + 2];
+    const float nx = nrm[3 * ii], ny = nrm[3 * ii + 1], nz = nrm[3 * ii + 2];
+    int N, N1;
+    if (dir == 0) cast_ray(g, rp, x, y, z, nx, ny, nz, N, N1);
+    else cast_ray(g, rp, x, y, z, -nx, -ny, -nz, N, N1);
+    const int No = __shfl_xor(N, 1, 64), N1o = __shfl_xor(N1, 1, 64);
+    if (!live || dir != 0) return;
+    const int Np = N, N1p = N1, Nm = No, N1m = N1o;
+    int s = (Np % 2 != 0) ? -1 : 1;   // iteration 0
     if (rp.refine) {
-        const int N0 = s > 0 ? Np : Nm, N1 = s > 0 ? N1p : N1m, Nopp = s > 0 ? Nm : Np;
-        if (N1 > rp.n_tol) {
+        const int N0 = s > 0 ? Np : Nm, Nc1 = s > 0 ? N1p : N1m, Nopp = s > 0 ? Nm : Np;
+        if (Nc1 > rp.n_tol) {
             s = -s;                         // iteration 1: N_i != 0 or N_one > N_tol holds
             if (Nopp > N0) s = -s;          // iteration 2: the flipped direction crosses more
         }
@@ -311,6 +415,15 @@ float key_to_float(uint32_t k) {
 
 struct Box {
     float lo[3], hi[3];
+    // search reach for a decision radius r: r widened by 0.1% and by a few
+    // FP32 ulps of the largest coordinate, so that rounding in cell
+    // boundaries and squared distances never hides a point the exact test
+    // would accept
+    double reach(double r) const {
+        double m = 0.0;
+        for (int a = 0; a < 3; ++a) m = std::max(m, std::max(std::fabs((double)lo[a]), std::fabs((double)hi[a])));
+        return r * 1.001 + 1e-6 * m;
+    }
 };
 
 // Bounding box of the cloud (exact, from order-preserving keys); a
@@ -341,7 +454,8 @@ constexpr double kMaxCells = double(1 << 25);
 
 // Sort the points into cells of size >= cs over the box (enlarged if the grid
 // would exceed kMaxCells); returns the grid and the cell size used.
-PGrid build_grid(const float *xyz, int npts, const Box &b, double cs, Scratch &sc, hipStream_t st, double &cs_used) {
+PGrid build_grid(const float *xyz, int npts, const Box &b, double cs, Scratch &sc, hipStream_t st, double &cs_used,
+                 const uint32_t **counts = nullptr) {
     double ext[3];
     for (int a = 0; a < 3; ++a) ext[a] = (double)b.hi[a] - (double)b.lo[a];
     int n[3];
@@ -381,6 +495,7 @@ PGrid build_grid(const float *xyz, int npts, const Box &b, double cs, Scratch &s
     k_set_word<<<1, 1, 0, st>>>(start + cells, (uint32_t)npts);
     k_pg_scatter<<<cdiv(npts, 256), 256, 0, st>>>(xyz, npts, cell, rank, start, pts);
     WG_LAUNCH_CHECK();
+    if (counts) *counts = cnt;
     return g;
 }
 
@@ -392,9 +507,25 @@ int dpca(const float *xyz, int npts, double R, double eps, float *nrm, hipStream
     Scratch sc(st);
     const Box b = cloud_box(xyz, npts, sc, st);
     double cs = 0.0;
-    const PGrid g = build_grid(xyz, npts, b, 0.5 * R, sc, st, cs);
+    const uint32_t *cnt = nullptr;
+    const PGrid g = build_grid(xyz, npts, b, 0.5 * R, sc, st, cs, &cnt);
+    // chunks of at most kDpcaChunk points of one cell
+    const uint32_t cells = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
+    uint32_t *ch_cnt = sc.take<uint32_t>(cells), *ch_off = sc.take<uint32_t>(cells), *act = sc.take<uint32_t>(cells);
+    const uint32_t nblk = cdiv(cells, scan::kScanBlock);
+    uint32_t *blk = sc.take<uint32_t>(2 * (size_t)nblk), *tot = sc.take<uint32_t>(2);
+    k_cell_chunks<<<cdiv(cells, 256), 256, 0, st>>>(cnt, cells, kDpcaChunk, ch_cnt);
+    scan::k_scan_partial<<<nblk, 256, 0, st>>>(ch_cnt, cells, blk);
+    scan::k_scan_top<<<1, 256, 0, st>>>(blk, nblk, tot);
+    scan::k_scan_final<<<nblk, 256, 0, st>>>(ch_cnt, cells, blk, ch_off, act);
+    WG_LAUNCH_CHECK();
+    uint32_t nch = 0;
+    WG_HIP(hipMemcpyAsync(&nch, tot, sizeof(nch), hipMemcpyDeviceToHost, st));
+    WG_HIP(hipStreamSynchronize(st));
+    uint32_t *chunk_cell = sc.take<uint32_t>(nch);
+    k_chunk_cells<<<cdiv(cells, 256), 256, 0, st>>>(ch_cnt, ch_off, cells, chunk_cell);
     const float R2 = (float)(R * R);
-    k_dpca<<<cdiv(npts, 256), 256, 0, st>>>(g, npts, R2, (float)(R * 1.001), eps, nrm);
+    k_dpca<<<nch, kDpcaChunk * kDpcaWaves, 0, st>>>(g, chunk_cell, ch_off, R2, (float)b.reach(R), (float)eps, nrm);
     WG_LAUNCH_CHECK();
     WG_HIP(hipStreamSynchronize(st));
     return WG_OK;
@@ -423,7 +554,8 @@ int orient(const float *xyz, int npts, float *nrm, const wg_orient_opts &o, int3
     const PGrid gn = build_grid(xyz, npts, b, cs_nn, sc, st, cs_used);
     uint32_t *dmax = sc.take<uint32_t>(1);
     WG_HIP(hipMemsetAsync(dmax, 0, sizeof(uint32_t), st));
-    k_nn_spacing<<<cdiv(npts, 256), 256, 0, st>>>(gn, (float)cs_used, npts, dmax);
+    k_nn_spacing<<<cdiv(npts, 256), 256, 0, st>>>(gn, (float)cs_used, (float)(b.reach(cs_used) - cs_used), npts,
+                                                  dmax);
     WG_LAUNCH_CHECK();
     uint32_t bits = 0;
     WG_HIP(hipMemcpyAsync(&bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, st));
@@ -439,14 +571,24 @@ int orient(const float *xyz, int npts, float *nrm, const wg_orient_opts &o, int3
     RayParams rp;
     rp.rd2 = (float)(rd * rd);
     rp.ds = (float)ds;
-    rp.reach = (float)(rd * 1.001);
+    rp.reach = (float)b.reach(rd);
     rp.M = (int)Md;
     rp.n_tol = o.n_tol;
     rp.refine = o.refine;
     const PGrid go = build_grid(xyz, npts, b, rd, sc, st, cs_used);
+    const size_t cells = (size_t)go.n[0] * go.n[1] * go.n[2];
+    uint32_t *near = sc.take<uint32_t>((cells + 31) / 32);
+    WG_HIP(hipMemsetAsync(near, 0, ((cells + 31) / 32) * sizeof(uint32_t), st));
+    k_mark_near<<<cdiv(npts, 256), 256, 0, st>>>(xyz, npts, go, rp.reach, near);
+    WG_LAUNCH_CHECK();
+    rp.near = near;
+    for (int a = 0; a < 3; ++a) {
+        rp.box_lo[a] = (float)((double)b.lo[a] - 2.0 * (double)rp.reach);
+        rp.box_hi[a] = (float)((double)b.hi[a] + 2.0 * (double)rp.reach);
+    }
     uint32_t *nflip = sc.take<uint32_t>(1);
     WG_HIP(hipMemsetAsync(nflip, 0, sizeof(uint32_t), st));
-    k_orient<<<cdiv(npts, 256), 256, 0, st>>>(go, rp, xyz, npts, nrm, counts, nflip);
+    k_orient<<<cdiv(2 * (size_t)npts, 256), 256, 0, st>>>(go, rp, xyz, npts, nrm, counts, nflip);
     WG_LAUNCH_CHECK();
     uint32_t hflip = 0;
     WG_HIP(hipMemcpyAsync(&hflip, nflip, sizeof(hflip), hipMemcpyDeviceToHost, st));

@@ -62,12 +62,15 @@ def test_dpca_matches_oracle(case):
     assert ang[ok].max() <= 1e-5
 
 
-@pytest.mark.parametrize("case", ["sphere", "torus", "thin_slab", "star_noisy"])
+@pytest.mark.parametrize("case", ["sphere", "sphere_shifted", "torus", "thin_slab", "star_noisy"])
 def test_orientation_bit_exact(case):
     from paper_2609_20964_amd.normals import orient_normals
     from test_normals_oracle import _thin_slab
     if case == "sphere":
         x, n = synth.sphere(2500, radius=0.3, seed=76)
+    elif case == "sphere_shifted":
+        x, n = synth.sphere(2500, radius=0.3, seed=76)
+        x = (x.astype(np.float64) + np.array([3.0, -2.0, 5.0])).astype(np.float32)
     elif case == "torus":
         x, n = synth.torus(6000, pos_sigma=0.0, ang_sigma_deg=0.0, seeds=(78, 79, 80))
     elif case == "thin_slab":
