@@ -97,6 +97,14 @@ def gpu_run(args):
     q = torch.from_numpy(synth.uniform_queries(nq, 4001)).cuda()
     r = Recon(n, npts)
     kinds = list(_lib.PROF_KINDS)
+    # the cold step: the first step on a new handle (cold solve, cold walk), outputs complete
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    r.step(*clouds[0], q, rel_tol=args.tol, warm_start=False)
+    r.wait()
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - c0) * 1e3
+    log(f"cold step 0: {cold_ms:.2f} ms")
     # warm-up, then the last three warm-up clouds again as plain steps (no
     # overlap, so each kind's event-timed duration is its own) with every
     # kernel kind profiled, to find the dominant one
@@ -166,6 +174,16 @@ def gpu_run(args):
     fields = r.fields()
     gpu_last = {"chi": fields["chi"].cpu().numpy(), "phi": fields["phi"].cpu().numpy(),
                 "iso_c": st2["iso_c"], "phi_q": phi.cpu().numpy(), "t": last_t}
+    # every 25th timed step again as a plain forward (warm-started from the step
+    # before it), its field and SDF kept for the oracle comparison
+    samples = []
+    for k in range(24, args.steps, 25):
+        t = args.warmup + k
+        r.forward(*clouds[t - 1], rel_tol=args.tol, warm_start=True)
+        stk = r.forward(*clouds[t], rel_tol=args.tol, warm_start=True)
+        fk = r.fields()
+        samples.append({"t": t, "chi": fk["chi"].cpu().numpy(), "phi": fk["phi"].cpu().numpy(),
+                        "iso_c": stk["iso_c"], "cloud": tuple(c.cpu().numpy() for c in clouds[t])})
 
     # reverse pass at the same size: L = mean phi(q)^2 (one untimed warm-up call first)
     adj_ms = []
@@ -182,7 +200,7 @@ def gpu_run(args):
     exact = exact_run(args, r, clouds, q, kinds) if args.exact_steps else None
     r.close()
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
-            "exact": exact,
+            "exact": exact, "cold_ms": cold_ms, "samples": samples,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
             "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof,
@@ -353,6 +371,88 @@ def load_pmc(kind):
     if vals.get("source_sha") != source_sha(src):
         return {}
     return vals
+
+
+def sample_errors(res, n, sample_nodes):
+    """GPU against the oracle on every 25th timed step (re-run as plain
+    forwards): field, iso-value and SDF on `sample_nodes` random nodes."""
+    from oracle import discretize as D
+    from oracle import pipeline as P
+
+    grid = D.Grid.unit(n)
+    rng = np.random.default_rng(4003)
+    out = []
+    for s in res["samples"]:
+        x, nrm = s["cloud"]
+        ref = P.Recon(grid, x, nrm)
+        nodes = rng.choice(n ** 3, sample_nodes, replace=False)
+        out.append({"step": int(s["t"]),
+                    "chi_rel_l2": float(np.linalg.norm(s["chi"] - ref.chi) / np.linalg.norm(ref.chi)),
+                    "iso_c_rel": float(abs(s["iso_c"] - ref.c) / np.abs(ref.chi).max()),
+                    "phi_max_abs_over_h": float(np.abs(s["phi"].reshape(-1)[nodes].astype(np.float64) -
+                                                       ref.phi_nodes(nodes)).max() * n),
+                    "nodes_compared": int(sample_nodes)})
+    return out
+
+
+def oracle_timing(cmp, reps=3):
+    """The oracle on the 32^3 sphere and the 128^3 torus at one thread and at
+    all cores (BLAS / OpenMP pools and scipy.fft workers), median of `reps`:
+    forward in full, distance on 1,500 random nodes scaled to the grid."""
+    from threadpoolctl import threadpool_limits
+    import scipy.fft
+
+    from oracle import discretize as D
+    from oracle import pipeline as P
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"cores_all": cores, "cpu_model": cpu_model()}
+    for name, n, key in (("sphere_32", 32, "sphere"), ("torus_128", 128, "torus")):
+        c = cmp[key]
+        rng = np.random.default_rng(4004)
+        nodes = rng.choice(n ** 3, 1500, replace=False)
+        row = {}
+        for label, th in (("one_thread", 1), ("all_cores", cores)):
+            times = []
+            for _ in range(reps):
+                with threadpool_limits(th), scipy.fft.set_workers(th):
+                    t0 = time.perf_counter()
+                    ref = P.Recon(D.Grid.unit(n), c["x"], c["nrm"])
+                    t1 = time.perf_counter()
+                    ref.phi_nodes(nodes)
+                    t2 = time.perf_counter()
+                times.append((t1 - t0) + (t2 - t1) / len(nodes) * n ** 3)
+            row[label] = {"recons_per_s": 1.0 / float(np.median(times)), "seconds_median": float(np.median(times)),
+                          "threads": th}
+        out[name] = row
+    out["sample"] = ("oracle forward in full; brute-force distance on 1,500 random nodes scaled to the grid; "
+                     f"median of {reps}")
+    return out
+
+
+def eikonal(phi, h, band=3.0):
+    """|grad phi| (Eq. 32) by central differences at the interior nodes within
+    `band` cells of the surface: median, percentiles and the share within 5%
+    of 1 (an SDF of a mesh has |grad phi| = 1 away from its medial axis)."""
+    p = np.asarray(phi, np.float64)
+    c = p[1:-1, 1:-1, 1:-1]
+    gx = (p[1:-1, 1:-1, 2:] - p[1:-1, 1:-1, :-2]) / (2 * h)
+    gy = (p[1:-1, 2:, 1:-1] - p[1:-1, :-2, 1:-1]) / (2 * h)
+    gz = (p[2:, 1:-1, 1:-1] - p[:-2, 1:-1, 1:-1]) / (2 * h)
+    g = np.sqrt(gx * gx + gy * gy + gz * gz)[np.abs(c) < band * h]
+    return {"nodes": int(g.size), "median": float(np.median(g)), "p01": float(np.percentile(g, 1)),
+            "p99": float(np.percentile(g, 99)), "within_5pct": float(np.mean(np.abs(g - 1.0) < 0.05)),
+            "band_cells": band}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(res, n, sample_nodes):
@@ -835,7 +935,7 @@ def pmc_summary(path, periods=()):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--points", type=int, default=300_000)
@@ -901,12 +1001,15 @@ def main():
                            for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
         "kernel_ms_per_step_plain": {k: v["ms"] / res["n_prof"] for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
+        "cold_step_ms": res["cold_ms"],
+        "eikonal": eikonal(res["gpu_last"]["phi"].reshape(args.n, args.n, args.n), 1.0 / args.n),
         "exact_quadrature": exact_summary(res, copy_gbs) if res["exact"] else None,
     }
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(res, args.n, args.cpu_sample_nodes)
         line["cpu_baseline"] = base
         line["oracle_error"] = err
+        line["oracle_error_every_25th_step"] = sample_errors(res, args.n, args.cpu_sample_nodes)
     if args.serving > 0:
         line["serving"], scmp = serving_run(args.serving, 4, 64.0)
         if not args.no_cpu_baseline:
@@ -920,6 +1023,7 @@ def main():
         if not args.no_cpu_baseline:
             for k, v in secondary_oracle_error(cmp).items():
                 line["secondary"][k]["oracle_error"] = v
+            line["secondary"]["oracle_timing"] = oracle_timing(cmp)
     print(json.dumps(line), flush=True)
 
 

@@ -75,3 +75,14 @@ def test_latency_by_grid():
     assert out["128"]["p50_ms"] == pytest.approx(10.0) and out["128"]["p99_ms"] == pytest.approx(10.0)
     assert out["256"]["p50_ms"] == pytest.approx(35.0)
     assert out["256"]["p99_ms"] == pytest.approx(30.0 + 0.99 * 10.0)
+
+
+def test_eikonal_diagnostic_of_exact_and_scaled_distances():
+    import numpy as np
+    n, h = 48, 1.0 / 48
+    z, y, x = np.meshgrid(*(np.arange(n) * h + h / 2,) * 3, indexing="ij")
+    phi = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2) - 0.3
+    e = bench.eikonal(phi, h)
+    assert e["within_5pct"] == 1.0 and abs(e["median"] - 1.0) < 1e-3 and e["nodes"] > 1000
+    e2 = bench.eikonal(2.0 * phi, h)
+    assert e2["within_5pct"] == 0.0 and abs(e2["median"] - 2.0) < 5e-3
