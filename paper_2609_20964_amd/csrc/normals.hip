@@ -291,23 +291,46 @@ struct RayParams {
     const uint32_t *near;         // bit per cell: some point within reach of the cell's range
 };
 
-// Bit c of `near`: cell c lies in [cell(q - reach), cell(q + reach)] on every
-// axis for some point q.  A probe within reach of q lies in that range too
-// (cell_of is monotone), so a probe whose cell has no bit detects nothing.
-__global__ __launch_bounds__(256) void k_mark_near(const float *__restrict__ xyz, int npts, PGrid g, float reach,
-                                                    uint32_t *near) {
+// Bit c of `near`: some point lies in a cell within one cell of c on every
+// axis.  The grid's cell size exceeds the detection reach, so a probe within
+// reach of a point lies within one cell of it: a probe whose cell has no bit
+// detects nothing.  Built as occupancy bits (one atomic per point), then
+// dilated by one cell (one thread per cell, 64 cells per wavefront, the bits
+// gathered by a ballot).
+__global__ __launch_bounds__(256) void k_mark_occ(const float *__restrict__ xyz, int npts, PGrid g,
+                                                   uint32_t *occ) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
-    const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-    const int x0 = cell_of(g, 0, x - reach), x1 = cell_of(g, 0, x + reach);
-    const int y0 = cell_of(g, 1, y - reach), y1 = cell_of(g, 1, y + reach);
-    const int z0 = cell_of(g, 2, z - reach), z1 = cell_of(g, 2, z + reach);
-    for (int cz = z0; cz <= z1; ++cz)
-        for (int cy = y0; cy <= y1; ++cy)
-            for (int cx = x0; cx <= x1; ++cx) {
-                const uint32_t c = (uint32_t)cx + (uint32_t)g.n[0] * ((uint32_t)cy + (uint32_t)g.n[1] * (uint32_t)cz);
-                atomicOr(near + (c >> 5), 1u << (c & 31));
-            }
+    const uint32_t c = (uint32_t)cell_of(g, 0, xyz[3 * i]) +
+                       (uint32_t)g.n[0] * ((uint32_t)cell_of(g, 1, xyz[3 * i + 1]) +
+                                           (uint32_t)g.n[1] * (uint32_t)cell_of(g, 2, xyz[3 * i + 2]));
+    atomicOr(occ + (c >> 5), 1u << (c & 31));
+}
+
+__global__ __launch_bounds__(256) void k_dilate(const uint32_t *__restrict__ occ, PGrid g, uint32_t cells,
+                                                 uint32_t *__restrict__ near) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;   // 64 consecutive cells per wavefront
+    bool any = false;
+    if (c < cells) {
+        const int cx = (int)(c % (uint32_t)g.n[0]), cy = (int)((c / (uint32_t)g.n[0]) % (uint32_t)g.n[1]),
+                  cz = (int)(c / ((uint32_t)g.n[0] * (uint32_t)g.n[1]));
+        for (int z = max(cz - 1, 0); z <= min(cz + 1, g.n[2] - 1) && !any; ++z)
+            for (int y = max(cy - 1, 0); y <= min(cy + 1, g.n[1] - 1) && !any; ++y)
+                for (int x = max(cx - 1, 0); x <= min(cx + 1, g.n[0] - 1); ++x) {
+                    const uint32_t d = (uint32_t)x + (uint32_t)g.n[0] * ((uint32_t)y + (uint32_t)g.n[1] * (uint32_t)z);
+                    if ((occ[d >> 5] >> (d & 31)) & 1u) {
+                        any = true;
+                        break;
+                    }
+                }
+    }
+    const unsigned long long m = __ballot(any);
+    const uint32_t base = c - (threadIdx.x % 64);   // first cell of this wavefront, a multiple of 64
+    if (threadIdx.x % 64 == 0) {
+        const uint32_t words = (cells + 31) / 32;
+        if ((base >> 5) < words) near[base >> 5] = (uint32_t)m;
+        if ((base >> 5) + 1 < words) near[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    }
 }
 
 // Detection array of one ray (Eq. 8-9) reduced on the fly to (N_i, N_one)
@@ -434,7 +457,7 @@ Box cloud_box(const float *xyz, int npts, Scratch &sc, hipStream_t st) {
     const uint32_t init[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
     WG_HIP(hipMemcpyAsync(dbox, init, sizeof(init), hipMemcpyHostToDevice, st));
     WG_HIP(hipMemsetAsync(derr, 0, sizeof(int), st));
-    k_bbox<<<std::min<unsigned>(cdiv(npts, 256), 1024u), 256, 0, st>>>(xyz, npts, dbox, derr);
+    k_bbox<<<std::min<unsigned>(cdiv(npts, 256), 256u), 256, 0, st>>>(xyz, npts, dbox, derr);
     WG_LAUNCH_CHECK();
     uint32_t hb[6];
     int herr = 0;
@@ -575,11 +598,14 @@ int orient(const float *xyz, int npts, float *nrm, const wg_orient_opts &o, int3
     rp.M = (int)Md;
     rp.n_tol = o.n_tol;
     rp.refine = o.refine;
-    const PGrid go = build_grid(xyz, npts, b, rd, sc, st, cs_used);
-    const size_t cells = (size_t)go.n[0] * go.n[1] * go.n[2];
-    uint32_t *near = sc.take<uint32_t>((cells + 31) / 32);
-    WG_HIP(hipMemsetAsync(near, 0, ((cells + 31) / 32) * sizeof(uint32_t), st));
-    k_mark_near<<<cdiv(npts, 256), 256, 0, st>>>(xyz, npts, go, rp.reach, near);
+    // cells a little larger than the reach, so that a probe within reach of a point is within one cell of it
+    const PGrid go = build_grid(xyz, npts, b, (double)rp.reach * 1.0001, sc, st, cs_used);
+    const uint32_t cells = (uint32_t)((size_t)go.n[0] * go.n[1] * go.n[2]);
+    const size_t words = ((size_t)cells + 31) / 32;
+    uint32_t *occ = sc.take<uint32_t>(words), *near = sc.take<uint32_t>(words);
+    WG_HIP(hipMemsetAsync(occ, 0, words * sizeof(uint32_t), st));
+    k_mark_occ<<<cdiv(npts, 256), 256, 0, st>>>(xyz, npts, go, occ);
+    k_dilate<<<cdiv(cells, 256), 256, 0, st>>>(occ, go, cells, near);
     WG_LAUNCH_CHECK();
     rp.near = near;
     for (int a = 0; a < 3; ++a) {

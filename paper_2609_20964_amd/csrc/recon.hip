@@ -557,7 +557,7 @@ void grid_from_cloud(const float *xyz, int npts, double density, int pad, wg_gri
     uint32_t host[8] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u, 0u};
     try {
         WG_HIP(hipMemcpyAsync(dev, host, sizeof(host), hipMemcpyHostToDevice, s));
-        const unsigned blocks = std::min<unsigned>(cdiv(npts, 256), 1024u);
+        const unsigned blocks = std::min<unsigned>(cdiv(npts, 256), 256u);
         k_bbox<<<blocks, 256, 0, s>>>(xyz, npts, dev, reinterpret_cast<int *>(dev + 6));
         WG_LAUNCH_CHECK();
         WG_HIP(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s));

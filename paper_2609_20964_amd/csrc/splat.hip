@@ -346,12 +346,29 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ xyz, int
             mn[a] = min(mn[a], (uint32_t)__shfl_xor((int)mn[a], o, 64));
             mx[a] = max(mx[a], (uint32_t)__shfl_xor((int)mx[a], o, 64));
         }
-    if (__ballot(bad) != 0 && threadIdx.x % 64 == 0) atomicOr(err, 1);
+    // the workgroup's wavefronts meet in LDS; one set of global atomics per workgroup
+    __shared__ uint32_t wmn[3], wmx[3];
+    __shared__ int wbad;
+    if (threadIdx.x < 3) {
+        wmn[threadIdx.x] = 0xffffffffu;
+        wmx[threadIdx.x] = 0u;
+    }
+    if (threadIdx.x == 0) wbad = 0;
+    __syncthreads();
+    if (__ballot(bad) != 0 && threadIdx.x % 64 == 0) atomicOr(&wbad, 1);
     if (threadIdx.x % 64 == 0)
         for (int a = 0; a < 3; ++a) {
-            atomicMin(box + a, mn[a]);
-            atomicMax(box + 3 + a, mx[a]);
+            atomicMin(&wmn[a], mn[a]);
+            atomicMax(&wmx[a], mx[a]);
         }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (wbad) atomicOr(err, 1);
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(box + a, wmn[a]);
+            atomicMax(box + 3 + a, wmx[a]);
+        }
+    }
 }
 
 namespace {
