@@ -945,6 +945,7 @@ def main():
     ap.add_argument("--exact-steps", type=int, default=5,
                     help="plain steps of the exact-quadrature system on the same clouds (0: skip)")
     ap.add_argument("--serving", type=int, default=160, help="requests in the serving replay (0: skip)")
+    ap.add_argument("--serving-inflight", type=int, default=4, help="worker threads of the batched server")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")
@@ -1011,7 +1012,7 @@ def main():
         line["oracle_error"] = err
         line["oracle_error_every_25th_step"] = sample_errors(res, args.n, args.cpu_sample_nodes)
     if args.serving > 0:
-        line["serving"], scmp = serving_run(args.serving, 4, 64.0)
+        line["serving"], scmp = serving_run(args.serving, args.serving_inflight, 64.0)
         if not args.no_cpu_baseline:
             line["serving"]["oracle_error"] = serving_oracle_error(scmp)
     if not args.no_normals:

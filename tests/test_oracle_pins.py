@@ -532,3 +532,38 @@ def test_whole_chain_gradient_with_normal_term_vs_frozen_fd(exact):
             vals.append(loss(xx.detach().numpy(), nn2.detach().numpy(), keys=r.keys)[0])
         fd[j] = (vals[0] - vals[1]) / (2 * eps)
     assert np.linalg.norm(grad - fd) <= 2e-3 * np.linalg.norm(fd), (grad, fd)
+
+
+def test_c3_gradient_at_128_vs_frozen_fd():
+    """The differentiable configuration at its own size (16-coefficient
+    superellipsoid, 100,000 points, 128^3): the oracle's dL/dc for two
+    coefficients against central differences (eps 1e-4) of the oracle forward
+    with frozen central cells, at 1000 of the targets."""
+    torch = pytest.importorskip("torch")
+    case = synth.diff_case(n_targets=1000)
+    g = D.Grid.unit(128)
+    c0 = case.shape.coeffs
+
+    def cloud(c):
+        ct = torch.tensor(c, dtype=torch.float64, requires_grad=True)
+        x, n = synth.star_points_torch(case.shape, case.dirs, ct)
+        return ct, x, n
+
+    ct, x, n = cloud(c0)
+    L0, r = P.loss_mean_sq(g, x.detach().numpy().astype(np.float32), n.detach().numpy().astype(np.float32),
+                           case.targets)
+    phi, _ = r.sample(case.targets)
+    g_x, g_n, _ = r.backward(case.targets, 2.0 * phi / len(case.targets))
+    (grad,) = torch.autograd.grad((x * torch.tensor(g_x)).sum() + (n * torch.tensor(g_n)).sum(), ct)
+    grad = grad.numpy()
+    eps = 1e-4
+    for j in (0, 7):
+        vals = []
+        for s in (+1, -1):
+            c = c0.copy()
+            c[j] += s * eps
+            _, xx, nn = cloud(c)
+            vals.append(P.loss_mean_sq(g, xx.detach().numpy().astype(np.float32),
+                                       nn.detach().numpy().astype(np.float32), case.targets, keys=r.keys)[0])
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert abs(grad[j] - fd) <= 1e-3 * abs(fd), (j, grad[j], fd)
