@@ -94,6 +94,8 @@ def gpu_run(args):
     for t in range(total):
         x, nrm = fl.step(t)
         clouds.append((torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda()))
+        if t % 100 == 99:
+            log(f"  {t + 1} clouds")
     q = torch.from_numpy(synth.uniform_queries(nq, 4001)).cuda()
     r = Recon(n, npts)
     kinds = list(_lib.PROF_KINDS)
@@ -132,12 +134,14 @@ def gpu_run(args):
     # timed: pipelined steps (each step's distance walk and sampling overlap the
     # next step's splat and solve), all outputs complete at the final synchronise
     stats = []
+    stamps = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         t = args.warmup + k
         st, phi, nq_out = r.step(*clouds[t], q, rel_tol=args.tol, warm_start=True)
         stats.append(st)
+        stamps.append(time.perf_counter())   # host time at each return (the pipeline's pace)
     r.wait()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -200,7 +204,7 @@ def gpu_run(args):
     exact = exact_run(args, r, clouds, q, kinds) if args.exact_steps else None
     r.close()
     return {"elapsed": elapsed, "stats": stats, "prof": prof, "dominant": dominant, "per_kind": per_kind,
-            "exact": exact, "cold_ms": cold_ms, "samples": samples,
+            "exact": exact, "cold_ms": cold_ms, "samples": samples, "stamps": np.asarray(stamps) - t0,
             "gpu_last": gpu_last, "clouds_last": tuple(c.cpu().numpy() for c in clouds[last_t]),
             "q": q.cpu().numpy(), "adj_ms": adj_ms, "solver_kinds": solver_kinds, "solve_ms": solve_ms,
             "plain_ms": plain_ms, "plain_steps": plain_steps, "plain_stats": plain_stats, "n_prof": n_prof,
@@ -379,20 +383,28 @@ def sample_errors(res, n, sample_nodes):
     from oracle import discretize as D
     from oracle import pipeline as P
 
+    from concurrent.futures import ThreadPoolExecutor
+
     grid = D.Grid.unit(n)
     rng = np.random.default_rng(4003)
-    out = []
-    for s in res["samples"]:
+    picks = [rng.choice(n ** 3, sample_nodes, replace=False) for _ in res["samples"]]
+
+    def one(k):
+        s, nodes = res["samples"][k], picks[k]
         x, nrm = s["cloud"]
         ref = P.Recon(grid, x, nrm)
-        nodes = rng.choice(n ** 3, sample_nodes, replace=False)
-        out.append({"step": int(s["t"]),
-                    "chi_rel_l2": float(np.linalg.norm(s["chi"] - ref.chi) / np.linalg.norm(ref.chi)),
-                    "iso_c_rel": float(abs(s["iso_c"] - ref.c) / np.abs(ref.chi).max()),
-                    "phi_max_abs_over_h": float(np.abs(s["phi"].reshape(-1)[nodes].astype(np.float64) -
-                                                       ref.phi_nodes(nodes)).max() * n),
-                    "nodes_compared": int(sample_nodes)})
-    return out
+        e = {"step": int(s["t"]),
+             "chi_rel_l2": float(np.linalg.norm(s["chi"] - ref.chi) / np.linalg.norm(ref.chi)),
+             "iso_c_rel": float(abs(s["iso_c"] - ref.c) / np.abs(ref.chi).max()),
+             "phi_max_abs_over_h": float(np.abs(s["phi"].reshape(-1)[nodes].astype(np.float64) -
+                                                ref.phi_nodes(nodes)).max() * n),
+             "nodes_compared": int(sample_nodes)}
+        log(f"oracle at step {e['step']}: field {e['chi_rel_l2']:.2e}, SDF {e['phi_max_abs_over_h']:.2e} h")
+        return e
+
+    # the oracle's heavy parts (numpy, scipy.fft, its C distance) release the GIL: four samples at a time
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        return list(ex.map(one, range(len(res["samples"]))))
 
 
 def oracle_timing(cmp, reps=3):
@@ -414,6 +426,7 @@ def oracle_timing(cmp, reps=3):
         row = {}
         for label, th in (("one_thread", 1), ("all_cores", cores)):
             times = []
+            log(f"oracle timing {name}, {th} thread(s)")
             for _ in range(reps):
                 with threadpool_limits(th), scipy.fft.set_workers(th):
                     t0 = time.perf_counter()
@@ -465,6 +478,7 @@ def cpu_baseline(res, n, sample_nodes):
     x, nrm = res["clouds_last"]
     grid = D.Grid.unit(n)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log("cpu baseline: the oracle on the last timed step")
     t0 = time.perf_counter()
     ref = P.Recon(grid, x, nrm)
     t1 = time.perf_counter()
@@ -687,6 +701,7 @@ def secondary_oracle_error(cmp):
     sphere = {"phi_grid_max_abs_over_h": float(np.abs(s["phi"].astype(np.float64) - ref.phi_grid()).max() * 32),
               "phi_queries_max_abs_over_h": float(np.abs(s["phi_q"] - vq).max() * 32),
               "normal_angle_max_rad": float(ang.max()), "nodes_compared": 32 ** 3, "queries_compared": len(s["q"])}
+    log("oracle: sphere done, torus next")
     grid = D.Grid.unit(128)
     t = cmp["torus"]
     ref = P.Recon(grid, t["x"], t["nrm"])
@@ -698,6 +713,7 @@ def secondary_oracle_error(cmp):
              "phi_queries_max_abs_over_h": float(np.abs(t["phi_q"] - vq).max() * 128),
              "normal_angle_max_rad": float(ang.max()), "nodes_compared": len(t["nodes"]),
              "queries_compared": len(t["q"])}
+    log("oracle: torus done, superellipsoid reverse pass next")
     e = cmp["superellipsoid"]
     ref = P.Recon(grid, e["x"], e["nrm"])
     phi, _ = ref.sample(e["targets"])
@@ -935,7 +951,8 @@ def pmc_summary(path, periods=()):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    # 6 warm-up steps + 494 timed ones: the configuration's 500 steps of the flapping wave (5 periods)
+    ap.add_argument("--steps", type=int, default=494)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--points", type=int, default=300_000)
@@ -1003,25 +1020,31 @@ def main():
         "kernel_ms_per_step_plain": {k: v["ms"] / res["n_prof"] for k, v in res["per_kind"].items()},
         "adjoint_ms_mean": float(np.mean(res["adj_ms"])) if res["adj_ms"] else None,
         "cold_step_ms": res["cold_ms"],
+        "ms_per_step_by_100_steps": [float(v) for v in np.diff(np.concatenate([[0.0], res["stamps"][99::100]])) / 100 * 1e3],
         "eikonal": eikonal(res["gpu_last"]["phi"].reshape(args.n, args.n, args.n), 1.0 / args.n),
         "exact_quadrature": exact_summary(res, copy_gbs) if res["exact"] else None,
     }
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(res, args.n, args.cpu_sample_nodes)
+        log(f"oracle every 25th step: {len(res['samples'])} steps")
         line["cpu_baseline"] = base
         line["oracle_error"] = err
         line["oracle_error_every_25th_step"] = sample_errors(res, args.n, args.cpu_sample_nodes)
     if args.serving > 0:
+        log("serving replay")
         line["serving"], scmp = serving_run(args.serving, args.serving_inflight, 64.0)
         if not args.no_cpu_baseline:
             line["serving"]["oracle_error"] = serving_oracle_error(scmp)
     if not args.no_normals:
+        log("normals run")
         line["normals"], ncmp = normals_run()
         if not args.no_cpu_baseline:
             line["normals"]["oracle_error"] = normals_oracle_error(ncmp)
     if not args.no_secondary:
+        log("secondary workloads")
         line["secondary"], cmp = secondary_run()
         if not args.no_cpu_baseline:
+            log("secondary workloads against the oracle")
             for k, v in secondary_oracle_error(cmp).items():
                 line["secondary"][k]["oracle_error"] = v
             line["secondary"]["oracle_timing"] = oracle_timing(cmp)
