@@ -610,6 +610,49 @@ def secondary_run():
     return out, cmp
 
 
+def cost_vs_grid(densities=(50, 100, 200, 400), reps=5):
+    """The paper's cost study (Sec. 3.4): the fish-like cloud (200,000 points)
+    on grids over its bounding box at several densities d; per grid the plain
+    forward + sampling of 65,536 queries (median of `reps` after one warm-up,
+    warm-started), the handle's resident bytes, and the log-log slopes of time
+    and memory against the number of cells."""
+    import torch
+
+    from paper_2609_20964_amd import synth
+    from paper_2609_20964_amd.recon import Recon, grid_from_cloud
+
+    x, nrm = synth.fish(200_000)
+    xd, nd = torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda()
+    rows = []
+    for d in densities:
+        n, lo, h = grid_from_cloud(xd, d)
+        q = torch.from_numpy((np.asarray(lo) + synth.uniform_queries(65_536, 4201) * np.asarray(n) * h)
+                             .astype(np.float32)).cuda()
+        r = Recon(n, len(x), lo=lo, h=h)
+        r.forward(xd, nd, rel_tol=1e-6)
+        r.sample(q)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = r.forward(xd, nd, rel_tol=1e-6, warm_start=True)
+            r.sample(q)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        cells = int(np.prod(n))
+        rows.append({"density": d, "grid": list(n), "cells": cells, "ms": float(np.median(times) * 1e3),
+                     "bytes_resident": int(st["bytes_resident"])})
+        r.close()
+    lc = np.log([rw["cells"] for rw in rows])
+    slope_t = float(np.polyfit(lc, np.log([rw["ms"] for rw in rows]), 1)[0])
+    slope_m = float(np.polyfit(lc, np.log([rw["bytes_resident"] for rw in rows]), 1)[0])
+    big = rows[-2:]   # the two largest grids, where fixed costs no longer dominate
+    slope_t_big = float(np.log(big[1]["ms"] / big[0]["ms"]) / np.log(big[1]["cells"] / big[0]["cells"]))
+    return {"rows": rows, "time_slope": slope_t, "time_slope_two_largest": slope_t_big, "memory_slope": slope_m,
+            "workload": "fish-like body, 200,000 points, grids over its bounding box (pad 3 cells), rel res 1e-6, "
+                        "forward + SDF/normals at 65,536 queries, median of 5"}
+
+
 def normals_run(n_points=200_000, radius=0.1, gamma_r=2.5, n_tol=2, reps=3):
     """Unoriented clouds (Sec. 2.1-2.2) at the defaults of Table 1: D-PCA
     normals and their orientation for the fish-like cloud (200,000 points,
@@ -764,8 +807,8 @@ def serving_run(n_requests, max_inflight, budget_gb):
             rng = np.random.default_rng(506)
             small = [i for i, (rq, *_) in enumerate(reqs) if rq.n == 64]
             big = [i for i, (rq, *_) in enumerate(reqs) if rq.n != 64]
-            pick = sorted(rng.choice(small, min(8, len(small)), replace=False).tolist() +
-                          rng.choice(big, min(2, len(big)), replace=False).tolist())
+            n_big = max(2, int(round(0.05 * len(big)))) if big else 0
+            pick = sorted(small + rng.choice(big, min(n_big, len(big)), replace=False).tolist())
             cmp = []
             for i in pick:
                 rq, x, nrm, q = reqs[i]
@@ -780,21 +823,25 @@ def serving_run(n_requests, max_inflight, budget_gb):
 
 def serving_oracle_error(cmp):
     """Part of the cpu_baseline leg: served results (batched, offered load)
-    against the FP64 oracle: SDF and normals at the first 200 queries of 8
-    seeded 64^3 requests and 2 seeded larger ones."""
+    against the FP64 oracle: SDF and normals at the first 200 queries of every
+    64^3 request and of a seeded 5% (at least 2) of the larger ones."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from oracle import discretize as D
     from oracle import pipeline as P
 
-    worst_phi, worst_ang = 0.0, 0.0
-    for c in cmp:
+    def one(c):
         ref = P.Recon(D.Grid.unit(c["n"]), c["x"], c["nrm"])
         vq, nq = ref.sample(c["q"])
-        worst_phi = max(worst_phi, float(np.abs(c["phi_q"] - vq).max() * c["n"]))
         ok = np.linalg.norm(nq, axis=1) > 0
         ang = angle_between(c["n_q"][ok], nq[ok])
-        worst_ang = max(worst_ang, float(ang.max()) if ang.size else 0.0)
-    return {"phi_queries_max_abs_over_h": worst_phi, "normal_angle_max_rad": worst_ang,
-            "requests_compared": [c["n"] for c in cmp], "queries_per_request": 200}
+        return float(np.abs(c["phi_q"] - vq).max() * c["n"]), float(ang.max()) if ang.size else 0.0
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        errs = list(ex.map(one, cmp))
+    sizes = [c["n"] for c in cmp]
+    return {"phi_queries_max_abs_over_h": max(e[0] for e in errs), "normal_angle_max_rad": max(e[1] for e in errs),
+            "requests_compared": {str(n): sizes.count(n) for n in sorted(set(sizes))}, "queries_per_request": 200}
 
 
 def latency_by_grid(grids, lat_s):
@@ -967,6 +1014,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the two 128^3 workloads")
     ap.add_argument("--no-normals", action="store_true", help="skip the normal estimation and orientation run")
+    ap.add_argument("--no-cost-sweep", action="store_true", help="skip the cost-versus-grid-size sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--pmc-period", metavar="NAME=P", action="append", default=[],
@@ -1035,6 +1083,9 @@ def main():
         line["serving"], scmp = serving_run(args.serving, args.serving_inflight, 64.0)
         if not args.no_cpu_baseline:
             line["serving"]["oracle_error"] = serving_oracle_error(scmp)
+    if not args.no_cost_sweep:
+        log("cost versus grid size")
+        line["cost_vs_grid"] = cost_vs_grid()
     if not args.no_normals:
         log("normals run")
         line["normals"], ncmp = normals_run()
