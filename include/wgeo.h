@@ -431,7 +431,8 @@ typedef struct {
  * (iteration 2).  d_nrm [n_points][3] float32, flipped in place (signs only);
  * d_counts NULL or [n_points][4] int32 (N, N_one along the input +n, then
  * along -n); info NULL or filled.  Allocates its work buffers on the stream
- * and frees them; blocks until done.  WG_EINVAL for n_points < 2, gamma_r < 1,
+ * and frees them; blocks until done.  WG_ENUMERIC for a NaN or infinite
+ * normal; WG_EINVAL for n_points < 2, gamma_r < 1,
  * a non-finite coordinate, or a cloud whose points all have coincident twins
  * (rd = 0) or one whose rays would need more than 1e5 probes. */
 int wg_orient_normals(const float *d_xyz, int n_points, float *d_nrm, const wg_orient_opts *opts,

@@ -90,6 +90,14 @@ __global__ __launch_bounds__(256) void k_pg_scatter(const float *__restrict__ xy
 
 __global__ void k_set_word(uint32_t *p, uint32_t v) { *p = v; }
 
+// *bad = 1 if any of the n values is NaN or infinite
+__global__ __launch_bounds__(256) void k_any_nonfinite(const float *__restrict__ v, size_t n, int *bad) {
+    bool b = false;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b |= !isfinite(v[i]);
+    if (__ballot(b) != 0 && threadIdx.x % 64 == 0) atomicOr(bad, 1);
+}
+
 // chunks of at most `per` points of one cell: their count per cell, then the
 // cell of every chunk
 __global__ __launch_bounds__(256) void k_cell_chunks(const uint32_t *__restrict__ cnt, uint32_t cells, uint32_t per,
@@ -563,6 +571,16 @@ int orient(const float *xyz, int npts, float *nrm, const wg_orient_opts &o, int3
     require(o.refine == 0 || o.refine == 1, WG_EINVAL, "refine must be 0 or 1");
     Scratch sc(st);
     const Box b = cloud_box(xyz, npts, sc, st);
+    {
+        int *dbad = sc.take<int>(1), hbad = 0;
+        WG_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+        k_any_nonfinite<<<std::min<unsigned>(cdiv(3 * (size_t)npts, 256), 256u), 256, 0, st>>>(nrm, 3 * (size_t)npts,
+                                                                                             dbad);
+        WG_LAUNCH_CHECK();
+        WG_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st));
+        WG_HIP(hipStreamSynchronize(st));
+        require(hbad == 0, WG_ENUMERIC, "a normal is NaN or infinite");
+    }
     // nearest spacing on a grid of about two surface spacings per cell (the
     // box's surface area over the point count), rings widen it where sparse
     double ext[3], area = 0.0, diag2 = 0.0;

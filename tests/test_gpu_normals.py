@@ -130,6 +130,12 @@ def test_normal_option_errors():
     twins = torch.cat([x, x])
     with pytest.raises(WgError):
         orient_normals(twins, twins)
+    from paper_2609_20964_amd._lib import WG_ENUMERIC
+    bad_n = x.clone()
+    bad_n[3, 0] = float("inf")
+    with pytest.raises(WgError) as e:
+        orient_normals(x, bad_n)
+    assert e.value.code == WG_ENUMERIC
 
 
 def test_unoriented_cloud_to_sdf():

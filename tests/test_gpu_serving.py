@@ -227,3 +227,37 @@ def test_served_results_match_the_oracle():
             assert _close(outs["g_nrm"].cpu().numpy(), gn_ref)
             if gnrm is not None:
                 assert _close(outs["g_q"].cpu().numpy(), gq_ref, comp_tol=3e-3)
+
+
+def test_served_exact_quadrature_requests():
+    """Requests for the exact-quadrature system beside 7-point ones: each
+    served result against the oracle of its own system (phi at the queries
+    within 1e-4 h; point gradients within 1e-3 relative in L2)."""
+    from oracle import discretize as D
+    from oracle import pipeline as P
+    from paper_2609_20964_amd.serving import Server
+    rng = np.random.default_rng(631)
+    spec = [(32, 5000, "exact"), (40, 6000, "vertex"), (48, 8000, "exact")]
+    reqs = []
+    for i, (n, npts, quad) in enumerate(spec):
+        c = synth.draw_star_coeffs(640 + i)
+        semi, p = rng.uniform(0.15, 0.28, 3), rng.uniform(2, 4)
+        x, nn = synth.star(c, npts, [641, i], semi_axes=semi, p=p)
+        q = _band_queries(c, semi, p, 1024, [642, i])
+        gphi = (rng.standard_normal(len(q)) / len(q)).astype(np.float32)
+        reqs.append((n, x, nn, q, gphi, quad))
+    srv = Server(hbm_budget_bytes=4 << 30, max_inflight=3)
+    tickets = [srv.submit(n, _cuda(x), _cuda(nn), _cuda(q), gphi=_cuda(gp), rel_tol=1e-10, max_iters=5000,
+                          quadrature=quad) for n, x, nn, q, gp, quad in reqs]
+    results = _wait(srv, tickets, timeout=300.0)
+    srv.close()
+    for (n, x, nn, q, gphi, quad), (st, outs, info) in zip(reqs, results):
+        assert st == 0, info
+        ref = P.Recon(D.Grid.unit(n), x, nn, exact=quad == "exact")
+        phi_ref, _ = ref.sample(q)
+        err = np.abs(outs["phi"].cpu().numpy() - phi_ref).max() * n
+        gx_ref, gn_ref, _ = ref.backward(q, gphi.astype(np.float64))
+        print(f"{quad} {n}^3: phi {err:.2e} h", flush=True)
+        assert err <= 1e-4
+        assert _close(outs["g_xyz"].cpu().numpy(), gx_ref)
+        assert _close(outs["g_nrm"].cpu().numpy(), gn_ref)
