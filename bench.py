@@ -773,33 +773,59 @@ def secondary_oracle_error(cmp):
     return {"sphere_32": sphere, "torus_128": torus, "superellipsoid_128_gradient": sup}
 
 
-def serving_run(n_requests, max_inflight, budget_gb):
-    """The request stream replayed on two resident servers, continuous
-    batching (max_inflight at once) and one request at a time: first once
-    untimed at saturation (the servers' handle pools fill, as a long-running
-    server's would), then at the stream's own Poisson arrival times (latency at
-    the offered load) and with every request arriving at once (throughput at
-    saturation)."""
+def _request_inputs(args):
+    """One request's cloud and queries (a process-pool task: the shapes'
+    normals come from torch autograd on the CPU, about 75 ms per request)."""
+    index, n_requests = args
     import torch
 
     from paper_2609_20964_amd import synth
+    torch.set_num_threads(1)
+    rq = synth.request_stream(n_requests)[index]
+    x, nrm = rq.cloud()
+    return x, nrm, rq.queries()
+
+
+def generate_requests(n_requests):
+    """The request stream's inputs, made by a pool of forked processes before
+    this process touches the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    from paper_2609_20964_amd import synth
+
+    reqs = synth.request_stream(n_requests)
+    with ProcessPoolExecutor(max_workers=12, mp_context=mp.get_context("fork")) as ex:
+        data = list(ex.map(_request_inputs, [(i, n_requests) for i in range(n_requests)], chunksize=8))
+    return [(rq,) + d for rq, d in zip(reqs, data)]
+
+
+def serving_run(generated, warmup, max_inflight, budget_gb):
+    """The request stream replayed on two resident servers, continuous
+    batching (max_inflight at once) and one request at a time: first the
+    `warmup` leading requests untimed at saturation (the servers' handle pools
+    fill, as a long-running server's would), then the rest at the stream's own
+    Poisson arrival times (latency at the offered load) and with every request
+    arriving at once (throughput at saturation)."""
+    import torch
+
     from paper_2609_20964_amd.serving import Server
 
-    reqs = []
-    for rq in synth.request_stream(n_requests):
-        x, nrm = rq.cloud()
-        reqs.append((rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(),
-                     torch.from_numpy(rq.queries()).cuda()))
+    reqs = [(rq, torch.from_numpy(x).cuda(), torch.from_numpy(nrm).cuda(), torch.from_numpy(q).cuda())
+            for rq, x, nrm, q in generated]
+    warm, reqs = reqs[:warmup], reqs[warmup:]
     out = {"offered_load": {}, "saturated": {}}
     cmp = None
     for mode, inflight in (("batched", max_inflight), ("plain", 1)):
         srv = Server(int(budget_gb * (1 << 30)), max_inflight=inflight)
-        replay(srv, reqs, 0.0)
+        if warm:
+            replay(srv, warm, 0.0)
         stats, done = replay(srv, reqs, 1.0, keep=True)
         out["offered_load"][mode] = dict(max_inflight=inflight, **stats)
         stats, _ = replay(srv, reqs, 0.0)
         out["saturated"][mode] = dict(max_inflight=inflight, **stats)
         srv.close()
+        log(f"serving {mode} done")
         if mode == "batched":
             # kept for the oracle comparison of the cpu_baseline leg: a seeded
             # subset of the 64^3 requests and of the others, SDF and normals at
@@ -815,9 +841,9 @@ def serving_run(n_requests, max_inflight, budget_gb):
                 outs = done[i][0][1]
                 cmp.append({"n": rq.n, "x": x.cpu().numpy(), "nrm": nrm.cpu().numpy(), "q": q[:200].cpu().numpy(),
                             "phi_q": outs["phi"][:200].cpu().numpy(), "n_q": outs["nrm"][:200].cpu().numpy()})
-    out["workload"] = (f"{len(reqs)} requests, Poisson arrivals 50/s, grids 64/128/256 (0.5/0.3/0.2), "
-                       "log-normal points (median 50k), 30% with gradient, rel. res 1e-6; "
-                       "saturated = all requests at t=0; servers warmed by one untimed saturated pass")
+    out["workload"] = (f"{len(reqs)} measured requests after {len(warm)} warm-up ones, Poisson arrivals 50/s, "
+                       "grids 64/128/256 (0.5/0.3/0.2), log-normal points (median 50k), 30% with gradient, "
+                       "65,536 queries each, rel. res 1e-6; saturated = all measured requests at t=0")
     return out, cmp
 
 
@@ -860,7 +886,8 @@ def replay(srv, reqs, time_scale, keep=False):
 
     import torch
 
-    arrival = [rq.arrival_s * time_scale for rq, *_ in reqs]
+    a0 = reqs[0][0].arrival_s
+    arrival = [(rq.arrival_s - a0) * time_scale for rq, *_ in reqs]
     tickets = [None] * len(reqs)
     start = time.perf_counter()
 
@@ -1008,7 +1035,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=3)
     ap.add_argument("--exact-steps", type=int, default=5,
                     help="plain steps of the exact-quadrature system on the same clouds (0: skip)")
-    ap.add_argument("--serving", type=int, default=160, help="requests in the serving replay (0: skip)")
+    ap.add_argument("--serving", type=int, default=1050,
+                    help="requests in the serving replay, warm-up ones included (0: skip)")
+    ap.add_argument("--serving-warmup", type=int, default=50, help="leading requests that only warm the servers")
     ap.add_argument("--serving-inflight", type=int, default=4, help="worker threads of the batched server")
     ap.add_argument("--cpu-sample-nodes", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1033,6 +1062,10 @@ def main():
               "multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    generated = None
+    if args.serving > 0:
+        log(f"generating {args.serving} serving requests")
+        generated = generate_requests(args.serving)   # before this process touches the GPU
     res = gpu_run(args)
     copy_gbs = copy_bandwidth()
     steps = args.steps
@@ -1080,7 +1113,9 @@ def main():
         line["oracle_error_every_25th_step"] = sample_errors(res, args.n, args.cpu_sample_nodes)
     if args.serving > 0:
         log("serving replay")
-        line["serving"], scmp = serving_run(args.serving, args.serving_inflight, 64.0)
+        line["serving"], scmp = serving_run(generated, min(args.serving_warmup, args.serving - 1),
+                                            args.serving_inflight, 64.0)
+        del generated
         if not args.no_cpu_baseline:
             line["serving"]["oracle_error"] = serving_oracle_error(scmp)
     if not args.no_cost_sweep:
