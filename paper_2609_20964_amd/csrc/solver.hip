@@ -170,19 +170,23 @@ __global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, doub
         const bool xl = i > 0, xr = i + 4 < d.nx;                 // neighbours exist
         const bool shl = sl > 0, shr = sl + 1 < wv.L && x4 + 1 < W4; // ... and sit in the next lane
         const int nb_y = (!ym) + (!yp);
-        V4<T> cm, cc;
-        for (int q = 0; q < 4; ++q) cm.v[q] = T(0);
+        // rows j-1 (a) and j+1 (b) of a plane are fetched with its row j, one
+        // plane ahead of their use, when the neighbouring wavefronts fetch them
+        // as their own rows
+        V4<T> cm, cc, a, b;
+        for (int q = 0; q < 4; ++q) cm.v[q] = cc.v[q] = a.v[q] = b.v[q] = T(0);
         if (valid && z0 > 0) cm = op.load4(base + (size_t)(z0 - 1) * plane);
         if (valid) cc = op.load4(base + (size_t)z0 * plane);
-        else for (int q = 0; q < 4; ++q) cc.v[q] = T(0);
+        if (valid && ym) a = op.load4(base + (size_t)z0 * plane - d.nx);
+        if (valid && yp) b = op.load4(base + (size_t)z0 * plane + d.nx);
         for (int k = z0; k < z1; ++k) {
             const size_t idx = base + (size_t)k * plane;
             const bool zp = k + 1 < d.nz;
-            V4<T> cp, a, b;
-            for (int q = 0; q < 4; ++q) cp.v[q] = a.v[q] = b.v[q] = T(0);
+            V4<T> cp, ap, bp;
+            for (int q = 0; q < 4; ++q) cp.v[q] = ap.v[q] = bp.v[q] = T(0);
             if (valid && zp) cp = op.load4(idx + plane);
-            if (valid && ym) a = op.load4(idx - d.nx);
-            if (valid && yp) b = op.load4(idx + d.nx);
+            if (valid && zp && ym) ap = op.load4(idx + plane - d.nx);
+            if (valid && zp && yp) bp = op.load4(idx + plane + d.nx);
             T left = __shfl_up(cc.v[3], 1, 64), right = __shfl_down(cc.v[0], 1, 64);
             if (!shl) left = (valid && xl) ? op.load1(idx - 1) : T(0);
             if (!shr) right = (valid && xr) ? op.load1(idx + 4) : T(0);
@@ -205,6 +209,8 @@ __global__ __launch_bounds__(256) void k_stencil4(Op op, Dims d, Waves4 wv, doub
             }
             cm = cc;
             cc = cp;
+            a = ap;
+            b = bp;
         }
     }
     if constexpr (Op::NRED > 0) {
@@ -800,14 +806,14 @@ __device__ __forceinline__ void zero_pads(float *s, int W, int Ht) {
 }
 
 // pre: xo = x2 of the pre-smoothing from a zero guess, crhs = 1/2 P^T (rhs - A xo).
-__global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, float *__restrict__ xo,
+__global__ __launch_bounds__(kVB, 4) void k_vc_pre(const float *__restrict__ rhs, float *__restrict__ xo,
                                                  float *__restrict__ crhs, Dims df, Dims dc, VTile vt, float wa,
                                                  float wb, const int *skip) {
     constexpr int H = kPreH, CPT = kPreCPT;
     if (skipped(skip)) return;
     __shared__ float sR[2][kPreLds];
     __shared__ float sX[2][kPreLds];
-    __shared__ float sr[2][kPreLds];
+    __shared__ __align__(16) float sr[2][kPreLds];   // read as float2 by the restriction
     const unsigned lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int bx = (int)(lb % (unsigned)vt.gx), by = (int)((lb / (unsigned)vt.gx) % (unsigned)vt.gy),
               bz = (int)(lb / ((unsigned)vt.gx * (unsigned)vt.gy));
@@ -828,10 +834,11 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
         col[q] = vcol((int)threadIdx.x + kVB * q, W, Ht, H, X0, Y0, vt.tx, vt.ty, df, i, j);
         col[q].c += kPrePad;
     }
-    // rhs is fetched two planes ahead into two buffers that the unrolled
-    // loop below uses in turn.  Fetches are unconditional (a plane outside
-    // [0, nz) is fetched clamped and scaled by 0), so a buffer keeps its
-    // registers across iterations and no fetch is waited for early.
+    // rhs is fetched four planes ahead into four buffers that the unrolled
+    // loop below uses in turn (the kernel's few workgroups per compute unit
+    // need that many fetches in flight).  Fetches are unconditional (a plane
+    // outside [0, nz) is fetched clamped and scaled by 0), so a buffer keeps
+    // its registers across iterations and no fetch is waited for early.
     const int s0 = 2 * K0 - 3, s1 = 2 * K1 + 2;   // s0 odd
     auto load = [&](int s, float(&buf)[CPT], float &sc) {
         sc = (s >= 0 && s < df.nz) ? 1.f : 0.f;
@@ -839,9 +846,11 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
 #pragma unroll
         for (int q = 0; q < CPT; ++q) buf[q] = rp[col[q].off];
     };
-    float bA[CPT], bB[CPT], sa, sb;
+    float bA[CPT], bB[CPT], bC[CPT], bD[CPT], sa, sb, sc, sd;
     load(s0, bA, sa);
     load(s0 + 1, bB, sb);
+    load(s0 + 2, bC, sc);
+    load(s0 + 3, bD, sd);
     // coarse cell of this thread in the restriction (x fastest)
     const int ctx = vt.tx / 2, cty = vt.ty / 2;
     const int ca = (int)threadIdx.x % ctx, cb = (int)threadIdx.x / ctx;
@@ -874,7 +883,7 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
             h1[q] = h2[q];
             h2[q] = buf[q] * (col[q].in * bsc);
         }
-        load(s + 2, buf, bsc);
+        load(s + 4, buf, bsc);
         {
             float *R = sR[par];
 #pragma unroll
@@ -919,9 +928,11 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
             const float *r = sr[par ^ 1] + rbase;
             float acc = 0.f;
 #pragma unroll
+            // rbase and W are even: each row's four cells are two 8-byte reads
             for (int ty = 0; ty < 4; ++ty) {
-                const float *row = r + W * ty;
-                acc += wy[ty] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+                const float2 *row = reinterpret_cast<const float2 *>(r + W * ty);
+                const float2 a = row[0], b = row[1];
+                acc += wy[ty] * (wx[0] * a.x + wx[1] * a.y + wx[2] * b.x + wx[3] * b.y);
             }
             z0 = z1;
             z1 = z2;
@@ -936,10 +947,14 @@ __global__ __launch_bounds__(kVB) void k_vc_pre(const float *__restrict__ rhs, f
         }
     };
     // the last restricted plane, 2 K1, is restricted at step 2 K1 + 3 = s1 + 1
-    for (int s = s0; s <= s1 + 1; s += 2) {
+    for (int s = s0; s <= s1 + 1; s += 4) {
         step(s, 1, bA, sa);
         if (s + 1 > s1 + 1) break;
         step(s + 1, 0, bB, sb);
+        if (s + 2 > s1 + 1) break;
+        step(s + 2, 1, bC, sc);
+        if (s + 3 > s1 + 1) break;
+        step(s + 3, 0, bD, sd);
     }
 }
 
@@ -1006,19 +1021,16 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
             Q[col[q].c] = cscale * (py.wa * (px.wa * c0[q] + px.wb * c1[q]) + py.wb * (px.wa * c2[q] + px.wb * c3[q]));
         }
     };
-    // x and rhs of the next plane, fetched one step ahead (unconditionally, so
-    // the buffers keep their registers across the loop).  A plane outside
-    // [0, nz) is fetched clamped:
-    // every value computed from it there is masked to 0, and rhs enters only
-    // the planes' own (in-range) updates.
-    auto load = [&](int s, float(&xb)[CPT], float(&hb)[CPT]) {
-        const size_t o = (size_t)min(max(s, 0), df.nz - 1) * plane;
-        const float *xp = x + o, *hp = rhs + o;
+    // x is used at the step that takes its plane, so it is fetched two steps
+    // ahead (a two-plane queue); rhs of plane s is first used at step s + 1,
+    // so it is fetched at step s.  The fetches are unconditional (the buffers
+    // keep their registers across the loop).  A plane outside [0, nz) is
+    // fetched clamped: every value computed from it there is masked to 0, and
+    // rhs enters only the planes' own (in-range) updates.
+    auto load = [&](const float *f, int s, float(&buf)[CPT]) {
+        const float *fp = f + (size_t)min(max(s, 0), df.nz - 1) * plane;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            xb[q] = xp[col[q].off];
-            hb[q] = hp[col[q].off];
-        }
+        for (int q = 0; q < CPT; ++q) buf[q] = fp[col[q].off];
     };
     const int s0 = k0 - 2, s1 = k1 + 1;   // k0 even: s0 even, s0 >> 1 >= -1
     qfetch((s0 >> 1) - 1);
@@ -1026,18 +1038,19 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
     qfetch(s0 >> 1);
     qstore(s0 >> 1);
     qfetch((s0 >> 1) + 1);
-    float xA[CPT], hA[CPT];
-    load(s0, xA, hA);
+    float xA[CPT], xB[CPT], hN[CPT];
+    load(x, s0, xA);
+    load(x, s0 + 1, xB);
     double acc[1] = {0.0};
-    // z rings: u on planes s-2 .. s, v on s-3 .. s-1, rhs on s-2 .. s
-    float u0[CPT], u1[CPT], u2[CPT], v0[CPT], v1[CPT], v2[CPT], h0[CPT], h1[CPT], h2[CPT];
+    // z rings: u on planes s-2 .. s, v on s-3 .. s-1, rhs on s-2 .. s-1 (and s in flight)
+    float u0[CPT], u1[CPT], u2[CPT], v0[CPT], v1[CPT], v2[CPT], h0[CPT], h1[CPT];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) u0[q] = u1[q] = u2[q] = v0[q] = v1[q] = v2[q] = h0[q] = h1[q] = h2[q] = 0.f;
+    for (int q = 0; q < CPT; ++q) u0[q] = u1[q] = u2[q] = v0[q] = v1[q] = v2[q] = h0[q] = h1[q] = hN[q] = 0.f;
     // One z step (par = s & 1) with one barrier: every LDS plane it reads was
     // written in the previous step, and every plane it writes was last read in
     // the previous step.  sQ is read back only by the thread that wrote it.
     //   u(s) -> sU[s];  v(s-1) from sU[s-1] -> sV[s-1];  xo(s-2) from sV[s-2].
-    auto step = [&](int s, int par, float(&xb)[CPT], float(&hb)[CPT]) {
+    auto step = [&](int s, int par) {
         __syncthreads();
         const int K = s >> 1;
         if (!par) {
@@ -1045,15 +1058,12 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
             qstore(K + 1);
             qfetch(K + 2);
         }
-        float xc[CPT];
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            xc[q] = xb[q];
             h0[q] = h1[q];
-            h1[q] = h2[q];
-            h2[q] = hb[q];
+            h1[q] = hN[q];
         }
-        load(s + 1, xb, hb);
+        load(rhs, s, hN);
         // u on plane s; z prolongation: plane s takes coarse K (3/4) and K-1 (even s) or K+1 (odd s)
         {
             const int N = par ? K + 1 : K - 1;
@@ -1064,12 +1074,14 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
             float *U = sU[par];
 #pragma unroll
             for (int q = 0; q < CPT; ++q) {
-                const float uv = (xc[q] + wK * QK[col[q].c] + wN * QN[col[q].c]) * (col[q].in * sm);
+                const float uv = (xA[q] + wK * QK[col[q].c] + wN * QN[col[q].c]) * (col[q].in * sm);
                 u0[q] = u1[q];
                 u1[q] = u2[q];
                 u2[q] = uv;
                 U[col[q].c] = uv;
+                xA[q] = xB[q];
             }
+            load(x, s + 2, xB);
         }
         const int p = s - 1;
         if (p >= k0 - 1) {
@@ -1102,7 +1114,7 @@ __global__ __launch_bounds__(kVB, 4) void k_vc_post(const float *__restrict__ x,
             }
         }
     };
-    for (int s = s0; s <= s1; ++s) step(s, s & 1, xA, hA);
+    for (int s = s0; s <= s1; ++s) step(s, s & 1);
     if constexpr (DOT) {
         __shared__ double lds[kVB / 64][1];
         block_sum<1>(acc, lds);
