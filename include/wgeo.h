@@ -320,8 +320,12 @@ typedef struct {
 /* Start a server on `device` with at most max_inflight concurrent requests,
  * each on its own stream, and a device-memory budget for resident handles.
  * Requests start in arrival order, except that requests whose grid has 2^23
- * cells or more (256^3, say: each keeps the whole device busy) run one at a
- * time: while one runs, a free slot takes the first smaller request queued. */
+ * cells or more (256^3, say: each keeps the whole device busy) take turns:
+ * while one holds the turn, a free slot takes the first smaller request
+ * queued.  A turn lasts to the end of the request, or, when another such
+ * request was queued as it started, until its distance walk is enqueued (the
+ * next one's splat and solve then run beside the walk; that request's
+ * stats.ms[4] is reported as 0). */
 int wg_server_create(wg_server **out, size_t hbm_budget_bytes, int max_inflight, int device);
 
 /* Queue a request (inputs are copied before return); *ticket identifies it.

@@ -15,13 +15,20 @@
 // beside others runs it as independent workgroups (see run()).
 //
 // A request whose grid alone keeps every compute unit busy (kFillCells cells
-// or more) gains nothing from overlapping another such request: both would
-// just take twice as long.  At most one of them runs at a time; while one
-// runs, a free worker takes the first queued request that is smaller, so the
-// large ones keep their arrival order and the small ones fill the gaps.
+// or more) gains nothing from overlapping another such request's same phase:
+// both would just take twice as long.  Such requests take turns; while one
+// holds the turn, a free worker takes the first queued request that is
+// smaller, so the large ones keep their arrival order and the small ones fill
+// the gaps.  When another large request is queued as one starts, the turn
+// ends once its distance walk is enqueued: the walk (ALU-bound) runs on the
+// handle's second stream with workgroup slots left free on every compute
+// unit, and the next large request bins, splats and solves (bandwidth-bound)
+// beside it, as consecutive steps of a moving-boundary loop do.  Without a
+// successor the walk keeps the whole device and the turn lasts to the end.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <deque>
 #include <list>
 #include <map>
@@ -270,23 +277,39 @@ class Server {
     // request's distance walk runs persistent (fastest alone); with others
     // running, walks go one workgroup per tile group so concurrent requests
     // interleave instead of queueing behind a walk that holds every slot.  A
-    // device-filling request runs it persistent in any case: only smaller
-    // requests run beside it, and they fit in the slots the walk leaves free.
-    void run(Job &j, Handle &h, bool alone) {
+    // device-filling request runs it persistent in any case.  pipe (a
+    // device-filling request with another one queued): the walk runs on the
+    // handle's second stream with slots left for the next one's solve
+    // (pipelined forward), and the turn ends (end_turn) once it is enqueued;
+    // the sampling follows the walk there, and finish() joins both and
+    // reports a failed walk.
+    void run(Job &j, Handle &h, bool alone, bool pipe, const std::function<void()> &end_turn) {
         const wg_request &rq = j.req;
-        h.r->set_persistent(alone || fills_device(rq.grid));
+        const bool fills = fills_device(rq.grid);
+        h.r->set_persistent(alone || fills);
         h.r->set_grow_hook([this, &h](size_t extra) { reserve_growth(h, extra); });
         wg_solve_opts o = rq.opts;
         o.warm_start = 0;   // a request's result must not depend on what ran before it
-        int st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats);
-        if (rq.n_q > 0) h.r->sample(j.q, rq.n_q, rq.d_phi, rq.d_nrm_out);
-        if (j.gphi) {
-            wg_stats bs{};
-            int st2 = h.r->backward(j.q, rq.n_q, j.gphi, j.gnrm, rq.d_gxyz, rq.d_gnrm_pts, rq.d_gq, o, &bs);
-            j.res.stats.ms[6] = bs.ms[6];
-            j.res.stats.ms[7] = bs.ms[7];
-            j.res.stats.iters += bs.iters;
-            if (st == WG_OK) st = st2;
+        int st = WG_OK;
+        try {
+            st = h.r->forward(j.xyz, j.nrm, rq.n_points, o, &j.res.stats, pipe);
+            if (pipe) end_turn();
+            if (rq.n_q > 0) h.r->sample(j.q, rq.n_q, rq.d_phi, rq.d_nrm_out, pipe);
+            if (j.gphi) {
+                wg_stats bs{};
+                int st2 = h.r->backward(j.q, rq.n_q, j.gphi, j.gnrm, rq.d_gxyz, rq.d_gnrm_pts, rq.d_gq, o, &bs);
+                j.res.stats.ms[6] = bs.ms[6];
+                j.res.stats.ms[7] = bs.ms[7];
+                j.res.stats.iters += bs.iters;
+                if (st == WG_OK) st = st2;
+            }
+            if (pipe) h.r->finish();
+        } catch (...) {
+            // nothing of a failed request may still run (its buffers go back
+            // to the pool): order the handle stream after the second one
+            h.r->join();
+            (void)hipStreamSynchronize(h.s);
+            throw;
         }
         WG_HIP(hipStreamSynchronize(h.s));
         j.res.status = st;
@@ -302,8 +325,19 @@ class Server {
             Job *j = *pick;
             queue_.erase(pick);
             const bool fills = fills_device(j->req.grid);
+            bool turn = fills;   // this request holds the device-filling turn
+            bool pipe = false;   // ... and ends it early: another one is queued
+            if (fills)
+                for (const Job *q : queue_) pipe = pipe || fills_device(q->req.grid);
             fill_running_ += fills;
             ++running_;
+            auto end_turn = [this, &turn] {
+                std::lock_guard<std::mutex> g(mu_);   // run() is called with lk released
+                if (!turn) return;
+                turn = false;
+                --fill_running_;
+                cv_.notify_all();   // a held device-filling request may start
+            };
             j->state = 1;
             Key k{};
             for (int a = 0; a < 3; ++a) {
@@ -321,7 +355,7 @@ class Server {
                 const bool alone = running_ == 1;
                 lk.unlock();
                 try {
-                    run(*j, h, alone);
+                    run(*j, h, alone, pipe, end_turn);
                 } catch (const Error &e) {
                     set_error(e.what());
                     j->res.status = e.code;
@@ -338,7 +372,10 @@ class Server {
             }
             j->state = 2;
             --running_;
-            fill_running_ -= fills;
+            if (turn) {   // a request that failed before its walk
+                turn = false;
+                --fill_running_;
+            }
             release_cv_.notify_all();
             drain_cv_.notify_all();
             if (fills) cv_.notify_all();   // a held device-filling request may start
@@ -346,7 +383,7 @@ class Server {
     }
 
     // First queued request that may start now: any request while no
-    // device-filling one runs, else the first smaller one.
+    // device-filling one holds the turn, else the first smaller one.
     std::deque<Job *>::iterator next_job() {
         auto it = queue_.begin();
         if (fill_running_ > 0)
