@@ -156,6 +156,50 @@ def test_device_filling_requests_take_turns():
     srv.close()
 
 
+def test_device_filling_successor_runs_beside_the_walk():
+    """A 256^3 request that starts with another one queued runs the pipelined
+    forward: its turn ends once its distance walk is enqueued (its walk time is
+    then reported as 0) and the next one may start beside the walk; its field,
+    normals and gradients equal those of the same request reconstructed alone,
+    and so does the field of the second (which starts with nothing queued and
+    keeps its turn to the end).  Two 128^3 requests of 10^6 points hold both
+    slots while the two 256^3 ones are queued, so the first of them starts
+    with the second queued."""
+    from paper_2609_20964_amd.recon import Recon
+    from paper_2609_20964_amd.serving import Server
+    blk = [tuple(_cuda(a) for a in synth.sphere(1000000, seed=630 + k)) for k in range(2)]
+    c = synth.draw_star_coeffs(632)
+    xa, na = (_cuda(a) for a in synth.star(c, 60000, 633))
+    q = _cuda(synth.uniform_queries(4096, 634))
+    qb = _cuda(synth.uniform_queries(1024, 636))
+    gphi = _cuda(np.random.default_rng(635).standard_normal(4096) / 4096)
+    srv = Server(hbm_budget_bytes=16 << 30, max_inflight=2)
+    tickets = [srv.submit(128, x, n, qb) for x, n in blk]
+    tickets.append(srv.submit(256, xa, na, q, gphi=gphi, rel_tol=1e-6))
+    tickets.append(srv.submit(256, xa, na, q, rel_tol=1e-6))
+    results = _wait(srv, tickets)
+    srv.close()
+    assert all(st == 0 for st, _, _ in results), [r[2] for r in results]
+    (_, oa, ia), (_, ob, ib) = results[2], results[3]
+    turn_s = sum(ia["stats"]["ms"][:4]) / 1e3
+    print("first", ia["t_start"], ia["t_done"], "turn", turn_s, "walk ms", ia["stats"]["ms"][4],
+          "second", ib["t_start"], ib["t_done"], "walk ms", ib["stats"]["ms"][4], flush=True)
+    assert ia["stats"]["ms"][4] == 0.0 and ib["stats"]["ms"][4] > 0.0
+    assert ib["t_start"] >= ia["t_start"] + 0.9 * turn_s
+    r = Recon(256, 60000)
+    r.forward(xa, na, rel_tol=1e-6)
+    phi, nrm = r.sample(q)
+    gx, gn, _ = r.backward(q, gphi, rel_tol=1e-6)
+    r.close()
+    h = 1.0 / 256
+    assert np.abs(oa["phi"].cpu().numpy() - phi.cpu().numpy()).max() <= 1e-4 * h
+    assert np.abs(ob["phi"].cpu().numpy() - phi.cpu().numpy()).max() <= 1e-4 * h
+    ok = np.linalg.norm(nrm.cpu().numpy(), axis=1) > 0
+    assert angle(oa["nrm"].cpu().numpy()[ok], nrm.cpu().numpy()[ok]).max() <= 1e-3
+    assert _close(oa["g_xyz"].cpu().numpy(), gx.cpu().numpy())
+    assert _close(oa["g_nrm"].cpu().numpy(), gn.cpu().numpy())
+
+
 def _close(got, want, tol=1e-3, comp_tol=1e-2):
     got = np.asarray(got, np.float64)
     want = np.asarray(want, np.float64)
