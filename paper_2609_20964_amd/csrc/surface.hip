@@ -487,6 +487,25 @@ __device__ __forceinline__ float obb_bound(float4 N0, float4 N1, float4 N2, floa
     return d0;
 }
 
+// The same oriented-box bound, as a mask: bit k set if node k of the lane is
+// below its best.
+template <int kTZ>
+__device__ __forceinline__ uint32_t obb_layers(float4 N0, float4 N1, float4 N2, float4 N3, float px, float py,
+                                               const float (&pz)[kTZ], const float (&best)[kTZ]) {
+    const float rx = px - N0.x, ry = py - N0.y;
+    const float bu = N1.x * rx + N1.y * ry - N1.z * N0.z, bv = N2.x * rx + N2.y * ry - N2.z * N0.z,
+                bn = N3.x * rx + N3.y * ry - N3.z * N0.z;
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < kTZ; ++k) {
+        const float du = fmaxf(fabsf(bu + N1.z * pz[k]) - N0.w, 0.f);
+        const float dv = fmaxf(fabsf(bv + N2.z * pz[k]) - N1.w, 0.f);
+        const float dn = fmaxf(fabsf(bn + N3.z * pz[k]) - N2.w, 0.f);
+        if (du * du + dv * dv + dn * dn < best[k]) m |= 1u << k;
+    }
+    return m;
+}
+
 template <int kTZ>
 __device__ __forceinline__ float aabb_bound(float4 A0, float4 A1, float px, float py, const float (&pz)[kTZ],
                                             const float (&best)[kTZ], bool &need) {
@@ -630,8 +649,9 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                                               SeedDims snc, unsigned long long *__restrict__ counts) {
     static_assert(LX * LY * LZ == 64, "one node column per lane");
     __shared__ uint32_t stk[4][kStack];
-    // test counts of this wavefront (wave-uniform; each applies to its 64 kTZ
-    // nodes), added to counts[] at exit when profiling
+    // test counts of this wavefront (wave-uniform; a box test applies to its
+    // 64 kTZ nodes, a triangle test to one layer of 64), added to counts[] at
+    // exit when profiling
     uint32_t n_tri = 0, n_aabb = 0, n_obb = 0, n_tiles = 0, n_seed = 0;
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     constexpr int TZ = LZ * kTZ;
@@ -697,21 +717,29 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
                 const uint32_t ent = __builtin_amdgcn_readfirstlane(stk[w][sp]);
                 const float4 *nd = nodes + (size_t)kNode * (ent & ~kLeafEntry);
                 if (ent & kLeafEntry) {
-                    // leaf: recheck its oriented box against the current bests, then its triangles
+                    // leaf: recheck its oriented box against the current bests,
+                    // then its triangles for the layers of the tile (node k of
+                    // every lane: LX x LY x LZ nodes) that some node still
+                    // needs; a node whose bound rules the box out cannot gain
+                    // from its triangles, so skipping the others is exact
                     const float4 N0 = nd[0], N1 = nd[1], N2 = nd[2], N3 = nd[3];
-                    bool need = false;
-                    obb_bound<kTZ>(N0, N1, N2, N3, px, py, pz, best, need);
+                    const uint32_t lane_layers = obb_layers<kTZ>(N0, N1, N2, N3, px, py, pz, best);
                     ++n_obb;
-                    if (__ballot(need) == 0) continue;
+                    uint32_t layers = 0;   // wave-uniform
+#pragma unroll
+                    for (int k = 0; k < kTZ; ++k)
+                        if (__ballot((lane_layers >> k) & 1u) != 0) layers |= 1u << k;
+                    if (layers == 0) continue;
                     work += kCostLeaf;
                     const uint32_t word = __float_as_uint(N3.w);
                     const uint32_t first = word & 0x07ffffffu, cnt = ((word >> 27) & 7u) + 1;
-                    n_tri += cnt;
+                    n_tri += cnt * (uint32_t)__popc(layers);
                     for (uint32_t t = first; t < first + cnt; ++t) {
                         const float4 *tr = tri + kTri * (size_t)t;
                         const float4 A = tr[0], B = tr[1], C = tr[2], R = tr[3];
 #pragma unroll
                         for (int k = 0; k < kTZ; ++k) {
+                            if (!(layers & (1u << k))) continue;
                             float v_, w_;
                             const float dd = tri_d2(px, py, pz[k], A, B, C, R, v_, w_);
                             if (dd < best[k]) {
@@ -812,7 +840,7 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
     }
     if (counts && lane == 0) {
         constexpr unsigned long long kNodes = 64ull * kTZ;
-        atomicAdd(counts + 0, kNodes * n_tri + n_seed);
+        atomicAdd(counts + 0, 64ull * n_tri + n_seed);
         atomicAdd(counts + 1, kNodes * n_aabb);
         atomicAdd(counts + 2, kNodes * n_obb);
         atomicAdd(counts + 3, kNodes * n_tiles);
