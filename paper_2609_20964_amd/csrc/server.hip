@@ -28,8 +28,8 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
-#include <functional>
 #include <deque>
+#include <functional>
 #include <list>
 #include <map>
 #include <mutex>
