@@ -258,7 +258,8 @@ def exact_summary(res, copy_gbs):
             "phase_ms_plain": {k: float(np.mean([s["ms"][i] for s in st]))
                                for i, k in enumerate(["splat", "solve", "iso", "surface", "sdf"])},
             "splat_kernel_ms": e["splat"]["ms"] / 2,
-            "solver_roofline": solver_hbm({"solver_kinds": e["solver_kinds"], "solve_ms": e["solve_ms"]}, copy_gbs),
+            "solver_roofline": solver_hbm({"solver_kinds": e["solver_kinds"], "solve_ms": e["solve_ms"]}, copy_gbs,
+                                          counters=False),
             "kernels": "k_splat_chunks<kSplatExact>, k_stencil27<OpPMatvec> (sweep), k_stencil27<OpResid64> "
                        "(resid64), k_stencil27<OpJacobi27a/b> + k_vc_pre (smooth)",
             "workload": "the headline clouds and grid, exact-quadrature system, plain steps, rel res "
@@ -277,11 +278,38 @@ KIND_KERNEL = {"sweep": "k_stencil4<OpPMatvec>", "smooth": "k_vc_pre", "resid64"
 SOLVER_KINDS = ("sweep", "smooth", "resid64", "transfer", "cgupdate")
 
 
-def solver_hbm(res, copy_gbs=None):
+# the kernel of each solver kind whose counter row prices the kind's bytes
+SOLVER_PMC_ROW = {"sweep": "k_stencil4<OpPMatvec<false> >", "smooth": "k_vc_pre", "transfer": "k_vc_post<true>",
+                  "resid64": "k_stencil4<OpResid64<float> >", "cgupdate": "k_cg_update<false>"}
+
+
+def solver_counter_ratios(path=None):
+    """Counter bytes over algorithmic bytes per solver kind, from the committed
+    rocprofv3 summary of the finest-level kernels (calibrated FETCH_SIZE +
+    WRITE_SIZE), if it was taken on the current solver source; else {}."""
+    path = path or os.path.join(ROOT, "profiles", "pmc_solver_flapping256.txt")
+    if not os.path.exists(path):
+        return {}
+    rows, sha = {}, None
+    for line in open(path):
+        if line.startswith("# source_sha "):
+            sha = line.split()[2]
+        elif line.startswith("  ") and len(line) > 46:
+            nums = line[46:].split("#")[0].split()
+            if len(nums) == 5:
+                rows[line[2:46].strip()] = float(nums[2]) / float(nums[3])
+    if sha != source_sha("paper_2609_20964_amd/csrc/solver.hip"):
+        return {}
+    return {k: rows[name] for k, name in SOLVER_PMC_ROW.items() if name in rows}
+
+
+def solver_hbm(res, copy_gbs=None, counters=True):
     """HBM roofline of the Poisson solve taken as a whole: algorithmic bytes of
     its bandwidth-bound kernels over (a) their own event-timed duration and
     (b) the whole solve phase (reductions, coarse solve and host waits
-    included); both also against a measured device copy."""
+    included); both also against a measured device copy, and the kernels'
+    bytes as the counters measured them (each kind priced by its finest-level
+    kernel's counter/algorithmic ratio) over their duration."""
     kinds = res["solver_kinds"]
     units = sum(v["units"] for v in kinds.values())
     ms = sum(v["ms"] for v in kinds.values())
@@ -298,6 +326,10 @@ def solver_hbm(res, copy_gbs=None):
     if copy_gbs:
         out.update({"copy_GB_s": copy_gbs, "kernels_frac_of_copy": out["kernels_GB_s"] / copy_gbs,
                     "phase_frac_of_copy": out["phase_GB_s"] / copy_gbs})
+    ratios = solver_counter_ratios() if counters else {}   # the rows are of the 7-point system's kernels
+    if ratios and all(k in ratios for k in kinds):
+        counted = sum(v["units"] * ratios[k] for k, v in kinds.items())
+        out.update({"counter_GB_s": counted / (ms * 1e6), "counter_frac": counted / (ms * 1e6) / HBM_PEAK_GBS})
     return out
 
 

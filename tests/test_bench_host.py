@@ -66,6 +66,31 @@ def test_solver_roofline_against_peak_and_copy():
     assert s["phase_ms"] == pytest.approx(2.0)
 
 
+def test_solver_counter_bytes_from_the_profile(tmp_path, monkeypatch):
+    # each kind's bytes are priced by its kernel's counter / algorithmic ratio,
+    # from a summary taken on the current solver source only
+    real = bench.source_sha("paper_2609_20964_amd/csrc/solver.hip")
+    rows = {"k_stencil4<OpPMatvec<false> >": 1.25, "k_vc_pre": 1.5, "k_vc_post<true>": 1.0,
+            "k_stencil4<OpResid64<float> >": 1.0, "k_cg_update<false>": 1.0}
+    lines = [f"# source_sha {real} (solver.hip)",
+             f"# {'kernel':<44} {'fetch_MB':>9} {'write_MB':>9} {'total_MB':>9} {'algorithmic_MB':>15} {'ratio':>6}"]
+    for name, r in rows.items():
+        lines.append(f"  {name:<44} {100.0 * r - 50:>9.1f} {50.0:>9.1f} {100.0 * r:>9.1f} {100.0:>15.1f} "
+                     f"{r:>6.2f}   # a comment")
+    path = tmp_path / "pmc_solver_flapping256.txt"
+    path.write_text("\n".join(lines) + "\n")
+    ratios = bench.solver_counter_ratios(str(path))
+    assert ratios == pytest.approx({"sweep": 1.25, "smooth": 1.5, "transfer": 1.0, "resid64": 1.0, "cgupdate": 1.0})
+    stale = tmp_path / "stale.txt"
+    stale.write_text("\n".join(["# source_sha 0123456789abcdef (solver.hip)"] + lines[1:]) + "\n")
+    assert bench.solver_counter_ratios(str(stale)) == {}
+    monkeypatch.setattr(bench, "solver_counter_ratios", lambda path=None: ratios)
+    kinds = {k: {"units": 1e9, "ms": 0.25, "launches": 4} for k in bench.SOLVER_KINDS}
+    s = bench.solver_hbm({"solver_kinds": kinds, "solve_ms": [2.0]})
+    assert s["counter_GB_s"] == pytest.approx(s["kernels_GB_s"] * (1.25 + 1.5 + 3.0) / 5)
+    assert "counter_GB_s" not in bench.solver_hbm({"solver_kinds": kinds, "solve_ms": [2.0]}, counters=False)
+
+
 def test_latency_by_grid():
     grids = [64, 256, 64, 128, 64, 256]
     lat = [0.001, 0.030, 0.003, 0.010, 0.002, 0.040]
