@@ -1090,7 +1090,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs one reconstruction per device and has no "
+        print("bench.py measures one GPU: the library runs one reconstruction per device and has no "
               "multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
