@@ -17,6 +17,11 @@ adjoint     the hand-derived transposes of every linear piece and the
             reverse pass of the whole chain.
 pipeline    forward / backward of the whole chain and the frozen-stencil
             finite-difference protocol.
+galerkin    the Galerkin system with exact quadrature (Eq. 21, 26): the
+            27-point stiffness, the consistent right-hand side, FP64 CG.
+domain      grids over a box or a cloud's bounding box at density d.
+normals     D-PCA normals (Eq. 1-6) and parity orientation with
+            finite-radius detection and the refinement (Eq. 7-14, Sec. 2.2).
 native      ctypes loader of the small C module (csrc/mcdist.c).
 
 Conventions: "grid units" put cell centre (i,j,k) at (i,j,k); world
