@@ -319,11 +319,13 @@ typedef struct {
 
 /* Start a server on `device` with at most max_inflight concurrent requests,
  * each on its own stream, and a device-memory budget for resident handles.
- * Requests start in arrival order, except that requests whose grid has 2^23
- * cells or more (256^3, say: each keeps the whole device busy) take turns:
+ * Requests start in arrival order, except that requests whose grid has 2^21
+ * cells or more (128^3 and 256^3, say: each one's distance walk alone holds
+ * every compute unit) take turns:
  * while one holds the turn, a free slot takes the first smaller request
  * queued.  A turn lasts to the end of the request, or, when another such
- * request was queued as it started, until its distance walk is enqueued (the
+ * request was queued as it started and it has no reverse pass (d_gphi null),
+ * until its distance walk is enqueued (the
  * next one's splat and solve then run beside the walk; that request's
  * stats.ms[4] is reported as 0). */
 int wg_server_create(wg_server **out, size_t hbm_budget_bytes, int max_inflight, int device);

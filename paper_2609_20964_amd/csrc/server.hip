@@ -16,15 +16,18 @@
 //
 // A request whose grid alone keeps every compute unit busy (kFillCells cells
 // or more) gains nothing from overlapping another such request's same phase:
-// both would just take twice as long.  Such requests take turns; while one
-// holds the turn, a free worker takes the first queued request that is
-// smaller, so the large ones keep their arrival order and the small ones fill
-// the gaps.  When another large request is queued as one starts, the turn
-// ends once its distance walk is enqueued: the walk (ALU-bound) runs on the
-// handle's second stream with workgroup slots left free on every compute
-// unit, and the next large request bins, splats and solves (bandwidth-bound)
-// beside it, as consecutive steps of a moving-boundary loop do.  Without a
-// successor the walk keeps the whole device and the turn lasts to the end.
+// both would just take twice as long.  Such requests take turns (all sizes
+// from kFillCells up share one turn: a 128^3 request beside a 256^3 one slowed
+// both); while one holds the turn, a free worker takes the first queued
+// request that is smaller, so the large ones keep their arrival order and the
+// small ones fill the gaps.  When another large request is queued as one
+// starts, the turn ends once its distance walk is
+// enqueued: the walk (ALU-bound) runs on the handle's second stream with
+// workgroup slots left free on every compute unit, and the next request bins,
+// splats and solves (bandwidth-bound) beside it, as consecutive steps of a
+// moving-boundary loop do.  Without a successor, or for a request with a
+// reverse pass (whose adjoint solve would meet the next one's solve), the
+// walk keeps the whole device and the turn lasts to the end.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -52,9 +55,13 @@ struct Key {
     }
 };
 
-// 2^23 cells: a distance walk of 32768 256-node tiles (128 per compute unit)
-// and sweeps of 2^15 or more workgroups
-constexpr size_t kFillCells = size_t(1) << 23;
+// 2^21 cells (128^3) or more: a distance walk of 32768 tiles or more (64-node
+// tiles below 2^23 cells, 256-node ones from there), several times the
+// wavefronts the device holds at once.  Two such walks only queue behind each
+// other and the solves beside them wait for slots: a stream of 128^3 requests
+// alone, served four at a time, ran at 0.77x the rate of one at a time while
+// only 2^23 cells and more took turns, and at 1.20x once 128^3 ones did too.
+constexpr size_t kFillCells = size_t(1) << 21;
 
 bool fills_device(const wg_grid &g) { return (size_t)g.n[0] * g.n[1] * g.n[2] >= kFillCells; }
 
@@ -90,7 +97,8 @@ struct Job {
 
 class Server {
   public:
-    Server(size_t budget, int max_inflight, int device) : budget_(budget), device_(device) {
+    Server(size_t budget, int max_inflight, int device)
+        : budget_(budget), device_(device), inflight_(max_inflight) {
         WG_HIP(hipSetDevice(device_));
         WG_HIP(hipStreamCreateWithFlags(&ingest_, hipStreamNonBlocking));
         t0_ = std::chrono::steady_clock::now();
@@ -273,20 +281,18 @@ class Server {
         }
     }
 
-    // alone: no other request was running when this one started.  A lone
-    // request's distance walk runs persistent (fastest alone); with others
-    // running, walks go one workgroup per tile group so concurrent requests
-    // interleave instead of queueing behind a walk that holds every slot.  A
-    // device-filling request runs it persistent in any case.  pipe (a
+    // persistent: the distance walk runs persistent (fastest alone), for a
+    // request that started alone and for a device-filling one; otherwise walks
+    // go one workgroup per tile group, so that concurrent requests interleave
+    // instead of queueing behind a walk that holds every slot.  pipe (a
     // device-filling request with another one queued): the walk runs on the
     // handle's second stream with slots left for the next one's solve
     // (pipelined forward), and the turn ends (end_turn) once it is enqueued;
     // the sampling follows the walk there, and finish() joins both and
     // reports a failed walk.
-    void run(Job &j, Handle &h, bool alone, bool pipe, const std::function<void()> &end_turn) {
+    void run(Job &j, Handle &h, bool persistent, bool pipe, const std::function<void()> &end_turn) {
         const wg_request &rq = j.req;
-        const bool fills = fills_device(rq.grid);
-        h.r->set_persistent(alone || fills);
+        h.r->set_persistent(persistent);
         h.r->set_grow_hook([this, &h](size_t extra) { reserve_growth(h, extra); });
         wg_solve_opts o = rq.opts;
         o.warm_start = 0;   // a request's result must not depend on what ran before it
@@ -327,7 +333,11 @@ class Server {
             const bool fills = fills_device(j->req.grid);
             bool turn = fills;   // this request holds the device-filling turn
             bool pipe = false;   // ... and ends it early: another one is queued
-            if (fills)
+            // (not with a reverse pass: its adjoint solve would
+            // meet the next one's solve, each then several times slower; not
+            // with one worker, where nothing could use the slots its walk
+            // leaves free)
+            if (fills && !j->gphi && inflight_ > 1)
                 for (const Job *q : queue_) pipe = pipe || fills_device(q->req.grid);
             fill_running_ += fills;
             ++running_;
@@ -352,10 +362,10 @@ class Server {
                 h = acquire(k, j->req.grid, lk);
                 have = true;
                 j->res.t_start = now();
-                const bool alone = running_ == 1;
+                const bool persistent = running_ == 1 || fills;
                 lk.unlock();
                 try {
-                    run(*j, h, alone, pipe, end_turn);
+                    run(*j, h, persistent, pipe, end_turn);
                 } catch (const Error &e) {
                     set_error(e.what());
                     j->res.status = e.code;
@@ -405,6 +415,7 @@ class Server {
     std::vector<std::thread> workers_;
     size_t resident_ = 0;
     uint64_t next_ticket_ = 0, clock_ = 0;
+    int inflight_;
     int running_ = 0, fill_running_ = 0;
     bool stop_ = false;
 };

@@ -133,16 +133,18 @@ def test_admission_by_footprint_and_rejection():
     srv.close()
 
 
-def test_device_filling_requests_take_turns():
-    """Two 256^3 requests (each fills the device alone) take turns in arrival
-    order: the second starts only once the first has binned, splatted, solved
-    and extracted its surface (its distance walk then runs beside the second's
-    solve), smaller ones may run beside them, and the two give the same field."""
+@pytest.mark.parametrize("n", [128, 256])
+def test_device_filling_requests_take_turns(n):
+    """Two 128^3 or two 256^3 requests (each one's walk fills the device alone)
+    take turns in arrival order: the second starts only once the first has
+    binned, splatted, solved and extracted its surface (its distance walk then
+    runs beside the second's solve), smaller ones may run beside them, and the
+    two give the same field."""
     from paper_2609_20964_amd.serving import Server
     srv = Server(hbm_budget_bytes=16 << 30, max_inflight=3)
     x, nn = synth.sphere(20000, seed=603)
     q = synth.uniform_queries(1024, 604)
-    reqs = [(256, x, nn), (256, x, nn), (32, *synth.sphere(4000, seed=605)), (64, *synth.sphere(8000, seed=606))]
+    reqs = [(n, x, nn), (n, x, nn), (32, *synth.sphere(4000, seed=605)), (64, *synth.sphere(8000, seed=606))]
     tickets = [srv.submit(n, _cuda(a), _cuda(b), _cuda(q), rel_tol=1e-6) for n, a, b in reqs]
     results = _wait(srv, tickets)
     assert all(st == 0 for st, _, _ in results), [r[2] for r in results]
@@ -152,52 +154,51 @@ def test_device_filling_requests_take_turns():
     turn_s = sum(i0["stats"]["ms"][:4]) / 1e3
     print("first", i0["t_start"], i0["t_done"], "turn", turn_s, "second", i1["t_start"], i1["t_done"], flush=True)
     assert i1["t_start"] >= i0["t_start"] + 0.9 * turn_s, (i0, i1)
-    assert np.abs(o0["phi"].cpu().numpy() - o1["phi"].cpu().numpy()).max() <= 1e-4 / 256
+    assert np.abs(o0["phi"].cpu().numpy() - o1["phi"].cpu().numpy()).max() <= 1e-4 / n
     srv.close()
 
 
 def test_device_filling_successor_runs_beside_the_walk():
     """A 256^3 request that starts with another one queued runs the pipelined
     forward: its turn ends once its distance walk is enqueued (its walk time is
-    then reported as 0) and the next one may start beside the walk; its field,
-    normals and gradients equal those of the same request reconstructed alone,
-    and so does the field of the second (which starts with nothing queued and
-    keeps its turn to the end).  Two 128^3 requests of 10^6 points hold both
-    slots while the two 256^3 ones are queued, so the first of them starts
-    with the second queued."""
+    then reported as 0) and the next one may start beside the walk.  A request
+    with a reverse pass keeps its turn to the end even with a successor queued
+    (its adjoint solve would meet the successor's solve), so that successor
+    starts only once it is done.  Fields, normals and gradients equal those of
+    the same request reconstructed alone.  A first 256^3 request holds the turn
+    while the others are submitted, so they are all queued behind it."""
     from paper_2609_20964_amd.recon import Recon
     from paper_2609_20964_amd.serving import Server
-    blk = [tuple(_cuda(a) for a in synth.sphere(1000000, seed=630 + k)) for k in range(2)]
     c = synth.draw_star_coeffs(632)
     xa, na = (_cuda(a) for a in synth.star(c, 60000, 633))
     q = _cuda(synth.uniform_queries(4096, 634))
-    qb = _cuda(synth.uniform_queries(1024, 636))
     gphi = _cuda(np.random.default_rng(635).standard_normal(4096) / 4096)
     srv = Server(hbm_budget_bytes=16 << 30, max_inflight=2)
-    tickets = [srv.submit(128, x, n, qb) for x, n in blk]
+    tickets = [srv.submit(256, xa, na, q, rel_tol=1e-6) for _ in range(2)]
     tickets.append(srv.submit(256, xa, na, q, gphi=gphi, rel_tol=1e-6))
     tickets.append(srv.submit(256, xa, na, q, rel_tol=1e-6))
     results = _wait(srv, tickets)
     srv.close()
     assert all(st == 0 for st, _, _ in results), [r[2] for r in results]
-    (_, oa, ia), (_, ob, ib) = results[2], results[3]
-    turn_s = sum(ia["stats"]["ms"][:4]) / 1e3
-    print("first", ia["t_start"], ia["t_done"], "turn", turn_s, "walk ms", ia["stats"]["ms"][4],
-          "second", ib["t_start"], ib["t_done"], "walk ms", ib["stats"]["ms"][4], flush=True)
-    assert ia["stats"]["ms"][4] == 0.0 and ib["stats"]["ms"][4] > 0.0
-    assert ib["t_start"] >= ia["t_start"] + 0.9 * turn_s
+    (_, ob, ib), (_, oc, ic), (_, od, id_) = results[1:]
+    turn_s = sum(ib["stats"]["ms"][:4]) / 1e3
+    for name, i in (("second", ib), ("third (reverse pass)", ic), ("fourth", id_)):
+        print(name, i["t_start"], i["t_done"], "walk ms", i["stats"]["ms"][4], flush=True)
+    assert ib["stats"]["ms"][4] == 0.0 and ic["stats"]["ms"][4] > 0.0
+    assert ic["t_start"] >= ib["t_start"] + 0.9 * turn_s
+    assert id_["t_start"] >= ic["t_done"]
     r = Recon(256, 60000)
     r.forward(xa, na, rel_tol=1e-6)
     phi, nrm = r.sample(q)
     gx, gn, _ = r.backward(q, gphi, rel_tol=1e-6)
     r.close()
     h = 1.0 / 256
-    assert np.abs(oa["phi"].cpu().numpy() - phi.cpu().numpy()).max() <= 1e-4 * h
-    assert np.abs(ob["phi"].cpu().numpy() - phi.cpu().numpy()).max() <= 1e-4 * h
     ok = np.linalg.norm(nrm.cpu().numpy(), axis=1) > 0
-    assert angle(oa["nrm"].cpu().numpy()[ok], nrm.cpu().numpy()[ok]).max() <= 1e-3
-    assert _close(oa["g_xyz"].cpu().numpy(), gx.cpu().numpy())
-    assert _close(oa["g_nrm"].cpu().numpy(), gn.cpu().numpy())
+    for _, o, _ in results:
+        assert np.abs(o["phi"].cpu().numpy() - phi.cpu().numpy()).max() <= 1e-4 * h
+        assert angle(o["nrm"].cpu().numpy()[ok], nrm.cpu().numpy()[ok]).max() <= 1e-3
+    assert _close(oc["g_xyz"].cpu().numpy(), gx.cpu().numpy())
+    assert _close(oc["g_nrm"].cpu().numpy(), gn.cpu().numpy())
 
 
 def _close(got, want, tol=1e-3, comp_tol=1e-2):
