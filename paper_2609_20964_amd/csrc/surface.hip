@@ -75,8 +75,9 @@ inline uint32_t walk_tiles(const Dims &d) {
 // A walk with no related walk before it (a new handle, or a cloud unrelated to
 // the last) orders its tiles by an estimate taken from the node sides: the
 // costliest tiles lie deep inside a body, where many triangles are at nearly
-// the same distance.  A tile with no outside node gets its depth in tile steps
-// (4 cells across x and y, 16 along z) to the nearest tile that has one, by
+// the same distance.  A tile with no outside node gets its depth in steps of 4
+// cells (a tile across x and y; 16-cell tiles count four along z) to the
+// nearest tile that has one, by
 // kDepthPasses relaxation passes over the tile grid; deeper tiles tie.  Every
 // other tile ranks below them by its count of inside nodes.
 constexpr int kDepthPasses = 12;
@@ -1066,9 +1067,10 @@ __global__ __launch_bounds__(256) void k_walk_order(const uint32_t *__restrict__
 
 // One wavefront per tile, lanes as in the walk: kTileFull with an unknown
 // depth if no node of the tile is outside, else its count of inside nodes.
+template <int KZ>
 __global__ __launch_bounds__(256) void k_tile_sides(const uint32_t *__restrict__ side, Dims d,
                                                      uint32_t *__restrict__ out) {
-    constexpr int LX = kWalkLX, LY = kWalkLY, LZ = kWalkLZ, KZ = kWalkKZ, TZ = LZ * KZ;
+    constexpr int LX = kWalkLX, LY = kWalkLY, LZ = kWalkLZ, TZ = LZ * KZ;
     const int lane = threadIdx.x % 64;
     const int tx = (d.nx + LX - 1) / LX, ty = (d.ny + LY - 1) / LY, tz = (d.nz + TZ - 1) / TZ;
     const uint32_t tile = blockIdx.x * 4 + threadIdx.x / 64;
@@ -1094,10 +1096,11 @@ __global__ __launch_bounds__(256) void k_tile_sides(const uint32_t *__restrict__
 // One relaxation pass of the depths (one thread per tile); tiles beyond the
 // grid count as outside.  last: write the sort keys instead, 512 << depth for
 // tiles with no outside node (above any inside count), the count otherwise.
+template <int KZ>
 __global__ __launch_bounds__(256) void k_tile_depth(const uint32_t *__restrict__ in, Dims d, uint32_t *__restrict__ out,
                                                      bool last) {
     const int tx = (d.nx + kWalkLX - 1) / kWalkLX, ty = (d.ny + kWalkLY - 1) / kWalkLY,
-              tz = (d.nz + kWalkLZ * kWalkKZ - 1) / (kWalkLZ * kWalkKZ);
+              tz = (d.nz + kWalkLZ * KZ - 1) / (kWalkLZ * KZ);
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (uint32_t)(tx * ty * tz)) return;
     uint32_t v = in[t];
@@ -1113,8 +1116,8 @@ __global__ __launch_bounds__(256) void k_tile_depth(const uint32_t *__restrict__
         m = min(m, dep(bx + 1, by, bz) + 1u);
         m = min(m, dep(bx, by - 1, bz) + 1u);
         m = min(m, dep(bx, by + 1, bz) + 1u);
-        m = min(m, dep(bx, by, bz - 1) + 4u);
-        m = min(m, dep(bx, by, bz + 1) + 4u);
+        m = min(m, dep(bx, by, bz - 1) + (uint32_t)KZ);   // a tile is KZ times as tall as wide
+        m = min(m, dep(bx, by, bz + 1) + (uint32_t)KZ);
         v = kTileFull | m;
     }
     if (last) v = (v & kTileFull) ? (512u << min(v & 0xffffu, kDepthCap)) : v;
@@ -1597,16 +1600,19 @@ static void launch_sdf_coop(const Dims &d, const uint32_t *sign, double h, const
 void Surface::sdf(double h, float *phi, int32_t *argmin, int *err, hipStream_t s, bool beside, bool related) {
     const unsigned blocks = !persistent_ ? ~0u : beside ? sdf_blocks_beside_ : sdf_blocks_full_;
     // Tile order: the last walk's costs when that walk was of a related
-    // surface; on large grids otherwise the estimate from the node sides (the
-    // walk_order_ buffer holds the alternate relaxation passes).
-    const bool cold = d_.count() >= kSeedMinNodes && (!related || !have_order_);
+    // surface; from kCoopMaxNodes nodes up otherwise the estimate from the
+    // node sides (the walk_order_ buffer holds the alternate relaxation passes).
+    const bool cold = d_.count() >= kCoopMaxNodes && (!related || !have_order_);
     if (cold) {
         const uint32_t nt = walk_tiles(d_);
-        k_tile_sides<<<cdiv(nt, 4), 256, 0, s>>>(sign_, d_, tile_cost_);
+        const bool tall = walk_kz(d_) == kWalkKZ;
+        if (tall) k_tile_sides<kWalkKZ><<<cdiv(nt, 4), 256, 0, s>>>(sign_, d_, tile_cost_);
+        else k_tile_sides<kWalkKZSmall><<<cdiv(nt, 4), 256, 0, s>>>(sign_, d_, tile_cost_);
         for (int p = 0; p < kDepthPasses; ++p) {
             const bool even = p % 2 == 0;
-            k_tile_depth<<<cdiv(nt, 256), 256, 0, s>>>(even ? tile_cost_ : walk_order_, d_,
-                                                        even ? walk_order_ : tile_cost_, p == kDepthPasses - 1);
+            uint32_t *src = even ? tile_cost_ : walk_order_, *dst = even ? walk_order_ : tile_cost_;
+            if (tall) k_tile_depth<kWalkKZ><<<cdiv(nt, 256), 256, 0, s>>>(src, d_, dst, p == kDepthPasses - 1);
+            else k_tile_depth<kWalkKZSmall><<<cdiv(nt, 256), 256, 0, s>>>(src, d_, dst, p == kDepthPasses - 1);
         }
         k_walk_order<<<kWalkParts, 256, 0, s>>>(tile_cost_, nt, walk_order_);
         WG_LAUNCH_CHECK();
