@@ -11,8 +11,9 @@
 // other classes are evicted (least recently used first) to make room, and a
 // worker waits when everything resident is busy.  Every handle owns its own
 // HIP stream, so the kernels of concurrent requests overlap on the device; a
-// request that starts alone runs its distance walk persistent, one that starts
-// beside others runs it as independent workgroups (see run()).
+// request that starts alone, or fills the device (below), runs its distance
+// walk persistent, one that starts beside others runs it as independent
+// workgroups (see run()).
 //
 // A request whose grid alone keeps every compute unit busy (kFillCells cells
 // or more) gains nothing from overlapping another such request's same phase:
@@ -21,13 +22,14 @@
 // both); while one holds the turn, a free worker takes the first queued
 // request that is smaller, so the large ones keep their arrival order and the
 // small ones fill the gaps.  When another large request is queued as one
-// starts, the turn ends once its distance walk is
-// enqueued: the walk (ALU-bound) runs on the handle's second stream with
-// workgroup slots left free on every compute unit, and the next request bins,
-// splats and solves (bandwidth-bound) beside it, as consecutive steps of a
-// moving-boundary loop do.  Without a successor, or for a request with a
-// reverse pass (whose adjoint solve would meet the next one's solve), the
-// walk keeps the whole device and the turn lasts to the end.
+// starts, the turn ends once its distance walk is enqueued: the walk
+// (ALU-bound) runs on the handle's second stream with workgroup slots left
+// free on every compute unit, and the next request bins, splats and solves
+// (bandwidth-bound) beside it, as consecutive steps of a moving-boundary loop
+// do.  Without a successor, for a request with a reverse pass (whose adjoint
+// solve would meet the next one's solve), and on a server with one worker
+// (where nothing could use the free slots), the walk keeps the whole device
+// and the turn lasts to the end.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
