@@ -93,6 +93,9 @@ template <class T>
 __global__ void k_fixed_to_b(const long long *acc, const FixedScale *fix, size_t n, T *b);
 __global__ void k_iso_partial(const float *xyz, int npts, GridF g, const double *chi, double *partials);
 __global__ void k_iso_finalize(const double *partials, int nb, int npts, double *out);
+__global__ void k_iso_absmax(const float *xyz, int npts, GridF g, const double *chi, unsigned long long *w);
+__global__ void k_iso_fixed(const float *xyz, int npts, GridF g, const double *chi, unsigned long long *w);
+__global__ void k_iso_fixed_finalize(const unsigned long long *w, int npts, double *out);
 __global__ void k_iso_T(const float *xyz, int npts, GridF g, const double *g_c, float *g_chi);
 // three cell fields (the exact-quadrature g_V by axis)
 struct Planes3 {

@@ -271,12 +271,21 @@ int Recon::forward(const float *xyz, const float *nrm, int npts, const wg_solve_
     if (sr.status == WG_ENUMERIC) throw Error(WG_ENUMERIC, "non-finite value in the Poisson solve");
     chi_mean_ = sr.x_mean;
     tm.mark(2);
-    // iso-value c = mean of chi_h at the points (0 without points)
+    // iso-value c = mean of chi_h at the points (0 without points); summed in
+    // fixed point, whatever the points' order, where the splat was
     if (npts > 0) {
         unsigned nb = cdiv(npts, 256);
         if (nb > (unsigned)kIsoBlocks) nb = kIsoBlocks;
-        k_iso_partial<<<nb, 256, 0, st_>>>(xyz_, npts, gf_, chi_, iso_part_);
-        k_iso_finalize<<<1, 256, 0, st_>>>(iso_part_, nb, npts, scal_);
+        if (fixed) {
+            auto *w = reinterpret_cast<unsigned long long *>(iso_part_);
+            WG_HIP(hipMemsetAsync(w, 0, 2 * sizeof(unsigned long long), st_));
+            k_iso_absmax<<<nb, 256, 0, st_>>>(xyz_, npts, gf_, chi_, w);
+            k_iso_fixed<<<nb, 256, 0, st_>>>(xyz_, npts, gf_, chi_, w);
+            k_iso_fixed_finalize<<<1, 1, 0, st_>>>(w, npts, scal_);
+        } else {
+            k_iso_partial<<<nb, 256, 0, st_>>>(xyz_, npts, gf_, chi_, iso_part_);
+            k_iso_finalize<<<1, 256, 0, st_>>>(iso_part_, nb, npts, scal_);
+        }
     } else {
         WG_HIP(hipMemsetAsync(scal_, 0, sizeof(double), st_));
         k_shift_scalar<<<1, 1, 0, st_>>>(scal_, -chi_mean_, scal_);

@@ -115,6 +115,7 @@ class Solver {
     const int *skip_ = nullptr;   // &dsc_->done while an inner PCG runs, else null
     float *coarseM_[2] = {nullptr, nullptr};   // [bc] 1-D eigenbases of the coarsest level
     int coarse_direct_ = 0;
+    bool eig64_ = false;   // the exact solve's slices are 64 x 64 (an extent above 32)
     unsigned post_blocks_ = 0;   // workgroups of the finest post-smoothing pass (partials of r.z)
     int bc_sign_ = -1;
     bool exact_ = false;   // fine-level operator: the 27-point exact-quadrature stiffness

@@ -24,7 +24,11 @@ constexpr int kRedBlocks = 2048;     // grid of the pointwise reductions
 constexpr int kMaxRed = 5;
 constexpr float kOmega = 6.0f / 7.0f;   // weighted-Jacobi factor of the sweeps on an odd-sized coarsest level
 constexpr int kCoarseTarget = 32;       // coarsen until every extent is <= this (or odd)
-constexpr int kCoarseAxis = 32;         // exact coarsest solve when every extent is <= this
+// Exact coarsest solve when every extent is <= kDirectAxis; a grid whose every
+// extent is that small is solved on one level, the exact solve being the whole
+// preconditioner (64^3 serving requests: about one inner iteration per
+// refinement instead of three to four V-cycled ones).
+constexpr int kDirectAxis = 64;
 
 // An inner PCG enqueues its next iteration before the host has seen whether
 // the current one stopped it; once a finalize has set the flag, the kernels of
@@ -1134,112 +1138,123 @@ __global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const 
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
 }
 
-// Exact solve on the coarsest level (every extent <= kCoarseAxis) by the
+// Exact solve on the coarsest level (every extent <= kDirectAxis) by the
 // separable eigenbasis of the 7-point operator: transform along x, y, z with
 // the orthonormal 1-D bases, divide by lambda_x + lambda_y + lambda_z (the
 // constant mode is dropped), transform back.  Three small kernels: the x and
 // y transforms of one z plane per workgroup, then the z transform, division
 // and inverse z transform of one y row of coefficients per workgroup, then
 // the inverse y and x transforms per z plane.  Each workgroup stages its
-// 32 x 32 slice and the bases in LDS (rows padded to 33 floats; the bases
-// stored so that a wavefront's lanes read consecutive or identical entries)
-// and computes four outputs per thread.  E = [phi_x (cx*cx), phi_y (cy*cy),
+// N x N slice (N = 32 or 64) and the bases in LDS (the bases stored so that a
+// wavefront's lanes read consecutive or identical entries) and computes N / 8
+// or N / 4 outputs per thread.  E = [phi_x (cx*cx), phi_y (cy*cy),
 // phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] = mode m at cell i.
-constexpr int kEigN = kCoarseAxis;
-constexpr int kEigG = 256 / kEigN;   // row groups of a 256-thread workgroup
-static_assert(256 % kEigN == 0, "a row of the slice is a whole number of lanes");
+// N: the slice edge, 32 or 64 (every extent of the level at most N).  At
+// N = 32 a wavefront spans two rows of a slice, so rows are padded; at N = 64
+// a wavefront is one row group, every slice access is a run of consecutive
+// entries or one broadcast entry, and four unpadded 64 x 64 arrays fill the
+// 64 KiB a workgroup may hold.
+template <int N> struct Eig {
+    static_assert(N == 32 || N == 64, "slice edge");
+    static constexpr int G = 256 / N;          // row groups of a 256-thread workgroup
+    static constexpr int P = N == 32 ? 1 : 0;  // row padding
+};
 
 // FWD: c[k][my][mx] = sum_j sum_i phi_y[my][j] phi_x[mx][i] f[k][j][i] for z plane k = blockIdx.x;
 // inverse: f[k][j][i] = sum_my sum_mx phi_y[my][j] phi_x[mx][i] c[k][my][mx].
-template <bool FWD>
+template <int N, bool FWD>
 __global__ __launch_bounds__(256) void k_eig_plane(const float *__restrict__ src, float *__restrict__ dst,
                                                    const float *__restrict__ E, int cx, int cy, const int *skip) {
     if (skipped(skip)) return;
-    __shared__ float T[kEigN][kEigN + 1];
-    __shared__ float U[kEigN][kEigN + 1];
-    __shared__ float Px[kEigN][kEigN + 1];   // Px[i][m] = phi_x[m][i]
-    __shared__ float Py[kEigN][kEigN + 1];   // Py[j][m] = phi_y[m][j]
+    constexpr int G = Eig<N>::G, P = Eig<N>::P;
+    __shared__ float T[N][N + P];
+    __shared__ float U[N][N + P];
+    // forward: Px[i][m] = phi_x[m][i]; inverse: Px[m][i] = phi_x[m][i] (lanes run along i either way)
+    __shared__ float Px[N][N + P];
+    __shared__ float Py[N][N + P];   // Py[j][m] = phi_y[m][j]
     const size_t plane = (size_t)cx * cy, k = blockIdx.x;
     const float *ex = E, *ey = E + cx * cx;
-    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
-        const int r = o / kEigN, c = o % kEigN;
-        Px[r][c] = (r < cx && c < cx) ? ex[c * cx + r] : 0.f;
+    for (int o = threadIdx.x; o < N * N; o += blockDim.x) {
+        const int r = o / N, c = o % N;
+        Px[r][c] = (r < cx && c < cx) ? (FWD ? ex[c * cx + r] : ex[r * cx + c]) : 0.f;
         Py[r][c] = (r < cy && c < cy) ? ey[c * cy + r] : 0.f;
         T[r][c] = (r < cy && c < cx) ? src[k * plane + (size_t)r * cx + c] : 0.f;
     }
     __syncthreads();
-    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;   // lane in a row, kEigG row groups
+    const int a = threadIdx.x % N, g = threadIdx.x / N;   // lane in a row, G row groups
     if (FWD) {
-        for (int j = g; j < kEigN; j += kEigG) {   // along x: U[j][m] = sum_i phi_x[m][i] T[j][i]
+        for (int j = g; j < N; j += G) {   // along x: U[j][m] = sum_i phi_x[m][i] T[j][i]
             float acc = 0.f;
 #pragma unroll 8
-            for (int i = 0; i < kEigN; ++i) acc += Px[i][a] * T[j][i];
+            for (int i = 0; i < N; ++i) acc += Px[i][a] * T[j][i];
             U[j][a] = acc;
         }
         __syncthreads();
-        for (int my = g; my < kEigN; my += kEigG) {   // along y: T[my][m] = sum_j phi_y[my][j] U[j][m]
+        for (int my = g; my < N; my += G) {   // along y: T[my][m] = sum_j phi_y[my][j] U[j][m]
             float acc = 0.f;
 #pragma unroll 8
-            for (int j = 0; j < kEigN; ++j) acc += Py[j][my] * U[j][a];
+            for (int j = 0; j < N; ++j) acc += Py[j][my] * U[j][a];
             T[my][a] = acc;
         }
     } else {
-        for (int j = g; j < kEigN; j += kEigG) {   // along y: U[j][m] = sum_my phi_y[my][j] T[my][m]
+        for (int j = g; j < N; j += G) {   // along y: U[j][m] = sum_my phi_y[my][j] T[my][m]
             float acc = 0.f;
 #pragma unroll 8
-            for (int my = 0; my < kEigN; ++my) acc += Py[j][my] * T[my][a];
+            for (int my = 0; my < N; ++my) acc += Py[j][my] * T[my][a];
             U[j][a] = acc;
         }
         __syncthreads();
-        for (int j = g; j < kEigN; j += kEigG) {   // along x: T[j][i] = sum_m phi_x[m][i] U[j][m]
+        for (int j = g; j < N; j += G) {   // along x: T[j][i] = sum_m phi_x[m][i] U[j][m]
             float acc = 0.f;
 #pragma unroll 8
-            for (int m = 0; m < kEigN; ++m) acc += Px[a][m] * U[j][m];
+            for (int m = 0; m < N; ++m) acc += Px[m][a] * U[j][m];
             T[j][a] = acc;
         }
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
-        const int r = o / kEigN, c = o % kEigN;
+    for (int o = threadIdx.x; o < N * N; o += blockDim.x) {
+        const int r = o / N, c = o % N;
         if (r < cy && c < cx) dst[k * plane + (size_t)r * cx + c] = T[r][c];
     }
 }
 
 // In place on the coefficients of y mode my = blockIdx.x: transform along z,
 // divide by the eigenvalue (0 for the constant mode), transform back.
+template <int N>
 __global__ __launch_bounds__(256) void k_eig_z(float *__restrict__ buf, const float *__restrict__ E, int cx, int cy,
                                                int cz, const int *skip) {
     if (skipped(skip)) return;
-    __shared__ float V[kEigN][kEigN + 1];
-    __shared__ float Wz[kEigN][kEigN + 1];
-    __shared__ float Pz[kEigN][kEigN + 1];   // Pz[k][n] = phi_z[n][k]
-    __shared__ float lx[kEigN], lz[kEigN];
+    constexpr int G = Eig<N>::G, P = Eig<N>::P;
+    __shared__ float V[N][N + P];
+    __shared__ float Wz[N][N + P];
+    __shared__ float Pz[N][N + P];   // Pz[k][n] = phi_z[n][k]
+    __shared__ float lx[N], lz[N];
     const size_t plane = (size_t)cx * cy, my = blockIdx.x;
     const float *ez = E + cx * cx + cy * cy, *lam = ez + cz * cz;
-    for (int o = threadIdx.x; o < kEigN * kEigN; o += blockDim.x) {
-        const int r = o / kEigN, c = o % kEigN;
+    for (int o = threadIdx.x; o < N * N; o += blockDim.x) {
+        const int r = o / N, c = o % N;
         Pz[r][c] = (r < cz && c < cz) ? ez[c * cz + r] : 0.f;
         V[r][c] = (r < cz && c < cx) ? buf[(size_t)r * plane + my * cx + c] : 0.f;
     }
-    if (threadIdx.x < kEigN) {
+    if (threadIdx.x < N) {
         lx[threadIdx.x] = threadIdx.x < cx ? lam[threadIdx.x] : 0.f;
         lz[threadIdx.x] = threadIdx.x < cz ? lam[cx + cy + threadIdx.x] : 0.f;
     }
     __syncthreads();
     const float ly = lam[cx + my];
-    const int a = threadIdx.x % kEigN, g = threadIdx.x / kEigN;
-    for (int n = g; n < kEigN; n += kEigG) {   // along z and divide: W[n][m] = sum_k phi_z[n][k] V[k][m] / lambda
+    const int a = threadIdx.x % N, g = threadIdx.x / N;
+    for (int n = g; n < N; n += G) {   // along z and divide: W[n][m] = sum_k phi_z[n][k] V[k][m] / lambda
         float acc = 0.f;
 #pragma unroll 8
-        for (int k = 0; k < kEigN; ++k) acc += Pz[k][n] * V[k][a];
+        for (int k = 0; k < N; ++k) acc += Pz[k][n] * V[k][a];
         const float l = lx[a] + ly + lz[n];
         Wz[n][a] = (a < cx && n < cz && l > 1e-12f) ? acc / l : 0.f;
     }
     __syncthreads();
-    for (int k = g; k < cz; k += kEigG) {   // back along z: V[k][m] = sum_n phi_z[n][k] W[n][m]
+    for (int k = g; k < cz; k += G) {   // back along z: V[k][m] = sum_n phi_z[n][k] W[n][m]
         float acc = 0.f;
 #pragma unroll 8
-        for (int n = 0; n < kEigN; ++n) acc += Pz[k][n] * Wz[n][a];
+        for (int n = 0; n < N; ++n) acc += Pz[k][n] * Wz[n][a];
         if (a < cx) buf[(size_t)k * plane + my * cx + a] = acc;
     }
 }
@@ -1373,12 +1388,14 @@ size_t basis_floats(const Dims &c) {
     return (size_t)c.nx * c.nx + (size_t)c.ny * c.ny + (size_t)c.nz * c.nz + c.nx + c.ny + c.nz;
 }
 
-// The multigrid hierarchy: halve every extent while all are even and >= 4 and
-// one exceeds kCoarseTarget.  Returns the level count.
+// The multigrid hierarchy: one level when every extent is <= kDirectAxis (the
+// exact solve alone preconditions), else halve every extent while all are
+// even and >= 4 and one exceeds kCoarseTarget.  Returns the level count.
 int level_dims(int nx, int ny, int nz, Dims (&out)[Solver::kMaxLevels]) {
     Dims d{nx, ny, nz, -1};
     int n = 0;
     out[n++] = d;
+    if (nx <= kDirectAxis && ny <= kDirectAxis && nz <= kDirectAxis) return n;
     while (d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 4 && d.ny >= 4 && d.nz >= 4 &&
            (d.nx > kCoarseTarget || d.ny > kCoarseTarget || d.nz > kCoarseTarget) && n < Solver::kMaxLevels) {
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, -1};
@@ -1427,7 +1444,7 @@ void Solver::plan(Arena &a, int nx, int ny, int nz) {
     a.reserve(sizeof(SolveScalars));
     a.reserve(sizeof(PublishedScalars));
     const Dims &c = dims[nl - 1];
-    if (c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis)
+    if (c.nx <= kDirectAxis && c.ny <= kDirectAxis && c.nz <= kDirectAxis)
         for (int bc = 0; bc < 2; ++bc) a.reserve(basis_floats(c) * sizeof(float));
 }
 
@@ -1469,7 +1486,8 @@ void Solver::bind(Arena &a, int nx, int ny, int nz, hipStream_t s, bool mapped) 
         hsc_ = &host_pub_.s;
     }
     const Dims &c = dims[nlv_ - 1];
-    coarse_direct_ = c.nx <= kCoarseAxis && c.ny <= kCoarseAxis && c.nz <= kCoarseAxis;
+    coarse_direct_ = c.nx <= kDirectAxis && c.ny <= kDirectAxis && c.nz <= kDirectAxis;
+    eig64_ = c.nx > 32 || c.ny > 32 || c.nz > 32;
     if (coarse_direct_) {
         const size_t nf = basis_floats(c);
         for (int bc = 0; bc < 2; ++bc) {
@@ -1571,9 +1589,15 @@ void Solver::vcycle(int l) {
     if (l == last) {
         if (coarse_direct_) {
             const float *E = coarseM_[bc_sign_ > 0 ? 1 : 0];
-            k_eig_plane<true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny, skip_);
-            k_eig_z<<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz, skip_);
-            k_eig_plane<false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny, skip_);
+            if (eig64_) {
+                k_eig_plane<64, true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny, skip_);
+                k_eig_z<64><<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz, skip_);
+                k_eig_plane<64, false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny, skip_);
+            } else {
+                k_eig_plane<32, true><<<L.d.nz, 256, 0, st_>>>(L.rhs, L.x2, E, L.d.nx, L.d.ny, skip_);
+                k_eig_z<32><<<L.d.ny, 256, 0, st_>>>(L.x2, E, L.d.nx, L.d.ny, L.d.nz, skip_);
+                k_eig_plane<32, false><<<L.d.nz, 256, 0, st_>>>(L.x2, L.x, E, L.d.nx, L.d.ny, skip_);
+            }
             WG_LAUNCH_CHECK();
         } else {
             // no direct solve possible (odd extents): a fixed, even number of sweeps

@@ -394,28 +394,68 @@ __device__ __forceinline__ Tri1 tri_axis(float x, double lo, double h, int n) {
 
 }  // namespace
 
+// chi_h at point i, interpolated trilinearly (the indicator values near the
+// samples that the iso-value is taken from, Sec. 2.4)
+__device__ __forceinline__ double iso_point(const float *__restrict__ xyz, int i, const GridF &g,
+                                            const double *__restrict__ chi) {
+    Tri1 X = tri_axis(xyz[3 * i], g.lo[0], g.h, g.d.nx);
+    Tri1 Y = tri_axis(xyz[3 * i + 1], g.lo[1], g.h, g.d.ny);
+    Tri1 Z = tri_axis(xyz[3 * i + 2], g.lo[2], g.h, g.d.nz);
+    const size_t sy = g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
+    const double *c = chi + X.i0 + sy * Y.i0 + sz * Z.i0;
+    double v = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? X.t : 1.0 - X.t) * (dy ? Y.t : 1.0 - Y.t) * (dz ? Z.t : 1.0 - Z.t);
+                v += w * c[dx + sy * dy + sz * dz];
+            }
+    return v;
+}
+
 // Iso-value partial sums: sum_i chi_h(x_i) with chi in FP64 (Sec. 2.4).
 __global__ __launch_bounds__(256) void k_iso_partial(const float *__restrict__ xyz, int npts, GridF g,
                                                       const double *__restrict__ chi, double *partials) {
     double acc[1] = {0.0};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x) {
-        Tri1 X = tri_axis(xyz[3 * i], g.lo[0], g.h, g.d.nx);
-        Tri1 Y = tri_axis(xyz[3 * i + 1], g.lo[1], g.h, g.d.ny);
-        Tri1 Z = tri_axis(xyz[3 * i + 2], g.lo[2], g.h, g.d.nz);
-        const size_t sy = g.d.nx, sz = (size_t)g.d.nx * g.d.ny;
-        const double *c = chi + X.i0 + sy * Y.i0 + sz * Z.i0;
-        double v = 0.0;
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    double w = (dx ? X.t : 1.0 - X.t) * (dy ? Y.t : 1.0 - Y.t) * (dz ? Z.t : 1.0 - Z.t);
-                    v += w * c[dx + sy * dy + sz * dz];
-                }
-        acc[0] += v;
-    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x)
+        acc[0] += iso_point(xyz, i, g, chi);
     __shared__ double lds[4][1];
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = acc[0];
+}
+
+// The same mean independent of the points' order (deterministic requests):
+// the largest |chi_h| at a point (atomicMax on the bits of a non-negative
+// double, which order like integers) fixes a unit 2^-e with npts * max < 2^61
+// units; each point's value rounded to that unit is summed with 64-bit
+// integer atomics, which associate.  w[0]: the bits of the largest value,
+// w[1]: the sum (both zero on entry).
+__device__ __forceinline__ int iso_unit_exp(unsigned long long maxbits, int npts) {
+    const double bound = __longlong_as_double((long long)maxbits) * (double)npts;
+    return bound > 0.0 ? 61 - (int)ceil(log2(bound)) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_iso_absmax(const float *__restrict__ xyz, int npts, GridF g,
+                                                     const double *__restrict__ chi, unsigned long long *w) {
+    unsigned long long m = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(iso_point(xyz, i, g, chi)));
+        m = b > m ? b : m;
+    }
+    if (m) atomicMax(w, m);
+}
+
+__global__ __launch_bounds__(256) void k_iso_fixed(const float *__restrict__ xyz, int npts, GridF g,
+                                                    const double *__restrict__ chi, unsigned long long *w) {
+    const int e = iso_unit_exp(w[0], npts);
+    long long acc = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += gridDim.x * blockDim.x)
+        acc += __double2ll_rn(ldexp(iso_point(xyz, i, g, chi), e));
+    if (acc) atomicAdd(w + 1, (unsigned long long)acc);
+}
+
+__global__ void k_iso_fixed_finalize(const unsigned long long *w, int npts, double *out) {
+    out[0] = ldexp((double)(long long)w[1], -iso_unit_exp(w[0], npts)) / (double)npts;
 }
 
 // c = (sum of partials) / N  (minus nothing: the caller subtracts the field mean)

@@ -1,14 +1,16 @@
 """A plain float64 numpy V-cycle, written from the definition of the Poisson
 solver's multigrid preconditioner z = M r (wg_mg_apply):
 
-* levels halve every extent while all are even and >= 4 and one exceeds 32;
+* one level when every extent is <= 64 (the exact solve below is then the
+  whole preconditioner); else levels halve every extent while all are even
+  and >= 4 and one exceeds 32;
 * pre-smoothing from a zero guess: x = wa rhs, x += wb (rhs - A x);
 * residual restricted with R = P^T / 2, P the cell-centred trilinear
   prolongation (3/4, 1/4 per axis; the missing neighbour past a boundary
   mirrors with sign +1 for zero flux, -1 for the Dirichlet test mode);
 * coarse correction x += P e, then x += wb (rhs - A x), x += wa (rhs - A x);
 * coarsest level: the exact solve (constant mode dropped for zero flux) when
-  every extent is <= 32, else 32 weighted-Jacobi sweeps (omega 6/7);
+  every extent is <= 64, else 32 weighted-Jacobi sweeps (omega 6/7);
 * wa, wb: 1 / (6 lambda_k) at the roots lambda_k of the degree-2 Chebyshev
   polynomial on [0.25, 2].
 
@@ -32,6 +34,8 @@ OMEGA = 6 / 7
 def levels(shape):
     out = [tuple(shape)]
     d = tuple(shape)
+    if all(v <= 64 for v in d):
+        return out
     while all(v % 2 == 0 and v >= 4 for v in d) and any(v > 32 for v in d):
         d = tuple(v // 2 for v in d)
         out.append(d)
@@ -74,7 +78,7 @@ def vcycle(lv, l, rhs, bc):
     """Level l of the V-cycle on the hierarchy lv (shapes [nz, ny, nx])."""
     A = lambda v: D.apply_A(v, bc)  # noqa: E731
     if l == len(lv) - 1:
-        if all(v <= 32 for v in lv[l]):
+        if all(v <= 64 for v in lv[l]):
             return D.solve(rhs, bc)
         dg = diag(lv[l], bc)
         x = OMEGA * rhs / dg
