@@ -104,9 +104,12 @@ typedef struct {
                            bit however points, threads and concurrent requests
                            interleave.  The fixed-point unit is 2^-e with e the
                            largest exponent for which npts * 3.75 h^-2 max|n_k|
-                           fits below 2^61 (a bound on any cell's sum).  Forward
-                           pass only: the reverse pass still scatters with FP32
-                           atomics.  0: FP32 atomics (WG_FP64 implies 1).      */
+                           fits below 2^61 (a bound on any cell's sum).  The
+                           iso-value's mean over the points is summed the same
+                           way (unit from the largest |chi_h| at a point).
+                           Forward pass only: the reverse pass still scatters
+                           with FP32 atomics.  0: FP32 atomics (WG_FP64
+                           implies 1).                                         */
     int quadrature;     /* WG_VERTEX_QUADRATURE (0) or WG_EXACT_QUADRATURE (1)     */
 } wg_solve_opts;
 
@@ -249,7 +252,10 @@ int wg_poisson_solve_noalloc(const wg_grid *grid, const float *d_b, double *d_x,
  * solves (Eq. 20-21 operator, Sec. 2.5's iterative solve) use on r's grid:
  * a V-cycle with cell-centred trilinear prolongation P, restriction P^T / 2,
  * degree-2 Chebyshev smoothing before and after the coarse correction and an
- * exact solve on the coarsest level.  M is symmetric and linear.  d_r, d_z:
+ * exact solve on the coarsest level (32 or 64 cells per axis at most; a grid
+ * whose every extent is at most 64 is that level alone, M = A^-1 up to FP32
+ * rounding, the constant mode dropped under zero flux).  M is symmetric and
+ * linear.  d_r, d_z:
  * float32 [N] on the device (distinct; d_r is not modified); bc as for
  * wg_poisson_solve.  Runs on the handle's stream without blocking the host;
  * shares the solver's work buffers with forward/backward/poisson calls on r,
