@@ -1151,9 +1151,9 @@ __global__ __launch_bounds__(256) void k_dot(const float *__restrict__ a, const 
 // phi_z (cz*cz), lam_x, lam_y, lam_z], phi_a[m * n_a + i] = mode m at cell i.
 // N: the slice edge, 32 or 64 (every extent of the level at most N).  At
 // N = 32 a wavefront spans two rows of a slice, so rows are padded; at N = 64
-// a wavefront is one row group, every slice access is a run of consecutive
-// entries or one broadcast entry, and four unpadded 64 x 64 arrays fill the
-// 64 KiB a workgroup may hold.
+// a wavefront is one row group and every slice access is a run of consecutive
+// entries or one broadcast entry, so the four 64 x 64 arrays go unpadded
+// (64 KiB of LDS per workgroup).
 template <int N> struct Eig {
     static_assert(N == 32 || N == 64, "slice edge");
     static constexpr int G = 256 / N;          // row groups of a 256-thread workgroup

@@ -73,11 +73,11 @@ inline uint32_t walk_tiles(const Dims &d) {
     return cdiv(d.nx, kWalkLX) * cdiv(d.ny, kWalkLY) * cdiv(d.nz, kWalkLZ * walk_kz(d));
 }
 // A walk with no related walk before it (a new handle, or a cloud unrelated to
-// the last) orders its tiles by an estimate taken from the node sides: the
-// costliest tiles lie deep inside a body, where many triangles are at nearly
-// the same distance.  A tile with no outside node gets its depth in steps of 4
-// cells (a tile across x and y; 16-cell tiles count four along z) to the
-// nearest tile that has one, by
+// the last) on a grid of kCoopMaxNodes nodes or more orders its tiles by an
+// estimate taken from the node sides: the costliest tiles lie deep inside a
+// body, where many triangles are at nearly the same distance.  A tile with no
+// outside node gets its depth in steps of 4 cells (a tile across x and y;
+// 16-cell tiles count four along z) to the nearest tile that has one, by
 // kDepthPasses relaxation passes over the tile grid; deeper tiles tie.  Every
 // other tile ranks below them by its count of inside nodes.
 constexpr int kDepthPasses = 12;
@@ -855,16 +855,18 @@ __global__ __launch_bounds__(256, 8) void k_sdf(const uint32_t *__restrict__ sig
 // that: 64^3 serving requests walked in 0.41 ms instead of 0.91.  The split
 // costs work (each wavefront descends its own part before the others' finds
 // prune it), so where tiles outnumber the resident wavefronts it is slower:
-// 128^3, 2.64 ms instead of 2.19.  Wavefront w walks
-// the nodes w, w + 4, ... of one level of the hierarchy (`first`, `n_start`
-// entries, leaves if `leaf_start`); lane l of every wavefront stands for node
-// l of the tile.  The nodes' bests meet in LDS as (squared distance bits << 32
-// | triangle) words under atomicMin, so each wavefront prunes with the others'
-// finds.  A lane takes a triangle whose word is below its best word, and
-// opens every box whose bound is at most its best distance (not only below
-// it), so a tie between triangles goes to the smallest index whatever the
-// timing.  The start level has at most 120 nodes (the highest level with 16 or
-// more), so a wavefront starts with at most 30 entries on its stack.
+// 128^3, 2.64 ms instead of 2.19 (one wavefront per tile, plain order).
+//
+// Wavefront w walks the nodes w, w + 4, ... of one level of the hierarchy
+// (`first`, `n_start` entries, leaves if `leaf_start`); lane l of every
+// wavefront stands for node l of the tile.  The nodes' bests meet in LDS as
+// (squared distance bits << 32 | triangle) words under atomicMin, so each
+// wavefront prunes with the others' finds.  A lane takes a triangle whose
+// word is below its best word, and opens every box whose bound is at most
+// its best distance (not only below it), so a tie between triangles goes to
+// the smallest index whatever the timing.  The start level has at most 120
+// nodes (the highest level with 16 or more), so a wavefront starts with at
+// most 30 entries on its stack.
 constexpr int kCoopStart = 16;
 constexpr size_t kCoopMaxNodes = (size_t)1 << 20;
 constexpr int kStackCoop = 32 + kStack;
